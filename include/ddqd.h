@@ -1,0 +1,118 @@
+/*
+ * ddqd — double-double (DD) and quad-double (QD) matrix products and DD LU
+ * on AMD Instinct MI355X (gfx950).  C ABI of libddqd.so.
+ *
+ * The operations follow Kouya, "Performance evaluation of multiple precision
+ * matrix multiplications using parallelized Strassen and Winograd
+ * algorithms" (arXiv 1510.08642):
+ *   - the product C := AB of an m x l matrix A and an l x n matrix B, any
+ *     sizes, with c_ij = sum_k a_ik b_kj (Sec. 2, Eq. 1), computed by the
+ *     Simple, Block, Strassen or Winograd algorithm (Sec. 2, Sec. 3);
+ *   - LU decomposition by blocks whose trailing update A22 := A22 - L21 U12
+ *     is such a product (Sec. 4, steps 1-3), and the solve of A x = b with
+ *     the factors (Sec. 4, Eq. 2).
+ *
+ * Numbers.  A DD number is an unevaluated sum hi + lo of two doubles (about
+ * 106 bits); a QD number is c0 + c1 + c2 + c3 (about 212 bits).  Inputs are
+ * expected non-overlapping (|lo| <= ulp(hi)/2); outputs are written that way.
+ *
+ * Matrices.  Every matrix argument is a device pointer p to P row-major
+ * float64 planes (P = 2 for DD, 4 for QD): component c of element (i, j) is
+ * p[c*ps + i*ld + j].  ld >= number of columns; ps (plane stride, in
+ * elements) must keep the planes from overlapping.  Only 8-byte alignment is
+ * required.
+ *
+ * Ownership and ordering.  The caller owns every buffer, including the
+ * workspace, whose size it obtains from the matching *_workspace query.  The
+ * library never allocates or frees device memory on these calls.  All work is
+ * enqueued on `stream` (a hipStream_t; NULL = the default stream) and the
+ * calls return without waiting for it.
+ *
+ * Errors.  The return value is decided before anything is enqueued (except
+ * DDQD_E_HIP, a failed launch).  ddqd_last_error() gives a message for the
+ * last failure on the calling thread.  Non-finite inputs give unspecified
+ * results.
+ */
+#ifndef DDQD_H
+#define DDQD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define DDQD_OK 0
+#define DDQD_E_ARG 1         /* an argument is out of range */
+#define DDQD_E_ALIAS 2       /* an output overlaps an input */
+#define DDQD_E_WORKSPACE 3   /* workspace missing or too small */
+#define DDQD_E_UNSUPPORTED 4 /* a valid combination this build does not do */
+#define DDQD_E_NODEVICE 5    /* no usable GPU */
+#define DDQD_E_HIP 6         /* a HIP call or launch failed */
+
+/* algorithms (Sec. 2 and Sec. 3 of the paper) */
+#define DDQD_SIMPLE 0   /* one thread per c_ij, k ascending (Eq. 1)      */
+#define DDQD_BLOCK 1    /* tiled product                                  */
+#define DDQD_STRASSEN 2 /* Strassen's recursion, `levels` deep            */
+#define DDQD_WINOGRAD 3 /* Strassen-Winograd recursion, `levels` deep     */
+
+/* base (leaf) product kernels */
+#define DDQD_BASE_FMA 0      /* FP64 FMA error-free products                 */
+#define DDQD_BASE_OZAKI_I8 1 /* slices on INT8 matrix cores, FP64 recombine  */
+
+/* pivoting for dd_getrf */
+#define DDQD_PIVOT_NONE 0
+#define DDQD_PIVOT_PARTIAL 1
+
+/* Human-readable name of a status code. */
+const char* ddqd_status_string(int status);
+
+/* Message describing the last failed call on this thread ("" if none). */
+const char* ddqd_last_error(void);
+
+/*
+ * C := beta*C + alpha*(A B) in DD (Sec. 2, Eq. 1).
+ *   m, n, l   A is m x l, B is l x n, C is m x n; each >= 0.  m == 0 or
+ *             n == 0 is a no-op; l == 0 gives C := beta*C.
+ *   alpha     +1 or -1.      beta  0 or 1 (0: C is not read).
+ *   A, B, C   device plane-layout DD matrices (2 planes) with leading
+ *             dimensions lda, ldb, ldc and plane strides psa, psb, psc.
+ *             C must not overlap A or B (DDQD_E_ALIAS); A and B may overlap.
+ *   algo      DDQD_SIMPLE, DDQD_BLOCK, DDQD_STRASSEN or DDQD_WINOGRAD.
+ *   levels    recursion depth for Strassen/Winograd (0..6); the depth
+ *             actually used stops early once a dimension would drop below 2.
+ *             Each level splits m, l and n in half; an odd dimension is
+ *             peeled (last row / column handled by rank-1 and panel products).
+ *   base      DDQD_BASE_FMA or DDQD_BASE_OZAKI_I8 for the leaf products
+ *             (ignored by DDQD_SIMPLE).
+ *   slices    Ozaki slice count (0 = automatic); ignored for FMA.
+ *   ws        device workspace of ws_bytes >= dd_gemm_workspace(...) bytes,
+ *             8-byte aligned (may be NULL when that size is 0).
+ *   stream    hipStream_t to enqueue on.
+ */
+int dd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
+            int64_t psa, const double* B, int64_t ldb, int64_t psb, int beta, double* C,
+            int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
+            size_t ws_bytes, void* stream);
+
+/* Workspace bytes dd_gemm needs for these arguments (0 if none; SIZE_MAX if
+ * the arguments are invalid). */
+size_t dd_gemm_workspace(int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
+                         int slices);
+
+/* As dd_gemm, in QD (4 planes per matrix).  base must be DDQD_BASE_FMA. */
+int qd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
+            int64_t psa, const double* B, int64_t ldb, int64_t psb, int beta, double* C,
+            int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
+            size_t ws_bytes, void* stream);
+
+size_t qd_gemm_workspace(int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
+                         int slices);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDQD_H */

@@ -1,0 +1,170 @@
+// Fused add/sub kernels of one Strassen or Strassen-Winograd level.
+//
+// The paper's Strassen and Winograd products (Sec. 2; its figures of the
+// parallel schemes are not available) are read as the textbook formulas.
+// With X = [X11 X12; X21 X22] split into quadrants:
+//
+// Strassen (1969), operands of the seven products M1..M7:
+//   left   A11+A22, A21+A22, A11, A22, A11+A12, A21-A11, A12-A22
+//   right  B11+B22, B11, B12-B22, B21-B11, B22, B11+B12, B21+B22
+//   C11 = M1+M4-M5+M7, C12 = M3+M5, C21 = M2+M4, C22 = M1-M2+M3+M6
+// Strassen-Winograd (7 products, 15 additions), products P1..P7:
+//   S1 = A21+A22, S2 = S1-A11, S3 = A11-A21, S4 = A12-S2
+//   T1 = B12-B11, T2 = B22-T1, T3 = B22-B12, T4 = T2-B21
+//   left   A11, A12, S4, A22, S1, S2, S3
+//   right  B11, B21, B22, T4, T1, T2, T3
+//   U2 = P1+P6, U3 = U2+P7, U4 = U2+P5
+//   C11 = P1+P2, C12 = U4+P3, C21 = U3-P4, C22 = U3+P5
+//
+// One pre-add kernel per operand side reads the four quadrants of every
+// parent once and writes all seven operands of its children (chains such as
+// S1 -> S2 -> S4 stay in registers); one post-add kernel reads the seven
+// products once and writes the four quadrants of the parent, applying
+// C := beta*C + alpha*result at the top level.  All sums are accurate DD
+// (or QD) additions.  These kernels are HBM-bound: per output element a
+// pre-add moves 4 reads + 7 writes, a post-add 7 reads + 4 writes (+4 reads
+// when beta = 1), P doubles each.
+#include "common.hpp"
+#include "eft.hpp"
+#include "qd.hpp"
+
+#pragma clang fp contract(off)
+
+namespace ddqd {
+
+namespace {
+
+template <class N>
+__global__ __launch_bounds__(256) void preadd_kernel(CMat src, Mat dst, int64_t rows,
+                                                     int64_t cols, int algo, int side) {
+  using T = typename N::T;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t p = blockIdx.y;
+  if (e >= rows * cols) return;
+  const int64_t i = e / cols, j = e % cols;
+  const double* s = src.p + p * src.bstride;
+  T x11 = N::load(s, src.ps, i * src.ld + j);
+  T x12 = N::load(s, src.ps, i * src.ld + j + cols);
+  T x21 = N::load(s, src.ps, (i + rows) * src.ld + j);
+  T x22 = N::load(s, src.ps, (i + rows) * src.ld + j + cols);
+  T o[7];
+  if (algo == 2) {  // Strassen
+    if (side == 0) {
+      o[0] = N::add(x11, x22);
+      o[1] = N::add(x21, x22);
+      o[2] = x11;
+      o[3] = x22;
+      o[4] = N::add(x11, x12);
+      o[5] = N::sub(x21, x11);
+      o[6] = N::sub(x12, x22);
+    } else {
+      o[0] = N::add(x11, x22);
+      o[1] = x11;
+      o[2] = N::sub(x12, x22);
+      o[3] = N::sub(x21, x11);
+      o[4] = x22;
+      o[5] = N::add(x11, x12);
+      o[6] = N::add(x21, x22);
+    }
+  } else {  // Winograd
+    if (side == 0) {
+      T s1 = N::add(x21, x22);
+      T s2 = N::sub(s1, x11);
+      T s3 = N::sub(x11, x21);
+      T s4 = N::sub(x12, s2);
+      o[0] = x11;
+      o[1] = x12;
+      o[2] = s4;
+      o[3] = x22;
+      o[4] = s1;
+      o[5] = s2;
+      o[6] = s3;
+    } else {
+      T t1 = N::sub(x12, x11);
+      T t2 = N::sub(x22, t1);
+      T t3 = N::sub(x22, x12);
+      T t4 = N::sub(t2, x21);
+      o[0] = x11;
+      o[1] = x21;
+      o[2] = x22;
+      o[3] = t4;
+      o[4] = t1;
+      o[5] = t2;
+      o[6] = t3;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 7; t++) N::store(dst.p + (7 * p + t) * dst.bstride, dst.ps, i * dst.ld + j, o[t]);
+}
+
+template <class N>
+__global__ __launch_bounds__(256) void postadd_kernel(CMat prod, Mat dst, int64_t rows,
+                                                      int64_t cols, int algo, int alpha,
+                                                      int beta) {
+  using T = typename N::T;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t p = blockIdx.y;
+  if (e >= rows * cols) return;
+  const int64_t i = e / cols, j = e % cols;
+  T M[7];
+#pragma unroll
+  for (int t = 0; t < 7; t++)
+    M[t] = N::load(prod.p + (7 * p + t) * prod.bstride, prod.ps, i * prod.ld + j);
+  T c[4];
+  if (algo == 2) {
+    c[0] = N::add(N::sub(N::add(M[0], M[3]), M[4]), M[6]);
+    c[1] = N::add(M[2], M[4]);
+    c[2] = N::add(M[1], M[3]);
+    c[3] = N::add(N::add(N::sub(M[0], M[1]), M[2]), M[5]);
+  } else {
+    T u2 = N::add(M[0], M[5]);
+    T u3 = N::add(u2, M[6]);
+    T u4 = N::add(u2, M[4]);
+    c[0] = N::add(M[0], M[1]);
+    c[1] = N::add(u4, M[2]);
+    c[2] = N::sub(u3, M[3]);
+    c[3] = N::add(u3, M[4]);
+  }
+  double* d = dst.p + p * dst.bstride;
+  const int64_t off[4] = {i * dst.ld + j, i * dst.ld + j + cols, (i + rows) * dst.ld + j,
+                          (i + rows) * dst.ld + j + cols};
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    T v = alpha < 0 ? N::neg(c[q]) : c[q];
+    if (beta) v = N::add(N::load(d, dst.ps, off[q]), v);
+    N::store(d, dst.ps, off[q], v);
+  }
+}
+
+}  // namespace
+
+template <class N>
+int launch_preadd(CMat src, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
+                  int side, hipStream_t stream) {
+  if (rows <= 0 || cols <= 0 || parents <= 0) return 0;
+  if (parents > 65535) return set_error(4, "too many recursion parents");
+  dim3 grid((unsigned)((rows * cols + 255) / 256), (unsigned)parents);
+  hipLaunchKernelGGL(preadd_kernel<N>, grid, dim3(256), 0, stream, src, dst, rows, cols, algo,
+                     side);
+  return check_launch("preadd_kernel");
+}
+
+template <class N>
+int launch_postadd(CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
+                   int alpha, int beta, hipStream_t stream) {
+  if (rows <= 0 || cols <= 0 || parents <= 0) return 0;
+  if (parents > 65535) return set_error(4, "too many recursion parents");
+  dim3 grid((unsigned)((rows * cols + 255) / 256), (unsigned)parents);
+  hipLaunchKernelGGL(postadd_kernel<N>, grid, dim3(256), 0, stream, prod, dst, rows, cols, algo,
+                     alpha, beta);
+  return check_launch("postadd_kernel");
+}
+
+template int launch_preadd<DDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, hipStream_t);
+template int launch_postadd<DDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, int,
+                                   hipStream_t);
+template int launch_preadd<QDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, hipStream_t);
+template int launch_postadd<QDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, int,
+                                   hipStream_t);
+
+}  // namespace ddqd

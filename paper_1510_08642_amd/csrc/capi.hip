@@ -1,0 +1,344 @@
+// C ABI of libddqd: argument validation, workspace planning and the
+// breadth-first Strassen / Winograd driver (declarations in include/ddqd.h).
+//
+// Recursion plan.  Level j (1..L) of the recursion has 7^j subproblems, all of
+// the same shape m_j x l_j x n_j with m_j = floor(m_{j-1}/2) (likewise l, n).
+// Instead of recursing depth-first (the paper runs the seven products of a
+// level as parallel OpenMP sections), the driver walks the tree breadth-first
+// so every step is one launch over all subproblems of a level:
+//   pre-adds   level 1..L: one kernel per side writes the 7 operands of every
+//              child into workspace (strided batches),
+//   leaves     one batched launch computes all 7^L leaf products,
+//   post-adds  level L..1: one kernel combines 7 products into each parent,
+//              the top level applying C := beta*C + alpha*result,
+//   peeling    where a parent dimension is odd, the last column of A / row of
+//              B (rank-1 update of the even core), the last column of C and
+//              the last row of C are batched Block products on the parents.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "../../include/ddqd.h"
+#include "common.hpp"
+#include "qd.hpp"
+
+namespace ddqd {
+
+int launch_dd_block(const GemmBatch& g, hipStream_t stream);
+int launch_dd_simple(const GemmBatch& g, hipStream_t stream);
+int launch_qd_block(const GemmBatch& g, hipStream_t stream);
+int launch_qd_simple(const GemmBatch& g, hipStream_t stream);
+template <class N>
+int launch_preadd(CMat src, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
+                  int side, hipStream_t stream);
+template <class N>
+int launch_postadd(CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
+                   int alpha, int beta, hipStream_t stream);
+size_t ozaki_workspace(int64_t m, int64_t n, int64_t l, int64_t batch, int slices);
+int launch_ozaki(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, hipStream_t stream);
+int ozaki_default_slices();
+
+static thread_local char g_msg[512];
+
+int set_error(int status, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof g_msg, fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(DDQD_E_HIP, "%s: %s", what, hipGetErrorString(e));
+  return DDQD_OK;
+}
+
+namespace {
+
+constexpr int kMaxLevels = 6;
+
+int64_t pow7(int j) {
+  int64_t r = 1;
+  while (j-- > 0) r *= 7;
+  return r;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Plan {
+  int P = 2, L = 0;
+  int64_t m[kMaxLevels + 1], n[kMaxLevels + 1], l[kMaxLevels + 1];
+  size_t offA[kMaxLevels + 1], offB[kMaxLevels + 1], offM[kMaxLevels + 1];
+  size_t off_leaf = 0, leaf_bytes = 0, total = 0;
+};
+
+// Depth actually used: stop before any dimension of a level's parents drops
+// below 2 (such a parent is a Block product in the paper's scheme too).
+Plan make_plan(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
+               int slices) {
+  Plan pl;
+  pl.P = P;
+  pl.m[0] = m;
+  pl.n[0] = n;
+  pl.l[0] = l;
+  int L = 0;
+  if (algo == DDQD_STRASSEN || algo == DDQD_WINOGRAD) {
+    while (L < levels && pl.m[L] >= 2 && pl.n[L] >= 2 && pl.l[L] >= 2) {
+      pl.m[L + 1] = pl.m[L] / 2;
+      pl.n[L + 1] = pl.n[L] / 2;
+      pl.l[L + 1] = pl.l[L] / 2;
+      L++;
+    }
+  }
+  pl.L = L;
+  size_t off = 0;
+  for (int j = 1; j <= L; j++) {
+    int64_t cnt = pow7(j);
+    pl.offA[j] = off;
+    off = align_up(off + sizeof(double) * (size_t)(cnt * P * pl.m[j] * pl.l[j]));
+    pl.offB[j] = off;
+    off = align_up(off + sizeof(double) * (size_t)(cnt * P * pl.l[j] * pl.n[j]));
+    pl.offM[j] = off;
+    off = align_up(off + sizeof(double) * (size_t)(cnt * P * pl.m[j] * pl.n[j]));
+  }
+  pl.off_leaf = off;
+  if (base == DDQD_BASE_OZAKI_I8 && algo != DDQD_SIMPLE)
+    pl.leaf_bytes = ozaki_workspace(pl.m[L], pl.n[L], pl.l[L], pow7(L), slices);
+  pl.total = off + pl.leaf_bytes;
+  return pl;
+}
+
+// view helpers for level-j batches (tight leading dimensions)
+CMat opA(const Plan& pl, char* ws, int j) {
+  int64_t r = pl.m[j], c = pl.l[j];
+  return CMat{(const double*)(ws + pl.offA[j]), c, r * c, pl.P * r * c};
+}
+CMat opB(const Plan& pl, char* ws, int j) {
+  int64_t r = pl.l[j], c = pl.n[j];
+  return CMat{(const double*)(ws + pl.offB[j]), c, r * c, pl.P * r * c};
+}
+Mat prodM(const Plan& pl, char* ws, int j) {
+  int64_t r = pl.m[j], c = pl.n[j];
+  return Mat{(double*)(ws + pl.offM[j]), c, r * c, pl.P * r * c};
+}
+
+int leaf(int P, const GemmBatch& g, int base, int slices, void* ws, size_t ws_bytes,
+         hipStream_t s) {
+  if (base == DDQD_BASE_OZAKI_I8) return launch_ozaki(g, slices, ws, ws_bytes, s);
+  return P == 2 ? launch_dd_block(g, s) : launch_qd_block(g, s);
+}
+
+int block_fma(int P, const GemmBatch& g, hipStream_t s) {
+  return P == 2 ? launch_dd_block(g, s) : launch_qd_block(g, s);
+}
+
+int preadd(int P, CMat src, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
+           int side, hipStream_t s) {
+  return P == 2 ? launch_preadd<DDNum>(src, dst, rows, cols, parents, algo, side, s)
+                : launch_preadd<QDNum>(src, dst, rows, cols, parents, algo, side, s);
+}
+
+int postadd(int P, CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
+            int alpha, int beta, hipStream_t s) {
+  return P == 2 ? launch_postadd<DDNum>(prod, dst, rows, cols, parents, algo, alpha, beta, s)
+                : launch_postadd<QDNum>(prod, dst, rows, cols, parents, algo, alpha, beta, s);
+}
+
+CMat shift(CMat X, int64_t i, int64_t j) {
+  X.p += i * X.ld + j;
+  return X;
+}
+Mat shift(Mat X, int64_t i, int64_t j) {
+  X.p += i * X.ld + j;
+  return X;
+}
+
+int run_gemm(int P, const GemmBatch& top, int algo, int levels, int base, int slices, void* ws,
+             size_t ws_bytes, hipStream_t s) {
+  if (algo == DDQD_SIMPLE) return P == 2 ? launch_dd_simple(top, s) : launch_qd_simple(top, s);
+  Plan pl = make_plan(P, top.m, top.n, top.l, algo, levels, base, slices);
+  char* w = (char*)ws;
+  const int L = pl.L;
+  if (L == 0) return leaf(P, top, base, slices, w, ws_bytes, s);
+  int rc;
+  // pre-adds, level by level
+  for (int j = 1; j <= L; j++) {
+    CMat srcA = j == 1 ? top.A : opA(pl, w, j - 1);
+    CMat srcB = j == 1 ? top.B : opB(pl, w, j - 1);
+    CMat dA = opA(pl, w, j), dB = opB(pl, w, j);
+    Mat dstA{(double*)dA.p, dA.ld, dA.ps, dA.bstride};
+    Mat dstB{(double*)dB.p, dB.ld, dB.ps, dB.bstride};
+    if ((rc = preadd(P, srcA, dstA, pl.m[j], pl.l[j], pow7(j - 1), algo, 0, s))) return rc;
+    if ((rc = preadd(P, srcB, dstB, pl.l[j], pl.n[j], pow7(j - 1), algo, 1, s))) return rc;
+  }
+  // all leaf products in one batched launch
+  GemmBatch lf{pl.m[L], pl.n[L], pl.l[L], 1, 0, opA(pl, w, L), opB(pl, w, L), prodM(pl, w, L),
+               pow7(L)};
+  if ((rc = leaf(P, lf, base, slices, w + pl.off_leaf, pl.leaf_bytes, s))) return rc;
+  // post-adds and peeling, level by level back up
+  for (int j = L; j >= 1; j--) {
+    const bool root = j == 1;
+    Mat dst = root ? top.C : prodM(pl, w, j - 1);
+    CMat pa = root ? top.A : opA(pl, w, j - 1);
+    CMat pb = root ? top.B : opB(pl, w, j - 1);
+    const int alpha = root ? top.alpha : 1, beta = root ? top.beta : 0;
+    const int64_t parents = pow7(j - 1);
+    if ((rc = postadd(P, cview(prodM(pl, w, j)), dst, pl.m[j], pl.n[j], parents, algo, alpha,
+                      beta, s)))
+      return rc;
+    const int64_t me = 2 * pl.m[j], ne = 2 * pl.n[j], le = 2 * pl.l[j];
+    const int64_t mp = pl.m[j - 1], np = pl.n[j - 1], lp = pl.l[j - 1];
+    if (lp != le) {  // rank-1: core += A[:, le] B[le, :]
+      GemmBatch g{me, ne, 1, alpha, 1, shift(pa, 0, le), shift(pb, le, 0), dst, parents};
+      if ((rc = block_fma(P, g, s))) return rc;
+    }
+    if (np != ne) {  // last column of C
+      GemmBatch g{me, 1, lp, alpha, beta, pa, shift(pb, 0, ne), shift(dst, 0, ne), parents};
+      if ((rc = block_fma(P, g, s))) return rc;
+    }
+    if (mp != me) {  // last row of C
+      GemmBatch g{1, np, lp, alpha, beta, shift(pa, me, 0), pb, shift(dst, me, 0), parents};
+      if ((rc = block_fma(P, g, s))) return rc;
+    }
+  }
+  return DDQD_OK;
+}
+
+bool overlaps(const double* a, int64_t a_len, const double* b, int64_t b_len) {
+  if (!a || !b || a_len <= 0 || b_len <= 0) return false;
+  return a < b + b_len && b < a + a_len;
+}
+
+int64_t extent(int P, int64_t rows, int64_t cols, int64_t ld, int64_t ps) {
+  if (rows <= 0 || cols <= 0) return 0;
+  return (P - 1) * ps + (rows - 1) * ld + cols;
+}
+
+int check_mat(const char* name, int P, const void* p, int64_t rows, int64_t cols, int64_t ld,
+              int64_t ps) {
+  if (rows <= 0 || cols <= 0) return DDQD_OK;
+  if (!p) return set_error(DDQD_E_ARG, "%s is NULL", name);
+  if ((uintptr_t)p % 8) return set_error(DDQD_E_ARG, "%s is not 8-byte aligned", name);
+  if (ld < cols) return set_error(DDQD_E_ARG, "ld of %s (%lld) < columns (%lld)", name,
+                                  (long long)ld, (long long)cols);
+  if (P > 1 && ps < (rows - 1) * ld + cols)
+    return set_error(DDQD_E_ARG, "plane stride of %s (%lld) lets planes overlap", name,
+                     (long long)ps);
+  return DDQD_OK;
+}
+
+int device_ok() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return set_error(DDQD_E_NODEVICE, "no HIP device available");
+  }
+  return DDQD_OK;
+}
+
+size_t gemm_ws(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
+               int slices) {
+  if (m < 0 || n < 0 || l < 0 || algo < 0 || algo > 3 || levels < 0 || levels > kMaxLevels ||
+      base < 0 || base > 1 || slices < 0 || slices > 40)
+    return SIZE_MAX;
+  if (P == 4 && base != DDQD_BASE_FMA) return SIZE_MAX;
+  if (m == 0 || n == 0 || l == 0) return 0;
+  return make_plan(P, m, n, l, algo, levels, base, slices).total;
+}
+
+int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
+               int64_t psa, const double* B, int64_t ldb, int64_t psb, int beta, double* C,
+               int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
+               size_t ws_bytes, void* stream) {
+  g_msg[0] = 0;
+  if (m < 0 || n < 0 || l < 0) return set_error(DDQD_E_ARG, "negative dimension");
+  if (alpha != 1 && alpha != -1) return set_error(DDQD_E_ARG, "alpha must be +1 or -1");
+  if (beta != 0 && beta != 1) return set_error(DDQD_E_ARG, "beta must be 0 or 1");
+  if (algo < 0 || algo > 3) return set_error(DDQD_E_ARG, "unknown algo %d", algo);
+  if (levels < 0 || levels > kMaxLevels)
+    return set_error(DDQD_E_ARG, "levels must be in 0..%d", kMaxLevels);
+  if (base != DDQD_BASE_FMA && base != DDQD_BASE_OZAKI_I8)
+    return set_error(DDQD_E_ARG, "unknown base %d", base);
+  if (slices < 0 || slices > 40) return set_error(DDQD_E_ARG, "slices must be in 0..40");
+  if (P == 4 && base != DDQD_BASE_FMA)
+    return set_error(DDQD_E_UNSUPPORTED, "QD products use the FMA base only");
+  int rc;
+  if ((rc = check_mat("C", P, C, m, n, ldc, psc))) return rc;
+  if (l > 0) {
+    if ((rc = check_mat("A", P, A, m, l, lda, psa))) return rc;
+    if ((rc = check_mat("B", P, B, l, n, ldb, psb))) return rc;
+  }
+  if (m == 0 || n == 0) return DDQD_OK;
+  const int64_t ec = extent(P, m, n, ldc, psc);
+  if (l > 0 && (overlaps(C, ec, A, extent(P, m, l, lda, psa)) ||
+                overlaps(C, ec, B, extent(P, l, n, ldb, psb))))
+    return set_error(DDQD_E_ALIAS, "C overlaps A or B");
+  size_t need = gemm_ws(P, m, n, l, algo, levels, base, slices);
+  if (need > ws_bytes || (need > 0 && !ws))
+    return set_error(DDQD_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
+                     ws_bytes);
+  if (need > 0 && (uintptr_t)ws % 8) return set_error(DDQD_E_WORKSPACE, "workspace misaligned");
+  if ((rc = device_ok())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  GemmBatch top{m, n, l, alpha, beta, CMat{A, lda, psa, 0}, CMat{B, ldb, psb, 0},
+                Mat{C, ldc, psc, 0}, 1};
+  if (l == 0) {  // C := beta*C: the Block kernel with an empty K loop does exactly this
+    top.A = CMat{C, ldc, psc, 0};
+    top.B = CMat{C, ldc, psc, 0};
+    return block_fma(P, top, s);
+  }
+  return run_gemm(P, top, algo, levels, base, slices, ws, ws_bytes, s);
+}
+
+}  // namespace
+}  // namespace ddqd
+
+using namespace ddqd;
+
+extern "C" {
+
+const char* ddqd_status_string(int status) {
+  switch (status) {
+    case DDQD_OK: return "DDQD_OK";
+    case DDQD_E_ARG: return "DDQD_E_ARG: invalid argument";
+    case DDQD_E_ALIAS: return "DDQD_E_ALIAS: output overlaps an input";
+    case DDQD_E_WORKSPACE: return "DDQD_E_WORKSPACE: workspace missing or too small";
+    case DDQD_E_UNSUPPORTED: return "DDQD_E_UNSUPPORTED: combination not supported";
+    case DDQD_E_NODEVICE: return "DDQD_E_NODEVICE: no usable GPU";
+    case DDQD_E_HIP: return "DDQD_E_HIP: HIP call or launch failed";
+    default: return "unknown status";
+  }
+}
+
+const char* ddqd_last_error(void) { return g_msg; }
+
+size_t dd_gemm_workspace(int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
+                         int slices) {
+  return gemm_ws(2, m, n, l, algo, levels, base, slices);
+}
+
+size_t qd_gemm_workspace(int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
+                         int slices) {
+  return gemm_ws(4, m, n, l, algo, levels, base, slices);
+}
+
+int dd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
+            int64_t psa, const double* B, int64_t ldb, int64_t psb, int beta, double* C,
+            int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
+            size_t ws_bytes, void* stream) {
+  return gemm_entry(2, m, n, l, alpha, A, lda, psa, B, ldb, psb, beta, C, ldc, psc, algo,
+                    levels, base, slices, ws, ws_bytes, stream);
+}
+
+int qd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
+            int64_t psa, const double* B, int64_t ldb, int64_t psb, int beta, double* C,
+            int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
+            size_t ws_bytes, void* stream) {
+  return gemm_entry(4, m, n, l, alpha, A, lda, psa, B, ldb, psb, beta, C, ldc, psc, algo,
+                    levels, base, slices, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

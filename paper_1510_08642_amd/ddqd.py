@@ -1,0 +1,121 @@
+"""Thin ctypes binding of libddqd.so over torch device tensors.
+
+Argument marshalling only: every arithmetic step runs in the HIP library.
+A DD matrix is a float64 tensor of shape ``(2, rows, cols)`` on a GPU (a QD
+matrix ``(4, rows, cols)``) whose last dimension is contiguous; its row
+stride is the leading dimension and its plane stride the plane stride of the
+C ABI (include/ddqd.h).  Work is enqueued on torch's current stream of the
+tensors' device; workspace comes from torch's caching allocator.
+
+If the library has not been built this module raises on import: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddqd.so")
+
+ALGO = {"simple": 0, "block": 1, "strassen": 2, "winograd": 3}
+BASE = {"fma": 0, "ozaki": 1}
+PIVOT = {"none": 0, "partial": 1}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_1510_08642_amd.build` (no CPU fallback exists)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_i64, _int, _vp, _sz = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
+
+_GEMM_ARGS = [_i64, _i64, _i64, _int, _vp, _i64, _i64, _vp, _i64, _i64, _int, _vp, _i64, _i64,
+              _int, _int, _int, _int, _vp, _sz, _vp]
+for _name in ("dd_gemm", "qd_gemm"):
+    getattr(_lib, _name).argtypes = _GEMM_ARGS
+    getattr(_lib, _name).restype = _int
+for _name in ("dd_gemm_workspace", "qd_gemm_workspace"):
+    getattr(_lib, _name).argtypes = [_i64, _i64, _i64, _int, _int, _int, _int]
+    getattr(_lib, _name).restype = _sz
+_lib.ddqd_status_string.argtypes = [_int]
+_lib.ddqd_status_string.restype = ctypes.c_char_p
+_lib.ddqd_last_error.argtypes = []
+_lib.ddqd_last_error.restype = ctypes.c_char_p
+
+SIZE_MAX = ctypes.c_size_t(-1).value
+
+
+class DDQDError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.ddqd_status_string(status).decode()
+        detail = _lib.ddqd_last_error().decode()
+        super().__init__(f"{where}: {msg}" + (f" ({detail})" if detail else ""))
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise DDQDError(status, where)
+
+
+def _mat(X: torch.Tensor, P: int, name: str):
+    if X.dim() != 3 or X.shape[0] != P:
+        raise ValueError(f"{name} must have shape ({P}, rows, cols)")
+    if X.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if X.shape[2] > 1 and X.stride(2) != 1:
+        raise ValueError(f"{name} must be contiguous along its last dimension")
+    return X.data_ptr(), X.stride(1), X.stride(0)
+
+
+def _stream_of(X: torch.Tensor):
+    if X.device.type != "cuda":
+        raise ValueError("tensors must be on a GPU")
+    return torch.cuda.current_stream(X.device).cuda_stream
+
+
+def gemm_workspace(P: int, m: int, n: int, l: int, algo="block", levels=0, base="fma",
+                   slices=0) -> int:
+    f = _lib.dd_gemm_workspace if P == 2 else _lib.qd_gemm_workspace
+    ws = f(m, n, l, ALGO[algo], levels, BASE[base], slices)
+    if ws == SIZE_MAX:
+        raise ValueError("invalid gemm arguments")
+    return ws
+
+
+def _gemm(P, A, B, C, alpha, beta, algo, levels, base, slices, ws):
+    m, l = A.shape[1], A.shape[2]
+    n = B.shape[2]
+    if B.shape[1] != l:
+        raise ValueError("inner dimensions differ")
+    if C is None:
+        C = torch.empty((P, m, n), dtype=torch.float64, device=A.device)
+        beta = 0
+    pa, lda, psa = _mat(A, P, "A")
+    pb, ldb, psb = _mat(B, P, "B")
+    pc, ldc, psc = _mat(C, P, "C")
+    need = gemm_workspace(P, m, n, l, algo, levels, base, slices)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    f = _lib.dd_gemm if P == 2 else _lib.qd_gemm
+    st = f(m, n, l, alpha, pa, lda, psa, pb, ldb, psb, beta, pc, ldc, psc, ALGO[algo], levels,
+           BASE[base], slices, ws.data_ptr(), ws.numel(), _stream_of(C))
+    _check(st, "dd_gemm" if P == 2 else "qd_gemm")
+    return C
+
+
+def dd_gemm(A, B, C=None, *, alpha=1, beta=0, algo="block", levels=0, base="fma", slices=0,
+            ws=None):
+    """C := beta*C + alpha*(A B) in double-double; returns C."""
+    return _gemm(2, A, B, C, alpha, beta, algo, levels, base, slices, ws)
+
+
+def qd_gemm(A, B, C=None, *, alpha=1, beta=0, algo="block", levels=0, slices=0, ws=None):
+    """C := beta*C + alpha*(A B) in quad-double; returns C."""
+    return _gemm(4, A, B, C, alpha, beta, algo, levels, "fma", slices, ws)

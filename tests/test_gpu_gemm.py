@@ -1,0 +1,243 @@
+"""GPU parity of dd_gemm / qd_gemm against the CPU oracle.
+
+Each case runs the HIP library through its C ABI (via the ctypes binding) on
+seeded inputs and compares, element by element, with the oracle's result for
+the same algorithm and with the exact product (the oracle's expansion dot
+product).  Bars:
+  * integer inputs: bit-exact (every algorithm is exact on them);
+  * DD: row-normwise error max_i max_j |C_ij - E_ij| / max_j (|A||B|)_ij
+    <= 2^-100 l, and GPU-vs-oracle difference within twice that;
+  * QD: the same with 2^-200 l.
+"""
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1510_08642_amd import inputs
+from tests.helpers import (all_entries, rownorm_den, rownorm_error, sample_entries, to_dev,
+                           to_host, value_diff)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1510_08642_amd import ddqd
+    return ddqd
+
+
+def run(dd, P, A, B, C0=None, **kw):
+    print(f"case P={P} A={A.shape} B={B.shape} {kw}", flush=True)
+    Ad, Bd = to_dev(A), to_dev(B)
+    Cd = to_dev(C0) if C0 is not None else None
+    f = dd.dd_gemm if P == 2 else dd.qd_gemm
+    out = f(Ad, Bd, Cd, **kw)
+    import torch
+    torch.cuda.synchronize()
+    return to_host(out)
+
+
+ALGS = [("simple", 0), ("block", 0), ("strassen", 1), ("strassen", 2), ("strassen", 3),
+        ("winograd", 1), ("winograd", 2), ("winograd", 3)]
+
+
+def test_config0_dd_128_simple_block_vs_oracle_and_exact(dd):
+    """m = n = l = 128, seed 0: GPU vs oracle elementwise, all entries vs the
+    exact product, and 8x8 sub-blocks against exact rationals."""
+    g = inputs.rng(0)
+    A = inputs.dd_uniform(128, 128, g)
+    B = inputs.dd_uniform(128, 128, g)
+    ii, jj = all_entries(128, 128)
+    den = rownorm_den(A, B)
+    for algo in ("simple", "block"):
+        C = run(dd, 2, A, B, algo=algo)
+        Co = oracle.gemm(A, B, algo)
+        assert np.max(value_diff(C, Co) / den[:, None]) <= 2 * 2.0 ** -100 * 128
+        assert rownorm_error(A, B, C, ii, jj, den=den) <= 2.0 ** -100 * 128
+        # the conventional kernels meet a rigorous bound well inside the tolerance
+        assert rownorm_error(A, B, C, ii, jj, den=den) <= 20 * 128 * 2.0 ** -106
+    C = run(dd, 2, A, B, algo="block")
+    rs = np.random.default_rng(1)
+    corners = [(0, 0), (0, 120), (120, 0), (120, 120), (60, 60), (60, 0), (0, 60)]
+    corners += [tuple(x) for x in rs.integers(0, 121, (4, 2))]
+    for (i0, j0) in corners:
+        for i in range(i0, i0 + 8):
+            for j in range(j0, j0 + 8):
+                ex = sum((F(A[0, i, k]) + F(A[1, i, k])) * (F(B[0, k, j]) + F(B[1, k, j]))
+                         for k in range(128))
+                got = F(C[0, i, j]) + F(C[1, i, j])
+                assert abs(got - ex) <= F(den[i]) * F(2) ** -100 * 128
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 1), (63, 65, 67), (100, 37, 129),
+                                   (129, 130, 131), (64, 64, 64), (200, 1, 77)])
+def test_ragged_shapes_all_algorithms(dd, shape):
+    m, n, l = shape
+    g = inputs.rng(m * 7 + n * 3 + l)
+    A = inputs.dd_uniform(m, l, g)
+    B = inputs.dd_uniform(l, n, g)
+    ii, jj = all_entries(m, n)
+    den = rownorm_den(A, B)
+    for algo, lv in ALGS:
+        C = run(dd, 2, A, B, algo=algo, levels=lv)
+        assert rownorm_error(A, B, C, ii, jj, den=den) <= 2.0 ** -100 * l, (algo, lv)
+        Co = oracle.gemm(A, B, algo, lv)
+        assert np.max(value_diff(C, Co) / den[:, None]) <= 2 * 2.0 ** -100 * l, (algo, lv)
+
+
+@pytest.mark.parametrize("alpha,beta", [(1, 1), (-1, 1), (-1, 0)])
+@pytest.mark.parametrize("algo,lv", [("simple", 0), ("block", 0), ("winograd", 2),
+                                     ("strassen", 1)])
+def test_alpha_beta(dd, alpha, beta, algo, lv):
+    g = inputs.rng(40)
+    m, n, l = 70, 45, 53
+    A = inputs.dd_uniform(m, l, g)
+    B = inputs.dd_uniform(l, n, g)
+    C0 = inputs.dd_uniform(m, n, g)
+    C = run(dd, 2, A, B, C0=C0, alpha=alpha, beta=beta, algo=algo, levels=lv)
+    ii, jj = all_entries(m, n)
+    e = rownorm_error(A, B, C, ii, jj, alpha=alpha, C0=C0 if beta else None)
+    assert e <= 2.0 ** -100 * l
+
+
+@pytest.mark.parametrize("P", [2, 4])
+@pytest.mark.parametrize("shape", [(9, 7, 11), (33, 31, 30), (64, 64, 64), (65, 66, 67)])
+def test_integer_inputs_bit_exact(dd, P, shape):
+    m, n, l = shape
+    g = inputs.rng(50 + m)
+    A = inputs.widen(inputs.dd_int(m, l, g), P)
+    B = inputs.widen(inputs.dd_int(l, n, g), P)
+    want = A[0] @ B[0]       # exact: |entries| <= 2^20, l < 2^12
+    for algo, lv in ALGS:
+        C = run(dd, P, A, B, algo=algo, levels=lv)
+        assert np.array_equal(C[0], want), (algo, lv)
+        assert not C[1:].any(), (algo, lv)
+
+
+def test_integer_inputs_beyond_one_double(dd):
+    g = inputs.rng(51)
+    m, n, l = 40, 36, 45
+    A = inputs.dd_int(m, l, g, bound=1 << 40)
+    B = inputs.dd_int(l, n, g, bound=1 << 40)
+    want = A[0].astype(np.int64).astype(object) @ B[0].astype(np.int64).astype(object)
+    for algo, lv in ALGS:
+        C = run(dd, 2, A, B, algo=algo, levels=lv)
+        for i in range(0, m, 7):
+            for j in range(0, n, 5):
+                assert F(C[0, i, j]) + F(C[1, i, j]) == want[i, j], (algo, lv)
+
+
+def test_empty_and_degenerate(dd):
+    import torch
+    g = inputs.rng(52)
+    A = inputs.dd_uniform(5, 0, g)
+    B = inputs.dd_uniform(0, 6, g)
+    C0 = inputs.dd_uniform(5, 6, g)
+    C = run(dd, 2, A, B, C0=C0, beta=1)
+    assert np.array_equal(C, C0)
+    C = run(dd, 2, A, B, C0=C0, beta=0)
+    assert not C.any()
+    Z = dd.dd_gemm(to_dev(inputs.dd_uniform(0, 4, g)), to_dev(inputs.dd_uniform(4, 3, g)))
+    assert tuple(Z.shape) == (2, 0, 3)
+
+
+def test_levels_zero_is_block_and_deterministic(dd):
+    g = inputs.rng(53)
+    A = inputs.dd_uniform(150, 140, g)
+    B = inputs.dd_uniform(140, 130, g)
+    Cb = run(dd, 2, A, B, algo="block")
+    assert np.array_equal(run(dd, 2, A, B, algo="strassen", levels=0), Cb)
+    assert np.array_equal(run(dd, 2, A, B, algo="block"), Cb)
+    Cw = run(dd, 2, A, B, algo="winograd", levels=2)
+    assert np.array_equal(run(dd, 2, A, B, algo="winograd", levels=2), Cw)
+    # exact power-of-two scaling commutes bitwise
+    Cs = run(dd, 2, np.ldexp(A, 5), np.ldexp(B, -9), algo="winograd", levels=2)
+    assert np.array_equal(np.ldexp(Cw, -4), Cs)
+
+
+@pytest.mark.parametrize("n", [1023, 1024, 1025])
+def test_paper_matrices_closed_form(dd, n):
+    """Sec. 3 inputs A = [sqrt5 (i+j-1)], B = [sqrt3 (n-i)]; the exact product
+    is sqrt15 n (n-1) (n+3i-2) / 6."""
+    import mpmath
+    A, B = inputs.paper_matrices(n)
+    rows = list(range(0, n, 97)) + [n - 1]
+    exact = inputs.paper_product_closed_form(n, rows)
+    for algo, lv in [("block", 0), ("strassen", 3), ("winograd", 3)]:
+        C = run(dd, 2, A, B, algo=algo, levels=lv)
+        worst = 0
+        with mpmath.workprec(300):
+            for r, ex in zip(rows, exact):
+                for j in (0, n // 3, n - 1):
+                    got = mpmath.mpf(float(C[0, r, j])) + mpmath.mpf(float(C[1, r, j]))
+                    worst = max(worst, abs(got - ex) / abs(ex))
+        bound = 24 * n * 2.0 ** -106 if algo == "block" else 2.0 ** -100 * n
+        assert float(worst) <= bound, (algo, float(worst) / 2.0 ** -106)
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+@pytest.mark.parametrize("algo,lv", [("block", 0), ("strassen", 1), ("strassen", 3),
+                                     ("winograd", 1), ("winograd", 2), ("winograd", 3)])
+def test_config1_full_size_sampled(dd, n, algo, lv):
+    g = inputs.rng(0)
+    A = inputs.dd_uniform(n, n, g)
+    B = inputs.dd_uniform(n, n, g)
+    C = run(dd, 2, A, B, algo=algo, levels=lv)
+    ii, jj = sample_entries(n, n, 300)
+    assert rownorm_error(A, B, C, ii, jj) <= 2.0 ** -100 * n
+
+
+def test_config1_row_scaled_variant(dd):
+    n = 1024
+    g = inputs.rng(1)
+    A = inputs.dd_uniform(n, n, g)
+    B = inputs.dd_uniform(n, n, g)
+    As, _ = inputs.row_scaled(A, g)
+    ii, jj = sample_entries(n, n, 300)
+    for algo, lv in [("block", 0), ("winograd", 2)]:
+        C = run(dd, 2, As, B, algo=algo, levels=lv)
+        assert rownorm_error(As, B, C, ii, jj) <= 2.0 ** -100 * n, algo
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (45, 38, 51), (70, 66, 64)])
+def test_qd_small_vs_oracle(dd, shape):
+    m, n, l = shape
+    g = inputs.rng(60 + m)
+    A = inputs.qd_uniform(m, l, g)
+    B = inputs.qd_uniform(l, n, g)
+    ii, jj = all_entries(m, n)
+    den = rownorm_den(A, B)
+    for algo, lv in ALGS:
+        C = run(dd, 4, A, B, algo=algo, levels=lv)
+        assert rownorm_error(A, B, C, ii, jj, den=den) <= 2.0 ** -200 * l, (algo, lv)
+        if (algo, lv) in [("block", 0), ("winograd", 2)]:
+            Co = oracle.gemm(A, B, algo, lv)
+            assert np.max(value_diff(C, Co) / den[:, None]) <= 2 * 2.0 ** -200 * l
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+@pytest.mark.parametrize("algo,lv", [("block", 0), ("strassen", 2), ("winograd", 1),
+                                     ("winograd", 3)])
+def test_config2_qd_full_size_sampled(dd, n, algo, lv):
+    g = inputs.rng(0)
+    A = inputs.qd_uniform(n, n, g)
+    B = inputs.qd_uniform(n, n, g)
+    C = run(dd, 4, A, B, algo=algo, levels=lv)
+    ii, jj = sample_entries(n, n, 120)
+    assert rownorm_error(A, B, C, ii, jj) <= 2.0 ** -200 * n
+
+
+def test_qd_alpha_beta(dd):
+    g = inputs.rng(61)
+    m, n, l = 40, 35, 47
+    A = inputs.qd_uniform(m, l, g)
+    B = inputs.qd_uniform(l, n, g)
+    C0 = inputs.qd_uniform(m, n, g)
+    ii, jj = all_entries(m, n)
+    for algo, lv in [("simple", 0), ("block", 0), ("winograd", 1)]:
+        C = run(dd, 4, A, B, C0=C0, alpha=-1, beta=1, algo=algo, levels=lv)
+        assert rownorm_error(A, B, C, ii, jj, alpha=-1, C0=C0) <= 2.0 ** -200 * l
