@@ -11,6 +11,8 @@
  *            additions), `levels` deep.
  * The paper's figures of the parallel Strassen and Winograd schemes are not
  * available, so the formulas are the textbook ones, written out below.
+ * A Strassen or Winograd product is equilibrated first (exact power-of-two
+ * row scaling of A and column scaling of B, undone on C; see product_top).
  * Below the recursion (levels == 0, or a dimension below 2) the product is
  * Block.  A dimension that is odd at some level is peeled: the even leading
  * part recurses, and the odd last column of A / row of B (a rank-one
@@ -23,6 +25,7 @@
  */
 #include <stdint.h>
 #include <stdlib.h>
+#include <math.h>
 #include <string.h>
 
 #include "num.h"
@@ -218,6 +221,49 @@ static void product(const arith *ar, int algo, int levels, int bs, int64_t m, in
     if (m != me) block(ar, bs, 1, n, l, sub(ar, A, me, 0), B, sub(ar, C, me, 0));
 }
 
+/* Exact power-of-two equilibration around a Strassen / Winograd product:
+ * row i of A is scaled by 2^-e_i and column j of B by 2^-f_j, where 2^e_i and
+ * 2^f_j bound the row's / column's largest leading component, the product of
+ * the scaled matrices is formed, and entry (i, j) is scaled back by
+ * 2^(e_i + f_j).  The recursion's sums then mix rows (and columns) of equal
+ * scale, so the row-normwise error does not depend on the rows' magnitudes.
+ * Conventional products need no scaling and get none. */
+static void product_top(const arith *ar, int algo, int levels, int bs, int64_t m, int64_t n,
+                        int64_t l, mat A, mat B, mat C) {
+    if (!(algo == 2 || algo == 3) || levels <= 0 || m < 2 || n < 2 || l < 2) {
+        product(ar, algo, levels, bs, m, n, l, A, B, C);
+        return;
+    }
+    int P = ar->P;
+    int *ea = (int *)calloc((size_t)m, sizeof(int)), *fb = (int *)calloc((size_t)n, sizeof(int));
+    for (int64_t i = 0; i < m; i++) {
+        double mx = 0.0;
+        for (int64_t k = 0; k < l; k++) mx = fmax(mx, fabs(at(ar, A, i, k)[0]));
+        if (mx > 0.0) frexp(mx, &ea[i]);
+    }
+    for (int64_t j = 0; j < n; j++) {
+        double mx = 0.0;
+        for (int64_t k = 0; k < l; k++) mx = fmax(mx, fabs(at(ar, B, k, j)[0]));
+        if (mx > 0.0) frexp(mx, &fb[j]);
+    }
+    mat As = mat_new(ar, m, l), Bs = mat_new(ar, l, n);
+    for (int64_t i = 0; i < m; i++)
+        for (int64_t k = 0; k < l; k++)
+            for (int c = 0; c < P; c++) at(ar, As, i, k)[c] = ldexp(at(ar, A, i, k)[c], -ea[i]);
+    for (int64_t k = 0; k < l; k++)
+        for (int64_t j = 0; j < n; j++)
+            for (int c = 0; c < P; c++) at(ar, Bs, k, j)[c] = ldexp(at(ar, B, k, j)[c], -fb[j]);
+    product(ar, algo, levels, bs, m, n, l, As, Bs, C);
+    for (int64_t i = 0; i < m; i++)
+        for (int64_t j = 0; j < n; j++)
+            for (int c = 0; c < P; c++)
+                at(ar, C, i, j)[c] = ldexp(at(ar, C, i, j)[c], ea[i] + fb[j]);
+    free(As.p);
+    free(Bs.p);
+    free(ea);
+    free(fb);
+}
+
 /* planes <-> numbers */
 static void from_planes(int P, int64_t r, int64_t c, const double *src, double *dst) {
     for (int64_t i = 0; i < r * c; i++)
@@ -254,7 +300,7 @@ int or_gemm(int P, int algo, int levels, int bs, int64_t m, int64_t n, int64_t l
     mat a = mat_new(&ar, m, l), b = mat_new(&ar, l, n), c = mat_new(&ar, m, n);
     from_planes(P, m, l, A, a.p);
     from_planes(P, l, n, B, b.p);
-    product(&ar, algo, levels, bs, m, n, l, a, b, c);
+    product_top(&ar, algo, levels, bs, m, n, l, a, b, c);
     to_planes(P, m, n, c.p, C);
     free(a.p);
     free(b.p);
@@ -268,5 +314,5 @@ void or_product_numbers(int P, int algo, int levels, int bs, int64_t m, int64_t 
     arith ar;
     arith_of(P, &ar);
     mat a = {A, lda}, b = {B, ldb}, c = {C, ldc};
-    product(&ar, algo, levels, bs, m, n, l, a, b, c);
+    product_top(&ar, algo, levels, bs, m, n, l, a, b, c);
 }

@@ -20,7 +20,11 @@
 // parent once and writes all seven operands of its children (chains such as
 // S1 -> S2 -> S4 stay in registers); one post-add kernel reads the seven
 // products once and writes the four quadrants of the parent, applying
-// C := beta*C + alpha*result at the top level.  All sums are accurate DD
+// C := beta*C + alpha*result at the top level.  At the top level the operands
+// are also equilibrated: row r of A is scaled by 2^-ea[r] and column c of B by
+// 2^-fb[c] as they are read (exact), and the result is scaled back by
+// 2^(ea[r] + fb[c]), so the sums never mix rows or columns of different
+// magnitude.  All sums are accurate DD
 // (or QD) additions.  These kernels are HBM-bound: per output element a
 // pre-add moves 4 reads + 7 writes, a post-add 7 reads + 4 writes (+4 reads
 // when beta = 1), P doubles each.
@@ -34,9 +38,12 @@ namespace ddqd {
 
 namespace {
 
+// expo (top level only, else NULL): the equilibration exponents, per row of
+// A (side 0) or per column of B (side 1); each input is scaled by 2^-expo.
 template <class N>
 __global__ __launch_bounds__(256) void preadd_kernel(CMat src, Mat dst, int64_t rows,
-                                                     int64_t cols, int algo, int side) {
+                                                     int64_t cols, int algo, int side,
+                                                     const int* expo) {
   using T = typename N::T;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t p = blockIdx.y;
@@ -47,6 +54,19 @@ __global__ __launch_bounds__(256) void preadd_kernel(CMat src, Mat dst, int64_t 
   T x12 = N::load(s, src.ps, i * src.ld + j + cols);
   T x21 = N::load(s, src.ps, (i + rows) * src.ld + j);
   T x22 = N::load(s, src.ps, (i + rows) * src.ld + j + cols);
+  if (expo) {
+    if (side == 0) {  // rows i and i + rows
+      x11 = N::scale(x11, -expo[i]);
+      x12 = N::scale(x12, -expo[i]);
+      x21 = N::scale(x21, -expo[i + rows]);
+      x22 = N::scale(x22, -expo[i + rows]);
+    } else {  // columns j and j + cols
+      x11 = N::scale(x11, -expo[j]);
+      x21 = N::scale(x21, -expo[j]);
+      x12 = N::scale(x12, -expo[j + cols]);
+      x22 = N::scale(x22, -expo[j + cols]);
+    }
+  }
   T o[7];
   if (algo == 2) {  // Strassen
     if (side == 0) {
@@ -97,10 +117,12 @@ __global__ __launch_bounds__(256) void preadd_kernel(CMat src, Mat dst, int64_t 
   for (int t = 0; t < 7; t++) N::store(dst.p + (7 * p + t) * dst.bstride, dst.ps, i * dst.ld + j, o[t]);
 }
 
+// ea, fb (top level only, else NULL): equilibration exponents of A's rows and
+// B's columns; entry (r, c) of the result is scaled by 2^(ea[r] + fb[c]).
 template <class N>
 __global__ __launch_bounds__(256) void postadd_kernel(CMat prod, Mat dst, int64_t rows,
                                                       int64_t cols, int algo, int alpha,
-                                                      int beta) {
+                                                      int beta, const int* ea, const int* fb) {
   using T = typename N::T;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t p = blockIdx.y;
@@ -131,6 +153,7 @@ __global__ __launch_bounds__(256) void postadd_kernel(CMat prod, Mat dst, int64_
 #pragma unroll
   for (int q = 0; q < 4; q++) {
     T v = alpha < 0 ? N::neg(c[q]) : c[q];
+    if (ea) v = N::scale(v, ea[i + (q >> 1) * rows] + fb[j + (q & 1) * cols]);
     if (beta) v = N::add(N::load(d, dst.ps, off[q]), v);
     N::store(d, dst.ps, off[q], v);
   }
@@ -140,31 +163,74 @@ __global__ __launch_bounds__(256) void postadd_kernel(CMat prod, Mat dst, int64_
 
 template <class N>
 int launch_preadd(CMat src, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
-                  int side, hipStream_t stream) {
+                  int side, const int* expo, hipStream_t stream) {
   if (rows <= 0 || cols <= 0 || parents <= 0) return 0;
   if (parents > 65535) return set_error(4, "too many recursion parents");
   dim3 grid((unsigned)((rows * cols + 255) / 256), (unsigned)parents);
   hipLaunchKernelGGL(preadd_kernel<N>, grid, dim3(256), 0, stream, src, dst, rows, cols, algo,
-                     side);
+                     side, expo);
   return check_launch("preadd_kernel");
 }
 
 template <class N>
 int launch_postadd(CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
-                   int alpha, int beta, hipStream_t stream) {
+                   int alpha, int beta, const int* ea, const int* fb, hipStream_t stream) {
   if (rows <= 0 || cols <= 0 || parents <= 0) return 0;
   if (parents > 65535) return set_error(4, "too many recursion parents");
   dim3 grid((unsigned)((rows * cols + 255) / 256), (unsigned)parents);
   hipLaunchKernelGGL(postadd_kernel<N>, grid, dim3(256), 0, stream, prod, dst, rows, cols, algo,
-                     alpha, beta);
+                     alpha, beta, ea, fb);
   return check_launch("postadd_kernel");
 }
 
-template int launch_preadd<DDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, hipStream_t);
+// Equilibration exponents: e[r] such that the largest |leading component| of
+// row r of A (rows == true) or column r of B lies in [2^(e-1), 2^e); 0 for an
+// all-zero line.  Rows: one 64-lane wave per row; columns: one lane per
+// column, coalesced across lanes.
+__global__ __launch_bounds__(256) void row_exponent_kernel(CMat A, int64_t m, int64_t l,
+                                                           int* e) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (r >= m) return;
+  double mx = 0.0;
+  for (int64_t k = lane; k < l; k += 64) mx = fmax(mx, fabs(A.p[r * A.ld + k]));
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) {
+    int ex = 0;
+    if (mx > 0.0) frexp(mx, &ex);
+    e[r] = ex;
+  }
+}
+
+__global__ __launch_bounds__(256) void col_exponent_kernel(CMat B, int64_t l, int64_t n,
+                                                           int* e) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= n) return;
+  double mx = 0.0;
+  for (int64_t k = 0; k < l; k++) mx = fmax(mx, fabs(B.p[k * B.ld + c]));
+  int ex = 0;
+  if (mx > 0.0) frexp(mx, &ex);
+  e[c] = ex;
+}
+
+int launch_exponents(CMat A, CMat B, int64_t m, int64_t n, int64_t l, int* ea, int* fb,
+                     hipStream_t stream) {
+  hipLaunchKernelGGL(row_exponent_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, stream,
+                     A, m, l, ea);
+  int rc = check_launch("row_exponent_kernel");
+  if (rc) return rc;
+  hipLaunchKernelGGL(col_exponent_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                     B, l, n, fb);
+  return check_launch("col_exponent_kernel");
+}
+
+template int launch_preadd<DDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, const int*,
+                                  hipStream_t);
 template int launch_postadd<DDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, int,
-                                   hipStream_t);
-template int launch_preadd<QDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, hipStream_t);
+                                   const int*, const int*, hipStream_t);
+template int launch_preadd<QDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, const int*,
+                                  hipStream_t);
 template int launch_postadd<QDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, int,
-                                   hipStream_t);
+                                   const int*, const int*, hipStream_t);
 
 }  // namespace ddqd

@@ -6,6 +6,9 @@
 // Instead of recursing depth-first (the paper runs the seven products of a
 // level as parallel OpenMP sections), the driver walks the tree breadth-first
 // so every step is one launch over all subproblems of a level:
+//   scaling    exponents for an exact power-of-two equilibration of A's rows
+//              and B's columns, applied as the top level reads A and B and
+//              undone as it writes C (sums then mix rows of equal scale),
 //   pre-adds   level 1..L: one kernel per side writes the 7 operands of every
 //              child into workspace (strided batches),
 //   leaves     one batched launch computes all 7^L leaf products,
@@ -32,10 +35,12 @@ int launch_qd_block(const GemmBatch& g, hipStream_t stream);
 int launch_qd_simple(const GemmBatch& g, hipStream_t stream);
 template <class N>
 int launch_preadd(CMat src, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
-                  int side, hipStream_t stream);
+                  int side, const int* expo, hipStream_t stream);
 template <class N>
 int launch_postadd(CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
-                   int alpha, int beta, hipStream_t stream);
+                   int alpha, int beta, const int* ea, const int* fb, hipStream_t stream);
+int launch_exponents(CMat A, CMat B, int64_t m, int64_t n, int64_t l, int* ea, int* fb,
+                     hipStream_t stream);
 size_t ozaki_workspace(int64_t m, int64_t n, int64_t l, int64_t batch, int slices);
 int launch_ozaki(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, hipStream_t stream);
 int ozaki_default_slices();
@@ -72,6 +77,7 @@ struct Plan {
   int P = 2, L = 0;
   int64_t m[kMaxLevels + 1], n[kMaxLevels + 1], l[kMaxLevels + 1];
   size_t offA[kMaxLevels + 1], offB[kMaxLevels + 1], offM[kMaxLevels + 1];
+  size_t off_exp = 0;  // int32 equilibration exponents: m for A's rows, n for B's columns
   size_t off_leaf = 0, leaf_bytes = 0, total = 0;
 };
 
@@ -103,6 +109,10 @@ Plan make_plan(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int
     off = align_up(off + sizeof(double) * (size_t)(cnt * P * pl.l[j] * pl.n[j]));
     pl.offM[j] = off;
     off = align_up(off + sizeof(double) * (size_t)(cnt * P * pl.m[j] * pl.n[j]));
+  }
+  if (L > 0) {
+    pl.off_exp = off;
+    off = align_up(off + sizeof(int) * (size_t)(m + n));
   }
   pl.off_leaf = off;
   if (base == DDQD_BASE_OZAKI_I8 && algo != DDQD_SIMPLE)
@@ -136,15 +146,16 @@ int block_fma(int P, const GemmBatch& g, hipStream_t s) {
 }
 
 int preadd(int P, CMat src, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
-           int side, hipStream_t s) {
-  return P == 2 ? launch_preadd<DDNum>(src, dst, rows, cols, parents, algo, side, s)
-                : launch_preadd<QDNum>(src, dst, rows, cols, parents, algo, side, s);
+           int side, const int* expo, hipStream_t s) {
+  return P == 2 ? launch_preadd<DDNum>(src, dst, rows, cols, parents, algo, side, expo, s)
+                : launch_preadd<QDNum>(src, dst, rows, cols, parents, algo, side, expo, s);
 }
 
 int postadd(int P, CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
-            int alpha, int beta, hipStream_t s) {
-  return P == 2 ? launch_postadd<DDNum>(prod, dst, rows, cols, parents, algo, alpha, beta, s)
-                : launch_postadd<QDNum>(prod, dst, rows, cols, parents, algo, alpha, beta, s);
+            int alpha, int beta, const int* ea, const int* fb, hipStream_t s) {
+  return P == 2
+             ? launch_postadd<DDNum>(prod, dst, rows, cols, parents, algo, alpha, beta, ea, fb, s)
+             : launch_postadd<QDNum>(prod, dst, rows, cols, parents, algo, alpha, beta, ea, fb, s);
 }
 
 CMat shift(CMat X, int64_t i, int64_t j) {
@@ -164,6 +175,10 @@ int run_gemm(int P, const GemmBatch& top, int algo, int levels, int base, int sl
   const int L = pl.L;
   if (L == 0) return leaf(P, top, base, slices, w, ws_bytes, s);
   int rc;
+  // equilibration exponents of A's rows and B's columns (top level only)
+  int* ea = (int*)(w + pl.off_exp);
+  int* fb = ea + top.m;
+  if ((rc = launch_exponents(top.A, top.B, top.m, top.n, top.l, ea, fb, s))) return rc;
   // pre-adds, level by level
   for (int j = 1; j <= L; j++) {
     CMat srcA = j == 1 ? top.A : opA(pl, w, j - 1);
@@ -171,8 +186,10 @@ int run_gemm(int P, const GemmBatch& top, int algo, int levels, int base, int sl
     CMat dA = opA(pl, w, j), dB = opB(pl, w, j);
     Mat dstA{(double*)dA.p, dA.ld, dA.ps, dA.bstride};
     Mat dstB{(double*)dB.p, dB.ld, dB.ps, dB.bstride};
-    if ((rc = preadd(P, srcA, dstA, pl.m[j], pl.l[j], pow7(j - 1), algo, 0, s))) return rc;
-    if ((rc = preadd(P, srcB, dstB, pl.l[j], pl.n[j], pow7(j - 1), algo, 1, s))) return rc;
+    const int* xa = j == 1 ? ea : nullptr;
+    const int* xb = j == 1 ? fb : nullptr;
+    if ((rc = preadd(P, srcA, dstA, pl.m[j], pl.l[j], pow7(j - 1), algo, 0, xa, s))) return rc;
+    if ((rc = preadd(P, srcB, dstB, pl.l[j], pl.n[j], pow7(j - 1), algo, 1, xb, s))) return rc;
   }
   // all leaf products in one batched launch
   GemmBatch lf{pl.m[L], pl.n[L], pl.l[L], 1, 0, opA(pl, w, L), opB(pl, w, L), prodM(pl, w, L),
@@ -187,7 +204,7 @@ int run_gemm(int P, const GemmBatch& top, int algo, int levels, int base, int sl
     const int alpha = root ? top.alpha : 1, beta = root ? top.beta : 0;
     const int64_t parents = pow7(j - 1);
     if ((rc = postadd(P, cview(prodM(pl, w, j)), dst, pl.m[j], pl.n[j], parents, algo, alpha,
-                      beta, s)))
+                      beta, root ? ea : nullptr, root ? fb : nullptr, s)))
       return rc;
     const int64_t me = 2 * pl.m[j], ne = 2 * pl.n[j], le = 2 * pl.l[j];
     const int64_t mp = pl.m[j - 1], np = pl.n[j - 1], lp = pl.l[j - 1];

@@ -121,6 +121,7 @@ struct DDNum {
   __device__ static T add(T a, T b) { return dd_add(a, b); }
   __device__ static T sub(T a, T b) { return dd_sub(a, b); }
   __device__ static T neg(T a) { return dd_neg(a); }
+  __device__ static T scale(T a, int e) { return T{ldexp(a.hi, e), ldexp(a.lo, e)}; }
 };
 
 struct QDNum {
@@ -138,6 +139,9 @@ struct QDNum {
   __device__ static T add(T a, T b) { return qd_add(a, b); }
   __device__ static T sub(T a, T b) { return qd_sub(a, b); }
   __device__ static T neg(T a) { return qd_neg(a); }
+  __device__ static T scale(T a, int e) {
+    return T{{ldexp(a.c[0], e), ldexp(a.c[1], e), ldexp(a.c[2], e), ldexp(a.c[3], e)}};
+  }
 };
 
 }  // namespace ddqd

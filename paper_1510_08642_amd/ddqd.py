@@ -69,6 +69,8 @@ def _mat(X: torch.Tensor, P: int, name: str):
         raise ValueError(f"{name} must have shape ({P}, rows, cols)")
     if X.dtype != torch.float64:
         raise TypeError(f"{name} must be float64")
+    if X.numel() == 0:          # empty: strides are meaningless and never used
+        return X.data_ptr(), max(1, X.shape[2]), max(1, X.shape[1] * X.shape[2])
     if X.shape[2] > 1 and X.stride(2) != 1:
         raise ValueError(f"{name} must be contiguous along its last dimension")
     return X.data_ptr(), X.stride(1), X.stride(0)

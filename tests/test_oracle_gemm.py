@@ -152,3 +152,21 @@ def test_rectangular_operand_order_matters():
     C = oracle.gemm(A, B, "winograd", 2, bs=1)
     assert C.shape == (2, 3, 2)
     assert np.array_equal(C[0], A[0] @ B[0])
+
+
+def test_row_scaled_inputs_keep_rownormwise_accuracy():
+    """Rows of A scaled by 2^r, r in [-30, 30]: the row-normwise error of every
+    algorithm stays within the tolerance (Strassen and Winograd through their
+    exact equilibration), and equals the unscaled error pattern."""
+    g = inputs.rng(13)
+    m, n, l = 40, 36, 38
+    A = inputs.dd_uniform(m, l, g)
+    B = inputs.dd_uniform(l, n, g)
+    As, r = inputs.row_scaled(A, g)
+    for algo, lv in ALGS:
+        C = oracle.gemm(As, B, algo, lv, bs=8)
+        e = rownorm_error(As, B, C)
+        assert e <= 2.0 ** -100 * l, (algo, lv, e)
+        # scaling back row i by 2^-r_i reproduces the unscaled product bitwise
+        C0 = oracle.gemm(A, B, algo, lv, bs=8)
+        assert np.array_equal(np.ldexp(C, -r[None, :, None]), C0), (algo, lv)
