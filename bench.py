@@ -40,6 +40,24 @@ DD_OPS_PER_MAC = 12 + 6 / 16
 QD_OPS_PER_MAC = 113 + 30 / 16
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE, WRITE_SIZE scaled by a plain copy's readings), or
+    None when the kernel's source has changed since they were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(root, "profiles", "traffic.json")) as f:
+            rec = json.load(f)[kernel]
+        with open(os.path.join(root, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
+                return None
+        return int(1024 * (rec["fetch_kib"] * rec["fetch_scale"] +
+                           rec["write_kib"] * rec["write_scale"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def time_steps(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -102,6 +120,9 @@ def main():
     ap.add_argument("--base", default="fma")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB, 5 times "
+                         "(reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -109,6 +130,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 5 copies of {nbytes} bytes")
+        return
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     from paper_1510_08642_amd import ddqd, inputs
 
@@ -142,7 +172,8 @@ def main():
         achieved = macs * DD_OPS_PER_MAC / (ms * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": "dd_gemm_block_kernel", "achieved": round(achieved, 3),
                 "peak": round(FP64_OPS_PEAK_T, 2), "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_OPS_PEAK_T, 4), "traffic": None,
+                "frac": round(achieved / FP64_OPS_PEAK_T, 4),
+                "traffic": measured_traffic("dd_gemm_block_kernel"),
                 "note": "FP64 VALU operations (add, mul or fma count 1 each; "
                         f"{DD_OPS_PER_MAC} per DD multiply-add) over the kernel's "
                         "average launch time; peak = 256 CU x 2.4 GHz x 64 lanes"}
