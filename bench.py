@@ -185,7 +185,9 @@ def main():
         for (algo, lv, base) in [("block", 0, "fma"), ("strassen", 1, "fma"),
                                  ("strassen", 2, "fma"), ("strassen", 3, "fma"),
                                  ("winograd", 1, "fma"), ("winograd", 2, "fma"),
-                                 ("winograd", 3, "fma")]:
+                                 ("winograd", 3, "fma"), ("block", 0, "ozaki"),
+                                 ("winograd", 1, "ozaki"), ("winograd", 2, "ozaki"),
+                                 ("strassen", 1, "ozaki")]:
             try:
                 t = time_steps(make(algo, lv, base), max(3, args.steps // 4), 1, stream)
                 variants[f"dd_{algo}{lv}_{base}"] = round(flops / (t * 1e-3) / 1e9, 1)

@@ -1,10 +1,386 @@
-// placeholder, replaced by the Ozaki INT8 path
+// DD matrix product on INT8 matrix cores by an Ozaki-style split
+// (a base kernel for the leaves of Sec. 2's algorithms; not in the paper,
+// which predates it).
+//
+// 1. Scale.  For row i of A take e_i with max_k |a_ik| < 2^(e_i - 1) (from the
+//    leading components), for column j of B likewise f_j; a'_ik = a_ik 2^-e_i
+//    and b'_kj = b_kj 2^-f_j lie in (-1/2, 1/2) exactly.
+// 2. Slice.  Each scaled DD value is written as sum_{t=1..S} d_t 2^-7t + r
+//    with signed digits d_t in [-64, 64] (round to nearest of 2^7 times the
+//    remainder, which is then formed exactly in DD), |r| <= 2^(-7S-1).  The
+//    digits are stored as INT8 in the fragment order of the 32x32x32 MFMA:
+//    for a 32-row (or 32-column) by 32-k block, lane l's 16 bytes are row
+//    (column) l % 32, k = 16 (l / 32) + 0..15.
+// 3. Products.  For every diagonal d = t + u <= S + 1 the INT32 sum
+//    P_d = sum_{t+u=d} A_t B_u is accumulated exactly on
+//    v_mfma_i32_32x32x32_i8 (|P_d| <= S l 65^2 < 2^31 for K chunks of at
+//    most 2^14).  A wave owns a 32x32 block of C and keeps all S diagonal
+//    accumulators (16 S registers) live, so each K step loads the 2S
+//    fragments once and issues S(S+1)/2 MFMAs on them.
+// 4. Recombine (epilogue of the same kernel).  Four consecutive diagonals
+//    combine exactly in FP64 (2^21 P_d + 2^14 P_d+1 + 2^7 P_d+2 + P_d+3 <
+//    2^53); the four group values, scaled by 2^(e_i + f_j - 7(d+3)), are
+//    summed by TwoSum into a DD, then C := beta C + alpha value.
+//
+// Error: slicing and the dropped diagonals d > S + 1 contribute at most about
+// l (S + 3) 2^(-7S-2) 2^(e_i + f_j) to entry (i, j); with S = 16 that is below
+// 2^-103 l max|a_i.| max|b_.j| -- the same accuracy class as the FMA kernel.
 #include "../../include/ddqd.h"
 #include "common.hpp"
+#include "eft.hpp"
+
+#pragma clang fp contract(off)
+
 namespace ddqd {
-size_t ozaki_workspace(int64_t, int64_t, int64_t, int64_t, int) { return 0; }
-int launch_ozaki(const GemmBatch&, int, void*, size_t, hipStream_t) {
-  return set_error(DDQD_E_UNSUPPORTED, "Ozaki base not built yet");
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kFrag = 1024;          // bytes of one 32x32 INT8 fragment block
+constexpr int64_t kKChunk = 16384;   // K per exact INT32 accumulation
+constexpr int kMinS = 8, kMaxS = 20;
+
+struct OzLayout {
+  int64_t m, n, l;       // problem
+  int64_t rb, cb, kb;    // 32-blocks: rows of A (even), columns of B (even), K
+  int S;
+  int64_t a_bytes, b_bytes;  // per batch entry
+};
+
+OzLayout oz_layout(int64_t m, int64_t n, int64_t l, int S) {
+  OzLayout o;
+  o.m = m;
+  o.n = n;
+  o.l = l;
+  o.S = S;
+  o.rb = ((m + 63) / 64) * 2;
+  o.cb = ((n + 63) / 64) * 2;
+  o.kb = (l + 31) / 32;
+  o.a_bytes = o.rb * o.kb * S * (int64_t)kFrag;
+  o.b_bytes = o.cb * o.kb * S * (int64_t)kFrag;
+  return o;
 }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Exponents e with max |leading component| < 2^(e-1): one wave per row of A.
+__global__ __launch_bounds__(256) void oz_row_exp_kernel(CMat A, int64_t m, int64_t l,
+                                                         int64_t rows_pad, int* e) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  const int64_t b = blockIdx.y;
+  const int lane = threadIdx.x % 64;
+  if (r >= rows_pad) return;
+  double mx = 0.0;
+  if (r < m) {
+    const double* p = A.p + b * A.bstride + r * A.ld;
+    for (int64_t k = lane; k < l; k += 64) mx = fmax(mx, fabs(p[k]));
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) {
+    int ex = 0;
+    if (mx > 0.0) frexp(mx, &ex);
+    e[b * rows_pad + r] = ex + 1;
+  }
+}
+
+// Same for the columns of B: one lane per column, coalesced across lanes.
+__global__ __launch_bounds__(256) void oz_col_exp_kernel(CMat B, int64_t l, int64_t n,
+                                                         int64_t cols_pad, int* e) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t b = blockIdx.y;
+  if (c >= cols_pad) return;
+  double mx = 0.0;
+  if (c < n) {
+    const double* p = B.p + b * B.bstride + c;
+    for (int64_t k = 0; k < l; k++) mx = fmax(mx, fabs(p[k * B.ld]));
+  }
+  int ex = 0;
+  if (mx > 0.0) frexp(mx, &ex);
+  e[b * cols_pad + c] = ex + 1;
+}
+
+// One thread per (32-block, K block, half): 16 consecutive k of one row of A
+// (side 0) or one column of B (side 1), all S digits, one 16-byte store per
+// slice.  Items are ordered so consecutive threads read consecutive memory.
+// Digits of a scaled DD value r (|r| < 1/2): d_t = rint(2^7 r_{t-1}) and
+// r_t = 2^7 r_{t-1} - d_t, formed exactly (the fractional part of the high
+// word is exact, TwoSum adds the low word).
+template <int S>
+__global__ __launch_bounds__(256) void oz_slice_kernel(CMat X, int side, int64_t rows,
+                                                       int64_t cols, OzLayout o,
+                                                       const int* e, signed char* out) {
+  // side 0: X is A (rows = m, cols = l); side 1: X is B (rows = l, cols = n)
+  const int64_t nblk32 = side == 0 ? o.rb : o.cb;
+  const int64_t items = nblk32 * 32 * o.kb * 2;
+  const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t b = blockIdx.y;
+  if (it >= items) return;
+  int64_t line, kb, half;
+  if (side == 0) {  // consecutive items: same row, consecutive 16-k chunks
+    half = it % 2;
+    kb = (it / 2) % o.kb;
+    line = it / (2 * o.kb);
+  } else {          // consecutive items: consecutive columns, same k chunk
+    line = it % (nblk32 * 32);
+    half = (it / (nblk32 * 32)) % 2;
+    kb = it / (nblk32 * 32 * 2);
+  }
+  const int64_t blk = line / 32, lane = (line % 32) + 32 * half;
+  const int64_t k0 = kb * 32 + 16 * half;
+  const int ex = e[b * (nblk32 * 32) + line];
+  const double* base = X.p + b * X.bstride;
+  const bool live = side == 0 ? line < rows : line < cols;
+  const int64_t kmax = side == 0 ? cols : rows;
+  double rh[16], rl[16];
+#pragma unroll
+  for (int q = 0; q < 16; q++) {
+    const int64_t k = k0 + q;
+    rh[q] = 0.0;
+    rl[q] = 0.0;
+    if (live && k < kmax) {
+      const int64_t idx = side == 0 ? line * X.ld + k : k * X.ld + line;
+      rh[q] = ldexp(base[idx], -ex);
+      rl[q] = ldexp(base[X.ps + idx], -ex);
+    }
+  }
+  signed char* dst = out + b * (side == 0 ? o.a_bytes : o.b_bytes) +
+                     ((blk * o.kb + kb) * S) * (int64_t)kFrag + lane * 16;
+  for (int t = 0; t < S; t++) {
+    v4i w;
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      uint32_t x = 0;
+#pragma unroll
+      for (int byte = 0; byte < 4; byte++) {
+        const int q = 4 * v + byte;
+        double h = rh[q] * 128.0, lo = rl[q] * 128.0;
+        double d = rint(h);
+        x |= (uint32_t)(uint8_t)(signed char)(int)d << (8 * byte);
+        two_sum(h - d, lo, rh[q], rl[q]);
+      }
+      w[v] = (int)x;
+    }
+    *reinterpret_cast<v4i*>(dst + t * (int64_t)kFrag) = w;
+  }
+}
+
+// The product kernel: 4 waves (2x2) per 64x64 tile of C, one 32x32 block per
+// wave with S INT32 diagonal accumulators (16 S accumulator registers).
+// Fragments move global -> LDS by direct loads (global_load_lds_dwordx4, no
+// registers): per K block the workgroup stages 4 S fragments of 1 KB (the S
+// slices of its two row blocks of A and two column blocks of B; wave w loads
+// group w), double-buffered.  Each wave then holds its S B fragments in
+// registers and reads one A fragment at a time from LDS.
+template <int S>
+__global__ __launch_bounds__(256) void oz_gemm_kernel(GemmBatch g, OzLayout o,
+                                                      const signed char* Asl,
+                                                      const signed char* Bsl, const int* ea,
+                                                      const int* fb, int64_t tiles_m,
+                                                      int64_t tiles_n, int64_t kc0, int64_t kc1,
+                                                      int beta) {
+  __shared__ v4i lds[2][4 * S][64];
+
+  const int64_t t = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
+  const int64_t per = tiles_m * tiles_n;
+  const int64_t b = t / per;
+  const int64_t tm = (t % per) / tiles_n, tn = (t % per) % tiles_n;
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wr = w / 2, wc = w % 2;
+  const int64_t rb = 2 * tm + wr, cb = 2 * tn + wc;
+
+  // fragment group this wave stages: 0, 1 = A row blocks 2tm, 2tm+1; 2, 3 = B column blocks
+  const signed char* src =
+      w < 2 ? Asl + b * o.a_bytes + (2 * tm + w) * o.kb * S * (int64_t)kFrag
+            : Bsl + b * o.b_bytes + (2 * tn + (w - 2)) * o.kb * S * (int64_t)kFrag;
+  src += lane * 16;
+  auto stage = [&](int st, int64_t kb) {
+    const signed char* p = src + kb * S * (int64_t)kFrag;
+#pragma unroll
+    for (int s = 0; s < S; s++)
+      __builtin_amdgcn_global_load_lds((const void*)(p + s * (int64_t)kFrag),
+                                       (__attribute__((address_space(3))) void*)&lds[st][w * S + s][0],
+                                       16, 0, 0);
+  };
+
+  // this lane's 16 outputs: column cb*32 + lane % 32, rows 8 (q / 4) + 4 (lane / 32) + q % 4
+  const double* Cb_ro = g.C.p + b * g.C.bstride;
+  double* Cb = g.C.p + b * g.C.bstride;
+
+  // K blocks [kc0, kc1): one exact INT32 accumulation (the host splits
+  // longer K into chunks and accumulates them into C with beta = 1)
+  {
+    v16i acc[S];
+#pragma unroll
+    for (int d = 0; d < S; d++)
+#pragma unroll
+      for (int q = 0; q < 16; q++) acc[d][q] = 0;
+    stage(0, kc0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int64_t kb = kc0; kb < kc1; kb++) {
+      const int st = (int)((kb - kc0) & 1);
+      // the other buffer was last read in the previous K block, before the barrier
+      if (kb + 1 < kc1) stage(st ^ 1, kb + 1);
+      v4i fbv[S];
+#pragma unroll
+      for (int s = 0; s < S; s++) fbv[s] = lds[st][2 * S + wc * S + s][lane];
+      // A fragments: one in use, the next one in flight (a barrier per slice
+      // keeps the scheduler from hoisting all S reads and their registers)
+      v4i fa = lds[st][wr * S][lane];
+#pragma unroll
+      for (int ta = 0; ta < S; ta++) {
+        const v4i fnext = lds[st][wr * S + (ta + 1 < S ? ta + 1 : ta)][lane];
+#pragma unroll
+        for (int ub = S - 1 - ta; ub >= 0; ub--)
+          acc[ta + ub] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa, fbv[ub], acc[ta + ub], 0, 0, 0);
+        fa = fnext;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+    // recombine: value = 2^(e_i + f_j) sum_d 2^(-7 (d + 2)) P_d, d = 0..S-1,
+    // four outputs at a time (scheduling barriers keep the temporaries of
+    // only those four live).
+    // Opaque copy of the lane index: the epilogue's row and address arithmetic
+    // derives from it, so none of it is hoisted into (and kept live through)
+    // the MFMA loop.
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const int rb2 = 4 * (ln / 32);
+    const int64_t col = cb * 32 + ln % 32;
+    const int fexp = col < g.n ? fb[b * (o.cb * 32) + col] : 0;
+#pragma unroll
+    for (int q4 = 0; q4 < 4; q4++) {
+      __builtin_amdgcn_sched_barrier(0);
+      int sc[4];
+      int64_t row[4];
+#pragma unroll
+      for (int z = 0; z < 4; z++) {
+        row[z] = rb * 32 + 8 * q4 + rb2 + z;
+        sc[z] = row[z] < g.m ? ea[b * (o.rb * 32) + row[z]] + fexp : 0;
+      }
+      double sh[4], sl[4];
+#pragma unroll
+      for (int gi = 0; gi < (S + 3) / 4; gi++) {
+        double G[4] = {0.0, 0.0, 0.0, 0.0};
+        int last = 0;
+#pragma unroll
+        for (int zz = 0; zz < 4; zz++) {
+          const int d = 4 * gi + zz;
+          if (d < S) {
+#pragma unroll
+            for (int z = 0; z < 4; z++)  // exact: integers < 2^53
+              G[z] = __builtin_fma(G[z], 128.0, (double)acc[d][4 * q4 + z]);
+            last = d;
+          }
+        }
+#pragma unroll
+        for (int z = 0; z < 4; z++) {
+          const double part = ldexp(G[z], sc[z] - 7 * (last + 2));
+          if (gi == 0) {
+            sh[z] = part;
+            sl[z] = 0.0;
+          } else {
+            double err;
+            two_sum(sh[z], part, sh[z], err);
+            sl[z] += err;
+          }
+        }
+      }
+#pragma unroll
+      for (int z = 0; z < 4; z++) {
+        if (row[z] >= g.m || col >= g.n) continue;
+        dd_t v;
+        two_sum(sh[z], sl[z], v.hi, v.lo);
+        if (g.alpha < 0) v = dd_neg(v);
+        const int64_t off = row[z] * g.C.ld + col;
+        if (beta) v = dd_add(dd_t{Cb_ro[off], Cb_ro[g.C.ps + off]}, v);
+        Cb[off] = v.hi;
+        Cb[g.C.ps + off] = v.lo;
+      }
+    }
+  }
+}
+
+template <int S>
+int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
+  OzLayout o = oz_layout(g.m, g.n, g.l, S);
+  signed char* Asl = (signed char*)ws;
+  signed char* Bsl = (signed char*)(ws + align256(o.a_bytes * g.batch));
+  int* ea = (int*)(ws + align256(o.a_bytes * g.batch) + align256(o.b_bytes * g.batch));
+  int* fb = ea + g.batch * o.rb * 32;
+  const int64_t rows_pad = o.rb * 32, cols_pad = o.cb * 32;
+  if (g.batch > 65535) return set_error(DDQD_E_UNSUPPORTED, "batch too large");
+  hipLaunchKernelGGL(oz_row_exp_kernel, dim3((unsigned)((rows_pad + 3) / 4), (unsigned)g.batch),
+                     dim3(256), 0, s, g.A, g.m, g.l, rows_pad, ea);
+  hipLaunchKernelGGL(oz_col_exp_kernel,
+                     dim3((unsigned)((cols_pad + 255) / 256), (unsigned)g.batch), dim3(256), 0, s,
+                     g.B, g.l, g.n, cols_pad, fb);
+  int rc = check_launch("oz_exp");
+  if (rc) return rc;
+  const int64_t ia = o.rb * 32 * o.kb * 2, ib = o.cb * 32 * o.kb * 2;
+  hipLaunchKernelGGL(oz_slice_kernel<S>, dim3((unsigned)((ia + 255) / 256), (unsigned)g.batch),
+                     dim3(256), 0, s, g.A, 0, g.m, g.l, o, (const int*)ea, Asl);
+  hipLaunchKernelGGL(oz_slice_kernel<S>, dim3((unsigned)((ib + 255) / 256), (unsigned)g.batch),
+                     dim3(256), 0, s, g.B, 1, g.l, g.n, o, (const int*)fb, Bsl);
+  if ((rc = check_launch("oz_slice_kernel"))) return rc;
+  const int64_t tm = o.rb / 2, tn = o.cb / 2;
+  const int64_t nblk = tm * tn * g.batch;
+  if (nblk > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "grid too large");
+  for (int64_t kc0 = 0; kc0 < o.kb; kc0 += kKChunk / 32) {
+    const int64_t kc1 = kc0 + kKChunk / 32 < o.kb ? kc0 + kKChunk / 32 : o.kb;
+    hipLaunchKernelGGL(oz_gemm_kernel<S>, dim3((unsigned)nblk), dim3(256), 0, s, g, o,
+                       (const signed char*)Asl, (const signed char*)Bsl, (const int*)ea,
+                       (const int*)fb, tm, tn, kc0, kc1, kc0 == 0 ? g.beta : 1);
+    if ((rc = check_launch("oz_gemm_kernel"))) return rc;
+  }
+  return DDQD_OK;
+}
+
+}  // namespace
+
 int ozaki_default_slices() { return 16; }
+
+static int resolve_slices(int slices) {
+  if (slices == 0) return ozaki_default_slices();
+  return slices;
+}
+
+size_t ozaki_workspace(int64_t m, int64_t n, int64_t l, int64_t batch, int slices) {
+  const int S = resolve_slices(slices);
+  if (S < kMinS || S > kMaxS || m <= 0 || n <= 0 || l <= 0) return 0;
+  OzLayout o = oz_layout(m, n, l, S);
+  return align256(o.a_bytes * batch) + align256(o.b_bytes * batch) +
+         align256(sizeof(int) * (size_t)(batch * (o.rb + o.cb) * 32));
+}
+
+int launch_ozaki(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return DDQD_OK;
+  const int S = resolve_slices(slices);
+  if (S < kMinS || S > kMaxS)
+    return set_error(DDQD_E_UNSUPPORTED, "Ozaki slices must be in %d..%d", kMinS, kMaxS);
+  if (ozaki_workspace(g.m, g.n, g.l, g.batch, S) > ws_bytes)
+    return set_error(DDQD_E_WORKSPACE, "Ozaki workspace too small");
+  char* w = (char*)ws;
+  switch (S) {
+    case 8: return run_ozaki<8>(g, w, s);
+    case 9: return run_ozaki<9>(g, w, s);
+    case 10: return run_ozaki<10>(g, w, s);
+    case 11: return run_ozaki<11>(g, w, s);
+    case 12: return run_ozaki<12>(g, w, s);
+    case 13: return run_ozaki<13>(g, w, s);
+    case 14: return run_ozaki<14>(g, w, s);
+    case 15: return run_ozaki<15>(g, w, s);
+    case 16: return run_ozaki<16>(g, w, s);
+    case 17: return run_ozaki<17>(g, w, s);
+    case 18: return run_ozaki<18>(g, w, s);
+    case 19: return run_ozaki<19>(g, w, s);
+    case 20: return run_ozaki<20>(g, w, s);
+  }
+  return set_error(DDQD_E_UNSUPPORTED, "slices");
+}
+
 }  // namespace ddqd
