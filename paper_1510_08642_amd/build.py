@@ -27,6 +27,7 @@ FLAGS = [
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+    "-I", os.path.join(os.path.dirname(HERE), "include"),
 ]
 
 

@@ -23,7 +23,7 @@
 
 #include <algorithm>
 
-#include "../../include/ddqd.h"
+#include "ddqd.h"
 #include "common.hpp"
 #include "qd.hpp"
 

@@ -25,7 +25,7 @@
 // Error: slicing and the dropped diagonals d > S + 1 contribute at most about
 // l (S + 3) 2^(-7S-2) 2^(e_i + f_j) to entry (i, j); with S = 16 that is below
 // 2^-103 l max|a_i.| max|b_.j| -- the same accuracy class as the FMA kernel.
-#include "../../include/ddqd.h"
+#include "ddqd.h"
 #include "common.hpp"
 #include "eft.hpp"
 
@@ -65,17 +65,30 @@ OzLayout oz_layout(int64_t m, int64_t n, int64_t l, int S) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Exponents e with max |leading component| < 2^(e-1): one wave per row of A.
+// Exponents e with max |leading component| < 2^(e-1): one wave per row of A
+// (padded rows get 1).  The same launch sets B's column exponents to the
+// sentinel the column pass raises atomically.
+constexpr int kNoExp = -(1 << 20);
+
 __global__ __launch_bounds__(256) void oz_row_exp_kernel(CMat A, int64_t m, int64_t l,
-                                                         int64_t rows_pad, int* e) {
+                                                         int64_t rows_pad, int* e, int* fb,
+                                                         int64_t nfb) {
   const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   const int64_t b = blockIdx.y;
   const int lane = threadIdx.x % 64;
+  if (b == 0)
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nfb;
+         i += (int64_t)gridDim.x * 256)
+      fb[i] = kNoExp;
   if (r >= rows_pad) return;
   double mx = 0.0;
   if (r < m) {
     const double* p = A.p + b * A.bstride + r * A.ld;
-    for (int64_t k = lane; k < l; k += 64) mx = fmax(mx, fabs(p[k]));
+    int64_t k = lane;
+    for (; k + 192 < l; k += 256)
+      mx = fmax(fmax(mx, fabs(p[k])),
+                fmax(fabs(p[k + 64]), fmax(fabs(p[k + 128]), fabs(p[k + 192]))));
+    for (; k < l; k += 64) mx = fmax(mx, fabs(p[k]));
   }
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
   if (lane == 0) {
@@ -85,84 +98,97 @@ __global__ __launch_bounds__(256) void oz_row_exp_kernel(CMat A, int64_t m, int6
   }
 }
 
-// Same for the columns of B: one lane per column, coalesced across lanes.
+// Columns of B: all-zero columns keep the sentinel kNoExp (the slicing then
+// scales zeros, which stay zero); otherwise the atomic maximum, over slabs of
+// 32 rows, of the exponent + 1 (exponents are monotone in |x|, so the maximum
+// of the partial exponents is the exponent of the maximum, in any order).
 __global__ __launch_bounds__(256) void oz_col_exp_kernel(CMat B, int64_t l, int64_t n,
                                                          int64_t cols_pad, int* e) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t b = blockIdx.y;
-  if (c >= cols_pad) return;
+  __shared__ double red[4][64];
+  const int c_in = threadIdx.x % 64, r = threadIdx.x / 64;
+  const int64_t c = (int64_t)blockIdx.x * 64 + c_in;
+  const int64_t k0 = (int64_t)blockIdx.y * 32 + r * 8;
+  const int64_t b = blockIdx.z;
   double mx = 0.0;
   if (c < n) {
     const double* p = B.p + b * B.bstride + c;
-    for (int64_t k = 0; k < l; k++) mx = fmax(mx, fabs(p[k * B.ld]));
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+      if (k0 + q < l) mx = fmax(mx, fabs(p[(k0 + q) * B.ld]));
   }
-  int ex = 0;
-  if (mx > 0.0) frexp(mx, &ex);
-  e[b * cols_pad + c] = ex + 1;
+  red[r][c_in] = mx;
+  __syncthreads();
+  if (r == 0 && c < cols_pad) {
+    mx = fmax(fmax(red[0][c_in], red[1][c_in]), fmax(red[2][c_in], red[3][c_in]));
+    if (mx > 0.0) {
+      int ex;
+      frexp(mx, &ex);
+      atomicMax(&e[b * cols_pad + c], ex + 1);
+    }
+  }
 }
 
-// One thread per (32-block, K block, half): 16 consecutive k of one row of A
-// (side 0) or one column of B (side 1), all S digits, one 16-byte store per
-// slice.  Items are ordered so consecutive threads read consecutive memory.
-// Digits of a scaled DD value r (|r| < 1/2): d_t = rint(2^7 r_{t-1}) and
-// r_t = 2^7 r_{t-1} - d_t, formed exactly (the fractional part of the high
-// word is exact, TwoSum adds the low word).
+// Slicing.  One thread per 4 consecutive k of one row of A or one column of
+// B (one 4-byte store per slice); both operands in one launch (blockIdx.y:
+// 0 = A, 1 = B).  A items run along k first (8 threads read a row's 32-k
+// block, 256 contiguous bytes), B items along the columns (coalesced rows of
+// B).  Digits of a scaled DD value r (|r| < 1/2): d_t = rint(2^7 r_{t-1}),
+// r_t = 2^7 r_{t-1} - d_t, formed exactly: the fractional part of the high
+// word is exact and is either 0 or at least ulp(high) >= 2 |low|, which is
+// FastTwoSum's precondition.
 template <int S>
-__global__ __launch_bounds__(256) void oz_slice_kernel(CMat X, int side, int64_t rows,
-                                                       int64_t cols, OzLayout o,
-                                                       const int* e, signed char* out) {
-  // side 0: X is A (rows = m, cols = l); side 1: X is B (rows = l, cols = n)
+__global__ __launch_bounds__(256) void oz_slice_kernel(CMat A, CMat B, int64_t m, int64_t n,
+                                                       int64_t l, OzLayout o, const int* ea,
+                                                       const int* fb, signed char* Asl,
+                                                       signed char* Bsl) {
+  const int side = blockIdx.y;
+  const int64_t b = blockIdx.z;
   const int64_t nblk32 = side == 0 ? o.rb : o.cb;
-  const int64_t items = nblk32 * 32 * o.kb * 2;
+  const int64_t lines = nblk32 * 32;
+  const int64_t items = lines * o.kb * 8;
   const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t b = blockIdx.y;
   if (it >= items) return;
-  int64_t line, kb, half;
-  if (side == 0) {  // consecutive items: same row, consecutive 16-k chunks
-    half = it % 2;
-    kb = (it / 2) % o.kb;
-    line = it / (2 * o.kb);
-  } else {          // consecutive items: consecutive columns, same k chunk
-    line = it % (nblk32 * 32);
-    half = (it / (nblk32 * 32)) % 2;
-    kb = it / (nblk32 * 32 * 2);
+  int64_t line, kb, g4;
+  if (side == 0) {
+    g4 = it % 8;
+    line = (it / 8) % lines;
+    kb = it / (8 * lines);
+  } else {
+    line = it % lines;
+    g4 = (it / lines) % 8;
+    kb = it / (8 * lines);
   }
-  const int64_t blk = line / 32, lane = (line % 32) + 32 * half;
-  const int64_t k0 = kb * 32 + 16 * half;
-  const int ex = e[b * (nblk32 * 32) + line];
+  const CMat X = side == 0 ? A : B;
+  const int ex = (side == 0 ? ea : fb)[b * lines + line];
   const double* base = X.p + b * X.bstride;
-  const bool live = side == 0 ? line < rows : line < cols;
-  const int64_t kmax = side == 0 ? cols : rows;
-  double rh[16], rl[16];
+  const bool live = line < (side == 0 ? m : n);
+  const int64_t k0 = kb * 32 + 4 * g4;
+  double rh[4], rl[4];
 #pragma unroll
-  for (int q = 0; q < 16; q++) {
+  for (int q = 0; q < 4; q++) {
     const int64_t k = k0 + q;
     rh[q] = 0.0;
     rl[q] = 0.0;
-    if (live && k < kmax) {
+    if (live && k < l) {
       const int64_t idx = side == 0 ? line * X.ld + k : k * X.ld + line;
       rh[q] = ldexp(base[idx], -ex);
       rl[q] = ldexp(base[X.ps + idx], -ex);
     }
   }
-  signed char* dst = out + b * (side == 0 ? o.a_bytes : o.b_bytes) +
-                     ((blk * o.kb + kb) * S) * (int64_t)kFrag + lane * 16;
+  const int64_t lane = (line % 32) + 32 * (g4 / 4);
+  signed char* dst = (side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
+                     ((line / 32) * o.kb + kb) * S * (int64_t)kFrag + lane * 16 + 4 * (g4 % 4);
+#pragma unroll 4
   for (int t = 0; t < S; t++) {
-    v4i w;
+    uint32_t x = 0;
 #pragma unroll
-    for (int v = 0; v < 4; v++) {
-      uint32_t x = 0;
-#pragma unroll
-      for (int byte = 0; byte < 4; byte++) {
-        const int q = 4 * v + byte;
-        double h = rh[q] * 128.0, lo = rl[q] * 128.0;
-        double d = rint(h);
-        x |= (uint32_t)(uint8_t)(signed char)(int)d << (8 * byte);
-        two_sum(h - d, lo, rh[q], rl[q]);
-      }
-      w[v] = (int)x;
+    for (int q = 0; q < 4; q++) {
+      const double h = rh[q] * 128.0, lo = rl[q] * 128.0;
+      const double d = rint(h);
+      x |= (uint32_t)(uint8_t)(signed char)(int)d << (8 * q);
+      fast_two_sum(h - d, lo, rh[q], rl[q]);
     }
-    *reinterpret_cast<v4i*>(dst + t * (int64_t)kFrag) = w;
+    *reinterpret_cast<uint32_t*>(dst + t * (int64_t)kFrag) = x;
   }
 }
 
@@ -209,37 +235,46 @@ __global__ __launch_bounds__(256) void oz_gemm_kernel(GemmBatch g, OzLayout o,
   double* Cb = g.C.p + b * g.C.bstride;
 
   // K blocks [kc0, kc1): one exact INT32 accumulation (the host splits
-  // longer K into chunks and accumulates them into C with beta = 1)
+  // longer K into chunks and accumulates them into C with beta = 1).
+  // Pipeline: registers hold all 2S fragments of block kb while its MFMAs
+  // run; A slice ta and B slice S-1-ta are dead after row ta of the triangle,
+  // and are reloaded there from LDS with block kb+1's fragments.  LDS buffer
+  // kb % 2 is refilled by DMA with block kb+2 once every wave has read it.
   {
     v16i acc[S];
 #pragma unroll
     for (int d = 0; d < S; d++)
 #pragma unroll
       for (int q = 0; q < 16; q++) acc[d][q] = 0;
+    v4i fa[S], fbv[S];
     stage(0, kc0);
+    if (kc0 + 1 < kc1) stage(1, kc0 + 1);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < S; s2++) {
+      fa[s2] = lds[0][wr * S + s2][lane];
+      fbv[s2] = lds[0][2 * S + wc * S + s2][lane];
+    }
     for (int64_t kb = kc0; kb < kc1; kb++) {
       const int st = (int)((kb - kc0) & 1);
-      // the other buffer was last read in the previous K block, before the barrier
-      if (kb + 1 < kc1) stage(st ^ 1, kb + 1);
-      v4i fbv[S];
-#pragma unroll
-      for (int s = 0; s < S; s++) fbv[s] = lds[st][2 * S + wc * S + s][lane];
-      // A fragments: one in use, the next one in flight (a barrier per slice
-      // keeps the scheduler from hoisting all S reads and their registers)
-      v4i fa = lds[st][wr * S][lane];
-#pragma unroll
-      for (int ta = 0; ta < S; ta++) {
-        const v4i fnext = lds[st][wr * S + (ta + 1 < S ? ta + 1 : ta)][lane];
-#pragma unroll
-        for (int ub = S - 1 - ta; ub >= 0; ub--)
-          acc[ta + ub] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa, fbv[ub], acc[ta + ub], 0, 0, 0);
-        fa = fnext;
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      // all waves have read buffer st (block kb) and block kb+1 has landed
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
+      if (kb + 2 < kc1) stage(st, kb + 2);
+      const bool more = kb + 1 < kc1;
+#pragma unroll
+      for (int ta = 0; ta < S; ta++) {
+#pragma unroll
+        for (int ub = S - 1 - ta; ub >= 0; ub--)
+          acc[ta + ub] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[ta], fbv[ub], acc[ta + ub], 0,
+                                                               0, 0);
+        if (more) {
+          fa[ta] = lds[st ^ 1][wr * S + ta][lane];
+          fbv[S - 1 - ta] = lds[st ^ 1][2 * S + wc * S + (S - 1 - ta)][lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
     // recombine: value = 2^(e_i + f_j) sum_d 2^(-7 (d + 2)) P_d, d = 0..S-1,
     // four outputs at a time (scheduling barriers keep the temporaries of
@@ -314,18 +349,22 @@ int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
   int* fb = ea + g.batch * o.rb * 32;
   const int64_t rows_pad = o.rb * 32, cols_pad = o.cb * 32;
   if (g.batch > 65535) return set_error(DDQD_E_UNSUPPORTED, "batch too large");
+  if (((o.rb > o.cb ? o.rb : o.cb) * 32 * o.kb * 8 + 255) / 256 > INT32_MAX ||
+      (g.l + 31) / 32 > 65535)
+    return set_error(DDQD_E_UNSUPPORTED, "matrix too large for one Ozaki launch");
+  const int64_t nfb = cols_pad * g.batch;
   hipLaunchKernelGGL(oz_row_exp_kernel, dim3((unsigned)((rows_pad + 3) / 4), (unsigned)g.batch),
-                     dim3(256), 0, s, g.A, g.m, g.l, rows_pad, ea);
+                     dim3(256), 0, s, g.A, g.m, g.l, rows_pad, ea, fb, nfb);
   hipLaunchKernelGGL(oz_col_exp_kernel,
-                     dim3((unsigned)((cols_pad + 255) / 256), (unsigned)g.batch), dim3(256), 0, s,
-                     g.B, g.l, g.n, cols_pad, fb);
+                     dim3((unsigned)((cols_pad + 63) / 64), (unsigned)((g.l + 31) / 32),
+                          (unsigned)g.batch),
+                     dim3(256), 0, s, g.B, g.l, g.n, cols_pad, fb);
   int rc = check_launch("oz_exp");
   if (rc) return rc;
-  const int64_t ia = o.rb * 32 * o.kb * 2, ib = o.cb * 32 * o.kb * 2;
-  hipLaunchKernelGGL(oz_slice_kernel<S>, dim3((unsigned)((ia + 255) / 256), (unsigned)g.batch),
-                     dim3(256), 0, s, g.A, 0, g.m, g.l, o, (const int*)ea, Asl);
-  hipLaunchKernelGGL(oz_slice_kernel<S>, dim3((unsigned)((ib + 255) / 256), (unsigned)g.batch),
-                     dim3(256), 0, s, g.B, 1, g.l, g.n, o, (const int*)fb, Bsl);
+  const int64_t items = (o.rb > o.cb ? o.rb : o.cb) * 32 * o.kb * 8;
+  hipLaunchKernelGGL(oz_slice_kernel<S>, dim3((unsigned)((items + 255) / 256), 2, (unsigned)g.batch),
+                     dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)ea, (const int*)fb,
+                     Asl, Bsl);
   if ((rc = check_launch("oz_slice_kernel"))) return rc;
   const int64_t tm = o.rb / 2, tn = o.cb / 2;
   const int64_t nblk = tm * tn * g.batch;
