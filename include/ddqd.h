@@ -111,6 +111,45 @@ int qd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t
 size_t qd_gemm_workspace(int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
                          int slices);
 
+/*
+ * In-place LU factorisation P A = L U of the n x n DD matrix A by the blocked
+ * right-looking method of the paper (Sec. 4, steps 1-3): panels of width
+ * `panel` (the last may be narrower); after each panel, U12 := L11^-1 A12 and
+ * the trailing update A22 := A22 - L21 U12 is a product computed with
+ * `algo`, `levels` and `base` as in dd_gemm.
+ *   A        device plane-layout DD matrix (lda >= n, psa), overwritten by L
+ *            (unit lower, below the diagonal) and U (upper, with diagonal).
+ *   ipiv     device int32[n]: row i was interchanged with row ipiv[i]
+ *            (0-based, LAPACK order).
+ *   perm     device int32[n] or NULL: the resulting permutation, row i of
+ *            P A is row perm[i] of A (lets dd_getrs gather in parallel).
+ *   info     device int32[1]: 0, or 1 + the first column whose pivot is
+ *            exactly zero (the factorisation still completes).
+ *   pivot    DDQD_PIVOT_PARTIAL (largest |a_ic| below the diagonal, first row
+ *            on ties, compared in DD) or DDQD_PIVOT_NONE (the paper's choice).
+ *   ws       workspace of dd_getrf_workspace(...) bytes (the product's).
+ * Orders above 8192 return DDQD_E_UNSUPPORTED.
+ */
+int dd_getrf(int64_t n, double* A, int64_t lda, int64_t psa, int32_t* ipiv, int32_t* perm,
+             int32_t* info, int panel, int pivot, int algo, int levels, int base, void* ws,
+             size_t ws_bytes, void* stream);
+
+size_t dd_getrf_workspace(int64_t n, int panel, int algo, int levels, int base);
+
+/*
+ * Solves A X = B (Sec. 4, Eq. 2) with dd_getrf's factors: X = U^-1 L^-1 P B.
+ *   LU       the factored matrix (ldlu, pslu); ipiv its interchanges; perm
+ *            its permutation or NULL (then it is rebuilt from ipiv, serially).
+ *   B        device DD n x nrhs (ldb >= nrhs), overwritten by X; must not
+ *            overlap LU.
+ *   ws       workspace of dd_getrs_workspace(n, nrhs) bytes.
+ */
+int dd_getrs(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t pslu,
+             const int32_t* ipiv, const int32_t* perm, double* B, int64_t ldb, int64_t psb,
+             void* ws, size_t ws_bytes, void* stream);
+
+size_t dd_getrs_workspace(int64_t n, int64_t nrhs);
+
 #ifdef __cplusplus
 }
 #endif

@@ -311,6 +311,42 @@ int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* 
 }
 
 }  // namespace
+
+// Internal entry points for other drivers (LU): no validation, no alias checks.
+int gemm_internal(int P, const GemmBatch& g, int algo, int levels, int base, int slices,
+                  void* ws, size_t ws_bytes, hipStream_t s) {
+  if (g.m <= 0 || g.n <= 0) return DDQD_OK;
+  if (g.l <= 0) {
+    GemmBatch t = g;
+    t.A = cview(g.C);
+    t.B = cview(g.C);
+    return block_fma(P, t, s);
+  }
+  return run_gemm(P, g, algo, levels, base, slices, ws, ws_bytes, s);
+}
+
+size_t gemm_internal_ws(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
+                        int slices) {
+  return gemm_ws(P, m, n, l, algo, levels, base, slices);
+}
+
+int check_device() { return device_ok(); }
+
+int check_matrix(const char* name, int P, const void* p, int64_t rows, int64_t cols, int64_t ld,
+                 int64_t ps) {
+  return check_mat(name, P, p, rows, cols, ld, ps);
+}
+
+int64_t matrix_extent(int P, int64_t rows, int64_t cols, int64_t ld, int64_t ps) {
+  return extent(P, rows, cols, ld, ps);
+}
+
+bool ranges_overlap(const void* a, int64_t a_len, const void* b, int64_t b_len) {
+  return overlaps((const double*)a, a_len, (const double*)b, b_len);
+}
+
+void clear_error() { g_msg[0] = 0; }
+
 }  // namespace ddqd
 
 using namespace ddqd;

@@ -39,6 +39,15 @@ for _name in ("dd_gemm", "qd_gemm"):
 for _name in ("dd_gemm_workspace", "qd_gemm_workspace"):
     getattr(_lib, _name).argtypes = [_i64, _i64, _i64, _int, _int, _int, _int]
     getattr(_lib, _name).restype = _sz
+_lib.dd_getrf_workspace.argtypes = [_i64, _int, _int, _int, _int]
+_lib.dd_getrf_workspace.restype = _sz
+_lib.dd_getrf.argtypes = [_i64, _vp, _i64, _i64, _vp, _vp, _vp, _int, _int, _int, _int, _int, _vp,
+                          _sz, _vp]
+_lib.dd_getrf.restype = _int
+_lib.dd_getrs_workspace.argtypes = [_i64, _i64]
+_lib.dd_getrs_workspace.restype = _sz
+_lib.dd_getrs.argtypes = [_i64, _i64, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _vp, _sz, _vp]
+_lib.dd_getrs.restype = _int
 _lib.ddqd_status_string.argtypes = [_int]
 _lib.ddqd_status_string.restype = ctypes.c_char_p
 _lib.ddqd_last_error.argtypes = []
@@ -121,3 +130,53 @@ def dd_gemm(A, B, C=None, *, alpha=1, beta=0, algo="block", levels=0, base="fma"
 def qd_gemm(A, B, C=None, *, alpha=1, beta=0, algo="block", levels=0, slices=0, ws=None):
     """C := beta*C + alpha*(A B) in quad-double; returns C."""
     return _gemm(4, A, B, C, alpha, beta, algo, levels, "fma", slices, ws)
+
+
+def getrf_workspace(n: int, panel=128, algo="winograd", levels=1, base="fma") -> int:
+    ws = _lib.dd_getrf_workspace(n, panel, ALGO[algo], levels, BASE[base])
+    if ws == SIZE_MAX:
+        raise ValueError("invalid getrf arguments")
+    return ws
+
+
+def dd_getrf(A, *, panel=128, pivot="partial", algo="winograd", levels=1, base="fma",
+             want_perm=True, ws=None):
+    """In-place DD LU of the square (2, n, n) tensor A (blocked right-looking,
+    panel width `panel`, trailing update by `algo`/`levels`/`base`).
+
+    Returns (ipiv, perm, info) as device int32 tensors: LAPACK-style 0-based
+    interchanges, the resulting row permutation (or None), and info (0, or the
+    1-based column of the first exactly-zero pivot)."""
+    n = A.shape[1]
+    if A.shape[2] != n:
+        raise ValueError("A must be square")
+    pa, lda, psa = _mat(A, 2, "A")
+    dev = A.device
+    ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if want_perm else None
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    need = getrf_workspace(n, panel, algo, levels, base)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    st = _lib.dd_getrf(n, pa, lda, psa, ipiv.data_ptr(), perm.data_ptr() if perm is not None
+                       else None, info.data_ptr(), panel, PIVOT[pivot], ALGO[algo], levels,
+                       BASE[base], ws.data_ptr(), ws.numel(), _stream_of(A))
+    _check(st, "dd_getrf")
+    return ipiv[:n], (perm[:n] if perm is not None else None), info
+
+
+def dd_getrs(LU, ipiv, B, *, perm=None, ws=None):
+    """Solves A X = B in place on B (2, n, nrhs) from dd_getrf's factors."""
+    n, nrhs = B.shape[1], B.shape[2]
+    pl, ldl, psl = _mat(LU, 2, "LU")
+    pb, ldb, psb = _mat(B, 2, "B")
+    need = _lib.dd_getrs_workspace(n, nrhs)
+    if need == SIZE_MAX:
+        raise ValueError("invalid getrs arguments")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=B.device)
+    st = _lib.dd_getrs(n, nrhs, pl, ldl, psl, ipiv.data_ptr() if ipiv is not None else None,
+                       perm.data_ptr() if perm is not None else None, pb, ldb, psb,
+                       ws.data_ptr(), ws.numel(), _stream_of(B))
+    _check(st, "dd_getrs")
+    return B

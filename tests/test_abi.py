@@ -114,3 +114,39 @@ def test_empty_problems_are_no_ops(lib):
 @pytest.mark.skipif(on_gpu(), reason="checks the no-device path")
 def test_valid_call_without_device_reports_nodevice(lib):
     assert _call(lib) == E["NODEVICE"]
+
+
+def test_lu_argument_errors(lib):
+    import ctypes as C
+    A, ip, info = 0x10000, 0x40000, 0x50000
+    # n, A, lda, psa, ipiv, perm, info, panel, pivot, algo, levels, base, ws, ws_bytes, stream
+    lib.dd_getrf.argtypes = [C.c_int64, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
+                             C.c_size_t, C.c_void_p]
+    ok = dict(n=8, A=A, lda=8, psa=64, ipiv=ip, perm=None, info=info, panel=4, pivot=1, algo=1,
+              levels=0, base=0, ws=None, wsb=0)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.dd_getrf(a["n"], a["A"], a["lda"], a["psa"], a["ipiv"], a["perm"], a["info"],
+                            a["panel"], a["pivot"], a["algo"], a["levels"], a["base"], a["ws"],
+                            a["wsb"], None)
+    assert call(n=-1) == E["ARG"]
+    assert call(panel=0) == E["ARG"]
+    assert call(pivot=3) == E["ARG"]
+    assert call(info=None) == E["ARG"]
+    assert call(lda=4) == E["ARG"]
+    assert call(n=9000, lda=9000, psa=9000 * 9000) == E["UNSUPPORTED"]
+    assert call(algo=3, levels=2) == E["WORKSPACE"]
+    assert lib.dd_getrf_workspace(1024, 128, 1, 0, 0) == 0
+    assert lib.dd_getrf_workspace(1024, 128, 3, 1, 0) > 0
+    lib.dd_getrs.argtypes = [C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_size_t,
+                             C.c_void_p]
+    # B overlapping LU
+    assert lib.dd_getrs(8, 2, A, 8, 64, ip, None, A + 16, 2, 16, 0x90000, 1 << 20,
+                        None) == E["ALIAS"]
+    assert lib.dd_getrs(8, 2, A, 8, 64, None, None, 0x70000, 2, 16, 0x90000, 1 << 20,
+                        None) == E["ARG"]
+    assert lib.dd_getrs(8, 2, A, 8, 64, ip, None, 0x70000, 2, 16, None, 0, None) == E["WORKSPACE"]
+    assert lib.dd_getrs(0, 2, A, 8, 64, ip, None, 0x70000, 2, 16, None, 0, None) == E["OK"]
