@@ -102,6 +102,30 @@ int dd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t
 size_t dd_gemm_workspace(int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
                          int slices);
 
+/* One problem of a grouped launch: C := beta*C + alpha*(A B), as in dd_gemm. */
+typedef struct {
+  int64_t m, n, l;
+  int alpha, beta;
+  const double* A;
+  int64_t lda, psa;
+  const double* B;
+  int64_t ldb, psb;
+  double* C;
+  int64_t ldc, psc;
+} ddqd_gemm_desc;
+
+/*
+ * `count` unrelated DD products of any shapes (host array of descriptors,
+ * read before the call returns) in persistent Block-FMA launches of up to 24
+ * problems each: one launch instead of one per problem, for the uneven small
+ * products of a serving batch or of the 7 sub-products of a recursion level
+ * (the paper runs those as parallel sections, Sec. 2).  Each problem's result
+ * is bit-identical to the same dd_gemm call with DDQD_BLOCK and the FMA base.
+ * No output may overlap any input or another output of the group
+ * (DDQD_E_ALIAS).  No workspace.
+ */
+int dd_gemm_grouped(int count, const ddqd_gemm_desc* descs, void* stream);
+
 /* As dd_gemm, in QD (4 planes per matrix).  base must be DDQD_BASE_FMA. */
 int qd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
             int64_t psa, const double* B, int64_t ldb, int64_t psb, int beta, double* C,

@@ -31,6 +31,8 @@ namespace ddqd {
 
 int launch_dd_block(const GemmBatch& g, hipStream_t stream);
 int launch_dd_simple(const GemmBatch& g, hipStream_t stream);
+int64_t dd_block_tiles(int64_t m, int64_t n);
+int launch_dd_grouped(const GroupArgs& ga, int grid, hipStream_t stream);
 int launch_qd_block(const GemmBatch& g, hipStream_t stream);
 int launch_qd_simple(const GemmBatch& g, hipStream_t stream);
 template <class N>
@@ -367,6 +369,63 @@ const char* ddqd_status_string(int status) {
 }
 
 const char* ddqd_last_error(void) { return g_msg; }
+
+int dd_gemm_grouped(int count, const ddqd_gemm_desc* d, void* stream) {
+  g_msg[0] = 0;
+  if (count < 0) return set_error(DDQD_E_ARG, "negative count");
+  if (count == 0) return DDQD_OK;
+  if (!d) return set_error(DDQD_E_ARG, "descriptor array is NULL");
+  int rc;
+  for (int i = 0; i < count; i++) {
+    const ddqd_gemm_desc& x = d[i];
+    if (x.m < 0 || x.n < 0 || x.l < 0)
+      return set_error(DDQD_E_ARG, "problem %d: negative dimension", i);
+    if ((x.alpha != 1 && x.alpha != -1) || (x.beta != 0 && x.beta != 1))
+      return set_error(DDQD_E_ARG, "problem %d: alpha must be +-1 and beta 0 or 1", i);
+    if ((rc = check_mat("C", 2, x.C, x.m, x.n, x.ldc, x.psc))) return rc;
+    if (x.l > 0 && x.m > 0 && x.n > 0) {
+      if ((rc = check_mat("A", 2, x.A, x.m, x.l, x.lda, x.psa))) return rc;
+      if ((rc = check_mat("B", 2, x.B, x.l, x.n, x.ldb, x.psb))) return rc;
+    }
+  }
+  // no output may overlap any input or any other output of the group
+  for (int i = 0; i < count; i++) {
+    const ddqd_gemm_desc& x = d[i];
+    const int64_t ec = extent(2, x.m, x.n, x.ldc, x.psc);
+    for (int j = 0; j < count; j++) {
+      const ddqd_gemm_desc& y = d[j];
+      if (y.l > 0 && (overlaps(x.C, ec, y.A, extent(2, y.m, y.l, y.lda, y.psa)) ||
+                      overlaps(x.C, ec, y.B, extent(2, y.l, y.n, y.ldb, y.psb))))
+        return set_error(DDQD_E_ALIAS, "output of problem %d overlaps an input of problem %d", i,
+                         j);
+      if (j != i && overlaps(x.C, ec, y.C, extent(2, y.m, y.n, y.ldc, y.psc)))
+        return set_error(DDQD_E_ALIAS, "outputs of problems %d and %d overlap", i, j);
+    }
+  }
+  if ((rc = device_ok())) return rc;
+  for (int c0 = 0; c0 < count; c0 += kMaxGroup) {
+    GroupArgs ga;
+    ga.count = 0;
+    ga.start[0] = 0;
+    for (int i = c0; i < count && i < c0 + kMaxGroup; i++) {
+      const ddqd_gemm_desc& x = d[i];
+      if (x.m == 0 || x.n == 0) continue;
+      GemmBatch g{x.m, x.n, x.l, x.alpha, x.beta, CMat{x.A, x.lda, x.psa, 0},
+                  CMat{x.B, x.ldb, x.psb, 0}, Mat{x.C, x.ldc, x.psc, 0}, 1};
+      if (x.l == 0) {  // C := beta C: the empty K loop reads nothing from A or B
+        g.A = CMat{x.C, x.ldc, x.psc, 0};
+        g.B = g.A;
+      }
+      ga.g[ga.count] = g;
+      ga.start[ga.count + 1] = ga.start[ga.count] + dd_block_tiles(x.m, x.n);
+      ga.count++;
+    }
+    const int64_t tiles = ga.start[ga.count];
+    const int grid = (int)(tiles < 512 ? tiles : 512);
+    if ((rc = launch_dd_grouped(ga, grid, (hipStream_t)stream))) return rc;
+  }
+  return DDQD_OK;
+}
 
 size_t dd_gemm_workspace(int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
                          int slices) {

@@ -28,6 +28,15 @@ struct GemmBatch {
 
 inline CMat cview(const Mat& M) { return CMat{M.p, M.ld, M.ps, M.bstride}; }
 
+// Unrelated products of one grouped launch (kernel argument, <= 4 KB):
+// problem p owns tiles [start[p], start[p+1]) of the concatenated list.
+constexpr int kMaxGroup = 24;
+struct GroupArgs {
+  int count;
+  GemmBatch g[kMaxGroup];
+  int64_t start[kMaxGroup + 1];
+};
+
 // Round-robin dispatch places workgroup b on XCD b % 8.  This permutation
 // gives each XCD one contiguous range of logical tiles, so tiles that share
 // operand panels share an L2.

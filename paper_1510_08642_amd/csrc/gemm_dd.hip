@@ -40,16 +40,13 @@ __device__ __forceinline__ void dd_mac(double& s, double& e, double ah, double a
   e = e + (err + q);
 }
 
-__global__ __launch_bounds__(kThreads) void dd_gemm_block_kernel(GemmBatch g, int64_t tiles_m,
-                                                                 int64_t tiles_n) {
-  __shared__ __attribute__((aligned(16))) double As[2][2][kBK][kBM + kPad];
-  __shared__ __attribute__((aligned(16))) double Bs[2][2][kBK][kBN + kPad];
+typedef double TileBuf[2][2][kBK][kBM + kPad];
 
-  const int64_t nblk = (int64_t)gridDim.x;
-  const int64_t t = xcd_remap((int64_t)blockIdx.x, nblk);
-  const int64_t per = tiles_m * tiles_n;
-  const int64_t b = t / per;
-  const int64_t tm = (t % per) / tiles_n, tn = (t % per) % tiles_n;
+// One 64x64 tile (tm, tn) of problem b of the batch g.  Shared by the
+// batched and the grouped kernels, so a product computed inside a group is
+// bit-identical to the same product launched on its own.
+__device__ __forceinline__ void dd_block_tile(const GemmBatch& g, int64_t b, int64_t tm,
+                                              int64_t tn, TileBuf& As, TileBuf& Bs) {
   const int64_t row0 = tm * kBM, col0 = tn * kBN;
 
   const double* Ab = g.A.p + b * g.A.bstride;
@@ -166,6 +163,30 @@ __global__ __launch_bounds__(kThreads) void dd_gemm_block_kernel(GemmBatch g, in
     }
 }
 
+__global__ __launch_bounds__(kThreads) void dd_gemm_block_kernel(GemmBatch g, int64_t tiles_m,
+                                                                 int64_t tiles_n) {
+  __shared__ __attribute__((aligned(16))) TileBuf As, Bs;
+  const int64_t t = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
+  const int64_t per = tiles_m * tiles_n;
+  dd_block_tile(g, t / per, (t % per) / tiles_n, (t % per) % tiles_n, As, Bs);
+}
+
+// Grouped: up to kMaxGroup unrelated problems of any shapes in one
+// persistent launch; workgroup w takes tiles w, w + grid, w + 2 grid, ... of
+// the concatenated tile list (a fixed order: results do not depend on the
+// grid size or on the other problems).
+__global__ __launch_bounds__(kThreads) void dd_gemm_grouped_kernel(GroupArgs ga) {
+  __shared__ __attribute__((aligned(16))) TileBuf As, Bs;
+  for (int64_t t = blockIdx.x; t < ga.start[ga.count]; t += gridDim.x) {
+    int p = 0;
+    while (t >= ga.start[p + 1]) p++;
+    const int64_t r = t - ga.start[p];
+    const int64_t tn_count = (ga.g[p].n + kBN - 1) / kBN;
+    dd_block_tile(ga.g[p], 0, r / tn_count, r % tn_count, As, Bs);
+    __syncthreads();
+  }
+}
+
 // Simple: one thread per c_ij, k ascending, each step a DD product and an
 // accurate DD sum (the paper's Eq. 1 with DD operators).
 __global__ __launch_bounds__(256) void dd_gemm_simple_kernel(GemmBatch g) {
@@ -198,6 +219,16 @@ int launch_dd_block(const GemmBatch& g, hipStream_t stream) {
   hipLaunchKernelGGL(dd_gemm_block_kernel, dim3((unsigned)nblk), dim3(kThreads), 0, stream, g,
                      tm, tn);
   return check_launch("dd_gemm_block_kernel");
+}
+
+int64_t dd_block_tiles(int64_t m, int64_t n) {
+  return ((m + kBM - 1) / kBM) * ((n + kBN - 1) / kBN);
+}
+
+int launch_dd_grouped(const GroupArgs& ga, int grid, hipStream_t stream) {
+  if (ga.count <= 0 || ga.start[ga.count] <= 0) return 0;
+  hipLaunchKernelGGL(dd_gemm_grouped_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream, ga);
+  return check_launch("dd_gemm_grouped_kernel");
 }
 
 int launch_dd_simple(const GemmBatch& g, hipStream_t stream) {

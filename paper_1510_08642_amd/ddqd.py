@@ -48,6 +48,17 @@ _lib.dd_getrs_workspace.argtypes = [_i64, _i64]
 _lib.dd_getrs_workspace.restype = _sz
 _lib.dd_getrs.argtypes = [_i64, _i64, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _vp, _sz, _vp]
 _lib.dd_getrs.restype = _int
+
+
+class GemmDesc(ctypes.Structure):
+    """ddqd_gemm_desc of include/ddqd.h."""
+    _fields_ = [("m", _i64), ("n", _i64), ("l", _i64), ("alpha", _int), ("beta", _int),
+                ("A", _vp), ("lda", _i64), ("psa", _i64), ("B", _vp), ("ldb", _i64),
+                ("psb", _i64), ("C", _vp), ("ldc", _i64), ("psc", _i64)]
+
+
+_lib.dd_gemm_grouped.argtypes = [_int, ctypes.POINTER(GemmDesc), _vp]
+_lib.dd_gemm_grouped.restype = _int
 _lib.ddqd_status_string.argtypes = [_int]
 _lib.ddqd_status_string.restype = ctypes.c_char_p
 _lib.ddqd_last_error.argtypes = []
@@ -180,3 +191,24 @@ def dd_getrs(LU, ipiv, B, *, perm=None, ws=None):
                        ws.data_ptr(), ws.numel(), _stream_of(B))
     _check(st, "dd_getrs")
     return B
+
+
+def dd_gemm_grouped(problems, stream_of=None):
+    """Several unrelated DD products in grouped launches.
+
+    problems: list of (A, B, C, alpha, beta) with C preallocated.  Results are
+    bit-identical to dd_gemm(A, B, C, algo="block", base="fma")."""
+    if not problems:
+        return
+    arr = (GemmDesc * len(problems))()
+    for i, (A, B, C, alpha, beta) in enumerate(problems):
+        pa, lda, psa = _mat(A, 2, "A")
+        pb, ldb, psb = _mat(B, 2, "B")
+        pc, ldc, psc = _mat(C, 2, "C")
+        if A.shape[2] != B.shape[1] or C.shape[1] != A.shape[1] or C.shape[2] != B.shape[2]:
+            raise ValueError(f"problem {i}: shapes do not match")
+        arr[i] = GemmDesc(A.shape[1], B.shape[2], A.shape[2], alpha, beta, pa, lda, psa, pb, ldb,
+                          psb, pc, ldc, psc)
+    st = _lib.dd_gemm_grouped(len(problems), arr,
+                              _stream_of(problems[0][2]) if stream_of is None else stream_of)
+    _check(st, "dd_gemm_grouped")

@@ -1,0 +1,86 @@
+"""Serving on the GPU: a mixed stream of DD products and LU solves with
+Poisson arrivals runs through the continuous-batching loop; every result is
+bit-identical to the same request run alone (no batching, one slot), and
+sampled results meet the DD tolerance against the exact answer."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1510_08642_amd import inputs
+from tests.helpers import sample_entries, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1510_08642_amd import serve
+    pools = serve.DevicePools(nmax_gemm=512, nmax_lu=512, nrhs_max=16, seed=0)
+    return serve, pools
+
+
+def build(serve, pools, seed, count=60, rate=3000.0):
+    trace = inputs.serving_trace(count, rate=rate, seed=seed, gemm_n=(32, 512), lu_n=(64, 512),
+                                 nrhs=(1, 16))
+    reqs = serve.make_requests(trace)
+    for r in reqs:
+        r.payload = pools.payload(r)
+    return reqs
+
+
+@pytest.mark.parametrize("base", ["fma", "ozaki"])
+def test_mixed_stream_equals_alone(env, base):
+    import torch
+    serve, pools = env
+    print(f"case serve base={base}", flush=True)
+    mix = build(serve, pools, seed=11)
+    ex = serve.GpuExecutor(slots=4, base=base, gemm_algo="winograd", gemm_levels=1)
+    st = serve.Server(ex, budget_bytes=1 << 30, slots=4, small_n=256).run(mix)
+    assert st.completed == len(mix) and st.failed == 0
+    if base == "fma":
+        assert st.batches < len(mix)          # some products were grouped
+    alone = build(serve, pools, seed=11)
+    for k, r in enumerate(alone):
+        r.t_arrive = 0.0
+    ex1 = serve.GpuExecutor(slots=1, base=base, gemm_algo="winograd", gemm_levels=1)
+    for r in alone:
+        serve.Server(ex1, budget_bytes=1 << 30, slots=1, small_n=0).run([r])
+    torch.cuda.synchronize()
+    for a, b in zip(mix, alone):
+        assert np.array_equal(to_host(a.result), to_host(b.result)), (a.rid, a.kind, a.n)
+
+
+def test_sampled_results_within_tolerance(env):
+    serve, pools = env
+    reqs = build(serve, pools, seed=12, count=30)
+    ex = serve.GpuExecutor(slots=3, base="fma")
+    serve.Server(ex, budget_bytes=1 << 30, slots=3).run(reqs)
+    checked = 0
+    for r in reqs:
+        A, B = (to_host(x.contiguous()) for x in r.payload)
+        R = to_host(r.result)
+        if r.kind == "gemm":
+            ii, jj = sample_entries(r.n, r.n, 20, seed=r.rid)
+            err = np.abs(oracle.exact_error(A, B, R, ii, jj))
+            den = (np.abs(A[0]) @ np.abs(B[0])).max(axis=1)[ii]
+            assert np.max(err / den) <= 2.0 ** -100 * r.n
+        else:
+            assert oracle.lu_residual(A, R, B) <= r.n * 2.0 ** -100
+        checked += 1
+    assert checked == 30
+
+
+def test_resident_factorization(env):
+    serve, pools = env
+    ex = serve.GpuExecutor(slots=1, base="fma")
+    A = pools.la[:, :300, :300]
+    key = ex.factorize(A, "k")
+    for seed in range(3):
+        B = pools.lb[:, :300, seed:seed + 2]
+        X = ex.solve(key, B)
+        assert oracle.lu_residual(to_host(A.contiguous()), to_host(X),
+                                  to_host(B.contiguous())) <= 300 * 2.0 ** -100
+    ex.release(key)
+    assert "k" not in ex.factors

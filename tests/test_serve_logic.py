@@ -1,0 +1,84 @@
+"""Serving loop logic on the CPU (fake executor, virtual clock): FIFO
+admission by memory footprint, back-pressure, slot limits, grouping of small
+products, rejection of oversize requests, and an injected executor failure
+that fails only its own batch."""
+import numpy as np
+
+from paper_1510_08642_amd import inputs
+from paper_1510_08642_amd.serve import Request, Server, make_requests
+from tests.fake_executor import FakeExecutor, VirtualClock
+
+
+def reqs_from(spec):
+    return [Request(rid=i, kind=k, n=n, nrhs=r, t_arrive=t) for i, (k, n, r, t) in enumerate(spec)]
+
+
+def test_all_complete_and_latency_order():
+    clock = VirtualClock()
+    ex = FakeExecutor(clock)
+    trace = inputs.serving_trace(200, rate=2000.0, seed=3, gemm_n=(8, 64), lu_n=(8, 64),
+                                 nrhs=(1, 4))
+    reqs = make_requests(trace)
+    st = Server(ex, budget_bytes=10 ** 9, slots=4, small_n=32).run(reqs, clock=clock)
+    assert st.completed == 200 and st.failed == 0
+    assert all(r.t_done >= r.t_admit >= r.t_arrive for r in reqs)
+    assert st.p99_ms >= st.p50_ms > 0
+    assert ex.max_concurrent <= 4
+
+
+def test_budget_is_never_exceeded_and_backpressure_waits():
+    clock = VirtualClock()
+    ex = FakeExecutor(clock)
+    # each n=100 product needs 16*100*100 + 16*100 bytes; the budget fits two
+    fp = 16 * 100 * 100 + 16 * 100
+    reqs = reqs_from([("gemm", 100, 0, 0.0)] * 6)
+    srv = Server(ex, budget_bytes=2 * fp + 10, slots=8, small_n=0)
+    st = srv.run(reqs, clock=clock)
+    assert st.completed == 6
+    assert st.max_inflight_bytes <= 2 * fp + 10
+    assert ex.max_concurrent == 2           # memory, not slots, limited concurrency
+    # FIFO: admission times are non-decreasing in request order
+    ta = [r.t_admit for r in reqs]
+    assert ta == sorted(ta)
+
+
+def test_small_products_are_grouped():
+    clock = VirtualClock()
+    ex = FakeExecutor(clock)
+    reqs = reqs_from([("gemm", 16, 0, 0.0)] * 10 + [("lu", 16, 2, 0.0)] + [("gemm", 16, 0, 0.0)] * 5)
+    st = Server(ex, budget_bytes=10 ** 9, slots=2, small_n=32, max_batch=8).run(reqs, clock=clock)
+    assert st.completed == 16
+    sizes = [len(b) for b, _, _ in ex.launched]
+    assert max(sizes) == 8
+    # the LU request is never merged with products
+    for b, _, _ in ex.launched:
+        kinds = {reqs[i].kind for i in b}
+        assert len(kinds) == 1
+        assert kinds == {"gemm"} or len(b) == 1
+
+
+def test_oversize_rejected_and_injected_failure_isolated():
+    clock = VirtualClock()
+    ex = FakeExecutor(clock, fail_rids={2})
+    reqs = reqs_from([("gemm", 20, 0, 0.0), ("gemm", 4000, 0, 0.0), ("lu", 20, 1, 0.0),
+                      ("gemm", 20, 0, 0.0)])
+    st = Server(ex, budget_bytes=10 ** 6, slots=1, small_n=0).run(reqs, clock=clock)
+    assert reqs[1].error and "budget" in reqs[1].error
+    assert reqs[2].error and "injected" in reqs[2].error
+    assert reqs[0].error is None and reqs[3].error is None
+    assert st.completed == 2 and st.failed == 2
+
+
+def test_results_flow_through_with_oracle_payloads():
+    clock = VirtualClock()
+    ex = FakeExecutor(clock)
+    g = inputs.rng(5)
+    reqs = reqs_from([("gemm", 12, 0, 0.0), ("lu", 10, 2, 0.0), ("gemm", 9, 0, 0.001)])
+    reqs[0].payload = (inputs.dd_uniform(12, 12, g), inputs.dd_uniform(12, 12, g))
+    reqs[1].payload = (inputs.dd_lu_matrix(10, g), inputs.dd_uniform(10, 2, g))
+    reqs[2].payload = (inputs.dd_uniform(9, 9, g), inputs.dd_uniform(9, 9, g))
+    Server(ex, budget_bytes=10 ** 7, slots=2, small_n=16).run(reqs, clock=clock)
+    A, B = reqs[0].payload
+    assert np.allclose(reqs[0].result[0], A[0] @ B[0])
+    A, B = reqs[1].payload
+    assert np.allclose(A[0] @ reqs[1].result[0], B[0])
