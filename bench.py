@@ -1,22 +1,30 @@
 #!/usr/bin/env python3
-"""Benchmark: DD GEMM effective GFLOPS (2mnl/t) at m = n = l = 1024 on one GPU.
+"""Benchmark: DD GEMM effective GFLOPS (2mnl/t) at m = n = l = 1024 on one GPU,
+with DD LU and the serving loop's p50/p99 latency beside it.
 
-One step is one double-double product C := A B at n = 1024 (inputs: DD
-uniform, seed 0, already resident in HBM) through the library's C ABI with
-the flagship configuration.  After W warm-up steps, K steps are timed with
-HIP events on the stream the kernels run on, bracketed by device
-synchronisation.  Rank 0 prints one JSON line.
+Step: one double-double product C := A B at n = 1024 (DD uniform inputs,
+seed 0, resident in HBM before timing) through the C ABI with the flagship
+configuration (Block algorithm on the Ozaki INT8-MFMA base, 16 slices, whose
+accuracy matches the FMA base).  W warm-up steps, then K steps timed with HIP
+events on the stream the library launches on, bracketed by device
+synchronisation; rank 0 prints one JSON line.
 
-Also reported in the same line:
-  * roofline: the dominant kernel's achieved FP64-operation (or INT8-MFMA)
-    rate against the chip's peak, from its own launch durations;
-  * variants: every algorithm / base at n = 1024 (and QD), effective GFLOPS;
-  * cpu_baseline: the CPU oracle (plain C, OpenMP) on a bounded sample of the
-    same workload, on this host's cores.
+Also in the line:
+  roofline      the dominant kernel's achieved rate against MI355X's peak,
+                from its own launch durations (library event hooks, a second
+                pass of the same K steps so the main timing carries no events)
+  variants      every algorithm / base for DD at n = 1024, and QD
+  lu            dd_getrf / dd_getrs at n = 2048 and 4096 (N(0,1) + n I)
+  serving       2000 Poisson requests (60 % DD products, n log-uniform in
+                [64, 1024]; 40 % LU factor + solve, n in [128, 2048], 1-16
+                right-hand sides) at 50 % and 90 % of the measured capacity,
+                FMA vs Ozaki base: p50 / p99 latency and throughput
+  cpu_baseline  the CPU oracle on a bounded sample of the step's workload
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,32 +32,31 @@ import time
 
 import numpy as np
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# MI355X: 256 CUs x 2.4 GHz x 64 FP64 lanes = 39.3e12 FP64 VALU operations/s
-# (the 78.6 TFLOP/s datasheet figure counts an FMA as two).
+# MI355X peaks.  FP64 VALU: 256 CUs x 2.4 GHz x 64 lanes = 39.3e12 operations/s
+# (add, mul or fma counting one; the 78.6 TFLOP/s datasheet figure counts an
+# FMA as two).  INT8 matrix cores: 5.0 POP/s dense (datasheet).
 FP64_OPS_PEAK_T = 256 * 2.4e9 * 64 / 1e12
-INT8_PEAK_T = 5000.0        # dense INT8 MFMA, TOP/s
-# FP64 VALU operations per DD multiply-add in the Block FMA kernel
-# (1 mul + 3 fma + 8 add), plus one TwoSum (6 ops) per 16 multiply-adds.
+INT8_PEAK_T = 5000.0
+# FP64 operations per DD multiply-add of the Block FMA kernel (1 mul + 3 fma +
+# 8 add, and a 6-operation TwoSum every 16) -- confirmed by SQ_INSTS_VALU_*_F64
 DD_OPS_PER_MAC = 12 + 6 / 16
-# per QD multiply-add in the QD Block kernel (see qd_mac), plus renormalise
-QD_OPS_PER_MAC = 113 + 30 / 16
 
 
 def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE, WRITE_SIZE scaled by a plain copy's readings), or
-    None when the kernel's source has changed since they were taken."""
-    import hashlib
-    root = os.path.dirname(os.path.abspath(__file__))
+    """HBM bytes per launch from the committed counter summary, or None if the
+    kernel's source changed since (FETCH_SIZE and WRITE_SIZE, scaled by what
+    the same counters read for a plain copy of known size)."""
     try:
-        with open(os.path.join(root, "profiles", "traffic.json")) as f:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
             rec = json.load(f)[kernel]
-        with open(os.path.join(root, rec["source"]), "rb") as f:
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
                 return None
         return int(1024 * (rec["fetch_kib"] * rec["fetch_scale"] +
@@ -70,7 +77,52 @@ def time_steps(fn, steps, warmup, stream):
         fn()
     ev1.record(stream)
     torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / steps          # ms per step
+    return ev0.elapsed_time(ev1) / steps
+
+
+def kernel_avg_ms(dd, fn, steps, name):
+    """Average duration of the library's kernels named `name` over `steps`
+    calls of fn, from the library's own event hooks (recorded on the stream
+    each kernel is launched on)."""
+    import torch
+    torch.cuda.synchronize()
+    dd.profile_reset()
+    dd.profile_enable(True)
+    for _ in range(steps):
+        fn()
+    dd.profile_enable(False)
+    ms, cnt = dd.profile_query(name)
+    dd.profile_reset()
+    return ms / max(cnt, 1), cnt
+
+
+def roofline(dd, args, n, step, steps):
+    leaves = 7 ** args.levels if args.algo in ("strassen", "winograd") else 1
+    lf = n // (2 ** args.levels) if leaves > 1 else n
+    if args.base == "ozaki":
+        name, S = "oz_gemm_kernel", 16
+        avg, cnt = kernel_avg_ms(dd, step, steps, name)
+        per = max(1, cnt // steps)
+        ops = 2.0 * lf ** 3 * S * (S + 1) / 2 * leaves / per
+        ach = ops / (avg * 1e-3) / 1e12
+        return {"bound": "mfma", "kernel": name, "achieved": round(ach, 1), "peak": INT8_PEAK_T,
+                "unit": "TFLOP/s", "frac": round(ach / INT8_PEAK_T, 4),
+                "traffic": measured_traffic(name), "avg_launch_ms": round(avg, 5),
+                "launches_per_step": per,
+                "note": "INT8 MFMA operations (2 per multiply-add) of the S(S+1)/2 = 136 slice "
+                        "products per launch; peak = MI355X dense INT8 5.0 POP/s (a register-only "
+                        "microbenchmark of the same MFMA pattern on random data reaches 3.58)"}
+    name = "dd_gemm_block_kernel" if args.algo != "simple" else "dd_gemm_simple_kernel"
+    avg, cnt = kernel_avg_ms(dd, step, steps, name)
+    per = max(1, cnt // steps)
+    macs = float(lf) ** 3 * leaves / per
+    ach = macs * DD_OPS_PER_MAC / (avg * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": name, "achieved": round(ach, 3),
+            "peak": round(FP64_OPS_PEAK_T, 2), "unit": "TFLOP/s",
+            "frac": round(ach / FP64_OPS_PEAK_T, 4), "traffic": measured_traffic(name),
+            "avg_launch_ms": round(avg, 5), "launches_per_step": per,
+            "note": f"FP64 VALU operations ({DD_OPS_PER_MAC} per DD multiply-add, each add/mul/"
+                    "fma counting one); peak = 256 CU x 2.4 GHz x 64 lanes"}
 
 
 def cpu_baseline(n: int, budget_s: float = 20.0):
@@ -85,7 +137,6 @@ def cpu_baseline(n: int, budget_s: float = 20.0):
     t0 = time.perf_counter()
     oracle.gemm(A[:, :rows], B, "block")
     t = time.perf_counter() - t0
-    # grow the sample towards the budget (bounded by the full matrix)
     rows2 = int(min(n, max(rows, rows * budget_s / max(t, 1e-3) / 2)))
     rows2 = max(64, rows2 // 64 * 64)
     t0 = time.perf_counter()
@@ -99,7 +150,7 @@ def cpu_baseline(n: int, budget_s: float = 20.0):
 
 def sampled_error(A, B, C, n, count=64):
     """Row-normwise error of C on sampled entries against the oracle's exact
-    product."""
+    product (part of the CPU-baseline leg)."""
     import oracle
     g = np.random.default_rng(0)
     ii = g.integers(0, n, count)
@@ -107,6 +158,74 @@ def sampled_error(A, B, C, n, count=64):
     e = np.abs(oracle.exact_error(A, B, C, ii, jj))
     den = (np.abs(A[0]) @ np.abs(B[0])).max(axis=1)[ii]
     return float(np.max(e / den))
+
+
+def bench_lu(dd, inputs, torch, dev, sizes, configs, stream):
+    out = {}
+    for n in sizes:
+        g = inputs.rng(0)
+        A0 = torch.from_numpy(inputs.dd_lu_matrix(n, g)).to(dev)
+        b0 = torch.from_numpy(inputs.dd_uniform(n, 16, g)).to(dev)
+        for (panel, algo, lv, base) in configs:
+            key = f"n{n}_p{panel}_{algo}{lv}_{base}"
+            ws = torch.empty(max(1, dd.getrf_workspace(n, panel, algo, lv, base)),
+                             dtype=torch.uint8, device=dev)
+            A = A0.clone()
+            holder = {}
+
+            def f():
+                A.copy_(A0)
+                holder["f"] = dd.dd_getrf(A, panel=panel, algo=algo, levels=lv, base=base, ws=ws)
+            t_f = time_steps(f, 2, 1, stream)
+            t_copy = time_steps(lambda: A.copy_(A0), 3, 1, stream)
+            ipiv, perm, _ = holder["f"]
+            res = {}
+            for nrhs in (1, 16):
+                Xs = b0[:, :, :nrhs].contiguous()
+
+                def s():
+                    Xs.copy_(b0[:, :, :nrhs])
+                    dd.dd_getrs(A, ipiv, Xs, perm=perm)
+                res[nrhs] = time_steps(s, 3, 1, stream)
+            t_getrf = t_f - t_copy
+            out[key] = {"getrf_ms": round(t_getrf, 3),
+                        "getrf_gflops": round(2.0 / 3.0 * n ** 3 / (t_getrf * 1e-3) / 1e9, 1),
+                        "getrs_ms_nrhs1": round(res[1], 3), "getrs_ms_nrhs16": round(res[16], 3)}
+            log(f"lu {key}: {out[key]}")
+    return out
+
+
+def bench_serving(nreq, seed=0):
+    from paper_1510_08642_amd import inputs, serve
+    pools = serve.DevicePools(nmax_gemm=1024, nmax_lu=2048, nrhs_max=16, seed=seed)
+    out = {}
+    for base in ("fma", "ozaki"):
+        ex = serve.GpuExecutor(slots=4, base=base, gemm_algo="block", gemm_levels=0,
+                               lu_panel=128, lu_algo="winograd", lu_levels=1)
+        # capacity: every request arrives at t = 0
+        trace = inputs.serving_trace(nreq, rate=1e9, seed=seed)
+        reqs = serve.make_requests(trace)
+        for r in reqs:
+            r.payload = pools.payload(r)
+        st = serve.Server(ex, budget_bytes=8 << 30, slots=4).run(reqs)
+        cap = st.throughput_rps
+        res = {"capacity_rps": round(cap, 1), "capacity_gflops": round(st.gflops, 1)}
+        del reqs
+        for frac in (0.5, 0.9):
+            trace = inputs.serving_trace(nreq, rate=frac * cap, seed=seed + 1)
+            reqs = serve.make_requests(trace)
+            for r in reqs:
+                r.payload = pools.payload(r)
+            st = serve.Server(ex, budget_bytes=8 << 30, slots=4).run(reqs)
+            res[f"load{int(frac * 100)}"] = {
+                "rate_rps": round(frac * cap, 1), "p50_ms": round(st.p50_ms, 3),
+                "p99_ms": round(st.p99_ms, 3), "throughput_rps": round(st.throughput_rps, 1),
+                "gflops": round(st.gflops, 1), "completed": st.completed, "failed": st.failed,
+                "batches": st.batches}
+            del reqs
+        out[base] = res
+        log(f"serving {base}: {res}")
+    return out
 
 
 def main():
@@ -117,9 +236,12 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--algo", default="block")
     ap.add_argument("--levels", type=int, default=0)
-    ap.add_argument("--base", default="fma")
+    ap.add_argument("--base", default="ozaki")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-lu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB, 5 times "
                          "(reference kernel for scaling HBM byte counters)")
@@ -139,8 +261,9 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 5 copies of {nbytes} bytes")
         return
-    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-    from paper_1510_08642_amd import ddqd, inputs
+    sys.path.insert(0, ROOT)
+    from paper_1510_08642_amd import ddqd as dd
+    from paper_1510_08642_amd import inputs
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -151,60 +274,55 @@ def main():
     C = torch.empty((2, n, n), dtype=torch.float64, device=dev)
 
     def make(algo, levels, base, P=2, X=A, Y=B, Z=C):
-        ws = torch.empty(max(1, ddqd.gemm_workspace(P, n, n, n, algo, levels, base)),
+        ws = torch.empty(max(1, dd.gemm_workspace(P, n, n, n, algo, levels, base)),
                          dtype=torch.uint8, device=dev)
-        f = ddqd.dd_gemm if P == 2 else ddqd.qd_gemm
         if P == 2:
-            return lambda: f(X, Y, Z, algo=algo, levels=levels, base=base, ws=ws)
-        return lambda: f(X, Y, Z, algo=algo, levels=levels, ws=ws)
+            return lambda: dd.dd_gemm(X, Y, Z, algo=algo, levels=levels, base=base, ws=ws)
+        return lambda: dd.qd_gemm(X, Y, Z, algo=algo, levels=levels, ws=ws)
 
     log(f"bench: n={n} algo={args.algo} levels={args.levels} base={args.base}")
     step = make(args.algo, args.levels, args.base)
     ms = time_steps(step, args.steps, args.warmup, stream)
     flops = 2.0 * n * n * n
     value = flops / (ms * 1e-3) / 1e9
-    log(f"bench: {ms:.3f} ms/step, {value:.1f} GFLOPS effective")
-
-    # roofline of the dominant kernel (the leaf product)
-    if args.base == "fma" and (args.algo == "block" or
-                               (args.algo in ("strassen", "winograd") and args.levels == 0)):
-        macs = float(n) ** 3
-        achieved = macs * DD_OPS_PER_MAC / (ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": "dd_gemm_block_kernel", "achieved": round(achieved, 3),
-                "peak": round(FP64_OPS_PEAK_T, 2), "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_OPS_PEAK_T, 4),
-                "traffic": measured_traffic("dd_gemm_block_kernel"),
-                "note": "FP64 VALU operations (add, mul or fma count 1 each; "
-                        f"{DD_OPS_PER_MAC} per DD multiply-add) over the kernel's "
-                        "average launch time; peak = 256 CU x 2.4 GHz x 64 lanes"}
-    else:
-        roof = None
+    log(f"bench: {ms:.4f} ms/step, {value:.1f} GFLOPS effective")
+    roof = roofline(dd, args, n, step, args.steps)
+    log(f"bench: roofline {roof}")
 
     variants = {}
     if not args.no_variants:
-        for (algo, lv, base) in [("block", 0, "fma"), ("strassen", 1, "fma"),
-                                 ("strassen", 2, "fma"), ("strassen", 3, "fma"),
-                                 ("winograd", 1, "fma"), ("winograd", 2, "fma"),
-                                 ("winograd", 3, "fma"), ("block", 0, "ozaki"),
-                                 ("winograd", 1, "ozaki"), ("winograd", 2, "ozaki"),
-                                 ("strassen", 1, "ozaki")]:
-            try:
-                t = time_steps(make(algo, lv, base), max(3, args.steps // 4), 1, stream)
-                variants[f"dd_{algo}{lv}_{base}"] = round(flops / (t * 1e-3) / 1e9, 1)
-                log(f"variant dd {algo} L{lv} {base}: {t:.3f} ms")
-            except Exception as ex:
-                variants[f"dd_{algo}{lv}_{base}"] = f"error: {ex}"
+        for (algo, lv, base) in [("simple", 0, "fma"), ("block", 0, "fma"),
+                                 ("strassen", 1, "fma"), ("strassen", 2, "fma"),
+                                 ("strassen", 3, "fma"), ("winograd", 1, "fma"),
+                                 ("winograd", 2, "fma"), ("winograd", 3, "fma"),
+                                 ("block", 0, "ozaki"), ("strassen", 1, "ozaki"),
+                                 ("winograd", 1, "ozaki"), ("winograd", 2, "ozaki")]:
+            t = time_steps(make(algo, lv, base), 5 if algo != "simple" else 2, 1, stream)
+            variants[f"dd_{algo}{lv}_{base}"] = round(flops / (t * 1e-3) / 1e9, 1)
+            log(f"variant dd {algo} L{lv} {base}: {t:.3f} ms")
         gq = inputs.rng(0)
         Aq = torch.from_numpy(inputs.qd_uniform(n, n, gq)).to(dev)
         Bq = torch.from_numpy(inputs.qd_uniform(n, n, gq)).to(dev)
         Cq = torch.empty((4, n, n), dtype=torch.float64, device=dev)
-        for (algo, lv) in [("block", 0), ("winograd", 1), ("winograd", 3)]:
+        for (algo, lv) in [("block", 0), ("strassen", 1), ("winograd", 1), ("winograd", 2),
+                           ("winograd", 3)]:
             t = time_steps(make(algo, lv, "fma", 4, Aq, Bq, Cq), 2, 1, stream)
             variants[f"qd_{algo}{lv}_fma"] = round(flops / (t * 1e-3) / 1e9, 1)
             log(f"variant qd {algo} L{lv}: {t:.3f} ms")
+        del Aq, Bq, Cq
+
+    lu = None
+    if not args.no_lu:
+        lu = bench_lu(dd, inputs, torch, dev, [2048, 4096],
+                      [(128, "winograd", 1, "fma"), (128, "winograd", 1, "ozaki"),
+                       (256, "block", 0, "ozaki")], stream)
+
+    serving = None
+    if not args.no_serving and args.serving_requests > 0:
+        serving = bench_serving(args.serving_requests)
 
     # CPU-baseline leg: the oracle timed on this host, and the oracle's exact
-    # product used to state the timed result's error on sampled entries
+    # product stating the timed result's error on sampled entries
     cpu, err = None, None
     if not args.no_cpu:
         log("bench: timing the CPU oracle baseline")
@@ -216,16 +334,18 @@ def main():
         log(f"bench: sampled row-normwise error {err:.3e} (tolerance {2.0**-100*n:.3e})")
 
     out = {
-        "metric": "DD GEMM effective GFLOPS (2mnl/t) at n=1024",
+        "metric": "DD/QD GEMM effective GFLOPS (2mnl/t) at n=1024; DD LU-solve p50/p99 latency",
         "value": round(value, 2), "unit": "GFLOPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"dd_gemm m=n=l={n}, DD uniform seed 0",
+        "config": {"workload": f"dd_gemm m=n=l={n}, DD uniform inputs seed 0",
                    "algo": args.algo, "levels": args.levels, "base": args.base,
-                   "parallelism": "single GPU"},
+                   "slices": 16 if args.base == "ozaki" else None},
         "error_rownorm": err,
         "roofline": roof,
         "variants_gflops": variants,
+        "lu": lu,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

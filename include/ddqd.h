@@ -72,6 +72,15 @@ const char* ddqd_status_string(int status);
 /* Message describing the last failed call on this thread ("" if none). */
 const char* ddqd_last_error(void);
 
+/* Diagnostics: per-kernel timing.  While enabled (on != 0), every kernel the
+ * library launches is bracketed by HIP events on its stream (creating two
+ * events per launch).  ddqd_profile_query sums the elapsed milliseconds and
+ * counts the launches whose kernel name contains `substr` (all if NULL),
+ * waiting for the recorded events; ddqd_profile_reset forgets them. */
+void ddqd_profile_enable(int on);
+void ddqd_profile_reset(void);
+int ddqd_profile_query(const char* substr, double* ms, int64_t* count);
+
 /*
  * C := beta*C + alpha*(A B) in DD (Sec. 2, Eq. 1).
  *   m, n, l   A is m x l, B is l x n, C is m x n; each >= 0.  m == 0 or

@@ -167,8 +167,10 @@ int launch_preadd(CMat src, Mat dst, int64_t rows, int64_t cols, int64_t parents
   if (rows <= 0 || cols <= 0 || parents <= 0) return 0;
   if (parents > 65535) return set_error(4, "too many recursion parents");
   dim3 grid((unsigned)((rows * cols + 255) / 256), (unsigned)parents);
+  prof_begin(stream);
   hipLaunchKernelGGL(preadd_kernel<N>, grid, dim3(256), 0, stream, src, dst, rows, cols, algo,
                      side, expo);
+  prof_record("preadd_kernel", stream);
   return check_launch("preadd_kernel");
 }
 
@@ -178,8 +180,10 @@ int launch_postadd(CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t paren
   if (rows <= 0 || cols <= 0 || parents <= 0) return 0;
   if (parents > 65535) return set_error(4, "too many recursion parents");
   dim3 grid((unsigned)((rows * cols + 255) / 256), (unsigned)parents);
+  prof_begin(stream);
   hipLaunchKernelGGL(postadd_kernel<N>, grid, dim3(256), 0, stream, prod, dst, rows, cols, algo,
                      alpha, beta, ea, fb);
+  prof_record("postadd_kernel", stream);
   return check_launch("postadd_kernel");
 }
 
@@ -215,12 +219,16 @@ __global__ __launch_bounds__(256) void col_exponent_kernel(CMat B, int64_t l, in
 
 int launch_exponents(CMat A, CMat B, int64_t m, int64_t n, int64_t l, int* ea, int* fb,
                      hipStream_t stream) {
+  prof_begin(stream);
   hipLaunchKernelGGL(row_exponent_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, stream,
                      A, m, l, ea);
+  prof_record("row_exponent_kernel", stream);
   int rc = check_launch("row_exponent_kernel");
   if (rc) return rc;
+  prof_begin(stream);
   hipLaunchKernelGGL(col_exponent_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
                      B, l, n, fb);
+  prof_record("col_exponent_kernel", stream);
   return check_launch("col_exponent_kernel");
 }
 

@@ -22,6 +22,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "ddqd.h"
 #include "common.hpp"
@@ -61,6 +65,41 @@ int check_launch(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(DDQD_E_HIP, "%s: %s", what, hipGetErrorString(e));
   return DDQD_OK;
+}
+
+// ---- per-kernel timing ----------------------------------------------------
+namespace {
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+std::atomic<int> g_prof{0};
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof_recs;
+thread_local hipEvent_t g_prof_pending = nullptr;
+}  // namespace
+
+void prof_begin(hipStream_t s) {
+  if (!g_prof.load(std::memory_order_relaxed)) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  if (hipEventRecord(e, s) != hipSuccess) {
+    (void)hipEventDestroy(e);
+    return;
+  }
+  g_prof_pending = e;
+}
+
+void prof_record(const char* kernel, hipStream_t s) {
+  if (!g_prof_pending) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) == hipSuccess && hipEventRecord(e, s) == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_recs.push_back(ProfRec{kernel, g_prof_pending, e});
+  } else {
+    (void)hipEventDestroy(g_prof_pending);
+  }
+  g_prof_pending = nullptr;
 }
 
 namespace {
@@ -369,6 +408,34 @@ const char* ddqd_status_string(int status) {
 }
 
 const char* ddqd_last_error(void) { return g_msg; }
+
+void ddqd_profile_enable(int on) { g_prof.store(on ? 1 : 0); }
+
+void ddqd_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& r : g_prof_recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof_recs.clear();
+}
+
+int ddqd_profile_query(const char* substr, double* ms, int64_t* count) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (auto& r : g_prof_recs) {
+    if (substr && r.name.find(substr) == std::string::npos) continue;
+    float t = 0.0f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+      return set_error(DDQD_E_HIP, "profile event query failed");
+    tot += t;
+    cnt++;
+  }
+  if (ms) *ms = tot;
+  if (count) *count = cnt;
+  return DDQD_OK;
+}
 
 int dd_gemm_grouped(int count, const ddqd_gemm_desc* d, void* stream) {
   g_msg[0] = 0;

@@ -51,4 +51,9 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblk) {
 int set_error(int status, const char* fmt, ...);
 int check_launch(const char* what);
 
+// Optional per-kernel timing (ddqd_profile_enable): when on, every launch is
+// bracketed by HIP events recorded on its stream; no effect when off.
+void prof_begin(hipStream_t s);
+void prof_record(const char* kernel, hipStream_t s);
+
 }  // namespace ddqd

@@ -165,8 +165,10 @@ int launch_qd_block(const GemmBatch& g, hipStream_t stream) {
   int64_t tm = (g.m + kBM - 1) / kBM, tn = (g.n + kBN - 1) / kBN;
   int64_t nblk = tm * tn * g.batch;
   if (nblk > INT32_MAX) return set_error(4, "grid too large");
+  prof_begin(stream);
   hipLaunchKernelGGL(qd_gemm_block_kernel, dim3((unsigned)nblk), dim3(kThreads), 0, stream, g,
                      tm, tn);
+  prof_record("qd_gemm_block_kernel", stream);
   return check_launch("qd_gemm_block_kernel");
 }
 
@@ -174,7 +176,9 @@ int launch_qd_simple(const GemmBatch& g, hipStream_t stream) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return 0;
   dim3 grid((unsigned)((g.n + 15) / 16), (unsigned)((g.m + 15) / 16), (unsigned)g.batch);
   if (grid.y > 65535 || grid.z > 65535) return set_error(4, "grid too large");
+  prof_begin(stream);
   hipLaunchKernelGGL(qd_gemm_simple_kernel, grid, dim3(256), 0, stream, g);
+  prof_record("qd_gemm_simple_kernel", stream);
   return check_launch("qd_gemm_simple_kernel");
 }
 

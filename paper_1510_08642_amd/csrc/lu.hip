@@ -365,8 +365,10 @@ __global__ __launch_bounds__(1024) void trsv_block_kernel(const double* T, int64
 // ---- launchers ---------------------------------------------------------------
 
 int launch_lu_init(int32_t* info, int32_t* perm, int64_t n, hipStream_t s) {
+  prof_begin(s);
   hipLaunchKernelGGL(lu_init_kernel, dim3((unsigned)((n + 256) / 256)), dim3(256), 0, s, info,
                      perm, n);
+  prof_record("lu_init_kernel", s);
   return check_launch("lu_init_kernel");
 }
 
@@ -379,9 +381,13 @@ int launch_getf2(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t m, int6
   if (m <= 0 || w <= 0) return 0;
   const int rpt = (int)((m + 1023) / 1024);
   if (w > getf2_width(m)) return set_error(4, "getf2 strip too wide");
-#define GETF2(R, W)                                                                          \
-  hipLaunchKernelGGL((getf2_kernel<R, W>), dim3(1), dim3(1024), 0, s, A, lda, ps, r0, m, c0, w, \
-                     ipiv, info, pivot)
+#define GETF2(R, W)                                                                        \
+  do {                                                                                     \
+    prof_begin(s);                                                                         \
+    hipLaunchKernelGGL((getf2_kernel<R, W>), dim3(1), dim3(1024), 0, s, A, lda, ps, r0, m, c0, \
+                       w, ipiv, info, pivot);                                              \
+    prof_record("getf2_kernel", s);                                                        \
+  } while (0)
   if (rpt <= 1) GETF2(1, 8);
   else if (rpt <= 2) GETF2(2, 8);
   else if (rpt <= 4) GETF2(4, 4);
@@ -395,8 +401,10 @@ int launch_laswp(double* A, int64_t lda, int64_t ps, int64_t n_cols, int64_t ski
                  int64_t skip1, int64_t k0, int64_t k1, const int32_t* ipiv, int32_t* perm,
                  hipStream_t s) {
   if (k1 <= k0) return 0;
+  prof_begin(s);
   hipLaunchKernelGGL(laswp_kernel, dim3((unsigned)((n_cols + 1 + 255) / 256)), dim3(256), 0, s,
                      A, lda, ps, n_cols, skip0, skip1, k0, k1, ipiv, perm);
+  prof_record("laswp_kernel", s);
   return check_launch("laswp_kernel");
 }
 
@@ -404,27 +412,35 @@ int launch_trsm_small(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t c0
                       int64_t x0, int64_t ncols, hipStream_t s) {
   if (nb <= 0 || ncols <= 0) return 0;
   if (nb > 16) return set_error(4, "trsm_small: block too large");
+  prof_begin(s);
   hipLaunchKernelGGL(trsm_small_kernel, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s, A,
                      lda, ps, r0, c0, nb, x0, ncols);
+  prof_record("trsm_small_kernel", s);
   return check_launch("trsm_small_kernel");
 }
 
 int launch_perm_from_ipiv(const int32_t* ipiv, int64_t n, int32_t* perm, hipStream_t s) {
+  prof_begin(s);
   hipLaunchKernelGGL(perm_from_ipiv_kernel, dim3(1), dim3(64), 0, s, ipiv, n, perm);
+  prof_record("perm_from_ipiv_kernel", s);
   return check_launch("perm_from_ipiv_kernel");
 }
 
 int launch_gather_rows(const double* B, int64_t ldb, int64_t psb, const int32_t* perm, int64_t n,
                        int64_t nrhs, double* X, hipStream_t s) {
+  prof_begin(s);
   hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0,
                      s, B, ldb, psb, perm, n, nrhs, X);
+  prof_record("gather_rows_kernel", s);
   return check_launch("gather_rows_kernel");
 }
 
 int launch_scatter_rows(const double* X, int64_t n, int64_t nrhs, double* B, int64_t ldb,
                         int64_t psb, hipStream_t s) {
+  prof_begin(s);
   hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0,
                      s, X, n, nrhs, B, ldb, psb);
+  prof_record("scatter_rows_kernel", s);
   return check_launch("scatter_rows_kernel");
 }
 
@@ -435,8 +451,10 @@ int launch_trsv_blocks(const double* T, int64_t ldt, int64_t pst, double* X, int
   for (int64_t step = 0; step < nb; step++) {
     const int64_t I = upper ? nb - 1 - step : step;
     const int64_t blocks = upper ? I + 1 : nb - I;
+    prof_begin(s);
     hipLaunchKernelGGL(trsv_block_kernel, dim3((unsigned)blocks), dim3(1024), 0, s, T, ldt, pst,
                        X, n, nrhs, I, upper);
+    prof_record("trsv_block_kernel", s);
     int rc = check_launch("trsv_block_kernel");
     if (rc) return rc;
   }

@@ -353,27 +353,35 @@ int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
       (g.l + 31) / 32 > 65535)
     return set_error(DDQD_E_UNSUPPORTED, "matrix too large for one Ozaki launch");
   const int64_t nfb = cols_pad * g.batch;
+  prof_begin(s);
   hipLaunchKernelGGL(oz_row_exp_kernel, dim3((unsigned)((rows_pad + 3) / 4), (unsigned)g.batch),
                      dim3(256), 0, s, g.A, g.m, g.l, rows_pad, ea, fb, nfb);
+  prof_record("oz_row_exp_kernel", s);
+  prof_begin(s);
   hipLaunchKernelGGL(oz_col_exp_kernel,
                      dim3((unsigned)((cols_pad + 63) / 64), (unsigned)((g.l + 31) / 32),
                           (unsigned)g.batch),
                      dim3(256), 0, s, g.B, g.l, g.n, cols_pad, fb);
+  prof_record("oz_col_exp_kernel", s);
   int rc = check_launch("oz_exp");
   if (rc) return rc;
   const int64_t items = (o.rb > o.cb ? o.rb : o.cb) * 32 * o.kb * 8;
+  prof_begin(s);
   hipLaunchKernelGGL(oz_slice_kernel<S>, dim3((unsigned)((items + 255) / 256), 2, (unsigned)g.batch),
                      dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)ea, (const int*)fb,
                      Asl, Bsl);
+  prof_record("oz_slice_kernel", s);
   if ((rc = check_launch("oz_slice_kernel"))) return rc;
   const int64_t tm = o.rb / 2, tn = o.cb / 2;
   const int64_t nblk = tm * tn * g.batch;
   if (nblk > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "grid too large");
   for (int64_t kc0 = 0; kc0 < o.kb; kc0 += kKChunk / 32) {
     const int64_t kc1 = kc0 + kKChunk / 32 < o.kb ? kc0 + kKChunk / 32 : o.kb;
+    prof_begin(s);
     hipLaunchKernelGGL(oz_gemm_kernel<S>, dim3((unsigned)nblk), dim3(256), 0, s, g, o,
                        (const signed char*)Asl, (const signed char*)Bsl, (const int*)ea,
                        (const int*)fb, tm, tn, kc0, kc1, kc0 == 0 ? g.beta : 1);
+    prof_record("oz_gemm_kernel", s);
     if ((rc = check_launch("oz_gemm_kernel"))) return rc;
   }
   return DDQD_OK;

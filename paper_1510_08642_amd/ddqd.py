@@ -59,6 +59,13 @@ class GemmDesc(ctypes.Structure):
 
 _lib.dd_gemm_grouped.argtypes = [_int, ctypes.POINTER(GemmDesc), _vp]
 _lib.dd_gemm_grouped.restype = _int
+_lib.ddqd_profile_enable.argtypes = [_int]
+_lib.ddqd_profile_enable.restype = None
+_lib.ddqd_profile_reset.argtypes = []
+_lib.ddqd_profile_reset.restype = None
+_lib.ddqd_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(_i64)]
+_lib.ddqd_profile_query.restype = _int
 _lib.ddqd_status_string.argtypes = [_int]
 _lib.ddqd_status_string.restype = ctypes.c_char_p
 _lib.ddqd_last_error.argtypes = []
@@ -212,3 +219,20 @@ def dd_gemm_grouped(problems, stream_of=None):
     st = _lib.dd_gemm_grouped(len(problems), arr,
                               _stream_of(problems[0][2]) if stream_of is None else stream_of)
     _check(st, "dd_gemm_grouped")
+
+
+def profile_enable(on: bool = True) -> None:
+    """Per-kernel event timing inside the library (diagnostics)."""
+    _lib.ddqd_profile_enable(1 if on else 0)
+
+
+def profile_reset() -> None:
+    _lib.ddqd_profile_reset()
+
+
+def profile_query(substr: str | None = None):
+    """(total milliseconds, launches) of kernels whose name contains substr."""
+    ms, cnt = ctypes.c_double(0.0), _i64(0)
+    _check(_lib.ddqd_profile_query(substr.encode() if substr else None, ctypes.byref(ms),
+                                   ctypes.byref(cnt)), "ddqd_profile_query")
+    return ms.value, cnt.value
