@@ -26,146 +26,306 @@ __device__ __forceinline__ void st_dd(double* A, int64_t ps, int64_t idx, dd_t v
 __device__ __forceinline__ dd_t dd_abs(dd_t x) { return x.hi < 0.0 ? dd_neg(x) : x; }
 
 // (x, i) beats (y, j): larger |value|; on equal values the smaller row index.
-// i < 0 marks "no candidate".
+// i < 0 marks "no candidate".  The high words decide when they differ by more
+// than the low words can make up (their difference is exact when they are
+// within a factor 2, and far larger than the low words otherwise); only
+// near-ties take the full DD comparison.
 __device__ __forceinline__ bool better(dd_t x, int i, dd_t y, int j) {
   if (i < 0) return false;
   if (j < 0) return true;
+  const double dh = fabs(x.hi) - fabs(y.hi);
+  const double lim = 2.0 * (fabs(x.lo) + fabs(y.lo));
+  if (dh > lim) return true;
+  if (-dh > lim) return false;
   const int c = dd_abs_cmp(x, y);
   return c > 0 || (c == 0 && i < j);
 }
 
+// x / y by three long-division digits, each the leading remainder times an
+// FP64 reciprocal of y.hi shared by the whole column (a digit may be off by
+// an ulp; the next remainder, formed in DD, absorbs it).
+__device__ __forceinline__ dd_t dd_div_digits(dd_t x, dd_t y, double yinv) {
+  const double q1 = x.hi * yinv;
+  dd_t r = dd_sub(x, dd_mul_d(y, q1));
+  const double q2 = r.hi * yinv;
+  r = dd_sub(r, dd_mul_d(y, q2));
+  const double q3 = r.hi * yinv;
+  dd_t q;
+  fast_two_sum(q1, q2, q.hi, q.lo);
+  return dd_add(q, dd_t{q3, 0.0});
+}
+
 // ---- getf2: factor an m x w strip (w <= W) held in registers ---------------
-// One 1024-thread workgroup; thread t owns local rows t + 1024 q, q < RPT.
-// Column by column: pivot search (wave shuffles, then LDS), interchange of the
-// two rows inside the strip, division of the column below the pivot by the
-// pivot (DD division), rank-1 update of the strip's remaining columns.
+// One workgroup of T threads; thread t owns local rows t + T q, q < RPT.
+// The strip moves between HBM and registers through an LDS tile, so that
+// global accesses run along the rows (coalesced); all of a thread's loads of a
+// chunk are issued before the first is used.
+// Column c, with one barrier:
+//   1. every wave finds its best candidate |a_ic| (rows i >= c; DD compare,
+//      ties to the smaller row; see wave_argmax); it publishes the value, the
+//      row index and the winning row's W values, and the owner of row c
+//      publishes row c;
+//   2. after the barrier every wave reduces the wave winners itself and reads
+//      the pivot row p from the winning wave's slot; the owners of rows c and
+//      p exchange them in registers;
+//   3. the column below the pivot is divided by the pivot (DD long division)
+//      and the remaining strip columns get the rank-1 update.
+// The published slots are double-buffered by the parity of c: a slot is
+// rewritten two columns later, after a barrier that every reader of its old
+// contents has passed.
 // ipiv[c0 + c] receives the global (0-based) pivot row; info the first
 // 1-based global column whose pivot is exactly zero, if none was recorded
 // before.  Other columns of the matrix are interchanged later by laswp.
-template <int RPT, int W>
-__global__ __launch_bounds__(1024) void getf2_kernel(double* A, int64_t lda, int64_t ps,
-                                                      int64_t r0, int64_t m, int64_t c0, int w,
-                                                      int32_t* ipiv, int32_t* info, int pivot) {
-  __shared__ double s_hi[16], s_lo[16];
-  __shared__ int s_idx[16];
-  __shared__ double rowp_hi[W], rowp_lo[W], rowc_hi[W], rowc_lo[W];
-  __shared__ int s_p;
+
+// DPP lane exchange of a 64-bit value inside rows of 16 lanes.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, kCtrl, 0xF, 0xF,
+                                                            false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), kCtrl,
+                                                            0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+template <int kCtrl>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xF, 0xF, false);
+}
+// lane i <- lane i^1, i^2 (quad permutes), 7-i and 15-i within the row
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int kCtrl>
+__device__ __forceinline__ void argmax_step_dpp(dd_t& b, int& bi, int& tag) {
+  const dd_t o{dpp_f64<kCtrl>(b.hi), dpp_f64<kCtrl>(b.lo)};
+  const int oi = dpp_i32<kCtrl>(bi), ot = dpp_i32<kCtrl>(tag);
+  if (better(o, oi, b, bi)) {
+    b = o;
+    bi = oi;
+    tag = ot;
+  }
+}
+__device__ __forceinline__ void argmax_step_shfl(dd_t& b, int& bi, int& tag, int off) {
+  const dd_t o{__shfl_xor(b.hi, off, 64), __shfl_xor(b.lo, off, 64)};
+  const int oi = __shfl_xor(bi, off, 64), ot = __shfl_xor(tag, off, 64);
+  if (better(o, oi, b, bi)) {
+    b = o;
+    bi = oi;
+    tag = ot;
+  }
+}
+// after the four steps every lane of a 16-lane row holds the row's best
+__device__ __forceinline__ void argmax_row16(dd_t& b, int& bi, int& tag) {
+  argmax_step_dpp<kDppXor1>(b, bi, tag);
+  argmax_step_dpp<kDppXor2>(b, bi, tag);
+  argmax_step_dpp<kDppHalfMirror>(b, bi, tag);
+  argmax_step_dpp<kDppMirror>(b, bi, tag);
+}
+__device__ __forceinline__ double row16_max(double x) {
+  x = fmax(x, dpp_f64<kDppXor1>(x));
+  x = fmax(x, dpp_f64<kDppXor2>(x));
+  x = fmax(x, dpp_f64<kDppHalfMirror>(x));
+  return fmax(x, dpp_f64<kDppMirror>(x));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int k) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, k);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), k);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// The lane holding the best candidate of a wave (largest |x| in DD, then the
+// smallest index; idx < 0 marks "no candidate"), the same in every lane, or
+// -1 if no lane has one.  FP64 maxima of |hi| and |lo| find the leader; a
+// lane can equal or beat it only if the gap between its |hi| and the largest
+// is within the low words' bound, and when that holds for one lane alone it
+// is the winner.  Otherwise the DD comparison decides among those lanes.
+// kRow0: candidates only in lanes 0..15.
+template <bool kRow0>
+__device__ __forceinline__ int wave_argmax(dd_t x, int idx) {
+  const int lane = threadIdx.x % 64;
+  const bool valid = idx >= 0;
+  const double h = valid ? fabs(x.hi) : -1.0, l = valid ? fabs(x.lo) : -1.0;
+  double M = row16_max(h), L = row16_max(l);
+  if (kRow0) {
+    M = readlane_f64(M, 0);
+    L = readlane_f64(L, 0);
+  } else {
+    M = fmax(fmax(readlane_f64(M, 0), readlane_f64(M, 16)),
+             fmax(readlane_f64(M, 32), readlane_f64(M, 48)));
+    L = fmax(fmax(readlane_f64(L, 0), readlane_f64(L, 16)),
+             fmax(readlane_f64(L, 32), readlane_f64(L, 48)));
+  }
+  if (!(M >= 0.0)) return -1;
+  const bool close = valid && (M - h) <= 2.0 * (L + l);
+  const uint64_t mask = __ballot(close);
+  if (__popcll(mask) == 1) return __ffsll((unsigned long long)mask) - 1;
+  dd_t b = close ? x : dd_t{0.0, 0.0};
+  int bi = close ? idx : -1, tag = lane;
+  argmax_row16(b, bi, tag);
+  if (!kRow0) {
+    argmax_step_shfl(b, bi, tag, 16);
+    argmax_step_shfl(b, bi, tag, 32);
+  }
+  return __builtin_amdgcn_readlane(tag, 0);
+}
+
+template <int T, int RPT, int W>
+__global__ __launch_bounds__(T) void getf2_kernel(double* A, int64_t lda, int64_t ps,
+                                                   int64_t r0, int64_t m, int64_t c0, int w,
+                                                   int32_t* ipiv, int32_t* info, int pivot) {
+  constexpr int kLd = W + 1;  // padded LDS row of the staging tile
+  constexpr int kWaves = T / 64;
+  static_assert(kWaves == 4 || kWaves == 8 || kWaves == 16, "T must be 256, 512 or 1024");
+  __shared__ double tile[T * kLd];
+  __shared__ double s_val[2][kWaves][2];
+  __shared__ int s_idx[2][kWaves];
+  __shared__ double s_row[2][kWaves][2][W];
+  __shared__ double s_rowc[2][2][W];
   const int t = threadIdx.x, lane = t % 64, wave = t / 64;
   dd_t v[RPT][W];
 #pragma unroll
-  for (int q = 0; q < RPT; q++)
+  for (int q = 0; q < RPT; q++) {
+    const int64_t rows = min((int64_t)T, m - (int64_t)T * q);
+    if (rows <= 0) {
 #pragma unroll
-    for (int k = 0; k < W; k++) {
-      const int64_t i = t + 1024 * q;
-      v[q][k] = (i < m && k < w) ? ld_dd(A, ps, (r0 + i) * lda + c0 + k) : dd_t{0.0, 0.0};
+      for (int k = 0; k < W; k++) v[q][k] = dd_t{0.0, 0.0};
+      continue;
     }
-  for (int c = 0; c < w; c++) {
-    // 1. pivot search among local rows >= c
+    const int n = (int)rows * w;
+    const double* src = A + (r0 + (int64_t)T * q) * lda + c0;
+    double xh[W], xl[W];
+#pragma unroll
+    for (int j = 0; j < W; j++) {  // every load in flight before the first use
+      const int e = min(t + T * j, n - 1), r = e / w, k = e - r * w;
+      xh[j] = src[(int64_t)r * lda + k];
+      xl[j] = src[ps + (int64_t)r * lda + k];
+    }
+#pragma unroll
+    for (int plane = 0; plane < 2; plane++) {
+#pragma unroll
+      for (int j = 0; j < W; j++) {
+        const int e = t + T * j, r = e / w, k = e - r * w;
+        if (e < n) tile[r * kLd + k] = plane == 0 ? xh[j] : xl[j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < W; k++) {
+        const double x = (t < rows && k < w) ? tile[t * kLd + k] : 0.0;
+        if (plane == 0)
+          v[q][k].hi = x;
+        else
+          v[q][k].lo = x;
+      }
+      __syncthreads();
+    }
+  }
+  // The column loop is unrolled so that every register index is a constant.
+#pragma unroll
+  for (int c = 0; c < W; c++) {
+    if (c >= w) break;
+    const int buf = c & 1;
+    // 1. wave-local pivot search among local rows >= c
     dd_t best{0.0, 0.0};
     int bi = -1;
 #pragma unroll
     for (int q = 0; q < RPT; q++) {
-      const int i = t + 1024 * q;
+      const int i = t + T * q;
       if (i >= c && i < m) {
-        dd_t x;
-#pragma unroll
-        for (int k = 0; k < W; k++)
-          if (k == c) x = dd_abs(v[q][k]);
+        const dd_t x = dd_abs(v[q][c]);
         if (better(x, i, best, bi)) {
           best = x;
           bi = i;
         }
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      dd_t o{__shfl_xor(best.hi, off, 64), __shfl_xor(best.lo, off, 64)};
-      int oi = __shfl_xor(bi, off, 64);
-      if (better(o, oi, best, bi)) {
-        best = o;
-        bi = oi;
-      }
-    }
+    const int wl = wave_argmax<false>(best, bi);
+    const int wbi = wl >= 0 ? __builtin_amdgcn_readlane(bi, wl) : -1;
     if (lane == 0) {
-      s_hi[wave] = best.hi;
-      s_lo[wave] = best.lo;
-      s_idx[wave] = bi;
+      s_val[buf][wave][0] = wl >= 0 ? readlane_f64(best.hi, wl) : 0.0;
+      s_val[buf][wave][1] = wl >= 0 ? readlane_f64(best.lo, wl) : 0.0;
+      s_idx[buf][wave] = wbi;
     }
-    __syncthreads();
-    if (t == 0) {
-      dd_t b{s_hi[0], s_lo[0]};
-      int p = s_idx[0];
-      for (int z = 1; z < 16; z++) {
-        dd_t o{s_hi[z], s_lo[z]};
-        if (better(o, s_idx[z], b, p)) {
-          b = o;
-          p = s_idx[z];
-        }
-      }
-      if (!pivot || p < 0) p = c;
-      s_p = p;
-      ipiv[c0 + c] = (int32_t)(r0 + p);
-    }
-    __syncthreads();
-    const int p = s_p;
-    // 2. interchange rows c and p of the strip through LDS
-    const int qc = c / 1024, tc = c % 1024, qp = p / 1024, tp = p % 1024;
 #pragma unroll
     for (int q = 0; q < RPT; q++) {
-      if (t == tp && q == qp)
+      const int i = t + T * q;
+      if (lane == wl && i == wbi)
 #pragma unroll
         for (int k = 0; k < W; k++) {
-          rowp_hi[k] = v[q][k].hi;
-          rowp_lo[k] = v[q][k].lo;
+          s_row[buf][wave][0][k] = v[q][k].hi;
+          s_row[buf][wave][1][k] = v[q][k].lo;
         }
-      if (p != c && t == tc && q == qc)
+      if (i == c)
 #pragma unroll
         for (int k = 0; k < W; k++) {
-          rowc_hi[k] = v[q][k].hi;
-          rowc_lo[k] = v[q][k].lo;
+          s_rowc[buf][0][k] = v[q][k].hi;
+          s_rowc[buf][1][k] = v[q][k].lo;
         }
     }
     __syncthreads();
-    if (p != c) {
+    // 2. the winners of all waves, reduced by every wave
+    dd_t b{0.0, 0.0};
+    int pi = -1;
+    if (lane < kWaves) {
+      b = dd_t{s_val[buf][lane][0], s_val[buf][lane][1]};
+      pi = s_idx[buf][lane];
+    }
+    const int wv = wave_argmax<true>(b, pi);
+    int p = wv >= 0 ? __builtin_amdgcn_readlane(pi, wv) : -1;
+    const bool use_c = !pivot || p < 0;
+    if (use_c) p = c;
+    const double* rph = use_c ? s_rowc[buf][0] : s_row[buf][wv][0];
+    const double* rpl = use_c ? s_rowc[buf][1] : s_row[buf][wv][1];
+    if (t == 0) ipiv[c0 + c] = (int32_t)(r0 + p);
 #pragma unroll
-      for (int q = 0; q < RPT; q++) {
-        if (t == tc && q == qc)
+    for (int q = 0; q < RPT; q++) {
+      const int i = t + T * q;
+      if (i == c) {
 #pragma unroll
-          for (int k = 0; k < W; k++) v[q][k] = dd_t{rowp_hi[k], rowp_lo[k]};
-        if (t == tp && q == qp)
+        for (int k = 0; k < W; k++) v[q][k] = dd_t{rph[k], rpl[k]};
+      } else if (i == p) {
 #pragma unroll
-          for (int k = 0; k < W; k++) v[q][k] = dd_t{rowc_hi[k], rowc_lo[k]};
+        for (int k = 0; k < W; k++) v[q][k] = dd_t{s_rowc[buf][0][k], s_rowc[buf][1][k]};
       }
     }
-    // 3. the pivot row is now row c; its values are rowp
-    const dd_t u{rowp_hi[c], rowp_lo[c]};
+    // 3. division by the pivot and rank-1 update of the strip
+    const dd_t u{rph[c], rpl[c]};
     if (t == 0 && u.hi == 0.0 && u.lo == 0.0 && *info == 0) *info = (int32_t)(c0 + c + 1);
     if (!(u.hi == 0.0 && u.lo == 0.0)) {
+      const double uinv = 1.0 / u.hi;
 #pragma unroll
       for (int q = 0; q < RPT; q++) {
-        const int i = t + 1024 * q;
+        const int i = t + T * q;
         if (i > c && i < m) {
-          dd_t l;
+          const dd_t l = dd_div_digits(v[q][c], u, uinv);
+          v[q][c] = l;
 #pragma unroll
-          for (int k = 0; k < W; k++)
-            if (k == c) {
-              l = dd_div(v[q][k], u);
-              v[q][k] = l;
-            }
-#pragma unroll
-          for (int k = 0; k < W; k++)
-            if (k > c && k < w) v[q][k] = dd_sub(v[q][k], dd_mul(l, dd_t{rowp_hi[k], rowp_lo[k]}));
+          for (int k = c + 1; k < W; k++)
+            if (k < w) v[q][k] = dd_sub(v[q][k], dd_mul(l, dd_t{rph[k], rpl[k]}));
         }
       }
     }
-    __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < RPT; q++)
+  for (int q = 0; q < RPT; q++) {
+    const int64_t rows = min((int64_t)T, m - (int64_t)T * q);
+    if (rows <= 0) continue;
+    const int n = (int)rows * w;
+    double* dst = A + (r0 + (int64_t)T * q) * lda + c0;
 #pragma unroll
-    for (int k = 0; k < W; k++) {
-      const int64_t i = t + 1024 * q;
-      if (i < m && k < w) st_dd(A, ps, (r0 + i) * lda + c0 + k, v[q][k]);
+    for (int plane = 0; plane < 2; plane++) {
+      __syncthreads();  // the tile's previous readers are done
+      if (t < rows)
+#pragma unroll
+        for (int k = 0; k < W; k++) tile[t * kLd + k] = plane == 0 ? v[q][k].hi : v[q][k].lo;
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < W; j++) {
+        const int e = t + T * j, r = e / w, k = e - r * w;
+        if (e < n) dst[plane * ps + (int64_t)r * lda + k] = tile[r * kLd + k];
+      }
     }
+  }
 }
 
 // ---- laswp: rows k <-> ipiv[k] for k in [k0, k1), in order ------------------
@@ -202,33 +362,54 @@ __global__ __launch_bounds__(256) void laswp_kernel(double* A, int64_t lda, int6
   }
 }
 
-// ---- small unit-lower triangular solve: X := L^-1 X ------------------------
-// L = A[r0 .. r0+nb, c0 .. c0+nb) (unit diagonal, nb <= 16), X = the nb rows
-// r0.. of columns [x0, x0 + ncols).  One thread per column.
-__global__ __launch_bounds__(256) void trsm_small_kernel(double* A, int64_t lda, int64_t ps,
+// ---- unit-lower triangular solve with one wave per column: X := L^-1 X -----
+// L = A[r0 .. r0+nb, c0 .. c0+nb) (unit diagonal, nb <= 64), X = the nb rows
+// r0.. of columns [x0, x0 + ncols).  Lane i of a wave holds x_i of one
+// column; step k broadcasts the finished x_k with readlane and the lanes
+// below it subtract L_ik x_k (forward substitution, one DD multiply and one
+// DD subtraction per entry).  A workgroup takes 16 adjacent columns, staging
+// L (transposed, so a step reads one LDS row) and its X tile through LDS so
+// that the global reads and writes run along the rows.
+
+constexpr int kTrsmRows = 64, kTrsmCols = 16;
+
+__global__ __launch_bounds__(1024) void trsm_wave_kernel(double* A, int64_t lda, int64_t ps,
                                                          int64_t r0, int64_t c0, int nb,
                                                          int64_t x0, int64_t ncols) {
-  __shared__ double Lh[16][16], Ll[16][16];
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    const int i = e / nb, k = e % nb;
-    Lh[i][k] = A[(r0 + i) * lda + c0 + k];
-    Ll[i][k] = A[ps + (r0 + i) * lda + c0 + k];
+  __shared__ double Lh[kTrsmRows][kTrsmRows + 1], Ll[kTrsmRows][kTrsmRows + 1];
+  __shared__ double Xh[kTrsmRows][kTrsmCols + 1], Xl[kTrsmRows][kTrsmCols + 1];
+  const int t = threadIdx.x, lane = t % 64, wave = t / 64, nt = blockDim.x;
+  const int64_t j0 = (int64_t)blockIdx.x * kTrsmCols;
+  const int nc = (int)min((int64_t)kTrsmCols, ncols - j0);
+  for (int e = t; e < nb * nb; e += nt) {
+    const int i = e / nb, k = e - i * nb;
+    Lh[k][i] = A[(r0 + i) * lda + c0 + k];
+    Ll[k][i] = A[ps + (r0 + i) * lda + c0 + k];
+  }
+  for (int e = t; e < nb * nc; e += nt) {
+    const int i = e / nc, c = e - i * nc;
+    Xh[i][c] = A[(r0 + i) * lda + x0 + j0 + c];
+    Xl[i][c] = A[ps + (r0 + i) * lda + x0 + j0 + c];
   }
   __syncthreads();
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= ncols) return;
-  dd_t x[16];
-#pragma unroll
-  for (int i = 0; i < 16; i++)
-    x[i] = i < nb ? ld_dd(A, ps, (r0 + i) * lda + x0 + j) : dd_t{0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < 16; k++)
-#pragma unroll
-    for (int i = k + 1; i < 16; i++)
-      if (i < nb) x[i] = dd_sub(x[i], dd_mul(dd_t{Lh[i][k], Ll[i][k]}, x[k]));
-#pragma unroll
-  for (int i = 0; i < 16; i++)
-    if (i < nb) st_dd(A, ps, (r0 + i) * lda + x0 + j, x[i]);
+  if (wave < nc) {
+    dd_t x{0.0, 0.0};
+    if (lane < nb) x = dd_t{Xh[lane][wave], Xl[lane][wave]};
+    for (int k = 0; k < nb - 1; k++) {
+      const dd_t xk{readlane_f64(x.hi, k), readlane_f64(x.lo, k)};
+      if (lane > k && lane < nb) x = dd_sub(x, dd_mul(dd_t{Lh[k][lane], Ll[k][lane]}, xk));
+    }
+    if (lane < nb) {
+      Xh[lane][wave] = x.hi;
+      Xl[lane][wave] = x.lo;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < nb * nc; e += nt) {
+    const int i = e / nc, c = e - i * nc;
+    A[(r0 + i) * lda + x0 + j0 + c] = Xh[i][c];
+    A[ps + (r0 + i) * lda + x0 + j0 + c] = Xl[i][c];
+  }
 }
 
 __global__ void lu_init_kernel(int32_t* info, int32_t* perm, int64_t n) {
@@ -374,24 +555,25 @@ int launch_lu_init(int32_t* info, int32_t* perm, int64_t n, hipStream_t s) {
 
 // Strip width for an m-row strip: the strip lives in registers, 1024 threads
 // of at most 128 registers each, so taller strips are narrower.
+// Strip shape by panel height: threads, rows per thread, strip width.  The
+// register tile (RPT x W DD values) stays within what one thread can hold.
 int getf2_width(int64_t m) { return m <= 2048 ? 8 : (m <= 4096 ? 4 : 2); }
 
 int launch_getf2(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t m, int64_t c0, int w,
                  int32_t* ipiv, int32_t* info, int pivot, hipStream_t s) {
   if (m <= 0 || w <= 0) return 0;
-  const int rpt = (int)((m + 1023) / 1024);
   if (w > getf2_width(m)) return set_error(4, "getf2 strip too wide");
-#define GETF2(R, W)                                                                        \
-  do {                                                                                     \
-    prof_begin(s);                                                                         \
-    hipLaunchKernelGGL((getf2_kernel<R, W>), dim3(1), dim3(1024), 0, s, A, lda, ps, r0, m, c0, \
-                       w, ipiv, info, pivot);                                              \
-    prof_record("getf2_kernel", s);                                                        \
+#define GETF2(T, R, W)                                                                          \
+  do {                                                                                          \
+    prof_begin(s);                                                                              \
+    hipLaunchKernelGGL((getf2_kernel<T, R, W>), dim3(1), dim3(T), 0, s, A, lda, ps, r0, m, c0, \
+                       w, ipiv, info, pivot);                                                   \
+    prof_record("getf2_kernel", s);                                                            \
   } while (0)
-  if (rpt <= 1) GETF2(1, 8);
-  else if (rpt <= 2) GETF2(2, 8);
-  else if (rpt <= 4) GETF2(4, 4);
-  else if (rpt <= 8) GETF2(8, 2);
+  if (m <= 1024) GETF2(1024, 1, 8);
+  else if (m <= 2048) GETF2(1024, 2, 8);
+  else if (m <= 4096) GETF2(512, 8, 4);
+  else if (m <= 8192) GETF2(1024, 8, 2);
   else return set_error(4, "LU of more than 8192 rows is not supported");
 #undef GETF2
   return check_launch("getf2_kernel");
@@ -408,15 +590,17 @@ int launch_laswp(double* A, int64_t lda, int64_t ps, int64_t n_cols, int64_t ski
   return check_launch("laswp_kernel");
 }
 
-int launch_trsm_small(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t c0, int nb,
-                      int64_t x0, int64_t ncols, hipStream_t s) {
+int launch_trsm_wave(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t c0, int nb,
+                     int64_t x0, int64_t ncols, hipStream_t s) {
   if (nb <= 0 || ncols <= 0) return 0;
-  if (nb > 16) return set_error(4, "trsm_small: block too large");
+  if (nb > kTrsmRows) return set_error(4, "trsm_wave: block too large");
+  const int64_t blocks = (ncols + kTrsmCols - 1) / kTrsmCols;
+  const int threads = 64 * (int)(ncols < kTrsmCols ? ncols : kTrsmCols);
   prof_begin(s);
-  hipLaunchKernelGGL(trsm_small_kernel, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s, A,
-                     lda, ps, r0, c0, nb, x0, ncols);
-  prof_record("trsm_small_kernel", s);
-  return check_launch("trsm_small_kernel");
+  hipLaunchKernelGGL(trsm_wave_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, A, lda, ps,
+                     r0, c0, nb, x0, ncols);
+  prof_record("trsm_wave_kernel", s);
+  return check_launch("trsm_wave_kernel");
 }
 
 int launch_perm_from_ipiv(const int32_t* ipiv, int64_t n, int32_t* perm, hipStream_t s) {

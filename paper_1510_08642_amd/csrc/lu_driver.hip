@@ -14,7 +14,8 @@
 // by one workgroup holding the strip in registers (getf2), and every strip's
 // interchanges are applied to all other columns by laswp, which also keeps
 // the row permutation in `perm`.  U12 = L11^-1 A12 is a recursive triangular
-// solve (16-row diagonal solves, Block products for the off-diagonal parts).
+// solve (diagonal solves of up to 64 rows, one wave per column; products for
+// the off-diagonal parts).
 #include "common.hpp"
 #include "ddqd.h"
 
@@ -38,8 +39,8 @@ int launch_getf2(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t m, int6
 int launch_laswp(double* A, int64_t lda, int64_t ps, int64_t n_cols, int64_t skip0,
                  int64_t skip1, int64_t k0, int64_t k1, const int32_t* ipiv, int32_t* perm,
                  hipStream_t s);
-int launch_trsm_small(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t c0, int nb,
-                      int64_t x0, int64_t ncols, hipStream_t s);
+int launch_trsm_wave(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t c0, int nb,
+                     int64_t x0, int64_t ncols, hipStream_t s);
 int launch_perm_from_ipiv(const int32_t* ipiv, int64_t n, int32_t* perm, hipStream_t s);
 int launch_gather_rows(const double* B, int64_t ldb, int64_t psb, const int32_t* perm, int64_t n,
                        int64_t nrhs, double* X, hipStream_t s);
@@ -66,18 +67,23 @@ struct Lu {
 
 Mat sub(const Lu& c, int64_t i, int64_t j) { return Mat{c.A + i * c.lda + j, c.lda, c.ps, 0}; }
 
-// C[rows] -= A B with the Block FMA kernel (no workspace)
+// C -= A B inside the panel and the triangular solves (no workspace).  These
+// products are thin (one side <= the panel width), so they rarely give the
+// Block kernel one 64 x 64 tile per compute unit; below that the Simple
+// kernel (one thread per entry, no tile staging) finishes sooner.
 int block_update(const Lu& c, int64_t m, int64_t n, int64_t l, Mat Am, Mat Bm, Mat Cm) {
   GemmBatch g{m, n, l, -1, 1, cview(Am), cview(Bm), Cm, 1};
-  return gemm_internal(2, g, DDQD_BLOCK, 0, DDQD_BASE_FMA, 0, nullptr, 0, c.s);
+  const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
+  return gemm_internal(2, g, tiles < 256 ? DDQD_SIMPLE : DDQD_BLOCK, 0, DDQD_BASE_FMA, 0, nullptr,
+                       0, c.s);
 }
 
 // X := L^-1 X, L unit lower nb x nb at (r0, r0), X = rows [r0, r0+nb) of
 // columns [x0, x0 + nc)
 int trsm(const Lu& c, int64_t r0, int64_t nb, int64_t x0, int64_t nc) {
   if (nb <= 0 || nc <= 0) return 0;
-  if (nb <= 16) return launch_trsm_small(c.A, c.lda, c.ps, r0, r0, (int)nb, x0, nc, c.s);
-  const int64_t n1 = nb / 2;
+  if (nb <= 64) return launch_trsm_wave(c.A, c.lda, c.ps, r0, r0, (int)nb, x0, nc, c.s);
+  const int64_t n1 = (nb / 2 + 63) / 64 * 64;
   int rc;
   if ((rc = trsm(c, r0, n1, x0, nc))) return rc;
   if ((rc = block_update(c, nb - n1, nc, n1, sub(c, r0 + n1, r0), sub(c, r0, x0),

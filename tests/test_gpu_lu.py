@@ -180,3 +180,33 @@ def test_winograd_update_error_close_to_block(dd):
         LU, ipiv, perm, _ = factor(dd, A, panel=64, algo=algo, levels=lv)
         res[algo] = oracle.lu_residual(A, solve(dd, LU, ipiv, B, perm), B)
     assert res["winograd"] <= 16 * res["block"] + n * 2.0 ** -106
+
+
+@pytest.mark.parametrize("n,panel,vals", [(100, 32, (-1, 1)), (129, 64, (-2, -1, 0, 1, 2)),
+                                          (300, 128, (-1, 1))])
+def test_pivot_ties_pick_first_row(dd, n, panel, vals):
+    """Integer matrices: exact ties in |a_ic| are frequent; partial pivoting
+    takes the first maximal row, as the oracle does (Sec. 4 with pivoting)."""
+    g = inputs.rng(250 + n)
+    A = ddm(g.choice(np.array(vals, dtype=np.float64), size=(n, n)))
+    LU, ipiv, _, info = factor(dd, A, panel=panel)
+    LUo, ipo, info_o = oracle.getrf(A, panel=panel, pivot=True, algo="block", levels=0)
+    assert info == info_o
+    assert np.array_equal(ipiv, ipo)
+    if info == 0:
+        scale = np.max(np.abs(LUo[0]))
+        assert np.max(np.abs((LU[0] - LUo[0]) + (LU[1] - LUo[1]))) <= n * 2.0 ** -96 * scale
+
+
+def test_pivot_decided_by_low_words(dd):
+    """Candidates with equal high words: the low words decide (DD compare)."""
+    n = 40
+    g = inputs.rng(260)
+    A = inputs.dd_lu_matrix(n, g, boost=False)
+    A[:, :, 0] = 0.0
+    A[0, [3, 11, 17, 30], 0] = [1.0, 1.0, -1.0, 0.5]
+    A[1, [3, 11, 17, 30], 0] = [2.0 ** -60, 2.0 ** -58, -(2.0 ** -57), 2.0 ** -55]
+    LU, ipiv, _, info = factor(dd, A, panel=16)
+    LUo, ipo, _ = oracle.getrf(A, panel=16, pivot=True, algo="block", levels=0)
+    assert ipiv[0] == ipo[0] == 17
+    assert np.array_equal(ipiv, ipo)
