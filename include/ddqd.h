@@ -183,6 +183,31 @@ int dd_getrs(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t ps
 
 size_t dd_getrs_workspace(int64_t n, int64_t nrhs);
 
+/*
+ * Captured launch sequences.  The calls above, issued on one non-null stream
+ * between ddqd_graph_begin and ddqd_graph_end, are recorded into a HIP graph
+ * instead of being executed; ddqd_graph_launch replays them on any stream:
+ * the same kernels with the same arguments, so every buffer (operands,
+ * outputs, workspaces, ipiv/perm/info) must stay allocated and in place, and
+ * each replay rewrites the outputs and workspaces exactly as the recorded
+ * calls would.  No library call allocates, frees, synchronises or clears
+ * memory with a memset node, so all of them can be recorded (this is how
+ * the LU's fixed chain of small launches, or a repeated small product, is
+ * replayed without the host cost of each launch).  Per-kernel profiling
+ * records nothing while capturing.
+ *   begin    DDQD_E_ARG for a null stream, DDQD_E_HIP if capture fails to start.
+ *   end      returns the graph in *graph (owned by the caller, released by
+ *            ddqd_graph_destroy); DDQD_E_HIP (and *graph = NULL) if the
+ *            capture was invalidated, e.g. by a foreign call on the stream.
+ *   launch   DDQD_E_ARG for a null graph; asynchronous on `stream`.
+ *   destroy  accepts NULL.
+ */
+typedef struct ddqd_graph* ddqd_graph_t;
+int ddqd_graph_begin(void* stream);
+int ddqd_graph_end(void* stream, ddqd_graph_t* graph);
+int ddqd_graph_launch(ddqd_graph_t graph, void* stream);
+int ddqd_graph_destroy(ddqd_graph_t graph);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,8 @@ thread_local hipEvent_t g_prof_pending = nullptr;
 
 void prof_begin(hipStream_t s) {
   if (!g_prof.load(std::memory_order_relaxed)) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   hipEvent_t e;
   if (hipEventCreate(&e) != hipSuccess) return;
   if (hipEventRecord(e, s) != hipSuccess) {

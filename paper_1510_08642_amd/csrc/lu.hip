@@ -362,15 +362,43 @@ __global__ __launch_bounds__(256) void laswp_kernel(double* A, int64_t lda, int6
   }
 }
 
+// ---- C -= A B for the thin products inside the panel ------------------------
+// A (m x l), B (l x n), C (m x n) are blocks of one plane-layout matrix (same
+// ld and plane stride).  One thread per entry of C; the products are summed
+// without renormalisation (TwoSum of the high parts, the low parts and the
+// TwoSum errors gathered in a second word), then subtracted from C in DD.
+__global__ __launch_bounds__(256) void lu_update_kernel(const double* A, const double* B,
+                                                        double* C, int64_t ld, int64_t ps,
+                                                        int64_t m, int64_t n, int64_t l) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= m * n) return;
+  const int64_t i = e / n, j = e - i * n;
+  const double* a = A + i * ld;
+  const double* b = B + j;
+  double s = 0.0, r = 0.0;
+  for (int64_t k = 0; k < l; k++) {
+    const double ah = a[k], al = a[ps + k], bh = b[k * ld], bl = b[ps + k * ld];
+    const double p = ah * bh;
+    const double pe = fma(ah, bl, fma(al, bh, fma(ah, bh, -p)));
+    double t;
+    two_sum(s, p, s, t);
+    r += t + pe;
+  }
+  dd_t x;
+  two_sum(s, r, x.hi, x.lo);
+  const dd_t c = ld_dd(C, ps, i * ld + j);
+  st_dd(C, ps, i * ld + j, dd_sub(c, x));
+}
+
 // ---- unit-lower triangular solve with one wave per column: X := L^-1 X -----
 // L = A[r0 .. r0+nb, c0 .. c0+nb) (unit diagonal, nb <= 64), X = the nb rows
-// r0.. of columns [x0, x0 + ncols).  Lane i of a wave holds x_i of one
-// column; step k broadcasts the finished x_k with readlane and the lanes
-// below it subtract L_ik x_k (forward substitution, one DD multiply and one
-// DD subtraction per entry).  A workgroup takes 16 adjacent columns, staging
-// L (transposed, so a step reads one LDS row) and its X tile through LDS so
-// that the global reads and writes run along the rows.
-
+// r0.. of columns [x0, x0 + ncols).  Lane i of a wave holds x_i of one column
+// as an unrenormalised pair (s, r); step k renormalises x_k, broadcasts it
+// with readlane, and the lanes below subtract L_ik x_k (TwoSum of the high
+// product into s, the low parts and the TwoSum error into r): forward
+// substitution with one rounding to DD per unknown.  A workgroup takes up to
+// 16 adjacent columns, staging L (transposed, so a step reads one LDS row)
+// and its X tile through LDS so that global accesses run along the rows.
 constexpr int kTrsmRows = 64, kTrsmCols = 16;
 
 __global__ __launch_bounds__(1024) void trsm_wave_kernel(double* A, int64_t lda, int64_t ps,
@@ -379,8 +407,9 @@ __global__ __launch_bounds__(1024) void trsm_wave_kernel(double* A, int64_t lda,
   __shared__ double Lh[kTrsmRows][kTrsmRows + 1], Ll[kTrsmRows][kTrsmRows + 1];
   __shared__ double Xh[kTrsmRows][kTrsmCols + 1], Xl[kTrsmRows][kTrsmCols + 1];
   const int t = threadIdx.x, lane = t % 64, wave = t / 64, nt = blockDim.x;
-  const int64_t j0 = (int64_t)blockIdx.x * kTrsmCols;
-  const int nc = (int)min((int64_t)kTrsmCols, ncols - j0);
+  const int cpb = nt / 64;  // columns per workgroup
+  const int64_t j0 = (int64_t)blockIdx.x * cpb;
+  const int nc = (int)min((int64_t)cpb, ncols - j0);
   for (int e = t; e < nb * nb; e += nt) {
     const int i = e / nb, k = e - i * nb;
     Lh[k][i] = A[(r0 + i) * lda + c0 + k];
@@ -393,15 +422,28 @@ __global__ __launch_bounds__(1024) void trsm_wave_kernel(double* A, int64_t lda,
   }
   __syncthreads();
   if (wave < nc) {
-    dd_t x{0.0, 0.0};
-    if (lane < nb) x = dd_t{Xh[lane][wave], Xl[lane][wave]};
+    double s = 0.0, r = 0.0;
+    if (lane < nb) {
+      s = Xh[lane][wave];
+      r = Xl[lane][wave];
+    }
     for (int k = 0; k < nb - 1; k++) {
-      const dd_t xk{readlane_f64(x.hi, k), readlane_f64(x.lo, k)};
-      if (lane > k && lane < nb) x = dd_sub(x, dd_mul(dd_t{Lh[k][lane], Ll[k][lane]}, xk));
+      double kh, kl;
+      two_sum(readlane_f64(s, k), readlane_f64(r, k), kh, kl);
+      if (lane > k && lane < nb) {
+        const double lh = Lh[k][lane], ll = Ll[k][lane];
+        const double p = lh * kh;
+        const double pe = fma(lh, kl, fma(ll, kh, fma(lh, kh, -p)));
+        double e;
+        two_sum(s, -p, s, e);
+        r += e - pe;
+      }
     }
     if (lane < nb) {
-      Xh[lane][wave] = x.hi;
-      Xl[lane][wave] = x.lo;
+      double h, l;
+      two_sum(s, r, h, l);
+      Xh[lane][wave] = h;
+      Xl[lane][wave] = l;
     }
   }
   __syncthreads();
@@ -570,7 +612,9 @@ int launch_getf2(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t m, int6
                        w, ipiv, info, pivot);                                                   \
     prof_record("getf2_kernel", s);                                                            \
   } while (0)
-  if (m <= 1024) GETF2(1024, 1, 8);
+  if (m <= 256) GETF2(256, 1, 8);
+  else if (m <= 512) GETF2(512, 1, 8);
+  else if (m <= 1024) GETF2(1024, 1, 8);
   else if (m <= 2048) GETF2(1024, 2, 8);
   else if (m <= 4096) GETF2(512, 8, 4);
   else if (m <= 8192) GETF2(1024, 8, 2);
@@ -594,13 +638,28 @@ int launch_trsm_wave(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t c0,
                      int64_t x0, int64_t ncols, hipStream_t s) {
   if (nb <= 0 || ncols <= 0) return 0;
   if (nb > kTrsmRows) return set_error(4, "trsm_wave: block too large");
-  const int64_t blocks = (ncols + kTrsmCols - 1) / kTrsmCols;
-  const int threads = 64 * (int)(ncols < kTrsmCols ? ncols : kTrsmCols);
+  // enough workgroups to reach every compute unit before stacking columns
+  int64_t cpb = (ncols + 255) / 256;
+  if (cpb > kTrsmCols) cpb = kTrsmCols;
+  if (cpb > ncols) cpb = ncols;
+  const int64_t blocks = (ncols + cpb - 1) / cpb;
   prof_begin(s);
-  hipLaunchKernelGGL(trsm_wave_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, A, lda, ps,
-                     r0, c0, nb, x0, ncols);
+  hipLaunchKernelGGL(trsm_wave_kernel, dim3((unsigned)blocks), dim3((unsigned)(64 * cpb)), 0, s,
+                     A, lda, ps, r0, c0, nb, x0, ncols);
   prof_record("trsm_wave_kernel", s);
   return check_launch("trsm_wave_kernel");
+}
+
+int launch_lu_update(const double* A, const double* B, double* C, int64_t ld, int64_t ps,
+                     int64_t m, int64_t n, int64_t l, hipStream_t s) {
+  if (m <= 0 || n <= 0 || l <= 0) return 0;
+  const int64_t blocks = (m * n + 255) / 256;
+  if (blocks > INT32_MAX) return set_error(4, "lu_update: grid too large");
+  prof_begin(s);
+  hipLaunchKernelGGL(lu_update_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, B, C, ld, ps, m,
+                     n, l);
+  prof_record("lu_update_kernel", s);
+  return check_launch("lu_update_kernel");
 }
 
 int launch_perm_from_ipiv(const int32_t* ipiv, int64_t n, int32_t* perm, hipStream_t s) {

@@ -41,6 +41,8 @@ int launch_laswp(double* A, int64_t lda, int64_t ps, int64_t n_cols, int64_t ski
                  hipStream_t s);
 int launch_trsm_wave(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t c0, int nb,
                      int64_t x0, int64_t ncols, hipStream_t s);
+int launch_lu_update(const double* A, const double* B, double* C, int64_t ld, int64_t ps,
+                     int64_t m, int64_t n, int64_t l, hipStream_t s);
 int launch_perm_from_ipiv(const int32_t* ipiv, int64_t n, int32_t* perm, hipStream_t s);
 int launch_gather_rows(const double* B, int64_t ldb, int64_t psb, const int32_t* perm, int64_t n,
                        int64_t nrhs, double* X, hipStream_t s);
@@ -69,13 +71,13 @@ Mat sub(const Lu& c, int64_t i, int64_t j) { return Mat{c.A + i * c.lda + j, c.l
 
 // C -= A B inside the panel and the triangular solves (no workspace).  These
 // products are thin (one side <= the panel width), so they rarely give the
-// Block kernel one 64 x 64 tile per compute unit; below that the Simple
-// kernel (one thread per entry, no tile staging) finishes sooner.
+// Block kernel one 64 x 64 tile per compute unit; below that a kernel with
+// one thread per entry and no tile staging finishes sooner.
 int block_update(const Lu& c, int64_t m, int64_t n, int64_t l, Mat Am, Mat Bm, Mat Cm) {
-  GemmBatch g{m, n, l, -1, 1, cview(Am), cview(Bm), Cm, 1};
   const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
-  return gemm_internal(2, g, tiles < 256 ? DDQD_SIMPLE : DDQD_BLOCK, 0, DDQD_BASE_FMA, 0, nullptr,
-                       0, c.s);
+  if (tiles < 256) return launch_lu_update(Am.p, Bm.p, Cm.p, c.lda, c.ps, m, n, l, c.s);
+  GemmBatch g{m, n, l, -1, 1, cview(Am), cview(Bm), Cm, 1};
+  return gemm_internal(2, g, DDQD_BLOCK, 0, DDQD_BASE_FMA, 0, nullptr, 0, c.s);
 }
 
 // X := L^-1 X, L unit lower nb x nb at (r0, r0), X = rows [r0, r0+nb) of

@@ -70,6 +70,14 @@ _lib.ddqd_status_string.argtypes = [_int]
 _lib.ddqd_status_string.restype = ctypes.c_char_p
 _lib.ddqd_last_error.argtypes = []
 _lib.ddqd_last_error.restype = ctypes.c_char_p
+_lib.ddqd_graph_begin.argtypes = [_vp]
+_lib.ddqd_graph_begin.restype = _int
+_lib.ddqd_graph_end.argtypes = [_vp, ctypes.POINTER(_vp)]
+_lib.ddqd_graph_end.restype = _int
+_lib.ddqd_graph_launch.argtypes = [_vp, _vp]
+_lib.ddqd_graph_launch.restype = _int
+_lib.ddqd_graph_destroy.argtypes = [_vp]
+_lib.ddqd_graph_destroy.restype = _int
 
 SIZE_MAX = ctypes.c_size_t(-1).value
 
@@ -158,21 +166,30 @@ def getrf_workspace(n: int, panel=128, algo="winograd", levels=1, base="fma") ->
 
 
 def dd_getrf(A, *, panel=128, pivot="partial", algo="winograd", levels=1, base="fma",
-             want_perm=True, ws=None):
+             want_perm=True, ws=None, out=None):
     """In-place DD LU of the square (2, n, n) tensor A (blocked right-looking,
     panel width `panel`, trailing update by `algo`/`levels`/`base`).
 
     Returns (ipiv, perm, info) as device int32 tensors: LAPACK-style 0-based
     interchanges, the resulting row permutation (or None), and info (0, or the
-    1-based column of the first exactly-zero pivot)."""
+    1-based column of the first exactly-zero pivot).  `out` may supply those
+    three tensors (perm may be None), e.g. for a call recorded in a graph."""
     n = A.shape[1]
     if A.shape[2] != n:
         raise ValueError("A must be square")
     pa, lda, psa = _mat(A, 2, "A")
     dev = A.device
-    ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
-    perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if want_perm else None
-    info = torch.empty(1, dtype=torch.int32, device=dev)
+    if out is not None:
+        ipiv, perm, info = out
+        if ipiv.numel() < n or info.numel() < 1 or (perm is not None and perm.numel() < n):
+            raise ValueError("out tensors are too small")
+        if any(t is not None and (t.dtype != torch.int32 or not t.is_contiguous())
+               for t in (ipiv, perm, info)):
+            raise TypeError("out tensors must be contiguous int32")
+    else:
+        ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if want_perm else None
+        info = torch.empty(1, dtype=torch.int32, device=dev)
     need = getrf_workspace(n, panel, algo, levels, base)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
@@ -236,3 +253,41 @@ def profile_query(substr: str | None = None):
     _check(_lib.ddqd_profile_query(substr.encode() if substr else None, ctypes.byref(ms),
                                    ctypes.byref(cnt)), "ddqd_profile_query")
     return ms.value, cnt.value
+
+
+class Graph:
+    """A recorded sequence of library calls (ddqd_graph_*): replay() launches
+    it again on a stream; every tensor the calls used must stay alive."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def replay(self, stream=None):
+        if self._h is None:
+            raise RuntimeError("graph was released")
+        s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+        _check(_lib.ddqd_graph_launch(self._h, s), "ddqd_graph_launch")
+
+    def release(self):
+        if self._h is not None:
+            _lib.ddqd_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.release()
+
+
+def capture(fn, stream):
+    """Records the library calls fn() makes on `stream` (a torch.cuda.Stream,
+    not the default stream) and returns them as a Graph.  fn must allocate
+    nothing on the device (pass workspaces and outputs in)."""
+    s = stream.cuda_stream
+    _check(_lib.ddqd_graph_begin(s), "ddqd_graph_begin")
+    try:
+        with torch.cuda.stream(stream):
+            fn()
+    finally:
+        h = _vp()
+        st = _lib.ddqd_graph_end(s, ctypes.byref(h))
+    _check(st, "ddqd_graph_end")
+    return Graph(h.value)

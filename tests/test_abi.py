@@ -150,3 +150,14 @@ def test_lu_argument_errors(lib):
                         None) == E["ARG"]
     assert lib.dd_getrs(8, 2, A, 8, 64, ip, None, 0x70000, 2, 16, None, 0, None) == E["WORKSPACE"]
     assert lib.dd_getrs(0, 2, A, 8, 64, ip, None, 0x70000, 2, 16, None, 0, None) == E["OK"]
+
+
+def test_graph_argument_errors(lib):
+    import ctypes as C
+    h = C.c_void_p(0x1234)
+    assert lib.ddqd_graph_begin(None) == E["ARG"]
+    assert lib.ddqd_graph_end(None, C.byref(h)) == E["ARG"]
+    assert h.value is None                      # cleared on every error path
+    assert lib.ddqd_graph_end(C.c_void_p(0x1000), None) == E["ARG"]
+    assert lib.ddqd_graph_launch(None, None) == E["ARG"]
+    assert lib.ddqd_graph_destroy(None) == E["OK"]
