@@ -57,6 +57,7 @@ extern "C" {
 #define DDQD_BLOCK 1    /* tiled product                                  */
 #define DDQD_STRASSEN 2 /* Strassen's recursion, `levels` deep            */
 #define DDQD_WINOGRAD 3 /* Strassen-Winograd recursion, `levels` deep     */
+#define DDQD_AUTO 4     /* tuned (dd_gemm_tune) or default configuration  */
 
 /* base (leaf) product kernels */
 #define DDQD_BASE_FMA 0      /* FP64 FMA error-free products                 */
@@ -89,7 +90,8 @@ int ddqd_profile_query(const char* substr, double* ms, int64_t* count);
  *   A, B, C   device plane-layout DD matrices (2 planes) with leading
  *             dimensions lda, ldb, ldc and plane strides psa, psb, psc.
  *             C must not overlap A or B (DDQD_E_ALIAS); A and B may overlap.
- *   algo      DDQD_SIMPLE, DDQD_BLOCK, DDQD_STRASSEN or DDQD_WINOGRAD.
+ *   algo      DDQD_SIMPLE, DDQD_BLOCK, DDQD_STRASSEN or DDQD_WINOGRAD, or
+ *             DDQD_AUTO (see dd_gemm_tune; `levels` is then ignored).
  *   levels    recursion depth for Strassen/Winograd (0..6); the depth
  *             actually used stops early once a dimension would drop below 2.
  *             Each level splits m, l and n in half; an odd dimension is
@@ -182,6 +184,50 @@ int dd_getrs(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t ps
              void* ws, size_t ws_bytes, void* stream);
 
 size_t dd_getrs_workspace(int64_t n, int64_t nrhs);
+
+/*
+ * Autotuning.  The paper leaves the choice of block size and recursion depth
+ * per shape as future work (Sec. 5); here the library times the candidate
+ * configurations of one shape on the device and keeps the fastest in a
+ * process-wide, thread-safe cache that algo = DDQD_AUTO then uses.
+ * Candidates: Block (FMA leaves: 64x64 and 32x32 tiles, which give
+ * bit-identical results), and Strassen and Winograd with 1..3 levels while
+ * the leaves keep at least 16 rows and columns.  The base and the slice
+ * count are the caller's: they set the accuracy, the tuner only the speed.
+ * Without a cache entry DDQD_AUTO takes a default: Block for DD (32x32 tiles
+ * when 64x64 would leave compute units idle), Winograd for QD with levels
+ * while the leaves stay >= 128.
+ *   A, B, C  as dd_gemm with alpha = 1, beta = 0; C receives A B (computed
+ *            by every candidate in turn).
+ *   reps     timed calls per candidate (>= 1; one untimed call precedes).
+ *   ws       dd_gemm_workspace(m, n, l, DDQD_AUTO, 0, base, slices) bytes,
+ *            which also covers every later DDQD_AUTO call of this shape.
+ *   out      the chosen configuration (may be NULL).
+ * Blocks the calling thread until the timing on `stream` is done; cannot be
+ * recorded in a graph.  Argument errors as dd_gemm.
+ */
+typedef struct {
+  int algo;       /* DDQD_BLOCK, DDQD_STRASSEN or DDQD_WINOGRAD */
+  int levels;     /* recursion depth */
+  int tile;       /* Block FMA leaf tile edge (64 or 32), 0 for other leaves */
+  int candidates; /* configurations timed; 0 = not tuned, default shown */
+  double ms;      /* time per call of the chosen configuration (0 if not tuned) */
+} ddqd_tune_result;
+
+int dd_gemm_tune(int64_t m, int64_t n, int64_t l, const double* A, int64_t lda, int64_t psa,
+                 const double* B, int64_t ldb, int64_t psb, double* C, int64_t ldc, int64_t psc,
+                 int base, int slices, int reps, void* ws, size_t ws_bytes, void* stream,
+                 ddqd_tune_result* out);
+int qd_gemm_tune(int64_t m, int64_t n, int64_t l, const double* A, int64_t lda, int64_t psa,
+                 const double* B, int64_t ldb, int64_t psb, double* C, int64_t ldc, int64_t psc,
+                 int base, int slices, int reps, void* ws, size_t ws_bytes, void* stream,
+                 ddqd_tune_result* out);
+/* The configuration DDQD_AUTO uses for this shape (precision 2 = DD, 4 = QD);
+ * DDQD_E_ARG for bad arguments. */
+int ddqd_tune_lookup(int precision, int64_t m, int64_t n, int64_t l, int base, int slices,
+                     ddqd_tune_result* out);
+/* Empties the cache. */
+void ddqd_tune_clear(void);
 
 /*
  * Captured launch sequences.  The calls above, issued on one non-null stream

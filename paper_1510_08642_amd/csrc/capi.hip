@@ -33,9 +33,13 @@
 
 namespace ddqd {
 
-int launch_dd_block(const GemmBatch& g, hipStream_t stream);
+int launch_dd_block(const GemmBatch& g, int tile, hipStream_t stream);
 int launch_dd_simple(const GemmBatch& g, hipStream_t stream);
 int64_t dd_block_tiles(int64_t m, int64_t n);
+// autotuning (tune.hip)
+void auto_choice(int P, int64_t m, int64_t n, int64_t l, int base, int slices, int* algo,
+                 int* levels, int* tile);
+size_t auto_workspace(int P, int64_t m, int64_t n, int64_t l, int base, int slices);
 int launch_dd_grouped(const GroupArgs& ga, int grid, hipStream_t stream);
 int launch_qd_block(const GemmBatch& g, hipStream_t stream);
 int launch_qd_simple(const GemmBatch& g, hipStream_t stream);
@@ -178,14 +182,14 @@ Mat prodM(const Plan& pl, char* ws, int j) {
   return Mat{(double*)(ws + pl.offM[j]), c, r * c, pl.P * r * c};
 }
 
-int leaf(int P, const GemmBatch& g, int base, int slices, void* ws, size_t ws_bytes,
+int leaf(int P, const GemmBatch& g, int base, int slices, int tile, void* ws, size_t ws_bytes,
          hipStream_t s) {
   if (base == DDQD_BASE_OZAKI_I8) return launch_ozaki(g, slices, ws, ws_bytes, s);
-  return P == 2 ? launch_dd_block(g, s) : launch_qd_block(g, s);
+  return P == 2 ? launch_dd_block(g, tile, s) : launch_qd_block(g, s);
 }
 
 int block_fma(int P, const GemmBatch& g, hipStream_t s) {
-  return P == 2 ? launch_dd_block(g, s) : launch_qd_block(g, s);
+  return P == 2 ? launch_dd_block(g, 64, s) : launch_qd_block(g, s);
 }
 
 int preadd(int P, CMat src, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
@@ -211,12 +215,12 @@ Mat shift(Mat X, int64_t i, int64_t j) {
 }
 
 int run_gemm(int P, const GemmBatch& top, int algo, int levels, int base, int slices, void* ws,
-             size_t ws_bytes, hipStream_t s) {
+             size_t ws_bytes, hipStream_t s, int tile = 64) {
   if (algo == DDQD_SIMPLE) return P == 2 ? launch_dd_simple(top, s) : launch_qd_simple(top, s);
   Plan pl = make_plan(P, top.m, top.n, top.l, algo, levels, base, slices);
   char* w = (char*)ws;
   const int L = pl.L;
-  if (L == 0) return leaf(P, top, base, slices, w, ws_bytes, s);
+  if (L == 0) return leaf(P, top, base, slices, tile, w, ws_bytes, s);
   int rc;
   // equilibration exponents of A's rows and B's columns (top level only)
   int* ea = (int*)(w + pl.off_exp);
@@ -237,7 +241,7 @@ int run_gemm(int P, const GemmBatch& top, int algo, int levels, int base, int sl
   // all leaf products in one batched launch
   GemmBatch lf{pl.m[L], pl.n[L], pl.l[L], 1, 0, opA(pl, w, L), opB(pl, w, L), prodM(pl, w, L),
                pow7(L)};
-  if ((rc = leaf(P, lf, base, slices, w + pl.off_leaf, pl.leaf_bytes, s))) return rc;
+  if ((rc = leaf(P, lf, base, slices, tile, w + pl.off_leaf, pl.leaf_bytes, s))) return rc;
   // post-adds and peeling, level by level back up
   for (int j = L; j >= 1; j--) {
     const bool root = j == 1;
@@ -301,23 +305,34 @@ int device_ok() {
 
 size_t gemm_ws(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
                int slices) {
-  if (m < 0 || n < 0 || l < 0 || algo < 0 || algo > 3 || levels < 0 || levels > kMaxLevels ||
-      base < 0 || base > 1 || slices < 0 || slices > 40)
+  if (m < 0 || n < 0 || l < 0 || algo < 0 || algo > DDQD_AUTO || levels < 0 ||
+      levels > kMaxLevels || base < 0 || base > 1 || slices < 0 || slices > 40)
     return SIZE_MAX;
   if (P == 4 && base != DDQD_BASE_FMA) return SIZE_MAX;
   if (m == 0 || n == 0 || l == 0) return 0;
+  if (algo == DDQD_AUTO) return auto_workspace(P, m, n, l, base, slices);
   return make_plan(P, m, n, l, algo, levels, base, slices).total;
 }
 
+}  // namespace
+
+size_t plan_workspace(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
+                      int slices) {
+  return gemm_ws(P, m, n, l, algo, levels, base, slices);
+}
+
+// tile: Block FMA leaf tile (0 = 64); algo DDQD_AUTO takes the tuned or
+// default configuration of this shape.
 int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
                int64_t psa, const double* B, int64_t ldb, int64_t psb, int beta, double* C,
                int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
-               size_t ws_bytes, void* stream) {
+               size_t ws_bytes, void* stream, int tile) {
   g_msg[0] = 0;
   if (m < 0 || n < 0 || l < 0) return set_error(DDQD_E_ARG, "negative dimension");
   if (alpha != 1 && alpha != -1) return set_error(DDQD_E_ARG, "alpha must be +1 or -1");
   if (beta != 0 && beta != 1) return set_error(DDQD_E_ARG, "beta must be 0 or 1");
-  if (algo < 0 || algo > 3) return set_error(DDQD_E_ARG, "unknown algo %d", algo);
+  if (algo < 0 || algo > DDQD_AUTO) return set_error(DDQD_E_ARG, "unknown algo %d", algo);
+  if (tile != 0 && tile != 32 && tile != 64) return set_error(DDQD_E_ARG, "tile must be 32 or 64");
   if (levels < 0 || levels > kMaxLevels)
     return set_error(DDQD_E_ARG, "levels must be in 0..%d", kMaxLevels);
   if (base != DDQD_BASE_FMA && base != DDQD_BASE_OZAKI_I8)
@@ -342,6 +357,8 @@ int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* 
                      ws_bytes);
   if (need > 0 && (uintptr_t)ws % 8) return set_error(DDQD_E_WORKSPACE, "workspace misaligned");
   if ((rc = device_ok())) return rc;
+  if (algo == DDQD_AUTO) auto_choice(P, m, n, l, base, slices, &algo, &levels, &tile);
+  if (tile == 0) tile = 64;
   hipStream_t s = (hipStream_t)stream;
   GemmBatch top{m, n, l, alpha, beta, CMat{A, lda, psa, 0}, CMat{B, ldb, psb, 0},
                 Mat{C, ldc, psc, 0}, 1};
@@ -350,10 +367,8 @@ int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* 
     top.B = CMat{C, ldc, psc, 0};
     return block_fma(P, top, s);
   }
-  return run_gemm(P, top, algo, levels, base, slices, ws, ws_bytes, s);
+  return run_gemm(P, top, algo, levels, base, slices, ws, ws_bytes, s, tile);
 }
-
-}  // namespace
 
 // Internal entry points for other drivers (LU): no validation, no alias checks.
 int gemm_internal(int P, const GemmBatch& g, int algo, int levels, int base, int slices,
@@ -511,7 +526,7 @@ int dd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t
             int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
             size_t ws_bytes, void* stream) {
   return gemm_entry(2, m, n, l, alpha, A, lda, psa, B, ldb, psb, beta, C, ldc, psc, algo,
-                    levels, base, slices, ws, ws_bytes, stream);
+                    levels, base, slices, ws, ws_bytes, stream, 0);
 }
 
 int qd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
@@ -519,7 +534,7 @@ int qd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t
             int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
             size_t ws_bytes, void* stream) {
   return gemm_entry(4, m, n, l, alpha, A, lda, psa, B, ldb, psb, beta, C, ldc, psc, algo,
-                    levels, base, slices, ws, ws_bytes, stream);
+                    levels, base, slices, ws, ws_bytes, stream, 0);
 }
 
 }  // extern "C"

@@ -5,7 +5,10 @@
 // a 4x4 register micro-tile.  K advances in steps of 16: the hi and lo planes
 // of the A tile (stored k-major, so a thread reads its 4 rows with two 16-byte
 // LDS reads per plane) and of the B tile are double-buffered in LDS while the
-// next step is prefetched into registers.
+// next step is prefetched into registers.  A 32x32 tile (2x2 per thread)
+// gives small products four times as many workgroups; every entry of C sees
+// the same operations in the same order with either tile, so the two results
+// are bit-identical.
 //
 // Per multiply-add (a_h + a_l)(b_h + b_l) the kernel forms the product's
 // leading part p = fl(a_h b_h) and its tail q = err(a_h b_h) + a_h b_l +
@@ -23,9 +26,8 @@ namespace ddqd {
 
 namespace {
 
-constexpr int kBM = 64, kBN = 64, kBK = 16, kTM = 4, kTN = 4;
-constexpr int kThreads = (kBM / kTM) * (kBN / kTN);  // 256
-constexpr int kPad = 2;                               // keeps 16-byte rows, spreads banks
+constexpr int kBK = 16, kThreads = 256;
+constexpr int kPad = 2;  // keeps 16-byte rows, spreads banks
 
 __device__ __forceinline__ void dd_mac(double& s, double& e, double ah, double al, double bh,
                                        double bl) {
@@ -40,14 +42,18 @@ __device__ __forceinline__ void dd_mac(double& s, double& e, double ah, double a
   e = e + (err + q);
 }
 
-typedef double TileBuf[2][2][kBK][kBM + kPad];
+template <int BM>
+using TileBuf = double[2][2][kBK][BM + kPad];
 
-// One 64x64 tile (tm, tn) of problem b of the batch g.  Shared by the
+// One BM x BM tile (tm, tn) of problem b of the batch g.  Shared by the
 // batched and the grouped kernels, so a product computed inside a group is
 // bit-identical to the same product launched on its own.
+template <int BM>
 __device__ __forceinline__ void dd_block_tile(const GemmBatch& g, int64_t b, int64_t tm,
-                                              int64_t tn, TileBuf& As, TileBuf& Bs) {
-  const int64_t row0 = tm * kBM, col0 = tn * kBN;
+                                              int64_t tn, TileBuf<BM>& As, TileBuf<BM>& Bs) {
+  constexpr int kBN = BM, kTM = BM / 16, kTN = BM / 16;
+  static_assert((BM / kTM) * (kBN / kTN) == kThreads, "16 x 16 threads per tile");
+  const int64_t row0 = tm * BM, col0 = tn * kBN;
 
   const double* Ab = g.A.p + b * g.A.bstride;
   const double* Bb = g.B.p + b * g.B.bstride;
@@ -73,7 +79,7 @@ __device__ __forceinline__ void dd_block_tile(const GemmBatch& g, int64_t b, int
     }
 
   // global -> register staging: 4 elements per plane per operand per thread
-  constexpr int kPer = kBM * kBK / kThreads;  // 4
+  constexpr int kPer = BM * kBK / kThreads;  // 4 (64x64) or 2 (32x32)
   double ra[2][kPer], rb[2][kPer];
   auto load_tiles = [&](int64_t k0) {
 #pragma unroll
@@ -163,12 +169,13 @@ __device__ __forceinline__ void dd_block_tile(const GemmBatch& g, int64_t b, int
     }
 }
 
+template <int BM>
 __global__ __launch_bounds__(kThreads) void dd_gemm_block_kernel(GemmBatch g, int64_t tiles_m,
                                                                  int64_t tiles_n) {
-  __shared__ __attribute__((aligned(16))) TileBuf As, Bs;
+  __shared__ __attribute__((aligned(16))) TileBuf<BM> As, Bs;
   const int64_t t = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
   const int64_t per = tiles_m * tiles_n;
-  dd_block_tile(g, t / per, (t % per) / tiles_n, (t % per) % tiles_n, As, Bs);
+  dd_block_tile<BM>(g, t / per, (t % per) / tiles_n, (t % per) % tiles_n, As, Bs);
 }
 
 // Grouped: up to kMaxGroup unrelated problems of any shapes in one
@@ -176,13 +183,13 @@ __global__ __launch_bounds__(kThreads) void dd_gemm_block_kernel(GemmBatch g, in
 // the concatenated tile list (a fixed order: results do not depend on the
 // grid size or on the other problems).
 __global__ __launch_bounds__(kThreads) void dd_gemm_grouped_kernel(GroupArgs ga) {
-  __shared__ __attribute__((aligned(16))) TileBuf As, Bs;
+  __shared__ __attribute__((aligned(16))) TileBuf<64> As, Bs;
   for (int64_t t = blockIdx.x; t < ga.start[ga.count]; t += gridDim.x) {
     int p = 0;
     while (t >= ga.start[p + 1]) p++;
     const int64_t r = t - ga.start[p];
-    const int64_t tn_count = (ga.g[p].n + kBN - 1) / kBN;
-    dd_block_tile(ga.g[p], 0, r / tn_count, r % tn_count, As, Bs);
+    const int64_t tn_count = (ga.g[p].n + 63) / 64;
+    dd_block_tile<64>(ga.g[p], 0, r / tn_count, r % tn_count, As, Bs);
     __syncthreads();
   }
 }
@@ -211,21 +218,26 @@ __global__ __launch_bounds__(256) void dd_gemm_simple_kernel(GemmBatch g) {
 
 }  // namespace
 
-int launch_dd_block(const GemmBatch& g, hipStream_t stream) {
+int launch_dd_block(const GemmBatch& g, int tile, hipStream_t stream) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return 0;
-  int64_t tm = (g.m + kBM - 1) / kBM, tn = (g.n + kBN - 1) / kBN;
+  if (tile != 64 && tile != 32) return set_error(1 /*DDQD_E_ARG*/, "tile must be 64 or 32");
+  int64_t tm = (g.m + tile - 1) / tile, tn = (g.n + tile - 1) / tile;
   int64_t nblk = tm * tn * g.batch;
   if (nblk > INT32_MAX) return set_error(4 /*DDQD_E_UNSUPPORTED*/, "grid too large");
   prof_begin(stream);
-  hipLaunchKernelGGL(dd_gemm_block_kernel, dim3((unsigned)nblk), dim3(kThreads), 0, stream, g,
-                     tm, tn);
-  prof_record("dd_gemm_block_kernel", stream);
+  if (tile == 64) {
+    hipLaunchKernelGGL(dd_gemm_block_kernel<64>, dim3((unsigned)nblk), dim3(kThreads), 0, stream,
+                       g, tm, tn);
+    prof_record("dd_gemm_block_kernel", stream);
+  } else {
+    hipLaunchKernelGGL(dd_gemm_block_kernel<32>, dim3((unsigned)nblk), dim3(kThreads), 0, stream,
+                       g, tm, tn);
+    prof_record("dd_gemm_block_kernel<32>", stream);
+  }
   return check_launch("dd_gemm_block_kernel");
 }
 
-int64_t dd_block_tiles(int64_t m, int64_t n) {
-  return ((m + kBM - 1) / kBM) * ((n + kBN - 1) / kBN);
-}
+int64_t dd_block_tiles(int64_t m, int64_t n) { return ((m + 63) / 64) * ((n + 63) / 64); }
 
 int launch_dd_grouped(const GroupArgs& ga, int grid, hipStream_t stream) {
   if (ga.count <= 0 || ga.start[ga.count] <= 0) return 0;

@@ -20,7 +20,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libddqd.so")
 
-ALGO = {"simple": 0, "block": 1, "strassen": 2, "winograd": 3}
+ALGO = {"simple": 0, "block": 1, "strassen": 2, "winograd": 3, "auto": 4}
+ALGO_NAME = {v: k for k, v in ALGO.items()}
 BASE = {"fma": 0, "ozaki": 1}
 PIVOT = {"none": 0, "partial": 1}
 
@@ -70,6 +71,23 @@ _lib.ddqd_status_string.argtypes = [_int]
 _lib.ddqd_status_string.restype = ctypes.c_char_p
 _lib.ddqd_last_error.argtypes = []
 _lib.ddqd_last_error.restype = ctypes.c_char_p
+
+
+class TuneResult(ctypes.Structure):
+    """ddqd_tune_result of include/ddqd.h."""
+    _fields_ = [("algo", _int), ("levels", _int), ("tile", _int), ("candidates", _int),
+                ("ms", ctypes.c_double)]
+
+
+for _name in ("dd_gemm_tune", "qd_gemm_tune"):
+    getattr(_lib, _name).argtypes = [_i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _i64, _vp,
+                                     _i64, _i64, _int, _int, _int, _vp, _sz, _vp,
+                                     ctypes.POINTER(TuneResult)]
+    getattr(_lib, _name).restype = _int
+_lib.ddqd_tune_lookup.argtypes = [_int, _i64, _i64, _i64, _int, _int, ctypes.POINTER(TuneResult)]
+_lib.ddqd_tune_lookup.restype = _int
+_lib.ddqd_tune_clear.argtypes = []
+_lib.ddqd_tune_clear.restype = None
 _lib.ddqd_graph_begin.argtypes = [_vp]
 _lib.ddqd_graph_begin.restype = _int
 _lib.ddqd_graph_end.argtypes = [_vp, ctypes.POINTER(_vp)]
@@ -291,3 +309,43 @@ def capture(fn, stream):
         st = _lib.ddqd_graph_end(s, ctypes.byref(h))
     _check(st, "ddqd_graph_end")
     return Graph(h.value)
+
+
+def _tune_dict(r: TuneResult):
+    return dict(algo=ALGO_NAME[r.algo], levels=r.levels, tile=r.tile, candidates=r.candidates,
+                ms=r.ms)
+
+
+def tune(A, B, C=None, *, base="fma", slices=0, reps=3, ws=None):
+    """Times the candidate configurations of this product shape (dd_gemm_tune /
+    qd_gemm_tune by the number of planes) and caches the fastest for
+    algo="auto"; C receives A B.  Returns the chosen configuration."""
+    P = A.shape[0]
+    if P not in (2, 4):
+        raise ValueError("A must have 2 (DD) or 4 (QD) planes")
+    m, l, n = A.shape[1], A.shape[2], B.shape[2]
+    if C is None:
+        C = torch.empty((P, m, n), dtype=torch.float64, device=A.device)
+    pa, lda, psa = _mat(A, P, "A")
+    pb, ldb, psb = _mat(B, P, "B")
+    pc, ldc, psc = _mat(C, P, "C")
+    need = gemm_workspace(P, m, n, l, "auto", 0, base, slices)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    r = TuneResult()
+    fn = _lib.dd_gemm_tune if P == 2 else _lib.qd_gemm_tune
+    _check(fn(m, n, l, pa, lda, psa, pb, ldb, psb, pc, ldc, psc, BASE[base], slices, reps,
+              ws.data_ptr(), ws.numel(), _stream_of(C), ctypes.byref(r)), "gemm_tune")
+    return _tune_dict(r)
+
+
+def tune_lookup(P: int, m: int, n: int, l: int, base="fma", slices=0):
+    """The configuration algo="auto" uses for this shape."""
+    r = TuneResult()
+    _check(_lib.ddqd_tune_lookup(P, m, n, l, BASE[base], slices, ctypes.byref(r)),
+           "ddqd_tune_lookup")
+    return _tune_dict(r)
+
+
+def tune_clear() -> None:
+    _lib.ddqd_tune_clear()

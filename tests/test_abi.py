@@ -161,3 +161,34 @@ def test_graph_argument_errors(lib):
     assert lib.ddqd_graph_end(C.c_void_p(0x1000), None) == E["ARG"]
     assert lib.ddqd_graph_launch(None, None) == E["ARG"]
     assert lib.ddqd_graph_destroy(None) == E["OK"]
+
+
+def test_tune_defaults_and_errors(lib):
+    from paper_1510_08642_amd import ddqd
+    ddqd.tune_clear()
+    d = ddqd.tune_lookup(2, 1024, 1024, 1024)
+    assert (d["algo"], d["levels"], d["tile"], d["candidates"]) == ("block", 0, 64, 0)
+    assert ddqd.tune_lookup(2, 100, 100, 100)["tile"] == 32        # 64x64 tiles would idle CUs
+    assert ddqd.tune_lookup(2, 100, 100, 100, base="ozaki")["tile"] == 0
+    q = ddqd.tune_lookup(4, 1024, 1024, 1024)
+    assert (q["algo"], q["levels"]) == ("winograd", 3)
+    assert ddqd.tune_lookup(4, 200, 200, 200)["algo"] == "block"
+    import ctypes as C
+    r = ddqd.TuneResult()
+    assert lib.ddqd_tune_lookup(3, 8, 8, 8, 0, 0, C.byref(r)) == E["ARG"]
+    assert lib.ddqd_tune_lookup(4, 8, 8, 8, 1, 0, C.byref(r)) == E["ARG"]
+    assert lib.ddqd_tune_lookup(2, 8, 8, 8, 0, 0, None) == E["ARG"]
+    # reps out of range is rejected before any device work
+    assert lib.dd_gemm_tune(8, 8, 8, 0x10000, 8, 64, 0x20000, 8, 64, 0x30000, 8, 64, 0, 0, 0,
+                            None, 0, None, None) == E["ARG"]
+
+
+def test_auto_workspace_covers_every_candidate(lib):
+    for P, f in ((2, lib.dd_gemm_workspace), (4, lib.qd_gemm_workspace)):
+        for (m, n, l) in [(1024, 1024, 1024), (300, 129, 257), (40, 40, 40)]:
+            auto = f(m, n, l, 4, 0, 0, 0)
+            for algo, levels in [(1, 0), (2, 1), (2, 2), (2, 3), (3, 1), (3, 2), (3, 3)]:
+                if min(m, n, l) >> levels >= 16 or levels == 0:
+                    assert auto >= f(m, n, l, algo, levels, 0, 0)
+    o = lib.dd_gemm_workspace(512, 512, 512, 4, 0, 1, 0)
+    assert o >= lib.dd_gemm_workspace(512, 512, 512, 3, 3, 1, 0)
