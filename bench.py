@@ -195,6 +195,111 @@ def bench_lu(dd, inputs, torch, dev, sizes, configs, stream):
     return out
 
 
+def bench_graphs(dd, inputs, torch, dev):
+    """Eager calls against a replay of the same calls recorded as a graph."""
+    out = {}
+    side = torch.cuda.Stream(dev)
+
+    def timed(fn, reps):
+        with torch.cuda.stream(side):
+            return time_steps(fn, reps, 2, side)
+
+    # small product (the 128 x 128 x 128 DD case): launch-bound
+    g = inputs.rng(5)
+    for m in (128, 512):
+        A = torch.from_numpy(inputs.dd_uniform(m, m, g)).to(dev)
+        B = torch.from_numpy(inputs.dd_uniform(m, m, g)).to(dev)
+        C = torch.empty((2, m, m), dtype=torch.float64, device=dev)
+        ws = torch.empty(max(1, dd.gemm_workspace(2, m, m, m, "winograd", 1, "fma")),
+                         dtype=torch.uint8, device=dev)
+
+        def f():
+            dd.dd_gemm(A, B, C, algo="winograd", levels=1, ws=ws)
+        gr = dd.capture(f, side)
+        e = timed(f, 50)
+        r = timed(lambda: gr.replay(side.cuda_stream), 50)
+        out[f"dd_gemm_winograd1_n{m}"] = {"eager_ms": round(e, 4), "graph_ms": round(r, 4)}
+        gr.release()
+    # LU factor + 1-RHS solve at n = 2048
+    n = 2048
+    kw = dict(panel=128, algo="winograd", levels=1, base="ozaki")
+    A0 = torch.from_numpy(inputs.dd_lu_matrix(n, inputs.rng(0))).to(dev)
+    b0 = torch.from_numpy(inputs.dd_uniform(n, 1, inputs.rng(1))).to(dev)
+    A, b = A0.clone(), b0.clone()
+    ws = torch.empty(max(1, dd.getrf_workspace(n, **kw)), dtype=torch.uint8, device=dev)
+    rws = torch.empty(max(1, dd.lib().dd_getrs_workspace(n, 1)), dtype=torch.uint8, device=dev)
+    piv = tuple(torch.empty(k, dtype=torch.int32, device=dev) for k in (n, n, 1))
+
+    def lu():
+        dd.dd_getrf(A, ws=ws, out=piv, **kw)
+        dd.dd_getrs(A, piv[0], b, perm=piv[1], ws=rws)
+    gr = dd.capture(lu, side)
+
+    def eager():
+        A.copy_(A0)
+        b.copy_(b0)
+        lu()
+
+    def replay():
+        A.copy_(A0)
+        b.copy_(b0)
+        gr.replay(side.cuda_stream)
+    out[f"dd_getrf_getrs_n{n}"] = {"eager_ms": round(timed(eager, 3), 3),
+                                    "graph_ms": round(timed(replay, 3), 3)}
+    gr.release()
+    log(f"graphs: {out}")
+    return out
+
+
+def bench_tuning(dd, inputs, torch, dev, n):
+    """Autotuned configuration per product kind at n (dd_gemm_tune / qd_gemm_tune)."""
+    out = {}
+    g = inputs.rng(7)
+    A = torch.from_numpy(inputs.dd_uniform(n, n, g)).to(dev)
+    B = torch.from_numpy(inputs.dd_uniform(n, n, g)).to(dev)
+    for base in ("fma", "ozaki"):
+        r = dd.tune(A, B, base=base, reps=3)
+        r["gflops"] = round(2.0 * n ** 3 / (r["ms"] * 1e-3) / 1e9, 1)
+        r["ms"] = round(r["ms"], 4)
+        out[f"dd_{base}_n{n}"] = r
+    Aq = torch.from_numpy(inputs.qd_uniform(n, n, g)).to(dev)
+    Bq = torch.from_numpy(inputs.qd_uniform(n, n, g)).to(dev)
+    r = dd.tune(Aq, Bq, reps=1)
+    r["gflops"] = round(2.0 * n ** 3 / (r["ms"] * 1e-3) / 1e9, 1)
+    r["ms"] = round(r["ms"], 4)
+    out[f"qd_fma_n{n}"] = r
+    log(f"tuning: {out}")
+    return out
+
+
+def bench_equal_accuracy(dd, inputs, torch, dev, n, stream):
+    """Ozaki slice counts against the FMA form: error on sampled entries
+    (exact reference from the oracle) and time, so that the two forms can be
+    compared at equal accuracy."""
+    g = inputs.rng(11)
+    A = torch.from_numpy(inputs.dd_uniform(n, n, g)).to(dev)
+    B = torch.from_numpy(inputs.dd_uniform(n, n, g)).to(dev)
+    C = torch.empty((2, n, n), dtype=torch.float64, device=dev)
+    Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
+    out = {}
+    for base, S in [("fma", 0), ("ozaki", 12), ("ozaki", 13), ("ozaki", 14), ("ozaki", 15),
+                    ("ozaki", 16)]:
+        ws = torch.empty(max(1, dd.gemm_workspace(2, n, n, n, "block", 0, base, S)),
+                         dtype=torch.uint8, device=dev)
+
+        def f():
+            dd.dd_gemm(A, B, C, algo="block", base=base, slices=S, ws=ws)
+        t = time_steps(f, 10, 2, stream)
+        f()
+        torch.cuda.synchronize()
+        err = sampled_error(Ah, Bh, C.cpu().numpy(), n)
+        out[f"{base}{S or ''}"] = {"ms": round(t, 4),
+                                   "gflops": round(2.0 * n ** 3 / (t * 1e-3) / 1e9, 1),
+                                   "error_rownorm": err}
+    log(f"equal accuracy: {out}")
+    return out
+
+
 def bench_serving(nreq, seed=0):
     from paper_1510_08642_amd import inputs, serve
     pools = serve.DevicePools(nmax_gemm=1024, nmax_lu=2048, nrhs_max=16, seed=seed)
@@ -311,6 +416,28 @@ def main():
             log(f"variant qd {algo} L{lv}: {t:.3f} ms")
         del Aq, Bq, Cq
 
+    tuning = equal = None
+    if not args.no_variants:
+        tuning = bench_tuning(dd, inputs, torch, dev, n)
+        if not args.no_cpu:
+            equal = bench_equal_accuracy(dd, inputs, torch, dev, n, stream)
+        n2 = 2 * n
+        g2 = inputs.rng(3)
+        A2 = torch.from_numpy(inputs.dd_uniform(n2, n2, g2)).to(dev)
+        B2 = torch.from_numpy(inputs.dd_uniform(n2, n2, g2)).to(dev)
+        C2 = torch.empty((2, n2, n2), dtype=torch.float64, device=dev)
+        for (algo, lv, base) in [("block", 0, "fma"), ("block", 0, "ozaki"),
+                                 ("winograd", 1, "ozaki")]:
+            ws2 = torch.empty(max(1, dd.gemm_workspace(2, n2, n2, n2, algo, lv, base)),
+                              dtype=torch.uint8, device=dev)
+            t = time_steps(lambda: dd.dd_gemm(A2, B2, C2, algo=algo, levels=lv, base=base,
+                                              ws=ws2), 3, 1, stream)
+            variants[f"dd_{algo}{lv}_{base}_n{n2}"] = round(2.0 * n2 ** 3 / (t * 1e-3) / 1e9, 1)
+            log(f"variant dd {algo} L{lv} {base} n={n2}: {t:.3f} ms")
+        del A2, B2, C2
+
+    graphs = None if args.no_lu else bench_graphs(dd, inputs, torch, dev)
+
     lu = None
     if not args.no_lu:
         lu = bench_lu(dd, inputs, torch, dev, [2048, 4096],
@@ -344,6 +471,9 @@ def main():
         "error_rownorm": err,
         "roofline": roof,
         "variants_gflops": variants,
+        "tuned": tuning,
+        "ozaki_vs_fma_equal_accuracy": equal,
+        "graphs": graphs,
         "lu": lu,
         "serving": serving,
         "cpu_baseline": cpu,
