@@ -503,81 +503,133 @@ constexpr int kTB = 64;  // block size of the blocked triangular solves
 
 // Forward (lower, unit) or backward (upper) step for block I of X (n x nrhs,
 // nrhs <= 16).  Every workgroup solves the diagonal block redundantly (one
-// wave per right-hand side, lane = row, values shared by shuffles); the
-// workgroup of block I stores it, every other workgroup W updates its rows
-// X_W -= T_WI X_I with a lazily accumulated DD dot product.
+// wave per right-hand side, lane = row); the workgroup of block I stores it,
+// every other workgroup W updates its rows X_W -= T_WI X_I.  The diagonal
+// block, T_WI, X_I and X_W are all requested from memory before any of them
+// is used (one round trip), and staged in LDS.  In the solve, lane i keeps
+// x_i as an unrenormalised pair (s, r); step k renormalises x_k, broadcasts
+// it with readlane, and the other lanes subtract T_ik x_k (TwoSum of the high
+// product into s, low parts and TwoSum errors into r).  The backward solve
+// multiplies by the diagonal's DD reciprocals, formed by all lanes at once
+// before the sequential steps begin.
 // Lower: blocks W > I are blockIdx.x + 1 + I; upper: W = blockIdx.x - 1 ... .
 __global__ __launch_bounds__(1024) void trsv_block_kernel(const double* T, int64_t ldt,
                                                           int64_t pst, double* X, int64_t n,
                                                           int64_t nrhs, int64_t I, int upper) {
   __shared__ double Th[kTB][kTB + 1], Tl[kTB][kTB + 1];
-  __shared__ double Xh[kTB][16], Xl[kTB][16];
+  __shared__ double Wh[kTB][kTB + 1], Wl[kTB][kTB + 1];
+  __shared__ double Xh[kTB][17], Xl[kTB][17];
   const int64_t nb = (n + kTB - 1) / kTB;
   const int64_t Wb = upper ? (I - (int64_t)blockIdx.x) : (I + (int64_t)blockIdx.x);
   if (Wb < 0 || Wb >= nb) return;
-  const int64_t i0 = I * kTB, rows = n - i0 < kTB ? n - i0 : kTB;
+  const int64_t i0 = I * kTB, w0 = Wb * kTB;
+  const int rows = (int)(n - i0 < kTB ? n - i0 : kTB);
+  const int wrows = (int)(n - w0 < kTB ? n - w0 : kTB);
+  const bool upd = Wb != I;
   const int t = threadIdx.x, lane = t % 64, wave = t / 64;
+  const int nr = (int)nrhs;
   const int64_t psx = n * nrhs;
-  for (int e = t; e < kTB * kTB; e += 1024) {
-    const int i = e / kTB, k = e % kTB;
+  constexpr int kPer = kTB * kTB / 1024;  // 4 tile elements per thread
+  double dh[kPer], dl[kPer], oh[kPer], ol[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    const int e = t + 1024 * j, i = e / kTB, k = e % kTB;
     const bool in = i < rows && k < rows;
-    Th[i][k] = in ? T[(i0 + i) * ldt + i0 + k] : (i == k ? 1.0 : 0.0);
-    Tl[i][k] = in ? T[pst + (i0 + i) * ldt + i0 + k] : 0.0;
+    const int64_t o = (i0 + (in ? i : 0)) * ldt + i0 + (in ? k : 0);
+    dh[j] = T[o];
+    dl[j] = T[pst + o];
+    if (!in) {
+      dh[j] = i == k ? 1.0 : 0.0;
+      dl[j] = 0.0;
+    }
+    const bool win = upd && i < wrows && k < rows;
+    const int64_t ow = (w0 + (win ? i : 0)) * ldt + i0 + (win ? k : 0);
+    oh[j] = win ? T[ow] : 0.0;
+    ol[j] = win ? T[pst + ow] : 0.0;
   }
-  for (int e = t; e < kTB * 16; e += 1024) {
-    const int i = e / 16, c = e % 16;
-    const bool in = i < rows && c < nrhs;
-    Xh[i][c] = in ? X[(i0 + i) * nrhs + c] : 0.0;
-    Xl[i][c] = in ? X[psx + (i0 + i) * nrhs + c] : 0.0;
+  // X_I (as staged) and this thread's entry of X_W
+  const int xi = t / 16, xc = t % 16;
+  const bool xin = xi < rows && xc < nr;
+  const double xih = xin ? X[(i0 + xi) * nrhs + xc] : 0.0;
+  const double xil = xin ? X[psx + (i0 + xi) * nrhs + xc] : 0.0;
+  const int ui = nr > 0 ? t / nr : 0, uc = nr > 0 ? t % nr : 0;
+  const bool uin = upd && t < wrows * nr;
+  const int64_t xo = (w0 + (uin ? ui : 0)) * nrhs + (uin ? uc : 0);
+  const double xwh = uin ? X[xo] : 0.0, xwl = uin ? X[psx + xo] : 0.0;
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    const int e = t + 1024 * j, i = e / kTB, k = e % kTB;
+    Th[i][k] = dh[j];
+    Tl[i][k] = dl[j];
+    Wh[i][k] = oh[j];
+    Wl[i][k] = ol[j];
   }
+  Xh[xi][xc] = xih;
+  Xl[xi][xc] = xil;
   __syncthreads();
-  if (wave < nrhs) {
-    dd_t x{Xh[lane][wave], Xl[lane][wave]};
+  if (wave < nr) {
+    double s = Xh[lane][wave], r = Xl[lane][wave];
     if (!upper) {
-      for (int k = 0; k < kTB; k++) {
-        dd_t xk{__shfl(x.hi, k, 64), __shfl(x.lo, k, 64)};
-        if (lane > k) x = dd_sub(x, dd_mul(dd_t{Th[lane][k], Tl[lane][k]}, xk));
+      for (int k = 0; k < rows - 1; k++) {
+        double kh, kl;
+        two_sum(readlane_f64(s, k), readlane_f64(r, k), kh, kl);
+        if (lane > k && lane < rows) {
+          const double th = Th[lane][k], tl = Tl[lane][k];
+          const double p = th * kh;
+          const double pe = fma(th, kl, fma(tl, kh, fma(th, kh, -p)));
+          double e;
+          two_sum(s, -p, s, e);
+          r += e - pe;
+        }
       }
     } else {
-      for (int k = kTB - 1; k >= 0; k--) {
-        if (lane == k) x = dd_div(x, dd_t{Th[k][k], Tl[k][k]});
-        dd_t xk{__shfl(x.hi, k, 64), __shfl(x.lo, k, 64)};
-        if (lane < k) x = dd_sub(x, dd_mul(dd_t{Th[lane][k], Tl[lane][k]}, xk));
+      // reciprocals of the diagonal, all lanes at once
+      const dd_t inv = lane < rows ? dd_div(dd_t{1.0, 0.0}, dd_t{Th[lane][lane], Tl[lane][lane]})
+                                   : dd_t{0.0, 0.0};
+      for (int k = rows - 1; k >= 0; k--) {
+        dd_t xk;
+        two_sum(readlane_f64(s, k), readlane_f64(r, k), xk.hi, xk.lo);
+        xk = dd_mul(xk, dd_t{readlane_f64(inv.hi, k), readlane_f64(inv.lo, k)});
+        if (lane == k) {
+          s = xk.hi;
+          r = xk.lo;
+        } else if (lane < k) {
+          const double th = Th[lane][k], tl = Tl[lane][k];
+          const double p = th * xk.hi;
+          const double pe = fma(th, xk.lo, fma(tl, xk.hi, fma(th, xk.hi, -p)));
+          double e;
+          two_sum(s, -p, s, e);
+          r += e - pe;
+        }
       }
     }
-    Xh[lane][wave] = x.hi;
-    Xl[lane][wave] = x.lo;
+    double h, l;
+    two_sum(s, r, h, l);
+    Xh[lane][wave] = h;
+    Xl[lane][wave] = l;
   }
   __syncthreads();
-  if (Wb == I) {
-    for (int e = t; e < rows * nrhs; e += 1024) {
-      const int i = e / (int)nrhs, c = e % (int)nrhs;
-      X[(i0 + i) * nrhs + c] = Xh[i][c];
-      X[psx + (i0 + i) * nrhs + c] = Xl[i][c];
+  if (!upd) {
+    if (xin) {
+      X[(i0 + xi) * nrhs + xc] = Xh[xi][xc];
+      X[psx + (i0 + xi) * nrhs + xc] = Xl[xi][xc];
     }
     return;
   }
-  // update rows of block Wb: X_W -= T_W,I X_I
-  const int64_t w0 = Wb * kTB, wrows = n - w0 < kTB ? n - w0 : kTB;
-  for (int e = t; e < wrows * nrhs; e += 1024) {
-    const int i = e / (int)nrhs, c = e % (int)nrhs;
+  // update rows of block Wb: X_W -= T_W,I X_I (one thread per entry)
+  if (uin) {
     double s = 0.0, err = 0.0;
     for (int k = 0; k < rows; k++) {
-      const int64_t o = (w0 + i) * ldt + i0 + k;
-      const double ah = T[o], al = T[pst + o], bh = Xh[k][c], bl = Xl[k][c];
-      double p = ah * bh;
-      double q = __builtin_fma(ah, bh, -p);
-      q = __builtin_fma(ah, bl, q);
-      q = __builtin_fma(al, bh, q);
-      double sn, e2;
-      two_sum(s, p, sn, e2);
-      s = sn;
-      err = err + (e2 + q);
+      const double ah = Wh[ui][k], al = Wl[ui][k], bh = Xh[k][uc], bl = Xl[k][uc];
+      const double p = ah * bh;
+      const double q = fma(ah, bl, fma(al, bh, fma(ah, bh, -p)));
+      double e2;
+      two_sum(s, p, s, e2);
+      err += e2 + q;
     }
     dd_t d;
     two_sum(s, err, d.hi, d.lo);
-    const int64_t xo = (w0 + i) * nrhs + c;
-    dd_t x = dd_sub(dd_t{X[xo], X[psx + xo]}, d);
+    const dd_t x = dd_sub(dd_t{xwh, xwl}, d);
     X[xo] = x.hi;
     X[psx + xo] = x.lo;
   }

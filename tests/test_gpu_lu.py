@@ -9,7 +9,8 @@ Checked against the oracle and against structure:
   * exact cases: diagonal / upper triangular / integer L U / permutation;
   * solve: residual ||b - A x||_inf / (||A||_inf ||x||_inf) <= n 2^-100,
     formed exactly by the oracle; the paper's x = [0, 1, ..., n-1] is
-    recovered to n 2^-96 relative.
+    recovered with a normwise forward error within 32 times the oracle's
+    (forward error grows with cond(A), the residual does not).
 """
 import numpy as np
 import pytest
@@ -126,12 +127,20 @@ def test_solve_residual_and_paper_solution(dd, n, nrhs, use_perm):
     B = inputs.dd_uniform(n, nrhs, g)
     X = solve(dd, LU, ipiv, B, perm if use_perm else None)
     assert oracle.lu_residual(A, X, B) <= n * 2.0 ** -100
-    # the paper's test solution x = [0, 1, ..., n-1], b := A x formed exactly
+    # the paper's test solution x = [0, 1, ..., n-1], b := A x formed exactly.
+    # Its forward error scales with cond(A) (about 1e4 for these unboosted
+    # N(0,1) matrices), so it is bounded against the oracle's own forward
+    # error on the same problem (same DD arithmetic, its own factors).
     x = ddm(np.arange(n, dtype=np.float64)[:, None])
     b = oracle.exact_entries(A, x, np.arange(n), np.zeros(n, dtype=np.int64), kout=2)
-    xs = solve(dd, LU, ipiv, b.reshape(2, n, 1), perm if use_perm else None)
-    rel = np.abs((xs[0, 1:, 0] - np.arange(1, n)) + xs[1, 1:, 0]) / np.arange(1, n)
-    assert np.max(rel) <= n * 2.0 ** -96
+    b = b.reshape(2, n, 1)
+    xs = solve(dd, LU, ipiv, b, perm if use_perm else None)
+    LUo, ipo, _ = oracle.getrf(A, panel=32, pivot=True, algo="block", levels=0)
+    xo = oracle.getrs(LUo, ipo, b)
+
+    def fwd(X):
+        return np.max(np.abs((X[0, :, 0] - np.arange(n)) + X[1, :, 0])) / (n - 1)
+    assert fwd(xs) <= 32 * fwd(xo) + n * 2.0 ** -106
 
 
 def test_solution_matches_oracle_solve(dd):
