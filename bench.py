@@ -125,27 +125,45 @@ def roofline(dd, args, n, step, steps):
                     "fma counting one); peak = 256 CU x 2.4 GHz x 64 lanes"}
 
 
-def cpu_baseline(n: int, budget_s: float = 20.0):
-    """The oracle's Block DD product on a row sample of the n x n workload."""
+def cpu_baseline(n: int, budget_s: float = 10.0):
+    """The oracle's Block DD product of the n x n workload, repeated on all
+    host threads for about budget_s seconds; plus one thread on a row sample."""
     import oracle
     from paper_1510_08642_amd import inputs
     g = inputs.rng(0)
     A = inputs.dd_uniform(n, n, g)
     B = inputs.dd_uniform(n, n, g)
-    cores = len(os.sched_getaffinity(0))
+    threads = oracle.num_threads()
+    reps, t = 0, 0.0
+    while t < budget_s or reps == 0:
+        t0 = time.perf_counter()
+        oracle.gemm(A, B, "block")
+        t += time.perf_counter() - t0
+        reps += 1
+    gf = 2.0 * n ** 3 * reps / t / 1e9
     rows = 64
-    t0 = time.perf_counter()
-    oracle.gemm(A[:, :rows], B, "block")
-    t = time.perf_counter() - t0
-    rows2 = int(min(n, max(rows, rows * budget_s / max(t, 1e-3) / 2)))
-    rows2 = max(64, rows2 // 64 * 64)
-    t0 = time.perf_counter()
-    oracle.gemm(A[:, :rows2], B, "block")
-    t = time.perf_counter() - t0
-    gf = 2.0 * rows2 * n * n / t / 1e9
-    return {"value": round(gf, 4), "unit": "GFLOPS", "cores": cores, "kind": "oracle",
-            "sample": f"oracle Block DD product of the first {rows2} rows of A (n={n}) by B, "
-                      f"{t:.2f} s on {cores} threads (OpenMP over row blocks)"}
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.gemm(A[:, :rows], B, "block")
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    gf1 = 2.0 * rows * n * n / t1 / 1e9
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": round(gf, 4), "unit": "GFLOPS", "cores": threads, "kind": "oracle",
+            "sample": f"oracle Block DD product of the whole n={n} workload, {reps} times in "
+                      f"{t:.1f} s on {threads} OpenMP threads ({model}); one thread on the "
+                      f"first {rows} rows: {gf1:.3f} GFLOPS",
+            "one_thread_gflops": round(gf1, 4), "cpu_model": model}
 
 
 def sampled_error(A, B, C, n, count=64):

@@ -68,6 +68,10 @@ def lib():
         L.or_getrf.restype = c_int
         L.or_getrs.argtypes = [i64, i64, _D, _I32, _D]
         L.or_getrs.restype = c_int
+        L.or_num_threads.argtypes = []
+        L.or_num_threads.restype = c_int
+        L.or_set_threads.argtypes = [c_int]
+        L.or_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -227,3 +231,12 @@ def lu_residual(A: np.ndarray, X: np.ndarray, B: np.ndarray) -> float:
     normA = np.max(np.sum(np.abs(A[0]), axis=1))
     normx = np.max(np.abs(X[0]), axis=0)
     return float(np.max(np.max(np.abs(r), axis=0) / (normA * normx)))
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return lib().or_num_threads()
+
+
+def set_threads(t: int) -> None:
+    lib().or_set_threads(t)

@@ -316,3 +316,8 @@ void or_product_numbers(int P, int algo, int levels, int bs, int64_t m, int64_t 
     mat a = {A, lda}, b = {B, ldb}, c = {C, ldc};
     product_top(&ar, algo, levels, bs, m, n, l, a, b, c);
 }
+
+/* Host thread control for timing the oracle (no arithmetic). */
+#include <omp.h>
+int or_num_threads(void) { return omp_get_max_threads(); }
+void or_set_threads(int t) { if (t > 0) omp_set_num_threads(t); }
