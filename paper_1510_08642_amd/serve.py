@@ -91,94 +91,231 @@ class Server:
     def _batchable(self, r: Request) -> bool:
         return r.kind == "gemm" and r.n <= self.small_n and self.ex.can_group
 
+    # -- the loop's state and one scheduling pass (shared with OnlineServer) --
+    def _reset(self):
+        self._queue: collections.deque = collections.deque()
+        self._inflight = []                 # (handle, batch, bytes, slot)
+        self._free_slots = list(range(self.slots))
+        self._free_bytes = self.budget
+        self._max_used = 0
+        self._batches = 0
+
+    def _step(self, now: float, on_done: Optional[Callable[[list], None]] = None) -> bool:
+        """Completes finished batches, then admits waiting requests oldest
+        first while a slot and enough of the budget are free.  Returns whether
+        anything changed.  on_done(batch) is called for every finished or
+        failed request list."""
+        progressed = False
+        for item in list(self._inflight):
+            h, batch, nbytes, slot = item
+            if self.ex.done(h):
+                t_done = self.ex.finish(h, batch)
+                for r in batch:
+                    r.t_done = t_done if t_done is not None else now
+                self._inflight.remove(item)
+                self._free_bytes += nbytes
+                self._free_slots.append(slot)
+                progressed = True
+                if on_done:
+                    on_done(batch)
+        queue = self._queue
+        while queue and self._free_slots:
+            head = queue[0]
+            fp = self.ex.footprint(head)
+            if fp > self.budget:
+                queue.popleft()
+                head.error = f"footprint {fp} exceeds the budget {self.budget}"
+                progressed = True
+                if on_done:
+                    on_done([head])
+                continue
+            if fp > self._free_bytes:
+                break                           # back-pressure: FIFO, the head waits
+            batch = [queue.popleft()]
+            used = fp
+            if self._batchable(head):
+                keep = collections.deque()
+                while queue and len(batch) < self.max_batch:
+                    r = queue.popleft()
+                    f = self.ex.footprint(r)
+                    if self._batchable(r) and used + f <= self._free_bytes:
+                        batch.append(r)
+                        used += f
+                    else:
+                        keep.append(r)
+                queue.extendleft(reversed(keep))
+            slot = self._free_slots.pop()
+            for r in batch:
+                r.t_admit = now
+                r.batch_size = len(batch)
+            try:
+                h = self.ex.launch(batch, slot)
+            except Exception as exc:           # the batch fails, the loop goes on
+                for r in batch:
+                    r.error = f"{type(exc).__name__}: {exc}"
+                    r.t_done = now
+                self._free_slots.append(slot)
+                progressed = True
+                if on_done:
+                    on_done(batch)
+                continue
+            self._free_bytes -= used
+            self._max_used = max(self._max_used, self.budget - self._free_bytes)
+            self._inflight.append((h, batch, used, slot))
+            self._batches += 1
+            progressed = True
+        return progressed
+
     def run(self, requests, clock: Callable[[], float] = time.perf_counter) -> Stats:
+        """Replays a trace: each request joins the queue at its t_arrive."""
         reqs = sorted(requests, key=lambda r: r.t_arrive)
         pending = collections.deque(reqs)
-        queue: collections.deque = collections.deque()
-        inflight = []                      # (handle, batch, bytes, slot)
-        free_slots = list(range(self.slots))
-        free_bytes = self.budget
-        max_used = 0
-        batches = 0
+        self._reset()
         self.ex.start()
         t0 = clock()
-        while pending or queue or inflight:
+        while pending or self._queue or self._inflight:
             now = clock() - t0
             while pending and pending[0].t_arrive <= now:
-                queue.append(pending.popleft())
-            progressed = False
-            # completions free their slot and memory
-            for item in list(inflight):
-                h, batch, nbytes, slot = item
-                if self.ex.done(h):
-                    t_done = self.ex.finish(h, batch)
-                    for r in batch:
-                        r.t_done = t_done if t_done is not None else clock() - t0
-                    inflight.remove(item)
-                    free_bytes += nbytes
-                    free_slots.append(slot)
-                    progressed = True
-            # admissions: oldest first; a request that does not fit waits
-            while queue and free_slots:
-                head = queue[0]
-                fp = self.ex.footprint(head)
-                if fp > self.budget:
-                    queue.popleft()
-                    head.error = f"footprint {fp} exceeds the budget {self.budget}"
-                    progressed = True
-                    continue
-                if fp > free_bytes:
-                    break
-                batch = [queue.popleft()]
-                used = fp
-                if self._batchable(head):
-                    keep = collections.deque()
-                    while queue and len(batch) < self.max_batch:
-                        r = queue.popleft()
-                        f = self.ex.footprint(r)
-                        if self._batchable(r) and used + f <= free_bytes:
-                            batch.append(r)
-                            used += f
-                        else:
-                            keep.append(r)
-                    queue.extendleft(reversed(keep))
-                slot = free_slots.pop()
-                t_admit = clock() - t0
-                for r in batch:
-                    r.t_admit = t_admit
-                    r.batch_size = len(batch)
-                try:
-                    h = self.ex.launch(batch, slot)
-                except Exception as exc:           # the batch fails, the loop goes on
-                    for r in batch:
-                        r.error = f"{type(exc).__name__}: {exc}"
-                        r.t_done = clock() - t0
-                    free_slots.append(slot)
-                    progressed = True
-                    continue
-                free_bytes -= used
-                max_used = max(max_used, self.budget - free_bytes)
-                inflight.append((h, batch, used, slot))
-                batches += 1
-                progressed = True
+                self._queue.append(pending.popleft())
+            progressed = self._step(clock() - t0)
             if not progressed:
                 if self.poll_sleep_s:
                     time.sleep(self.poll_sleep_s)
-                elif not inflight and pending and not queue:
+                elif not self._inflight and pending and not self._queue:
                     # idle until the next arrival
                     wait = pending[0].t_arrive - (clock() - t0)
                     if wait > 0:
                         time.sleep(min(wait, 1e-3))
         wall = clock() - t0
         self.ex.stop()
-        done = [r for r in reqs if r.error is None and r.t_done is not None]
-        lat = np.array([r.latency for r in done]) * 1e3 if done else np.zeros(1)
-        flops = sum(request_flops(r) for r in done)
-        return Stats(completed=len(done), failed=len(reqs) - len(done), wall_s=wall,
-                     p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                     mean_ms=float(np.mean(lat)), throughput_rps=len(done) / wall if wall else 0.0,
-                     gflops=flops / wall / 1e9 if wall else 0.0, batches=batches,
-                     max_inflight_bytes=max_used)
+        return summarize(reqs, wall, self._batches, self._max_used)
+
+
+def summarize(reqs, wall: float, batches: int, max_used: int) -> Stats:
+    done = [r for r in reqs if r.error is None and r.t_done is not None]
+    lat = np.array([r.latency for r in done]) * 1e3 if done else np.zeros(1)
+    flops = sum(request_flops(r) for r in done)
+    return Stats(completed=len(done), failed=len(reqs) - len(done), wall_s=wall,
+                 p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                 mean_ms=float(np.mean(lat)), throughput_rps=len(done) / wall if wall else 0.0,
+                 gflops=flops / wall / 1e9 if wall else 0.0, batches=batches,
+                 max_inflight_bytes=max_used)
+
+
+class OnlineServer:
+    """Live front end of the same loop: requests are submitted from any
+    thread and answered through futures, while a scheduler thread admits,
+    batches and completes them.
+
+        srv = OnlineServer(GpuExecutor(slots=4), budget_bytes=1 << 30)
+        f = srv.submit_gemm(A, B)          # square DD (2, n, n) device tensors
+        g = srv.submit_lu_solve(A, B)      # A (2, n, n), B (2, n, nrhs)
+        C, X = f.result(), g.result()
+        h = srv.factorize(A); X2 = srv.solve(h, B2)   # resident factors
+        srv.close()                                   # finishes queued work
+    """
+
+    def __init__(self, executor, budget_bytes: int, slots: int = 4, small_n: int = 256,
+                 max_batch: int = 24, clock: Callable[[], float] = time.perf_counter,
+                 idle_sleep_s: float = 50e-6):
+        import concurrent.futures
+        import itertools
+        import queue
+        import threading
+        self._Future = concurrent.futures.Future
+        self.core = Server(executor, budget_bytes, slots, small_n, max_batch)
+        self.ex = executor
+        self.clock = clock
+        self.idle_sleep_s = idle_sleep_s
+        self._in = queue.SimpleQueue()
+        self._futs = {}
+        self._done_reqs = []
+        self._ids = itertools.count()
+        self._lock = threading.Lock()
+        self._stop = threading.Event()
+        self._keys = itertools.count()
+        self.core._reset()
+        self.ex.start()
+        self._t0 = clock()
+        self._thread = threading.Thread(target=self._loop, name="ddqd-serve", daemon=True)
+        self._thread.start()
+
+    def _submit(self, kind: str, n: int, nrhs: int, payload):
+        if self._stop.is_set():
+            raise RuntimeError("server is closed")
+        fut = self._Future()
+        r = Request(rid=next(self._ids), kind=kind, n=n, nrhs=nrhs, payload=payload)
+        with self._lock:
+            self._futs[r.rid] = (fut, r)
+        self._in.put(r)
+        return fut
+
+    def submit_gemm(self, A, B):
+        """C = A B (DD, square n x n operands); the future's result is C."""
+        n = A.shape[1]
+        if A.shape[0] != 2 or B.shape[0] != 2 or tuple(A.shape[1:]) != (n, n) or \
+                tuple(B.shape[1:]) != (n, n):
+            raise ValueError("submit_gemm takes square DD operands of one size")
+        return self._submit("gemm", n, 0, (A, B))
+
+    def submit_lu_solve(self, A, B):
+        """X = A^-1 B by LU with partial pivoting; the future's result is X."""
+        n = A.shape[1]
+        if A.shape[0] != 2 or tuple(A.shape[1:]) != (n, n) or B.shape[0] != 2 or \
+                B.shape[1] != n:
+            raise ValueError("submit_lu_solve takes A (2, n, n) and B (2, n, nrhs)")
+        return self._submit("lu", n, B.shape[2], (A, B))
+
+    def factorize(self, A):
+        """Factors A and keeps the factors on the device; returns a handle."""
+        return self.ex.factorize(A, ("resident", next(self._keys)))
+
+    def solve(self, handle, B):
+        return self.ex.solve(handle, B)
+
+    def release(self, handle):
+        self.ex.release(handle)
+
+    def stats(self) -> Stats:
+        with self._lock:
+            reqs = list(self._done_reqs)
+        return summarize(reqs, self.clock() - self._t0, self.core._batches, self.core._max_used)
+
+    def close(self, timeout: Optional[float] = None):
+        self._stop.set()
+        self._thread.join(timeout)
+        self.ex.stop()
+
+    def _complete(self, batch):
+        with self._lock:
+            for r in batch:
+                fut, _ = self._futs.pop(r.rid)
+                self._done_reqs.append(r)
+                r.payload = None
+                if r.error is not None:
+                    fut.set_exception(RuntimeError(r.error))
+                else:
+                    fut.set_result(r.result)
+
+    def _loop(self):
+        core = self.core
+        while True:
+            now = self.clock() - self._t0
+            got = False
+            while True:
+                try:
+                    r = self._in.get_nowait()
+                except Exception:
+                    break
+                r.t_arrive = now
+                core._queue.append(r)
+                got = True
+            progressed = core._step(self.clock() - self._t0, on_done=self._complete) or got
+            if self._stop.is_set() and not core._queue and not core._inflight and \
+                    self._in.empty():
+                return
+            if not progressed:
+                time.sleep(self.idle_sleep_s)
 
 
 class GpuExecutor:

@@ -84,3 +84,45 @@ def test_resident_factorization(env):
                                   to_host(B.contiguous())) <= 300 * 2.0 ** -100
     ex.release(key)
     assert "k" not in ex.factors
+
+
+def test_online_server_matches_direct_calls(env):
+    """Live submissions from two threads while earlier ones run; every
+    future's result is bit-identical to the same library calls made alone."""
+    import threading
+
+    import torch
+    serve, pools = env
+    from paper_1510_08642_amd import ddqd as dd
+    print("case online server", flush=True)
+    reqs = build(serve, pools, seed=13, count=40)
+    ex = serve.GpuExecutor(slots=3, base="fma", gemm_algo="winograd", gemm_levels=1)
+    srv = serve.OnlineServer(ex, budget_bytes=1 << 30, slots=3, small_n=256)
+    futs = [None] * len(reqs)
+
+    def submit(ks):
+        for k in ks:
+            A, B = reqs[k].payload
+            futs[k] = srv.submit_gemm(A, B) if reqs[k].kind == "gemm" else \
+                srv.submit_lu_solve(A, B)
+    th = [threading.Thread(target=submit, args=(range(j, len(reqs), 2),)) for j in (0, 1)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    got = [f.result(timeout=120) for f in futs]
+    srv.close(timeout=120)
+    torch.cuda.synchronize()
+    assert srv.stats().completed == len(reqs)
+    for r, x in zip(reqs, got):
+        A, B = r.payload
+        if r.kind == "gemm":
+            small = r.n <= 256
+            ref = dd.dd_gemm(A, B, algo="block" if small else "winograd", levels=0 if small else 1)
+        else:
+            LU = A.clone()
+            ipiv, perm, _ = dd.dd_getrf(LU, panel=min(128, r.n), algo="winograd", levels=1)
+            ref = B.clone()
+            dd.dd_getrs(LU, ipiv, ref, perm=perm)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(x), to_host(ref)), (r.rid, r.kind, r.n)

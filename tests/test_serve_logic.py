@@ -82,3 +82,59 @@ def test_results_flow_through_with_oracle_payloads():
     assert np.allclose(reqs[0].result[0], A[0] @ B[0])
     A, B = reqs[1].payload
     assert np.allclose(A[0] @ reqs[1].result[0], B[0])
+
+
+def test_online_server_futures_from_threads():
+    """The live front end: submissions from several threads, answers through
+    futures, equal to the oracle's direct results; an oversize request and an
+    injected failure fail only their own futures."""
+    import threading
+
+    import oracle
+    from paper_1510_08642_amd.serve import OnlineServer
+
+    clock = VirtualClock()
+    ex = FakeExecutor(clock, fail_rids={3})
+    srv = OnlineServer(ex, budget_bytes=10 ** 6, slots=2, small_n=0, clock=clock,
+                       idle_sleep_s=0.0)
+    g = inputs.rng(9)
+    jobs = [("gemm", inputs.dd_uniform(12, 12, g), inputs.dd_uniform(12, 12, g)),
+            ("lu", inputs.dd_lu_matrix(10, g), inputs.dd_uniform(10, 3, g)),
+            ("gemm", inputs.dd_uniform(7, 7, g), inputs.dd_uniform(7, 7, g)),
+            ("gemm", inputs.dd_uniform(5, 5, g), inputs.dd_uniform(5, 5, g)),
+            ("gemm", inputs.dd_uniform(9, 9, g), inputs.dd_uniform(9, 9, g))]
+    futs = [None] * len(jobs)
+
+    def submit(k):
+        kind, A, B = jobs[k]
+        futs[k] = srv.submit_gemm(A, B) if kind == "gemm" else srv.submit_lu_solve(A, B)
+    # request ids follow submission order; submit 0..2 from threads, then 3, 4
+    for k in range(3):
+        t = threading.Thread(target=submit, args=(k,))
+        t.start()
+        t.join()
+    submit(3)
+    submit(4)
+    big = srv.submit_gemm(np.zeros((2, 400, 400)), np.zeros((2, 400, 400)))
+    for k, (kind, A, B) in enumerate(jobs):
+        if k == 3:
+            try:
+                futs[k].result(timeout=30)
+                raise AssertionError("the injected failure must surface")
+            except RuntimeError as e:
+                assert "injected" in str(e)
+            continue
+        got = futs[k].result(timeout=30)
+        if kind == "gemm":
+            assert np.array_equal(got, oracle.gemm(A, B, "block"))
+        else:
+            LU, ipiv, _ = oracle.getrf(A, panel=8)
+            assert np.array_equal(got, oracle.getrs(LU, ipiv, B))
+    try:
+        big.result(timeout=30)
+        raise AssertionError("oversize request must fail")
+    except RuntimeError as e:
+        assert "budget" in str(e)
+    srv.close(timeout=30)
+    st = srv.stats()
+    assert st.completed == 4 and st.failed == 2
