@@ -221,13 +221,16 @@ __global__ __launch_bounds__(256) void oz_gemm_kernel(GemmBatch g, OzLayout o,
       w < 2 ? Asl + b * o.a_bytes + (2 * tm + w) * o.kb * S * (int64_t)kFrag
             : Bsl + b * o.b_bytes + (2 * tn + (w - 2)) * o.kb * S * (int64_t)kFrag;
   src += lane * 16;
+  // the wave index as a scalar, so LDS destinations are scalar arithmetic
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  auto stage_one = [&](int st, int64_t kb, int s) {
+    __builtin_amdgcn_global_load_lds(
+        (const void*)(src + (kb * S + s) * (int64_t)kFrag),
+        (__attribute__((address_space(3))) void*)&lds[st][wu * S + s][0], 16, 0, 0);
+  };
   auto stage = [&](int st, int64_t kb) {
-    const signed char* p = src + kb * S * (int64_t)kFrag;
 #pragma unroll
-    for (int s = 0; s < S; s++)
-      __builtin_amdgcn_global_load_lds((const void*)(p + s * (int64_t)kFrag),
-                                       (__attribute__((address_space(3))) void*)&lds[st][w * S + s][0],
-                                       16, 0, 0);
+    for (int s = 0; s < S; s++) stage_one(st, kb, s);
   };
 
   // this lane's 16 outputs: column cb*32 + lane % 32, rows 8 (q / 4) + 4 (lane / 32) + q % 4
@@ -261,21 +264,35 @@ __global__ __launch_bounds__(256) void oz_gemm_kernel(GemmBatch g, OzLayout o,
       // all waves have read buffer st (block kb) and block kb+1 has landed
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
-      if (kb + 2 < kc1) stage(st, kb + 2);
-      const bool more = kb + 1 < kc1;
+      // block kb+2 goes into buffer st, one slice after each MFMA of the
+      // first row, so the DMA issue hides behind the matrix cores.  Near the
+      // end the last block is loaded again (harmless: buffer st is not read
+      // before it is refilled), which keeps the MFMA stream free of branches.
+      const int64_t kn = kb + 2 < kc1 ? kb + 2 : kc1 - 1;
+      // The reloads are unconditional (after the last block they read a
+      // stale buffer and are never used), which keeps the MFMA stream free
+      // of branches.  A slice is reloaded one row after its last use, so the
+      // LDS write into its registers never waits on the MFMA still reading
+      // them: fa[ta] (last used by the final MFMA of row ta) after row ta+1,
+      // fbv[S-1-ta] (last used by the first MFMA of row ta) after row ta.
 #pragma unroll
       for (int ta = 0; ta < S; ta++) {
 #pragma unroll
-        for (int ub = S - 1 - ta; ub >= 0; ub--)
+        for (int ub = S - 1 - ta; ub >= 0; ub--) {
           acc[ta + ub] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[ta], fbv[ub], acc[ta + ub], 0,
                                                                0, 0);
-        if (more) {
-          fa[ta] = lds[st ^ 1][wr * S + ta][lane];
-          fbv[S - 1 - ta] = lds[st ^ 1][2 * S + wc * S + (S - 1 - ta)][lane];
+          if (ta == 0) {
+            stage_one(st, kn, S - 1 - ub);
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
+        if (ta > 0) fa[ta - 1] = lds[st ^ 1][wr * S + ta - 1][lane];
+        fbv[S - 1 - ta] = lds[st ^ 1][2 * S + wc * S + (S - 1 - ta)][lane];
         __builtin_amdgcn_sched_barrier(0);
       }
+      fa[S - 1] = lds[st ^ 1][wr * S + S - 1][lane];
     }
+    __builtin_amdgcn_s_waitcnt(0);  // the last blocks' loads land before LDS is released
     // recombine: value = 2^(e_i + f_j) sum_d 2^(-7 (d + 2)) P_d, d = 0..S-1,
     // four outputs at a time (scheduling barriers keep the temporaries of
     // only those four live).
