@@ -128,67 +128,82 @@ __global__ __launch_bounds__(256) void oz_col_exp_kernel(CMat B, int64_t l, int6
   }
 }
 
-// Slicing.  One thread per 4 consecutive k of one row of A or one column of
-// B (one 4-byte store per slice); both operands in one launch (blockIdx.y:
-// 0 = A, 1 = B).  A items run along k first (8 threads read a row's 32-k
-// block, 256 contiguous bytes), B items along the columns (coalesced rows of
-// B).  Digits of a scaled DD value r (|r| < 1/2): d_t = rint(2^7 r_{t-1}),
-// r_t = 2^7 r_{t-1} - d_t, formed exactly: the fractional part of the high
-// word is exact and is either 0 or at least ulp(high) >= 2 |low|, which is
-// FastTwoSum's precondition.
+// Slicing.  A workgroup takes 32 lines (rows of A or columns of B) by 128 k
+// (four 32-k blocks): the DD values are read with coalesced loads (along k
+// for A, along the columns for B) into an LDS tile, then each wave slices one
+// 32x32 block and each lane one fragment slot: 16 consecutive k of one line,
+// exactly what one lane of the 32x32x32 MFMA holds, so each slice is one
+// 16-byte store and a wave writes a whole 1 KB fragment.  Both operands in
+// one launch (blockIdx.y: 0 = A, 1 = B).  Digits of a scaled DD value r
+// (|r| < 1/2): d_t = rint(2^7 r_{t-1}), r_t = 2^7 r_{t-1} - d_t, formed
+// exactly: the fractional part of the high word is exact and is either 0 or
+// at least ulp(high) >= 2 |low|, FastTwoSum's precondition.
+constexpr int kSliceK = 128;  // k per slicing workgroup (four 32-k blocks)
+
 template <int S>
 __global__ __launch_bounds__(256) void oz_slice_kernel(CMat A, CMat B, int64_t m, int64_t n,
                                                        int64_t l, OzLayout o, const int* ea,
                                                        const int* fb, signed char* Asl,
                                                        signed char* Bsl) {
+  __shared__ double tile[2][32][kSliceK + 1];
   const int side = blockIdx.y;
   const int64_t b = blockIdx.z;
   const int64_t nblk32 = side == 0 ? o.rb : o.cb;
-  const int64_t lines = nblk32 * 32;
-  const int64_t items = lines * o.kb * 8;
-  const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (it >= items) return;
-  int64_t line, kb, g4;
-  if (side == 0) {
-    g4 = it % 8;
-    line = (it / 8) % lines;
-    kb = it / (8 * lines);
-  } else {
-    line = it % lines;
-    g4 = (it / lines) % 8;
-    kb = it / (8 * lines);
-  }
+  const int64_t kgroups = (o.kb + 3) / 4;
+  if ((int64_t)blockIdx.x >= nblk32 * kgroups) return;  // uniform per workgroup
+  const int64_t blk = blockIdx.x / kgroups, kg = blockIdx.x % kgroups;
+  const int64_t line0 = blk * 32, kbase = kg * kSliceK;
   const CMat X = side == 0 ? A : B;
-  const int ex = (side == 0 ? ea : fb)[b * lines + line];
+  const int64_t lines_live = side == 0 ? m : n;
   const double* base = X.p + b * X.bstride;
-  const bool live = line < (side == 0 ? m : n);
-  const int64_t k0 = kb * 32 + 4 * g4;
-  double rh[4], rl[4];
+  const int t = threadIdx.x;
+  // coalesced loads of the 32 x 128 tile (16 values per plane per thread)
+  double vh[16], vl[16];
 #pragma unroll
-  for (int q = 0; q < 4; q++) {
-    const int64_t k = k0 + q;
-    rh[q] = 0.0;
-    rl[q] = 0.0;
-    if (live && k < l) {
-      const int64_t idx = side == 0 ? line * X.ld + k : k * X.ld + line;
-      rh[q] = ldexp(base[idx], -ex);
-      rl[q] = ldexp(base[X.ps + idx], -ex);
-    }
+  for (int j = 0; j < 16; j++) {
+    const int e = t + 256 * j;
+    const int ln = side == 0 ? e / kSliceK : e % 32;
+    const int kk = side == 0 ? e % kSliceK : e / 32;
+    const int64_t line = line0 + ln, k = kbase + kk;
+    const bool in = line < lines_live && k < l;
+    const int64_t idx = side == 0 ? (in ? line * X.ld + k : 0) : (in ? k * X.ld + line : 0);
+    vh[j] = in ? base[idx] : 0.0;
+    vl[j] = in ? base[X.ps + idx] : 0.0;
   }
-  const int64_t lane = (line % 32) + 32 * (g4 / 4);
-  signed char* dst = (side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
-                     ((line / 32) * o.kb + kb) * S * (int64_t)kFrag + lane * 16 + 4 * (g4 % 4);
-#pragma unroll 4
-  for (int t = 0; t < S; t++) {
-    uint32_t x = 0;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
+  for (int j = 0; j < 16; j++) {
+    const int e = t + 256 * j;
+    const int ln = side == 0 ? e / kSliceK : e % 32;
+    const int kk = side == 0 ? e % kSliceK : e / 32;
+    tile[0][ln][kk] = vh[j];
+    tile[1][ln][kk] = vl[j];
+  }
+  __syncthreads();
+  const int w = t / 64, lane = t % 64;
+  const int64_t kb = kg * 4 + w;
+  if (kb >= o.kb) return;
+  const int ln = lane % 32, k0 = w * 32 + 16 * (lane / 32);
+  const int ex = (side == 0 ? ea : fb)[b * (nblk32 * 32) + line0 + ln];
+  double rh[16], rl[16];
+#pragma unroll
+  for (int q = 0; q < 16; q++) {
+    rh[q] = ldexp(tile[0][ln][k0 + q], -ex);
+    rl[q] = ldexp(tile[1][ln][k0 + q], -ex);
+  }
+  signed char* dst = (side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
+                     (blk * o.kb + kb) * S * (int64_t)kFrag + lane * 16;
+#pragma unroll 2
+  for (int s = 0; s < S; s++) {
+    uint32_t x[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
       const double h = rh[q] * 128.0, lo = rl[q] * 128.0;
       const double d = rint(h);
-      x |= (uint32_t)(uint8_t)(signed char)(int)d << (8 * q);
+      x[q / 4] |= (uint32_t)(uint8_t)(signed char)(int)d << (8 * (q % 4));
       fast_two_sum(h - d, lo, rh[q], rl[q]);
     }
-    *reinterpret_cast<uint32_t*>(dst + t * (int64_t)kFrag) = x;
+    *reinterpret_cast<v4i*>(dst + s * (int64_t)kFrag) = v4i{(int)x[0], (int)x[1], (int)x[2],
+                                                           (int)x[3]};
   }
 }
 
@@ -366,7 +381,7 @@ int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
   int* fb = ea + g.batch * o.rb * 32;
   const int64_t rows_pad = o.rb * 32, cols_pad = o.cb * 32;
   if (g.batch > 65535) return set_error(DDQD_E_UNSUPPORTED, "batch too large");
-  if (((o.rb > o.cb ? o.rb : o.cb) * 32 * o.kb * 8 + 255) / 256 > INT32_MAX ||
+  if ((o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 3) / 4) > INT32_MAX ||
       (g.l + 31) / 32 > 65535)
     return set_error(DDQD_E_UNSUPPORTED, "matrix too large for one Ozaki launch");
   const int64_t nfb = cols_pad * g.batch;
@@ -382,9 +397,9 @@ int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
   prof_record("oz_col_exp_kernel", s);
   int rc = check_launch("oz_exp");
   if (rc) return rc;
-  const int64_t items = (o.rb > o.cb ? o.rb : o.cb) * 32 * o.kb * 8;
+  const int64_t sblocks = (o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 3) / 4);
   prof_begin(s);
-  hipLaunchKernelGGL(oz_slice_kernel<S>, dim3((unsigned)((items + 255) / 256), 2, (unsigned)g.batch),
+  hipLaunchKernelGGL(oz_slice_kernel<S>, dim3((unsigned)sblocks, 2, (unsigned)g.batch),
                      dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)ea, (const int*)fb,
                      Asl, Bsl);
   prof_record("oz_slice_kernel", s);
