@@ -194,8 +194,8 @@ def bench_lu(dd, inputs, torch, dev, sizes, configs, stream):
             def f():
                 A.copy_(A0)
                 holder["f"] = dd.dd_getrf(A, panel=panel, algo=algo, levels=lv, base=base, ws=ws)
-            t_f = time_steps(f, 2, 1, stream)
             t_copy = time_steps(lambda: A.copy_(A0), 3, 1, stream)
+            t_f = time_steps(f, 2, 1, stream)         # A holds the factors after this
             ipiv, perm, _ = holder["f"]
             res = {}
             for nrhs in (1, 16):
@@ -318,6 +318,87 @@ def bench_equal_accuracy(dd, inputs, torch, dev, n, stream):
     return out
 
 
+def bench_paper(dd, inputs, torch, dev, stream):
+    """The paper's own experiment shapes on this GPU.
+
+    Products (Sec. 3, Tables 1-2): the Sec. 3 matrices A = [sqrt5 (i+j-1)],
+    B = [sqrt3 (n-i)] at n = 1023, 1024, 1025 in DD and QD, Block against
+    Strassen and Winograd with the paper's n_min = 32 (5 levels at n = 1024);
+    error = max relative error against the closed form sqrt15 n (n-1)
+    (n + 3i - 2) / 6 on sampled entries (mpmath, 400 bits).
+    LU (Sec. 4): the random matrix with entries in [-1, 1], no pivoting,
+    n = 1024, block size K = alpha n_min for alpha = 1, 2, 4, 8, trailing
+    update by Block or Winograd (depth down to n_min); x = [0, 1, ..., n-1],
+    b = A x formed by the DD product, and the maximum relative error of the
+    computed x over x_i != 0."""
+    import mpmath
+    out = {"products": {}, "lu": {}}
+    for P in (2, 4):
+        for n in (1023, 1024, 1025):
+            A, B = inputs.paper_matrices(n, P)
+            Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+            C = torch.empty((P, n, n), dtype=torch.float64, device=dev)
+            rs = np.random.default_rng(n)
+            rows = np.unique(np.concatenate([[0, n // 2, n - 1], rs.integers(0, n, 29)]))
+            exact = inputs.paper_product_closed_form(n, rows)
+            configs = [("block", 0, "fma"), ("strassen", 5, "fma"), ("winograd", 5, "fma")]
+            if P == 2:
+                configs.append(("block", 0, "ozaki"))
+            for algo, lv, base in configs:
+                ws = torch.empty(max(1, dd.gemm_workspace(P, n, n, n, algo, lv, base)),
+                                 dtype=torch.uint8, device=dev)
+                if P == 2:
+                    f = lambda: dd.dd_gemm(Ad, Bd, C, algo=algo, levels=lv, base=base, ws=ws)
+                else:
+                    f = lambda: dd.qd_gemm(Ad, Bd, C, algo=algo, levels=lv, ws=ws)
+                t = time_steps(f, 3 if P == 2 else 1, 1, stream)
+                Ch = C.cpu().numpy()
+                err = 0.0
+                with mpmath.workprec(400):
+                    for r, e in zip(rows, exact):
+                        for j in (0, n - 1, int(rs.integers(0, n))):
+                            v = mpmath.fsum(mpmath.mpf(float(Ch[c, r, j])) for c in range(P))
+                            err = max(err, float(abs(v - e) / e))
+                key = f"{'dd' if P == 2 else 'qd'}_n{n}_{algo}{lv}_{base}"
+                out["products"][key] = {"ms": round(t, 3),
+                                        "gflops": round(2.0 * n ** 3 / (t * 1e-3) / 1e9, 1),
+                                        "max_rel_error": err}
+                log(f"paper {key}: {out['products'][key]}")
+            del Ad, Bd, C
+    n = 1024
+    A0 = torch.from_numpy(inputs.paper_random_matrix(n, inputs.rng(0))).to(dev)
+    x = np.zeros((2, n, 1))
+    x[0, :, 0] = np.arange(n)
+    b = dd.dd_gemm(A0, torch.from_numpy(x).to(dev))
+    for alpha in (1, 2, 4, 8):
+        K = 32 * alpha
+        for algo in ("block", "winograd"):
+            lv = 0 if algo == "block" else alpha.bit_length() - 1
+            if algo == "winograd" and lv == 0:
+                continue
+            ws = torch.empty(max(1, dd.getrf_workspace(n, K, algo, lv, "fma")),
+                             dtype=torch.uint8, device=dev)
+            A = A0.clone()
+            hold = {}
+
+            def f():
+                A.copy_(A0)
+                hold["r"] = dd.dd_getrf(A, panel=K, pivot="none", algo=algo, levels=lv, ws=ws)
+            t_copy = time_steps(lambda: A.copy_(A0), 3, 1, stream)
+            t = time_steps(f, 2, 1, stream) - t_copy      # A holds the factors after this
+            ipiv, perm, info = hold["r"]
+            X = b.clone()
+            dd.dd_getrs(A, ipiv, X, perm=perm)
+            Xh = X.cpu().numpy()[:, :, 0]
+            d = np.abs((Xh[0, 1:] - np.arange(1, n)) + Xh[1, 1:])
+            key = f"lu_n{n}_K{K}_{algo}{lv}"
+            out["lu"][key] = {"getrf_ms": round(t, 3), "info": int(info.cpu()[0]),
+                              "max_rel_error_x": float(np.max(d / np.arange(1, n))),
+                              "normwise_error_x": float(np.max(d) / (n - 1))}
+            log(f"paper {key}: {out['lu'][key]}")
+    return out
+
+
 def bench_serving(nreq, seed=0):
     from paper_1510_08642_amd import inputs, serve
     pools = serve.DevicePools(nmax_gemm=1024, nmax_lu=2048, nrhs_max=16, seed=seed)
@@ -365,6 +446,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--paper", action="store_true",
+                    help="also run the paper's experiment shapes (Sec. 3 tables, Sec. 4 LU)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB, 5 times "
                          "(reference kernel for scaling HBM byte counters)")
@@ -462,6 +545,8 @@ def main():
                       [(128, "winograd", 1, "fma"), (128, "winograd", 1, "ozaki"),
                        (256, "block", 0, "ozaki")], stream)
 
+    paper = bench_paper(dd, inputs, torch, dev, stream) if args.paper else None
+
     serving = None
     if not args.no_serving and args.serving_requests > 0:
         serving = bench_serving(args.serving_requests)
@@ -494,6 +579,7 @@ def main():
         "graphs": graphs,
         "lu": lu,
         "serving": serving,
+        "paper_replication": paper,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -79,24 +79,33 @@ def row_scaled(X: np.ndarray, g: np.random.Generator, lo: int = -30, hi: int = 3
     return np.ldexp(X, r[None, :, None]), r
 
 
+def _mp_terms(v, P: int) -> tuple:
+    """The first P terms of v, each the double nearest the remaining value."""
+    import mpmath
+    out = []
+    for _ in range(P):
+        h = float(v)
+        out.append(h)
+        v = v - mpmath.mpf(h)
+    return tuple(out)
+
+
 def _mp_dd(v) -> tuple[float, float]:
-    import mpmath
-    h = float(v)
-    return h, float(v - mpmath.mpf(h))
+    return _mp_terms(v, 2)
 
 
-def paper_matrices(n: int) -> tuple[np.ndarray, np.ndarray]:
-    """A = [sqrt5 (i+j-1)], B = [sqrt3 (n-i)], 1-based, as DD (Sec. 3)."""
+def paper_matrices(n: int, P: int = 2) -> tuple[np.ndarray, np.ndarray]:
+    """A = [sqrt5 (i+j-1)], B = [sqrt3 (n-i)], 1-based, as DD (P = 2) or QD
+    (P = 4) numbers nearest the real values (Sec. 3)."""
     import mpmath
-    with mpmath.workprec(300):
+    with mpmath.workprec(400):
         s5, s3 = mpmath.sqrt(5), mpmath.sqrt(3)
-        a_vals = np.array([_mp_dd(s5 * t) for t in range(1, 2 * n)])        # i+j-1 = 1..2n-1
-        b_vals = np.array([_mp_dd(s3 * (n - i)) for i in range(1, n + 1)])  # n-i, i = 1..n
+        a_vals = np.array([_mp_terms(s5 * t, P) for t in range(1, 2 * n)])        # i+j-1
+        b_vals = np.array([_mp_terms(s3 * (n - i), P) for i in range(1, n + 1)])  # n-i
     i = np.arange(n)[:, None]
     j = np.arange(n)[None, :]
-    A = np.stack([a_vals[i + j, 0], a_vals[i + j, 1]])
-    B = np.stack([np.broadcast_to(b_vals[:, 0][:, None], (n, n)),
-                  np.broadcast_to(b_vals[:, 1][:, None], (n, n))]).copy()
+    A = np.stack([a_vals[i + j, c] for c in range(P)])
+    B = np.stack([np.broadcast_to(b_vals[:, c][:, None], (n, n)) for c in range(P)]).copy()
     return A, B
 
 
@@ -104,9 +113,15 @@ def paper_product_closed_form(n: int, rows) -> list:
     """mpmath values of C_ij = sqrt15 n (n-1) (n + 3i - 2) / 6 (1-based i),
     the exact product of the paper's matrices; independent of j."""
     import mpmath
-    with mpmath.workprec(300):
+    with mpmath.workprec(400):
         s15 = mpmath.sqrt(15)
         return [s15 * n * (n - 1) * (n + 3 * (int(r) + 1) - 2) / 6 for r in rows]
+
+
+def paper_random_matrix(n: int, g: np.random.Generator) -> np.ndarray:
+    """The Sec. 4 random matrix: entries uniform in [-1, 1] (DD, low part
+    below half an ulp)."""
+    return dd_uniform(n, n, g)
 
 
 def serving_trace(nreq: int, rate: float, seed: int = 0, gemm_frac: float = 0.6,
