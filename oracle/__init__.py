@@ -68,6 +68,10 @@ def lib():
         L.or_getrf.restype = c_int
         L.or_getrs.argtypes = [i64, i64, _D, _I32, _D]
         L.or_getrs.restype = c_int
+        L.or_getrf_p.argtypes = [c_int, i64, _D, _I32, c_int, c_int, c_int, c_int, c_int]
+        L.or_getrf_p.restype = c_int
+        L.or_getrs_p.argtypes = [c_int, i64, i64, _D, _I32, _D]
+        L.or_getrs_p.restype = c_int
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = c_int
         L.or_set_threads.argtypes = [c_int]
@@ -198,24 +202,27 @@ def eft(op: str, a, b):
 
 def getrf(A: np.ndarray, panel: int = 64, pivot: bool = True, algo: str = "winograd",
           levels: int = 1, bs: int = 32):
-    """Blocked DD LU.  Returns (LU in plane layout, ipiv int32, info)."""
+    """Blocked LU in DD (A of shape (2, n, n)) or QD ((4, n, n)).  Returns
+    (LU in plane layout, ipiv int32, info)."""
     LU = _f64(A).copy()
-    n = LU.shape[1]
+    P, n = LU.shape[0], LU.shape[1]
     ipiv = np.zeros(n, dtype=np.int32)
-    info = lib().or_getrf(n, _dp(LU), ipiv.ctypes.data_as(_I32), panel, int(pivot),
-                          ALGOS[algo], levels, bs)
+    info = lib().or_getrf_p(P, n, _dp(LU), ipiv.ctypes.data_as(_I32), panel, int(pivot),
+                            ALGOS[algo], levels, bs)
     if info < 0:
-        raise ValueError("or_getrf rejected its arguments")
+        raise ValueError("or_getrf_p rejected its arguments")
     return LU, ipiv, info
 
 
 def getrs(LU: np.ndarray, ipiv: np.ndarray, B: np.ndarray) -> np.ndarray:
-    """Solves A X = B from getrf's factors; B is (2, n, nrhs)."""
+    """Solves A X = B from getrf's factors; B is (P, n, nrhs) like LU."""
     LU = _f64(LU)
     X = _f64(B).copy()
-    n, nrhs = X.shape[1], X.shape[2]
+    P, n, nrhs = X.shape[0], X.shape[1], X.shape[2]
+    assert LU.shape[0] == P
     ipiv = np.ascontiguousarray(ipiv, dtype=np.int32)
-    lib().or_getrs(n, nrhs, _dp(LU), ipiv.ctypes.data_as(_I32), _dp(X))
+    if lib().or_getrs_p(P, n, nrhs, _dp(LU), ipiv.ctypes.data_as(_I32), _dp(X)) < 0:
+        raise ValueError("or_getrs_p rejected its arguments")
     return X
 
 

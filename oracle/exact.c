@@ -155,7 +155,8 @@ void or_elementwise(int P, int op, int64_t cnt, const double *x, const double *y
         } else {
             if (op == 0) or_qd_add(a, b, c);
             else if (op == 1) or_qd_sub(a, b, c);
-            else or_qd_mul(a, b, c);
+            else if (op == 2) or_qd_mul(a, b, c);
+            else or_qd_div(a, b, c);
         }
     }
 }

@@ -155,3 +155,23 @@ void or_qd_mul(const double *x, const double *y, double *z) {
         }
     or_exp_round(e, n, z, 4);
 }
+
+void or_qd_div(const double *x, const double *y, double *z) {
+    /* Long division: each quotient digit is the leading term of the current
+     * remainder divided by y's leading term; the remainder r - q y is formed
+     * exactly (the product q y as an expansion, the difference rounded to
+     * four terms) and five digits are summed exactly, then rounded to four
+     * terms. */
+    double r[4] = {x[0], x[1], x[2], x[3]}, q[5], qy[4], qq[4];
+    for (int t = 0; t < 5; t++) {
+        q[t] = r[0] / y[0];
+        qq[0] = q[t];
+        qq[1] = qq[2] = qq[3] = 0.0;
+        or_qd_mul(y, qq, qy);
+        or_qd_sub(r, qy, r);
+    }
+    double e[6];
+    int n = 0;
+    for (int t = 4; t >= 0; t--) n = or_exp_grow(e, n, q[t]);
+    or_exp_round(e, n, z, 4);
+}

@@ -96,5 +96,6 @@ void or_dd_div(const double *x, const double *y, double *z);
 void or_qd_add(const double *x, const double *y, double *z);
 void or_qd_sub(const double *x, const double *y, double *z);
 void or_qd_mul(const double *x, const double *y, double *z);
+void or_qd_div(const double *x, const double *y, double *z);
 
 #endif

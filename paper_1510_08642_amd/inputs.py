@@ -54,6 +54,19 @@ def qd_uniform(rows: int, cols: int, g: np.random.Generator) -> np.ndarray:
     return np.stack(c)
 
 
+def qd_lu_matrix(n: int, g: np.random.Generator, boost: bool = True) -> np.ndarray:
+    """QD version of dd_lu_matrix: leading term N(0, 1) (+ n on the diagonal),
+    trailing terms as in qd_uniform."""
+    c = [g.standard_normal((n, n))]
+    if boost:
+        c[0][np.arange(n), np.arange(n)] += float(n)
+    for _ in range(3):
+        mag = g.uniform(0.5, 1.0, (n, n))
+        sgn = np.where(g.random((n, n)) < 0.5, -1.0, 1.0)
+        c.append(_half_ulp_scaled(c[-1], sgn * mag))
+    return np.stack(c)
+
+
 def dd_lu_matrix(n: int, g: np.random.Generator, boost: bool = True) -> np.ndarray:
     hi = g.standard_normal((n, n))
     if boost:

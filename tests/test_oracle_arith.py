@@ -132,11 +132,11 @@ def test_qd_ops_error_bounds(seed):
     y = _qd_batch(200, g)
     y[:30] = -x[:30]
     y[:30, 3] *= 0.25
-    for op in ["add", "sub", "mul"]:
+    for op in ["add", "sub", "mul", "div"]:
         z = oracle.elementwise(op, x, y)
         for t in range(len(x)):
             a, b = fr(x[t]), fr(y[t])
-            ex = {"add": a + b, "sub": a - b, "mul": a * b}[op]
+            ex = {"add": a + b, "sub": a - b, "mul": a * b, "div": a / b}[op]
             got = fr(z[t])
             if ex == 0:
                 assert got == 0

@@ -126,3 +126,77 @@ def test_winograd_update_error_close_to_block():
         X = oracle.getrs(LU, ipiv, b)
         errs[algo] = oracle.lu_residual(A, X, b)
     assert errs["winograd"] <= 16 * errs["block"] + n * 2.0 ** -106
+
+
+# ---- QD (the paper's second LU workload, Sec. 4 with QD arithmetic) --------
+
+def qd(hi):
+    hi = np.asarray(hi, dtype=np.float64)
+    return np.stack([hi] + [np.zeros_like(hi)] * 3)
+
+
+def fq(x):
+    return sum(F(float(c)) for c in x)
+
+
+@pytest.mark.parametrize("algo,levels", [("block", 0), ("winograd", 2)])
+def test_qd_integer_factors_recovered_exactly(algo, levels):
+    g = inputs.rng(35)
+    n = 20
+    L = np.tril(g.integers(-3, 4, (n, n)), -1) + np.eye(n, dtype=np.int64)
+    d = 2.0 ** g.integers(-2, 3, n)
+    U = np.triu(g.integers(-3, 4, (n, n)), 1).astype(np.float64) + np.diag(d)
+    A = L.astype(np.float64) @ U
+    LU, ipiv, info = oracle.getrf(qd(A), panel=8, pivot=False, algo=algo, levels=levels)
+    assert info == 0
+    assert np.array_equal(np.tril(LU[0], -1), np.tril(L, -1).astype(np.float64))
+    assert np.array_equal(np.triu(LU[0]), U)
+    assert not LU[1:].any()
+
+
+def test_qd_random_small_against_rational_lu():
+    g = inputs.rng(36)
+    n = 10
+    A = inputs.qd_lu_matrix(n, g, boost=False)
+    LU, ipiv, info = oracle.getrf(A, panel=4, pivot=True, algo="winograd", levels=1)
+    M = [[fq(A[:, i, j]) for j in range(n)] for i in range(n)]
+    for c in range(n):
+        p = max(range(c, n), key=lambda r: (abs(M[r][c]), -r))
+        assert p == ipiv[c]
+        M[c], M[p] = M[p], M[c]
+        for r in range(c + 1, n):
+            M[r][c] = M[r][c] / M[c][c]
+            for cc in range(c + 1, n):
+                M[r][cc] -= M[r][c] * M[c][cc]
+    scale = max(abs(x) for row in M for x in row)
+    for i in range(n):
+        for j in range(n):
+            assert abs(fq(LU[:, i, j]) - M[i][j]) <= scale * F(2) ** -196
+
+
+def test_qd_pivot_decided_below_the_leading_term():
+    """Candidates whose leading terms are equal: the second and third terms
+    decide, as the exact comparison does."""
+    n = 8
+    A = qd(np.eye(n) * 0.25)
+    A[:, :, 0] = 0.0
+    A[0, [2, 5, 6], 0] = [1.0, 1.0, -1.0]
+    A[1, [2, 5, 6], 0] = [2.0 ** -60, 2.0 ** -60, -(2.0 ** -60)]
+    A[2, [2, 5, 6], 0] = [2.0 ** -120, 2.0 ** -118, -(2.0 ** -119)]
+    LU, ipiv, info = oracle.getrf(A, panel=4, pivot=True, algo="block")
+    assert ipiv[0] == 5
+
+
+@pytest.mark.parametrize("algo,levels,panel", [("block", 0, 16), ("winograd", 1, 16)])
+def test_qd_paper_solution_forward_error_and_residual(algo, levels, panel):
+    g = inputs.rng(37)
+    n = 48
+    A = inputs.qd_lu_matrix(n, g)
+    x = qd(np.arange(n, dtype=np.float64)[:, None])
+    b = oracle.exact_entries(A, x, np.arange(n), np.zeros(n, dtype=np.int64), kout=4)
+    b = b.reshape(4, n, 1)
+    LU, ipiv, info = oracle.getrf(A, panel=panel, pivot=True, algo=algo, levels=levels)
+    X = oracle.getrs(LU, ipiv, b)
+    rel = [abs((fq(X[:, i, 0]) - i) / i) for i in range(1, n)]
+    assert float(max(rel)) <= n * 2.0 ** -196
+    assert oracle.lu_residual(A, X, b) <= n * 2.0 ** -200
