@@ -186,6 +186,22 @@ int dd_getrs(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t ps
 size_t dd_getrs_workspace(int64_t n, int64_t nrhs);
 
 /*
+ * The same factorisation and solve in QD (4 planes per matrix; the paper's
+ * second LU workload, Sec. 4): arguments, layouts, ipiv / perm / info and
+ * errors as dd_getrf / dd_getrs.  Pivots are compared, and the panel is
+ * factored, in QD; the trailing update is qd_gemm's product, so base must be
+ * DDQD_BASE_FMA (DDQD_E_UNSUPPORTED otherwise).  Orders up to 8192.
+ */
+int qd_getrf(int64_t n, double* A, int64_t lda, int64_t psa, int32_t* ipiv, int32_t* perm,
+             int32_t* info, int panel, int pivot, int algo, int levels, int base, void* ws,
+             size_t ws_bytes, void* stream);
+size_t qd_getrf_workspace(int64_t n, int panel, int algo, int levels, int base);
+int qd_getrs(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t pslu,
+             const int32_t* ipiv, const int32_t* perm, double* B, int64_t ldb, int64_t psb,
+             void* ws, size_t ws_bytes, void* stream);
+size_t qd_getrs_workspace(int64_t n, int64_t nrhs);
+
+/*
  * Autotuning.  The paper leaves the choice of block size and recursion depth
  * per shape as future work (Sec. 5); here the library times the candidate
  * configurations of one shape on the device and keeps the fastest in a

@@ -1,7 +1,8 @@
-// Blocked right-looking DD LU (dd_getrf) and the solve (dd_getrs): host-side
-// drivers over the kernels of lu.hip and the matrix product.
+// Blocked right-looking LU (dd_getrf / qd_getrf) and the solve (dd_getrs /
+// qd_getrs): host-side drivers over the kernels of lu.hip and the matrix
+// product, the same for DD (P = 2 planes) and QD (P = 4).
 //
-// dd_getrf follows the paper's Sec. 4: for each block column of width K,
+// getrf follows the paper's Sec. 4: for each block column of width K,
 //   step 2  factor the (n - j) x K panel, form U12 = L11^-1 A12 (and L21),
 //   step 3  A22 := A22 - L21 U12 through the chosen product algorithm
 //           (Simple / Block / Strassen / Winograd, FMA or Ozaki leaves),
@@ -10,12 +11,13 @@
 //
 // The panel itself is factored recursively: halves of the panel are
 // factored in turn, the right half updated with a triangular solve and a
-// Block product in between; strips of at most 8 (or 4) columns are factored
-// by one workgroup holding the strip in registers (getf2), and every strip's
+// thin product in between; strips of at most 8 columns (fewer for tall or QD
+// panels) are factored by one workgroup holding the strip in registers
+// (getf2), and every strip's
 // interchanges are applied to all other columns by laswp, which also keeps
 // the row permutation in `perm`.  U12 = L11^-1 A12 is a recursive triangular
-// solve (diagonal solves of up to 64 rows, one wave per column; products for
-// the off-diagonal parts).
+// solve (diagonal solves of up to 64 rows in DD, 32 in QD, one wave per
+// column; products for the off-diagonal parts).
 #include "common.hpp"
 #include "ddqd.h"
 
@@ -33,22 +35,23 @@ bool ranges_overlap(const void* a, int64_t a_len, const void* b, int64_t b_len);
 void clear_error();
 
 int launch_lu_init(int32_t* info, int32_t* perm, int64_t n, hipStream_t s);
-int getf2_width(int64_t m);
-int launch_getf2(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t m, int64_t c0, int w,
-                 int32_t* ipiv, int32_t* info, int pivot, hipStream_t s);
-int launch_laswp(double* A, int64_t lda, int64_t ps, int64_t n_cols, int64_t skip0,
+int getf2_width(int P, int64_t m);
+int trsm_max_rows(int P);
+int launch_getf2(int P, double* A, int64_t lda, int64_t ps, int64_t r0, int64_t m, int64_t c0,
+                 int w, int32_t* ipiv, int32_t* info, int pivot, hipStream_t s);
+int launch_laswp(int P, double* A, int64_t lda, int64_t ps, int64_t n_cols, int64_t skip0,
                  int64_t skip1, int64_t k0, int64_t k1, const int32_t* ipiv, int32_t* perm,
                  hipStream_t s);
-int launch_trsm_wave(double* A, int64_t lda, int64_t ps, int64_t r0, int64_t c0, int nb,
+int launch_trsm_wave(int P, double* A, int64_t lda, int64_t ps, int64_t r0, int64_t c0, int nb,
                      int64_t x0, int64_t ncols, hipStream_t s);
-int launch_lu_update(const double* A, const double* B, double* C, int64_t ld, int64_t ps,
+int launch_lu_update(int P, const double* A, const double* B, double* C, int64_t ld, int64_t ps,
                      int64_t m, int64_t n, int64_t l, hipStream_t s);
 int launch_perm_from_ipiv(const int32_t* ipiv, int64_t n, int32_t* perm, hipStream_t s);
-int launch_gather_rows(const double* B, int64_t ldb, int64_t psb, const int32_t* perm, int64_t n,
-                       int64_t nrhs, double* X, hipStream_t s);
-int launch_scatter_rows(const double* X, int64_t n, int64_t nrhs, double* B, int64_t ldb,
+int launch_gather_rows(int P, const double* B, int64_t ldb, int64_t psb, const int32_t* perm,
+                       int64_t n, int64_t nrhs, double* X, hipStream_t s);
+int launch_scatter_rows(int P, const double* X, int64_t n, int64_t nrhs, double* B, int64_t ldb,
                         int64_t psb, hipStream_t s);
-int launch_trsv_blocks(const double* T, int64_t ldt, int64_t pst, double* X, int64_t n,
+int launch_trsv_blocks(int P, const double* T, int64_t ldt, int64_t pst, double* X, int64_t n,
                        int64_t nrhs, int upper, hipStream_t s);
 
 namespace {
@@ -56,6 +59,7 @@ namespace {
 constexpr int64_t kMaxLuRows = 8192;
 
 struct Lu {
+  int P;  // 2 = DD, 4 = QD
   double* A;
   int64_t lda, ps, n;
   int32_t* ipiv;
@@ -75,17 +79,18 @@ Mat sub(const Lu& c, int64_t i, int64_t j) { return Mat{c.A + i * c.lda + j, c.l
 // one thread per entry and no tile staging finishes sooner.
 int block_update(const Lu& c, int64_t m, int64_t n, int64_t l, Mat Am, Mat Bm, Mat Cm) {
   const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
-  if (tiles < 256) return launch_lu_update(Am.p, Bm.p, Cm.p, c.lda, c.ps, m, n, l, c.s);
+  if (tiles < 256) return launch_lu_update(c.P, Am.p, Bm.p, Cm.p, c.lda, c.ps, m, n, l, c.s);
   GemmBatch g{m, n, l, -1, 1, cview(Am), cview(Bm), Cm, 1};
-  return gemm_internal(2, g, DDQD_BLOCK, 0, DDQD_BASE_FMA, 0, nullptr, 0, c.s);
+  return gemm_internal(c.P, g, DDQD_BLOCK, 0, DDQD_BASE_FMA, 0, nullptr, 0, c.s);
 }
 
 // X := L^-1 X, L unit lower nb x nb at (r0, r0), X = rows [r0, r0+nb) of
 // columns [x0, x0 + nc)
 int trsm(const Lu& c, int64_t r0, int64_t nb, int64_t x0, int64_t nc) {
   if (nb <= 0 || nc <= 0) return 0;
-  if (nb <= 64) return launch_trsm_wave(c.A, c.lda, c.ps, r0, r0, (int)nb, x0, nc, c.s);
-  const int64_t n1 = (nb / 2 + 63) / 64 * 64;
+  const int64_t R = trsm_max_rows(c.P);
+  if (nb <= R) return launch_trsm_wave(c.P, c.A, c.lda, c.ps, r0, r0, (int)nb, x0, nc, c.s);
+  const int64_t n1 = (nb / 2 + R - 1) / R * R;
   int rc;
   if ((rc = trsm(c, r0, n1, x0, nc))) return rc;
   if ((rc = block_update(c, nb - n1, nc, n1, sub(c, r0 + n1, r0), sub(c, r0, x0),
@@ -97,12 +102,13 @@ int trsm(const Lu& c, int64_t r0, int64_t nb, int64_t x0, int64_t nc) {
 // factor columns [c0, c0 + w) of rows [c0, n)
 int panel(const Lu& c, int64_t c0, int64_t w) {
   const int64_t m = c.n - c0;
-  const int wb = getf2_width(m);
+  const int wb = getf2_width(c.P, m);
   int rc;
   if (w <= wb) {
-    if ((rc = launch_getf2(c.A, c.lda, c.ps, c0, m, c0, (int)w, c.ipiv, c.info, c.pivot, c.s)))
+    if ((rc = launch_getf2(c.P, c.A, c.lda, c.ps, c0, m, c0, (int)w, c.ipiv, c.info, c.pivot,
+                           c.s)))
       return rc;
-    return launch_laswp(c.A, c.lda, c.ps, c.n, c0, c0 + w, c0, c0 + w, c.ipiv, c.perm, c.s);
+    return launch_laswp(c.P, c.A, c.lda, c.ps, c.n, c0, c0 + w, c0, c0 + w, c.ipiv, c.perm, c.s);
   }
   int64_t w1 = (w / 2) / wb * wb;
   if (w1 < wb) w1 = wb;
@@ -127,27 +133,108 @@ int getrf(const Lu& c, int64_t K) {
     // step 3: A22 := A22 - L21 U12
     GemmBatch g{r, r, kb, -1, 1, cview(sub(c, j0 + kb, j0)), cview(sub(c, j0, j0 + kb)),
                 sub(c, j0 + kb, j0 + kb), 1};
-    if ((rc = gemm_internal(2, g, c.algo, c.levels, c.base, 0, c.ws, c.ws_bytes, c.s))) return rc;
+    if ((rc = gemm_internal(c.P, g, c.algo, c.levels, c.base, 0, c.ws, c.ws_bytes, c.s)))
+      return rc;
   }
   return 0;
 }
 
-size_t getrf_ws(int64_t n, int64_t K, int algo, int levels, int base) {
+size_t getrf_ws(int P, int64_t n, int64_t K, int algo, int levels, int base) {
   size_t mx = 0;
   for (int64_t j0 = 0; j0 < n; j0 += K) {
     const int64_t kb = n - j0 < K ? n - j0 : K, r = n - j0 - kb;
     if (r <= 0) break;
-    size_t w = gemm_internal_ws(2, r, r, kb, algo, levels, base, 0);
+    size_t w = gemm_internal_ws(P, r, r, kb, algo, levels, base, 0);
     if (w == SIZE_MAX) return SIZE_MAX;
     if (w > mx) mx = w;
   }
   return mx;
 }
 
-size_t getrs_ws(int64_t n, int64_t nrhs) {
+size_t getrs_ws(int P, int64_t n, int64_t nrhs) {
   const int64_t c = nrhs < 16 ? nrhs : 16;
-  return ((sizeof(double) * 2 * (size_t)(n * c) + 255) & ~(size_t)255) +
+  return ((sizeof(double) * P * (size_t)(n * c) + 255) & ~(size_t)255) +
          sizeof(int32_t) * (size_t)n;
+}
+
+size_t getrf_workspace_entry(int P, int64_t n, int panel_width, int algo, int levels, int base) {
+  if (n < 0 || panel_width < 1 || algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 ||
+      base > 1 || (P == 4 && base != DDQD_BASE_FMA))
+    return SIZE_MAX;
+  return getrf_ws(P, n, panel_width, algo, levels, base);
+}
+
+int getrf_entry(int P, int64_t n, double* A, int64_t lda, int64_t psa, int32_t* ipiv,
+                int32_t* perm, int32_t* info, int panel_width, int pivot, int algo, int levels,
+                int base, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (n < 0) return set_error(DDQD_E_ARG, "negative order");
+  if (panel_width < 1) return set_error(DDQD_E_ARG, "panel width must be >= 1");
+  if (pivot != DDQD_PIVOT_NONE && pivot != DDQD_PIVOT_PARTIAL)
+    return set_error(DDQD_E_ARG, "pivot must be DDQD_PIVOT_NONE or DDQD_PIVOT_PARTIAL");
+  if (algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 || base > 1)
+    return set_error(DDQD_E_ARG, "bad product algorithm / levels / base");
+  if (P == 4 && base != DDQD_BASE_FMA)
+    return set_error(DDQD_E_UNSUPPORTED, "QD products use the FMA base only");
+  if (!info) return set_error(DDQD_E_ARG, "info is NULL");
+  if (n > 0 && !ipiv) return set_error(DDQD_E_ARG, "ipiv is NULL");
+  if (n > kMaxLuRows)
+    return set_error(DDQD_E_UNSUPPORTED, "LU of order above %lld", (long long)kMaxLuRows);
+  int rc;
+  if ((rc = check_matrix("A", P, A, n, n, lda, psa))) return rc;
+  const size_t need = getrf_ws(P, n, panel_width, algo, levels, base);
+  if (need == SIZE_MAX) return set_error(DDQD_E_ARG, "bad product arguments");
+  if (need > ws_bytes || (need > 0 && !ws))
+    return set_error(DDQD_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
+                     ws_bytes);
+  if ((rc = check_device())) return rc;
+  Lu c{P, A, lda, psa, n, ipiv, perm, info, pivot, algo, levels, base, ws, ws_bytes,
+       (hipStream_t)stream};
+  if (n == 0) return launch_lu_init(info, nullptr, 0, c.s);
+  return getrf(c, panel_width);
+}
+
+size_t getrs_workspace_entry(int P, int64_t n, int64_t nrhs) {
+  if (n < 0 || nrhs < 0) return SIZE_MAX;
+  if (n == 0 || nrhs == 0) return 0;
+  return getrs_ws(P, n, nrhs);
+}
+
+int getrs_entry(int P, int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t pslu,
+                const int32_t* ipiv, const int32_t* perm, double* B, int64_t ldb, int64_t psb,
+                void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (n < 0 || nrhs < 0) return set_error(DDQD_E_ARG, "negative dimension");
+  if (n == 0 || nrhs == 0) return DDQD_OK;
+  if (!ipiv && !perm) return set_error(DDQD_E_ARG, "ipiv and perm are both NULL");
+  int rc;
+  if ((rc = check_matrix("LU", P, LU, n, n, ldlu, pslu))) return rc;
+  if ((rc = check_matrix("B", P, B, n, nrhs, ldb, psb))) return rc;
+  if (ranges_overlap(LU, matrix_extent(P, n, n, ldlu, pslu), B,
+                     matrix_extent(P, n, nrhs, ldb, psb)))
+    return set_error(DDQD_E_ALIAS, "B overlaps LU");
+  const size_t need = getrs_ws(P, n, nrhs);
+  if (need > ws_bytes || !ws)
+    return set_error(DDQD_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
+                     ws_bytes);
+  if ((rc = check_device())) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t chunk = nrhs < 16 ? nrhs : 16;
+  double* X = (double*)ws;
+  int32_t* pm = (int32_t*)((char*)ws + (((sizeof(double) * P * (size_t)(n * chunk)) + 255) &
+                                        ~(size_t)255));
+  if (!perm) {
+    if ((rc = launch_perm_from_ipiv(ipiv, n, pm, s))) return rc;
+    perm = pm;
+  }
+  for (int64_t c0 = 0; c0 < nrhs; c0 += chunk) {
+    const int64_t nc = nrhs - c0 < chunk ? nrhs - c0 : chunk;
+    if ((rc = launch_gather_rows(P, B + c0, ldb, psb, perm, n, nc, X, s))) return rc;
+    if ((rc = launch_trsv_blocks(P, LU, ldlu, pslu, X, n, nc, 0, s))) return rc;
+    if ((rc = launch_trsv_blocks(P, LU, ldlu, pslu, X, n, nc, 1, s))) return rc;
+    if ((rc = launch_scatter_rows(P, X, n, nc, B + c0, ldb, psb, s))) return rc;
+  }
+  return DDQD_OK;
 }
 
 }  // namespace
@@ -158,80 +245,41 @@ using namespace ddqd;
 extern "C" {
 
 size_t dd_getrf_workspace(int64_t n, int panel_width, int algo, int levels, int base) {
-  if (n < 0 || panel_width < 1 || algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 ||
-      base > 1)
-    return SIZE_MAX;
-  return getrf_ws(n, panel_width, algo, levels, base);
+  return getrf_workspace_entry(2, n, panel_width, algo, levels, base);
 }
 
 int dd_getrf(int64_t n, double* A, int64_t lda, int64_t psa, int32_t* ipiv, int32_t* perm,
              int32_t* info, int panel_width, int pivot, int algo, int levels, int base, void* ws,
              size_t ws_bytes, void* stream) {
-  clear_error();
-  if (n < 0) return set_error(DDQD_E_ARG, "negative order");
-  if (panel_width < 1) return set_error(DDQD_E_ARG, "panel width must be >= 1");
-  if (pivot != DDQD_PIVOT_NONE && pivot != DDQD_PIVOT_PARTIAL)
-    return set_error(DDQD_E_ARG, "pivot must be DDQD_PIVOT_NONE or DDQD_PIVOT_PARTIAL");
-  if (algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 || base > 1)
-    return set_error(DDQD_E_ARG, "bad product algorithm / levels / base");
-  if (!info) return set_error(DDQD_E_ARG, "info is NULL");
-  if (n > 0 && !ipiv) return set_error(DDQD_E_ARG, "ipiv is NULL");
-  if (n > kMaxLuRows)
-    return set_error(DDQD_E_UNSUPPORTED, "LU of order above %lld", (long long)kMaxLuRows);
-  int rc;
-  if ((rc = check_matrix("A", 2, A, n, n, lda, psa))) return rc;
-  const size_t need = getrf_ws(n, panel_width, algo, levels, base);
-  if (need == SIZE_MAX) return set_error(DDQD_E_ARG, "bad product arguments");
-  if (need > ws_bytes || (need > 0 && !ws))
-    return set_error(DDQD_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
-                     ws_bytes);
-  if ((rc = check_device())) return rc;
-  Lu c{A, lda, psa, n, ipiv, perm, info, pivot, algo, levels, base, ws, ws_bytes,
-       (hipStream_t)stream};
-  if (n == 0) return launch_lu_init(info, nullptr, 0, c.s);
-  return getrf(c, panel_width);
+  return getrf_entry(2, n, A, lda, psa, ipiv, perm, info, panel_width, pivot, algo, levels, base,
+                     ws, ws_bytes, stream);
 }
 
-size_t dd_getrs_workspace(int64_t n, int64_t nrhs) {
-  if (n < 0 || nrhs < 0) return SIZE_MAX;
-  if (n == 0 || nrhs == 0) return 0;
-  return getrs_ws(n, nrhs);
-}
+size_t dd_getrs_workspace(int64_t n, int64_t nrhs) { return getrs_workspace_entry(2, n, nrhs); }
 
 int dd_getrs(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t pslu,
              const int32_t* ipiv, const int32_t* perm, double* B, int64_t ldb, int64_t psb,
              void* ws, size_t ws_bytes, void* stream) {
-  clear_error();
-  if (n < 0 || nrhs < 0) return set_error(DDQD_E_ARG, "negative dimension");
-  if (n == 0 || nrhs == 0) return DDQD_OK;
-  if (!ipiv && !perm) return set_error(DDQD_E_ARG, "ipiv and perm are both NULL");
-  int rc;
-  if ((rc = check_matrix("LU", 2, LU, n, n, ldlu, pslu))) return rc;
-  if ((rc = check_matrix("B", 2, B, n, nrhs, ldb, psb))) return rc;
-  if (ranges_overlap(LU, matrix_extent(2, n, n, ldlu, pslu), B, matrix_extent(2, n, nrhs, ldb, psb)))
-    return set_error(DDQD_E_ALIAS, "B overlaps LU");
-  const size_t need = getrs_ws(n, nrhs);
-  if (need > ws_bytes || !ws)
-    return set_error(DDQD_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
-                     ws_bytes);
-  if ((rc = check_device())) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t chunk = nrhs < 16 ? nrhs : 16;
-  double* X = (double*)ws;
-  int32_t* pm = (int32_t*)((char*)ws + (((sizeof(double) * 2 * (size_t)(n * chunk)) + 255) &
-                                        ~(size_t)255));
-  if (!perm) {
-    if ((rc = launch_perm_from_ipiv(ipiv, n, pm, s))) return rc;
-    perm = pm;
-  }
-  for (int64_t c0 = 0; c0 < nrhs; c0 += chunk) {
-    const int64_t nc = nrhs - c0 < chunk ? nrhs - c0 : chunk;
-    if ((rc = launch_gather_rows(B + c0, ldb, psb, perm, n, nc, X, s))) return rc;
-    if ((rc = launch_trsv_blocks(LU, ldlu, pslu, X, n, nc, 0, s))) return rc;
-    if ((rc = launch_trsv_blocks(LU, ldlu, pslu, X, n, nc, 1, s))) return rc;
-    if ((rc = launch_scatter_rows(X, n, nc, B + c0, ldb, psb, s))) return rc;
-  }
-  return DDQD_OK;
+  return getrs_entry(2, n, nrhs, LU, ldlu, pslu, ipiv, perm, B, ldb, psb, ws, ws_bytes, stream);
+}
+
+size_t qd_getrf_workspace(int64_t n, int panel_width, int algo, int levels, int base) {
+  return getrf_workspace_entry(4, n, panel_width, algo, levels, base);
+}
+
+int qd_getrf(int64_t n, double* A, int64_t lda, int64_t psa, int32_t* ipiv, int32_t* perm,
+             int32_t* info, int panel_width, int pivot, int algo, int levels, int base, void* ws,
+             size_t ws_bytes, void* stream) {
+  return getrf_entry(4, n, A, lda, psa, ipiv, perm, info, panel_width, pivot, algo, levels, base,
+                     ws, ws_bytes, stream);
+}
+
+size_t qd_getrs_workspace(int64_t n, int64_t nrhs) { return getrs_workspace_entry(4, n, nrhs); }
+
+int qd_getrs(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t pslu,
+             const int32_t* ipiv, const int32_t* perm, double* B, int64_t ldb, int64_t psb,
+             void* ws, size_t ws_bytes, void* stream) {
+  return getrs_entry(4, n, nrhs, LU, ldlu, pslu, ipiv, perm, B, ldb, psb, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

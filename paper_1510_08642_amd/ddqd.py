@@ -40,15 +40,18 @@ for _name in ("dd_gemm", "qd_gemm"):
 for _name in ("dd_gemm_workspace", "qd_gemm_workspace"):
     getattr(_lib, _name).argtypes = [_i64, _i64, _i64, _int, _int, _int, _int]
     getattr(_lib, _name).restype = _sz
-_lib.dd_getrf_workspace.argtypes = [_i64, _int, _int, _int, _int]
-_lib.dd_getrf_workspace.restype = _sz
-_lib.dd_getrf.argtypes = [_i64, _vp, _i64, _i64, _vp, _vp, _vp, _int, _int, _int, _int, _int, _vp,
-                          _sz, _vp]
-_lib.dd_getrf.restype = _int
-_lib.dd_getrs_workspace.argtypes = [_i64, _i64]
-_lib.dd_getrs_workspace.restype = _sz
-_lib.dd_getrs.argtypes = [_i64, _i64, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _vp, _sz, _vp]
-_lib.dd_getrs.restype = _int
+for _p in ("dd", "qd"):
+    getattr(_lib, f"{_p}_getrf_workspace").argtypes = [_i64, _int, _int, _int, _int]
+    getattr(_lib, f"{_p}_getrf_workspace").restype = _sz
+    getattr(_lib, f"{_p}_getrf").argtypes = [_i64, _vp, _i64, _i64, _vp, _vp, _vp, _int, _int,
+                                             _int, _int, _int, _vp, _sz, _vp]
+    getattr(_lib, f"{_p}_getrf").restype = _int
+    getattr(_lib, f"{_p}_getrs_workspace").argtypes = [_i64, _i64]
+    getattr(_lib, f"{_p}_getrs_workspace").restype = _sz
+    getattr(_lib, f"{_p}_getrs").argtypes = [_i64, _i64, _vp, _i64, _i64, _vp, _vp, _vp, _i64,
+                                             _i64, _vp, _sz, _vp]
+    getattr(_lib, f"{_p}_getrs").restype = _int
+_PREC = {2: "dd", 4: "qd"}
 
 
 class GemmDesc(ctypes.Structure):
@@ -176,8 +179,8 @@ def qd_gemm(A, B, C=None, *, alpha=1, beta=0, algo="block", levels=0, slices=0, 
     return _gemm(4, A, B, C, alpha, beta, algo, levels, "fma", slices, ws)
 
 
-def getrf_workspace(n: int, panel=128, algo="winograd", levels=1, base="fma") -> int:
-    ws = _lib.dd_getrf_workspace(n, panel, ALGO[algo], levels, BASE[base])
+def getrf_workspace(n: int, panel=128, algo="winograd", levels=1, base="fma", P: int = 2) -> int:
+    ws = getattr(_lib, f"{_PREC[P]}_getrf_workspace")(n, panel, ALGO[algo], levels, BASE[base])
     if ws == SIZE_MAX:
         raise ValueError("invalid getrf arguments")
     return ws
@@ -192,10 +195,20 @@ def dd_getrf(A, *, panel=128, pivot="partial", algo="winograd", levels=1, base="
     interchanges, the resulting row permutation (or None), and info (0, or the
     1-based column of the first exactly-zero pivot).  `out` may supply those
     three tensors (perm may be None), e.g. for a call recorded in a graph."""
+    return _getrf(2, A, panel, pivot, algo, levels, base, want_perm, ws, out)
+
+
+def qd_getrf(A, *, panel=128, pivot="partial", algo="winograd", levels=1, want_perm=True,
+             ws=None, out=None):
+    """As dd_getrf for a QD (4, n, n) tensor (FMA-based products only)."""
+    return _getrf(4, A, panel, pivot, algo, levels, "fma", want_perm, ws, out)
+
+
+def _getrf(P, A, panel, pivot, algo, levels, base, want_perm, ws, out):
     n = A.shape[1]
     if A.shape[2] != n:
         raise ValueError("A must be square")
-    pa, lda, psa = _mat(A, 2, "A")
+    pa, lda, psa = _mat(A, P, "A")
     dev = A.device
     if out is not None:
         ipiv, perm, info = out
@@ -208,30 +221,41 @@ def dd_getrf(A, *, panel=128, pivot="partial", algo="winograd", levels=1, base="
         ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
         perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if want_perm else None
         info = torch.empty(1, dtype=torch.int32, device=dev)
-    need = getrf_workspace(n, panel, algo, levels, base)
+    need = getrf_workspace(n, panel, algo, levels, base, P)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
-    st = _lib.dd_getrf(n, pa, lda, psa, ipiv.data_ptr(), perm.data_ptr() if perm is not None
-                       else None, info.data_ptr(), panel, PIVOT[pivot], ALGO[algo], levels,
-                       BASE[base], ws.data_ptr(), ws.numel(), _stream_of(A))
-    _check(st, "dd_getrf")
+    st = getattr(_lib, f"{_PREC[P]}_getrf")(
+        n, pa, lda, psa, ipiv.data_ptr(), perm.data_ptr() if perm is not None else None,
+        info.data_ptr(), panel, PIVOT[pivot], ALGO[algo], levels, BASE[base], ws.data_ptr(),
+        ws.numel(), _stream_of(A))
+    _check(st, f"{_PREC[P]}_getrf")
     return ipiv[:n], (perm[:n] if perm is not None else None), info
 
 
 def dd_getrs(LU, ipiv, B, *, perm=None, ws=None):
     """Solves A X = B in place on B (2, n, nrhs) from dd_getrf's factors."""
+    return _getrs(2, LU, ipiv, B, perm, ws)
+
+
+def qd_getrs(LU, ipiv, B, *, perm=None, ws=None):
+    """Solves A X = B in place on B (4, n, nrhs) from qd_getrf's factors."""
+    return _getrs(4, LU, ipiv, B, perm, ws)
+
+
+def _getrs(P, LU, ipiv, B, perm, ws):
     n, nrhs = B.shape[1], B.shape[2]
-    pl, ldl, psl = _mat(LU, 2, "LU")
-    pb, ldb, psb = _mat(B, 2, "B")
-    need = _lib.dd_getrs_workspace(n, nrhs)
+    pl, ldl, psl = _mat(LU, P, "LU")
+    pb, ldb, psb = _mat(B, P, "B")
+    need = getattr(_lib, f"{_PREC[P]}_getrs_workspace")(n, nrhs)
     if need == SIZE_MAX:
         raise ValueError("invalid getrs arguments")
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=B.device)
-    st = _lib.dd_getrs(n, nrhs, pl, ldl, psl, ipiv.data_ptr() if ipiv is not None else None,
-                       perm.data_ptr() if perm is not None else None, pb, ldb, psb,
-                       ws.data_ptr(), ws.numel(), _stream_of(B))
-    _check(st, "dd_getrs")
+    st = getattr(_lib, f"{_PREC[P]}_getrs")(
+        n, nrhs, pl, ldl, psl, ipiv.data_ptr() if ipiv is not None else None,
+        perm.data_ptr() if perm is not None else None, pb, ldb, psb, ws.data_ptr(), ws.numel(),
+        _stream_of(B))
+    _check(st, f"{_PREC[P]}_getrs")
     return B
 
 

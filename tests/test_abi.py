@@ -192,3 +192,16 @@ def test_auto_workspace_covers_every_candidate(lib):
                     assert auto >= f(m, n, l, algo, levels, 0, 0)
     o = lib.dd_gemm_workspace(512, 512, 512, 4, 0, 1, 0)
     assert o >= lib.dd_gemm_workspace(512, 512, 512, 3, 3, 1, 0)
+
+
+def test_qd_lu_argument_errors(lib):
+    import ctypes as C
+    from paper_1510_08642_amd import ddqd  # noqa: F401  (sets argtypes)
+    A, ip, info = 0x10000, 0x40000, 0x50000
+    call = lambda base, n=8, lda=8: lib.qd_getrf(n, A, lda, lda * n, ip, None, info, 4, 1, 1, 0,
+                                                 base, None, 0, None)
+    assert call(1) == E["UNSUPPORTED"]              # Ozaki products are DD only
+    assert call(0, lda=4) == E["ARG"]
+    assert lib.qd_getrf_workspace(64, 16, 3, 1, 1) == C.c_size_t(-1).value
+    assert lib.qd_getrs_workspace(100, 3) >= 4 * 8 * 100 * 3
+    assert lib.qd_getrs_workspace(100, 3) > lib.dd_getrs_workspace(100, 3)
