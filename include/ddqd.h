@@ -62,6 +62,11 @@ extern "C" {
 /* base (leaf) product kernels */
 #define DDQD_BASE_FMA 0      /* FP64 FMA error-free products                 */
 #define DDQD_BASE_OZAKI_I8 1 /* slices on INT8 matrix cores, FP64 recombine  */
+/* (an Ozaki-style split, not in the paper: each operand is scaled by powers
+ * of two per row of A / column of B and cut into `slices` signed 7-bit digits;
+ * the digit products run exactly on v_mfma_i32_32x32x32_i8 and are recombined
+ * in FP64.  Leaf error at most about l (S+3) 2^(-7S-2) max|a_i.| max|b_.j|
+ * times 4, S the slice count.) */
 
 /* pivoting for dd_getrf */
 #define DDQD_PIVOT_NONE 0
@@ -137,7 +142,10 @@ typedef struct {
  */
 int dd_gemm_grouped(int count, const ddqd_gemm_desc* descs, void* stream);
 
-/* As dd_gemm, in QD (4 planes per matrix).  base must be DDQD_BASE_FMA. */
+/* As dd_gemm, in QD (4 planes per matrix; Sec. 3, Table 2's precision).
+ * With DDQD_BASE_OZAKI_I8 the slice count is 0 = 31 or 28..31 (else
+ * DDQD_E_UNSUPPORTED); 31 slices keep the leaf error below about
+ * 2^-211 l max|a_i.| max|b_.j|, QD's accuracy class. */
 int qd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
             int64_t psa, const double* B, int64_t ldb, int64_t psb, int beta, double* C,
             int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
@@ -189,8 +197,8 @@ size_t dd_getrs_workspace(int64_t n, int64_t nrhs);
  * The same factorisation and solve in QD (4 planes per matrix; the paper's
  * second LU workload, Sec. 4): arguments, layouts, ipiv / perm / info and
  * errors as dd_getrf / dd_getrs.  Pivots are compared, and the panel is
- * factored, in QD; the trailing update is qd_gemm's product, so base must be
- * DDQD_BASE_FMA (DDQD_E_UNSUPPORTED otherwise).  Orders up to 8192.
+ * factored, in QD; the trailing update is qd_gemm's product (either base;
+ * Ozaki leaves with 31 slices).  Orders up to 8192.
  */
 int qd_getrf(int64_t n, double* A, int64_t lda, int64_t psa, int32_t* ipiv, int32_t* perm,
              int32_t* info, int panel, int pivot, int algo, int levels, int base, void* ws,

@@ -51,9 +51,10 @@ int launch_postadd(CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t paren
                    int alpha, int beta, const int* ea, const int* fb, hipStream_t stream);
 int launch_exponents(CMat A, CMat B, int64_t m, int64_t n, int64_t l, int* ea, int* fb,
                      hipStream_t stream);
-size_t ozaki_workspace(int64_t m, int64_t n, int64_t l, int64_t batch, int slices);
-int launch_ozaki(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, hipStream_t stream);
-int ozaki_default_slices();
+size_t ozaki_workspace(int P, int64_t m, int64_t n, int64_t l, int64_t batch, int slices);
+int launch_ozaki(int P, const GemmBatch& g, int slices, void* ws, size_t ws_bytes,
+                 hipStream_t stream);
+bool ozaki_slices_ok(int P, int slices);
 
 static thread_local char g_msg[512];
 
@@ -163,7 +164,7 @@ Plan make_plan(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int
   }
   pl.off_leaf = off;
   if (base == DDQD_BASE_OZAKI_I8 && algo != DDQD_SIMPLE)
-    pl.leaf_bytes = ozaki_workspace(pl.m[L], pl.n[L], pl.l[L], pow7(L), slices);
+    pl.leaf_bytes = ozaki_workspace(P, pl.m[L], pl.n[L], pl.l[L], pow7(L), slices);
   pl.total = off + pl.leaf_bytes;
   return pl;
 }
@@ -184,7 +185,7 @@ Mat prodM(const Plan& pl, char* ws, int j) {
 
 int leaf(int P, const GemmBatch& g, int base, int slices, int tile, void* ws, size_t ws_bytes,
          hipStream_t s) {
-  if (base == DDQD_BASE_OZAKI_I8) return launch_ozaki(g, slices, ws, ws_bytes, s);
+  if (base == DDQD_BASE_OZAKI_I8) return launch_ozaki(P, g, slices, ws, ws_bytes, s);
   return P == 2 ? launch_dd_block(g, tile, s) : launch_qd_block(g, s);
 }
 
@@ -308,7 +309,6 @@ size_t gemm_ws(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int
   if (m < 0 || n < 0 || l < 0 || algo < 0 || algo > DDQD_AUTO || levels < 0 ||
       levels > kMaxLevels || base < 0 || base > 1 || slices < 0 || slices > 40)
     return SIZE_MAX;
-  if (P == 4 && base != DDQD_BASE_FMA) return SIZE_MAX;
   if (m == 0 || n == 0 || l == 0) return 0;
   if (algo == DDQD_AUTO) return auto_workspace(P, m, n, l, base, slices);
   return make_plan(P, m, n, l, algo, levels, base, slices).total;
@@ -338,8 +338,9 @@ int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* 
   if (base != DDQD_BASE_FMA && base != DDQD_BASE_OZAKI_I8)
     return set_error(DDQD_E_ARG, "unknown base %d", base);
   if (slices < 0 || slices > 40) return set_error(DDQD_E_ARG, "slices must be in 0..40");
-  if (P == 4 && base != DDQD_BASE_FMA)
-    return set_error(DDQD_E_UNSUPPORTED, "QD products use the FMA base only");
+  if (base == DDQD_BASE_OZAKI_I8 && !ozaki_slices_ok(P, slices))
+    return set_error(DDQD_E_UNSUPPORTED, "%d slices not supported (DD 8..20, QD 28..31)",
+                     slices);
   int rc;
   if ((rc = check_mat("C", P, C, m, n, ldc, psc))) return rc;
   if (l > 0) {

@@ -159,7 +159,7 @@ size_t getrs_ws(int P, int64_t n, int64_t nrhs) {
 
 size_t getrf_workspace_entry(int P, int64_t n, int panel_width, int algo, int levels, int base) {
   if (n < 0 || panel_width < 1 || algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 ||
-      base > 1 || (P == 4 && base != DDQD_BASE_FMA))
+      base > 1)
     return SIZE_MAX;
   return getrf_ws(P, n, panel_width, algo, levels, base);
 }
@@ -174,8 +174,6 @@ int getrf_entry(int P, int64_t n, double* A, int64_t lda, int64_t psa, int32_t* 
     return set_error(DDQD_E_ARG, "pivot must be DDQD_PIVOT_NONE or DDQD_PIVOT_PARTIAL");
   if (algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 || base > 1)
     return set_error(DDQD_E_ARG, "bad product algorithm / levels / base");
-  if (P == 4 && base != DDQD_BASE_FMA)
-    return set_error(DDQD_E_UNSUPPORTED, "QD products use the FMA base only");
   if (!info) return set_error(DDQD_E_ARG, "info is NULL");
   if (n > 0 && !ipiv) return set_error(DDQD_E_ARG, "ipiv is NULL");
   if (n > kMaxLuRows)

@@ -33,6 +33,9 @@
 
 namespace ddqd {
 
+int launch_oz_exponents(const GemmBatch& g, int64_t rows_pad, int64_t cols_pad, int* ea, int* fb,
+                        hipStream_t s);
+
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -384,18 +387,7 @@ int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
   if ((o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 3) / 4) > INT32_MAX ||
       (g.l + 31) / 32 > 65535)
     return set_error(DDQD_E_UNSUPPORTED, "matrix too large for one Ozaki launch");
-  const int64_t nfb = cols_pad * g.batch;
-  prof_begin(s);
-  hipLaunchKernelGGL(oz_row_exp_kernel, dim3((unsigned)((rows_pad + 3) / 4), (unsigned)g.batch),
-                     dim3(256), 0, s, g.A, g.m, g.l, rows_pad, ea, fb, nfb);
-  prof_record("oz_row_exp_kernel", s);
-  prof_begin(s);
-  hipLaunchKernelGGL(oz_col_exp_kernel,
-                     dim3((unsigned)((cols_pad + 63) / 64), (unsigned)((g.l + 31) / 32),
-                          (unsigned)g.batch),
-                     dim3(256), 0, s, g.B, g.l, g.n, cols_pad, fb);
-  prof_record("oz_col_exp_kernel", s);
-  int rc = check_launch("oz_exp");
+  int rc = launch_oz_exponents(g, rows_pad, cols_pad, ea, fb, s);
   if (rc) return rc;
   const int64_t sblocks = (o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 3) / 4);
   prof_begin(s);
@@ -421,27 +413,56 @@ int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
 
 }  // namespace
 
-int ozaki_default_slices() { return 16; }
-
-static int resolve_slices(int slices) {
-  if (slices == 0) return ozaki_default_slices();
-  return slices;
+// Row exponents of A (rows_pad per batch entry, padded rows 1) and column
+// exponents of B (cols_pad per entry; all-zero columns keep the sentinel).
+int launch_oz_exponents(const GemmBatch& g, int64_t rows_pad, int64_t cols_pad, int* ea, int* fb,
+                        hipStream_t s) {
+  const int64_t nfb = cols_pad * g.batch;
+  prof_begin(s);
+  hipLaunchKernelGGL(oz_row_exp_kernel, dim3((unsigned)((rows_pad + 3) / 4), (unsigned)g.batch),
+                     dim3(256), 0, s, g.A, g.m, g.l, rows_pad, ea, fb, nfb);
+  prof_record("oz_row_exp_kernel", s);
+  prof_begin(s);
+  hipLaunchKernelGGL(oz_col_exp_kernel,
+                     dim3((unsigned)((cols_pad + 63) / 64), (unsigned)((g.l + 31) / 32),
+                          (unsigned)g.batch),
+                     dim3(256), 0, s, g.B, g.l, g.n, cols_pad, fb);
+  prof_record("oz_col_exp_kernel", s);
+  return check_launch("oz_exp");
 }
 
-size_t ozaki_workspace(int64_t m, int64_t n, int64_t l, int64_t batch, int slices) {
-  const int S = resolve_slices(slices);
+int ozaki_qd_default_slices();
+size_t ozaki_qd_workspace(int64_t m, int64_t n, int64_t l, int64_t batch, int slices);
+int launch_ozaki_qd(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, hipStream_t s);
+
+int ozaki_default_slices(int P) { return P == 4 ? ozaki_qd_default_slices() : 16; }
+
+bool ozaki_slices_ok(int P, int slices) {
+  if (slices == 0) return true;
+  return P == 4 ? ozaki_qd_workspace(1, 1, 1, 1, slices) != 0 : slices >= kMinS && slices <= kMaxS;
+}
+
+static size_t ozaki_dd_workspace(int64_t m, int64_t n, int64_t l, int64_t batch, int slices) {
+  const int S = slices == 0 ? ozaki_default_slices(2) : slices;
   if (S < kMinS || S > kMaxS || m <= 0 || n <= 0 || l <= 0) return 0;
   OzLayout o = oz_layout(m, n, l, S);
   return align256(o.a_bytes * batch) + align256(o.b_bytes * batch) +
          align256(sizeof(int) * (size_t)(batch * (o.rb + o.cb) * 32));
 }
 
-int launch_ozaki(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, hipStream_t s) {
+size_t ozaki_workspace(int P, int64_t m, int64_t n, int64_t l, int64_t batch, int slices) {
+  return P == 4 ? ozaki_qd_workspace(m, n, l, batch, slices)
+                : ozaki_dd_workspace(m, n, l, batch, slices);
+}
+
+int launch_ozaki(int P, const GemmBatch& g, int slices, void* ws, size_t ws_bytes,
+                 hipStream_t s) {
+  if (P == 4) return launch_ozaki_qd(g, slices, ws, ws_bytes, s);
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return DDQD_OK;
-  const int S = resolve_slices(slices);
+  const int S = slices == 0 ? ozaki_default_slices(2) : slices;
   if (S < kMinS || S > kMaxS)
     return set_error(DDQD_E_UNSUPPORTED, "Ozaki slices must be in %d..%d", kMinS, kMaxS);
-  if (ozaki_workspace(g.m, g.n, g.l, g.batch, S) > ws_bytes)
+  if (ozaki_dd_workspace(g.m, g.n, g.l, g.batch, S) > ws_bytes)
     return set_error(DDQD_E_WORKSPACE, "Ozaki workspace too small");
   char* w = (char*)ws;
   switch (S) {

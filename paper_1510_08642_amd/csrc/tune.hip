@@ -75,7 +75,7 @@ std::vector<Choice> candidates(int P, int64_t m, int64_t n, int64_t l, int base)
 }
 
 Choice default_choice(int P, int64_t m, int64_t n, int64_t l, int base) {
-  if (P == 4) {
+  if (P == 4 && base == DDQD_BASE_FMA) {
     int L = 0;
     while (L < kMaxTuneLevels && (min3(m, n, l) >> (L + 1)) >= 128) L++;
     return Choice{L ? DDQD_WINOGRAD : DDQD_BLOCK, L, 0, 0, 0.0};
@@ -193,8 +193,7 @@ int ddqd_tune_lookup(int precision, int64_t m, int64_t n, int64_t l, int base, i
   clear_error();
   if (!out) return set_error(DDQD_E_ARG, "out is NULL");
   if ((precision != 2 && precision != 4) || m < 0 || n < 0 || l < 0 ||
-      (base != DDQD_BASE_FMA && base != DDQD_BASE_OZAKI_I8) || slices < 0 || slices > 40 ||
-      (precision == 4 && base != DDQD_BASE_FMA))
+      (base != DDQD_BASE_FMA && base != DDQD_BASE_OZAKI_I8) || slices < 0 || slices > 40)
     return set_error(DDQD_E_ARG, "invalid tune lookup arguments");
   Choice c = default_choice(precision, m, n, l, base);
   {

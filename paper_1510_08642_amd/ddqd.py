@@ -174,9 +174,11 @@ def dd_gemm(A, B, C=None, *, alpha=1, beta=0, algo="block", levels=0, base="fma"
     return _gemm(2, A, B, C, alpha, beta, algo, levels, base, slices, ws)
 
 
-def qd_gemm(A, B, C=None, *, alpha=1, beta=0, algo="block", levels=0, slices=0, ws=None):
-    """C := beta*C + alpha*(A B) in quad-double; returns C."""
-    return _gemm(4, A, B, C, alpha, beta, algo, levels, "fma", slices, ws)
+def qd_gemm(A, B, C=None, *, alpha=1, beta=0, algo="block", levels=0, base="fma", slices=0,
+            ws=None):
+    """C := beta*C + alpha*(A B) in quad-double; returns C.  base="ozaki" runs
+    the leaves on INT8 matrix cores with `slices` digits (0 = 31)."""
+    return _gemm(4, A, B, C, alpha, beta, algo, levels, base, slices, ws)
 
 
 def getrf_workspace(n: int, panel=128, algo="winograd", levels=1, base="fma", P: int = 2) -> int:
@@ -198,10 +200,10 @@ def dd_getrf(A, *, panel=128, pivot="partial", algo="winograd", levels=1, base="
     return _getrf(2, A, panel, pivot, algo, levels, base, want_perm, ws, out)
 
 
-def qd_getrf(A, *, panel=128, pivot="partial", algo="winograd", levels=1, want_perm=True,
-             ws=None, out=None):
-    """As dd_getrf for a QD (4, n, n) tensor (FMA-based products only)."""
-    return _getrf(4, A, panel, pivot, algo, levels, "fma", want_perm, ws, out)
+def qd_getrf(A, *, panel=128, pivot="partial", algo="winograd", levels=1, base="fma",
+             want_perm=True, ws=None, out=None):
+    """As dd_getrf for a QD (4, n, n) tensor."""
+    return _getrf(4, A, panel, pivot, algo, levels, base, want_perm, ws, out)
 
 
 def _getrf(P, A, panel, pivot, algo, levels, base, want_perm, ws, out):

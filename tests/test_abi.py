@@ -82,8 +82,10 @@ def test_argument_errors(lib, fn):
     assert _call(lib, C=0x10000 + 8, **kw) == E["ALIAS"]
     # workspace for a Strassen level is required
     assert _call(lib, algo=2, levels=1, **kw) == E["WORKSPACE"]
-    if P == 4:
-        assert _call(lib, base=1, **kw) == E["UNSUPPORTED"]
+    # Ozaki leaves need their slice workspace; unsupported slice counts are
+    # rejected before any device work
+    assert _call(lib, base=1, **kw) == E["WORKSPACE"]
+    assert _call(lib, base=1, slices=24 if P == 2 else 20, **kw) == E["UNSUPPORTED"]
 
 
 def test_last_error_message(lib):
@@ -176,7 +178,8 @@ def test_tune_defaults_and_errors(lib):
     import ctypes as C
     r = ddqd.TuneResult()
     assert lib.ddqd_tune_lookup(3, 8, 8, 8, 0, 0, C.byref(r)) == E["ARG"]
-    assert lib.ddqd_tune_lookup(4, 8, 8, 8, 1, 0, C.byref(r)) == E["ARG"]
+    assert lib.ddqd_tune_lookup(4, 8, 8, 8, 2, 0, C.byref(r)) == E["ARG"]
+    assert ddqd.tune_lookup(4, 1024, 1024, 1024, base="ozaki")["algo"] == "block"
     assert lib.ddqd_tune_lookup(2, 8, 8, 8, 0, 0, None) == E["ARG"]
     # reps out of range is rejected before any device work
     assert lib.dd_gemm_tune(8, 8, 8, 0x10000, 8, 64, 0x20000, 8, 64, 0x30000, 8, 64, 0, 0, 0,
@@ -192,6 +195,19 @@ def test_auto_workspace_covers_every_candidate(lib):
                     assert auto >= f(m, n, l, algo, levels, 0, 0)
     o = lib.dd_gemm_workspace(512, 512, 512, 4, 0, 1, 0)
     assert o >= lib.dd_gemm_workspace(512, 512, 512, 3, 3, 1, 0)
+    qo = lib.qd_gemm_workspace(512, 512, 512, 4, 0, 1, 0)
+    assert qo >= lib.qd_gemm_workspace(512, 512, 512, 3, 3, 1, 0)
+
+
+def test_qd_ozaki_workspace(lib):
+    """QD Ozaki leaves: S INT8 slices of A and B in 32x32 fragment blocks
+    plus the row / column exponents; slice counts outside 28..31 give none."""
+    n = 256
+    ws = lib.qd_gemm_workspace(n, n, n, 1, 0, 1, 0)
+    assert ws >= 2 * 31 * n * n + 4 * 2 * n
+    assert lib.qd_gemm_workspace(n, n, n, 1, 0, 1, 28) < ws
+    assert lib.qd_gemm_workspace(n, n, n, 1, 0, 1, 20) == 0
+    assert lib.qd_gemm_workspace(n, n, n, 1, 0, 1, 16) == 0
 
 
 def test_qd_lu_argument_errors(lib):
@@ -200,8 +216,10 @@ def test_qd_lu_argument_errors(lib):
     A, ip, info = 0x10000, 0x40000, 0x50000
     call = lambda base, n=8, lda=8: lib.qd_getrf(n, A, lda, lda * n, ip, None, info, 4, 1, 1, 0,
                                                  base, None, 0, None)
-    assert call(1) == E["UNSUPPORTED"]              # Ozaki products are DD only
     assert call(0, lda=4) == E["ARG"]
-    assert lib.qd_getrf_workspace(64, 16, 3, 1, 1) == C.c_size_t(-1).value
+    assert call(2) == E["ARG"]
+    assert lib.qd_getrf_workspace(64, 16, 3, 1, 2) == C.c_size_t(-1).value
+    # QD trailing updates may run on Ozaki leaves (31 slices by default)
+    assert lib.qd_getrf_workspace(1024, 128, 3, 1, 1) > lib.qd_getrf_workspace(1024, 128, 3, 1, 0)
     assert lib.qd_getrs_workspace(100, 3) >= 4 * 8 * 100 * 3
     assert lib.qd_getrs_workspace(100, 3) > lib.dd_getrs_workspace(100, 3)

@@ -143,3 +143,29 @@ def test_full_size_residual(dd, n, panel, algo, levels):
     normA = np.max(np.sum(np.abs(A[0]), axis=1))
     res = np.max(np.abs(r)) / (normA * np.max(np.abs(x[0])))
     assert res <= n * 2.0 ** -200, res
+
+
+def test_ozaki_trailing_updates(dd):
+    """Trailing products on QD Ozaki leaves (31 slices): the same pivots as
+    the oracle's QD LU and factors within the same bound; residual at n = 1024."""
+    n = 150
+    g = inputs.rng(530)
+    A = inputs.qd_lu_matrix(n, g, boost=False)
+    LU, ipiv, perm, info = factor(dd, A, panel=16, algo="block", levels=0, base="ozaki")
+    LUo, ipo, info_o = oracle.getrf(A, panel=16, pivot=True, algo="block", levels=0)
+    assert info == info_o == 0
+    assert np.array_equal(ipiv, ipo)
+    assert np.max(vdiff(LU, LUo)) <= n * 2.0 ** -196 * np.max(np.abs(LUo[0]))
+    n = 1024
+    g = inputs.rng(2)
+    A = inputs.qd_lu_matrix(n, g)
+    b = inputs.qd_uniform(n, 1, g)
+    LU, ipiv, perm, info = factor(dd, A, panel=128, algo="block", levels=0, base="ozaki")
+    assert info == 0
+    x = solve(dd, LU, ipiv, b, perm)
+    rows = np.arange(0, n, 37)
+    r = oracle.exact_entries(A[:, rows, :], x, np.arange(len(rows)),
+                             np.zeros(len(rows), dtype=np.int64), kout=1, alpha=-1,
+                             C0=b[:, rows, :])[0]
+    normA = np.max(np.sum(np.abs(A[0]), axis=1))
+    assert np.max(np.abs(r)) / (normA * np.max(np.abs(x[0]))) <= n * 2.0 ** -200
