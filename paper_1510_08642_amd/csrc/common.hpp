@@ -47,6 +47,21 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblk) {
   return x * q + (x < r ? x : r) + local;
 }
 
+// Row and column of logical tile t in a rows x cols grid whose tiles are
+// taken in bands of `band` rows, column by column inside a band.  The tiles
+// one XCD runs at the same time (consecutive t) then form a compact block
+// (band rows by a few columns) that shares A row panels and B column panels
+// in its L2, instead of one long row.
+__device__ __forceinline__ void banded_tile(int64_t t, int64_t rows, int64_t cols, int64_t band,
+                                            int64_t& r, int64_t& c) {
+  const int64_t per = band * cols;
+  const int64_t first = (t / per) * band;
+  const int64_t h = rows - first < band ? rows - first : band;
+  const int64_t k = t % per;
+  r = first + k % h;
+  c = k / h;
+}
+
 // Host-side status plumbing shared by the launchers.
 int set_error(int status, const char* fmt, ...);
 int check_launch(const char* what);

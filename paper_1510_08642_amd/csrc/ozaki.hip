@@ -1,6 +1,7 @@
 // DD matrix product on INT8 matrix cores by an Ozaki-style split
 // (a base kernel for the leaves of Sec. 2's algorithms; not in the paper,
-// which predates it).
+// which predates it).  Steps 1 and 2 run in ozaki_split.hip, steps 3 and 4
+// here.
 //
 // 1. Scale.  For row i of A take e_i with max_k |a_ik| < 2^(e_i - 1) (from the
 //    leading components), for column j of B likewise f_j; a'_ik = a_ik 2^-e_i
@@ -28,187 +29,22 @@
 #include "ddqd.h"
 #include "common.hpp"
 #include "eft.hpp"
+#include "ozaki.hpp"
 
 #pragma clang fp contract(off)
 
 namespace ddqd {
-
-int launch_oz_exponents(const GemmBatch& g, int64_t rows_pad, int64_t cols_pad, int* ea, int* fb,
-                        hipStream_t s);
 
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kFrag = 1024;          // bytes of one 32x32 INT8 fragment block
+constexpr int kFrag = kOzFrag;
 constexpr int64_t kKChunk = 16384;   // K per exact INT32 accumulation
 constexpr int kMinS = 8, kMaxS = 20;
 
-struct OzLayout {
-  int64_t m, n, l;       // problem
-  int64_t rb, cb, kb;    // 32-blocks: rows of A (even), columns of B (even), K
-  int S;
-  int64_t a_bytes, b_bytes;  // per batch entry
-};
-
-OzLayout oz_layout(int64_t m, int64_t n, int64_t l, int S) {
-  OzLayout o;
-  o.m = m;
-  o.n = n;
-  o.l = l;
-  o.S = S;
-  o.rb = ((m + 63) / 64) * 2;
-  o.cb = ((n + 63) / 64) * 2;
-  o.kb = (l + 31) / 32;
-  o.a_bytes = o.rb * o.kb * S * (int64_t)kFrag;
-  o.b_bytes = o.cb * o.kb * S * (int64_t)kFrag;
-  return o;
-}
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// Exponents e with max |leading component| < 2^(e-1): one wave per row of A
-// (padded rows get 1).  The same launch sets B's column exponents to the
-// sentinel the column pass raises atomically.
-constexpr int kNoExp = -(1 << 20);
-
-__global__ __launch_bounds__(256) void oz_row_exp_kernel(CMat A, int64_t m, int64_t l,
-                                                         int64_t rows_pad, int* e, int* fb,
-                                                         int64_t nfb) {
-  const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  const int64_t b = blockIdx.y;
-  const int lane = threadIdx.x % 64;
-  if (b == 0)
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nfb;
-         i += (int64_t)gridDim.x * 256)
-      fb[i] = kNoExp;
-  if (r >= rows_pad) return;
-  double mx = 0.0;
-  if (r < m) {
-    const double* p = A.p + b * A.bstride + r * A.ld;
-    int64_t k = lane;
-    for (; k + 192 < l; k += 256)
-      mx = fmax(fmax(mx, fabs(p[k])),
-                fmax(fabs(p[k + 64]), fmax(fabs(p[k + 128]), fabs(p[k + 192]))));
-    for (; k < l; k += 64) mx = fmax(mx, fabs(p[k]));
-  }
-  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-  if (lane == 0) {
-    int ex = 0;
-    if (mx > 0.0) frexp(mx, &ex);
-    e[b * rows_pad + r] = ex + 1;
-  }
-}
-
-// Columns of B: all-zero columns keep the sentinel kNoExp (the slicing then
-// scales zeros, which stay zero); otherwise the atomic maximum, over slabs of
-// 32 rows, of the exponent + 1 (exponents are monotone in |x|, so the maximum
-// of the partial exponents is the exponent of the maximum, in any order).
-__global__ __launch_bounds__(256) void oz_col_exp_kernel(CMat B, int64_t l, int64_t n,
-                                                         int64_t cols_pad, int* e) {
-  __shared__ double red[4][64];
-  const int c_in = threadIdx.x % 64, r = threadIdx.x / 64;
-  const int64_t c = (int64_t)blockIdx.x * 64 + c_in;
-  const int64_t k0 = (int64_t)blockIdx.y * 32 + r * 8;
-  const int64_t b = blockIdx.z;
-  double mx = 0.0;
-  if (c < n) {
-    const double* p = B.p + b * B.bstride + c;
-#pragma unroll
-    for (int q = 0; q < 8; q++)
-      if (k0 + q < l) mx = fmax(mx, fabs(p[(k0 + q) * B.ld]));
-  }
-  red[r][c_in] = mx;
-  __syncthreads();
-  if (r == 0 && c < cols_pad) {
-    mx = fmax(fmax(red[0][c_in], red[1][c_in]), fmax(red[2][c_in], red[3][c_in]));
-    if (mx > 0.0) {
-      int ex;
-      frexp(mx, &ex);
-      atomicMax(&e[b * cols_pad + c], ex + 1);
-    }
-  }
-}
-
-// Slicing.  A workgroup takes 32 lines (rows of A or columns of B) by 128 k
-// (four 32-k blocks): the DD values are read with coalesced loads (along k
-// for A, along the columns for B) into an LDS tile, then each wave slices one
-// 32x32 block and each lane one fragment slot: 16 consecutive k of one line,
-// exactly what one lane of the 32x32x32 MFMA holds, so each slice is one
-// 16-byte store and a wave writes a whole 1 KB fragment.  Both operands in
-// one launch (blockIdx.y: 0 = A, 1 = B).  Digits of a scaled DD value r
-// (|r| < 1/2): d_t = rint(2^7 r_{t-1}), r_t = 2^7 r_{t-1} - d_t, formed
-// exactly: the fractional part of the high word is exact and is either 0 or
-// at least ulp(high) >= 2 |low|, FastTwoSum's precondition.
-constexpr int kSliceK = 128;  // k per slicing workgroup (four 32-k blocks)
-
-template <int S>
-__global__ __launch_bounds__(256) void oz_slice_kernel(CMat A, CMat B, int64_t m, int64_t n,
-                                                       int64_t l, OzLayout o, const int* ea,
-                                                       const int* fb, signed char* Asl,
-                                                       signed char* Bsl) {
-  __shared__ double tile[2][32][kSliceK + 1];
-  const int side = blockIdx.y;
-  const int64_t b = blockIdx.z;
-  const int64_t nblk32 = side == 0 ? o.rb : o.cb;
-  const int64_t kgroups = (o.kb + 3) / 4;
-  if ((int64_t)blockIdx.x >= nblk32 * kgroups) return;  // uniform per workgroup
-  const int64_t blk = blockIdx.x / kgroups, kg = blockIdx.x % kgroups;
-  const int64_t line0 = blk * 32, kbase = kg * kSliceK;
-  const CMat X = side == 0 ? A : B;
-  const int64_t lines_live = side == 0 ? m : n;
-  const double* base = X.p + b * X.bstride;
-  const int t = threadIdx.x;
-  // coalesced loads of the 32 x 128 tile (16 values per plane per thread)
-  double vh[16], vl[16];
-#pragma unroll
-  for (int j = 0; j < 16; j++) {
-    const int e = t + 256 * j;
-    const int ln = side == 0 ? e / kSliceK : e % 32;
-    const int kk = side == 0 ? e % kSliceK : e / 32;
-    const int64_t line = line0 + ln, k = kbase + kk;
-    const bool in = line < lines_live && k < l;
-    const int64_t idx = side == 0 ? (in ? line * X.ld + k : 0) : (in ? k * X.ld + line : 0);
-    vh[j] = in ? base[idx] : 0.0;
-    vl[j] = in ? base[X.ps + idx] : 0.0;
-  }
-#pragma unroll
-  for (int j = 0; j < 16; j++) {
-    const int e = t + 256 * j;
-    const int ln = side == 0 ? e / kSliceK : e % 32;
-    const int kk = side == 0 ? e % kSliceK : e / 32;
-    tile[0][ln][kk] = vh[j];
-    tile[1][ln][kk] = vl[j];
-  }
-  __syncthreads();
-  const int w = t / 64, lane = t % 64;
-  const int64_t kb = kg * 4 + w;
-  if (kb >= o.kb) return;
-  const int ln = lane % 32, k0 = w * 32 + 16 * (lane / 32);
-  const int ex = (side == 0 ? ea : fb)[b * (nblk32 * 32) + line0 + ln];
-  double rh[16], rl[16];
-#pragma unroll
-  for (int q = 0; q < 16; q++) {
-    rh[q] = ldexp(tile[0][ln][k0 + q], -ex);
-    rl[q] = ldexp(tile[1][ln][k0 + q], -ex);
-  }
-  signed char* dst = (side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
-                     (blk * o.kb + kb) * S * (int64_t)kFrag + lane * 16;
-#pragma unroll 2
-  for (int s = 0; s < S; s++) {
-    uint32_t x[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int q = 0; q < 16; q++) {
-      const double h = rh[q] * 128.0, lo = rl[q] * 128.0;
-      const double d = rint(h);
-      x[q / 4] |= (uint32_t)(uint8_t)(signed char)(int)d << (8 * (q % 4));
-      fast_two_sum(h - d, lo, rh[q], rl[q]);
-    }
-    *reinterpret_cast<v4i*>(dst + s * (int64_t)kFrag) = v4i{(int)x[0], (int)x[1], (int)x[2],
-                                                           (int)x[3]};
-  }
-}
+size_t align256(size_t x) { return oz_align256(x); }
 
 // The product kernel: 4 waves (2x2) per 64x64 tile of C, one 32x32 block per
 // wave with S INT32 diagonal accumulators (16 S accumulator registers).
@@ -229,7 +65,8 @@ __global__ __launch_bounds__(256) void oz_gemm_kernel(GemmBatch g, OzLayout o,
   const int64_t t = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
   const int64_t per = tiles_m * tiles_n;
   const int64_t b = t / per;
-  const int64_t tm = (t % per) / tiles_n, tn = (t % per) % tiles_n;
+  int64_t tm, tn;
+  banded_tile(t % per, tiles_m, tiles_n, 4, tm, tn);
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int wr = w / 2, wc = w % 2;
   const int64_t rb = 2 * tm + wr, cb = 2 * tn + wc;
@@ -377,25 +214,13 @@ __global__ __launch_bounds__(256) void oz_gemm_kernel(GemmBatch g, OzLayout o,
 
 template <int S>
 int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
-  OzLayout o = oz_layout(g.m, g.n, g.l, S);
-  signed char* Asl = (signed char*)ws;
-  signed char* Bsl = (signed char*)(ws + align256(o.a_bytes * g.batch));
-  int* ea = (int*)(ws + align256(o.a_bytes * g.batch) + align256(o.b_bytes * g.batch));
-  int* fb = ea + g.batch * o.rb * 32;
-  const int64_t rows_pad = o.rb * 32, cols_pad = o.cb * 32;
-  if (g.batch > 65535) return set_error(DDQD_E_UNSUPPORTED, "batch too large");
-  if ((o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 3) / 4) > INT32_MAX ||
-      (g.l + 31) / 32 > 65535)
-    return set_error(DDQD_E_UNSUPPORTED, "matrix too large for one Ozaki launch");
-  int rc = launch_oz_exponents(g, rows_pad, cols_pad, ea, fb, s);
+  OzLayout o = oz_layout(2, g.m, g.n, g.l, S);
+  const OzWs w = oz_ws(ws, o, g.batch);
+  signed char *Asl = w.Asl, *Bsl = w.Bsl;
+  const int *ea = w.ea, *fb = w.fb;
+  int rc = launch_oz_exponents(g, o, w, s);
   if (rc) return rc;
-  const int64_t sblocks = (o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 3) / 4);
-  prof_begin(s);
-  hipLaunchKernelGGL(oz_slice_kernel<S>, dim3((unsigned)sblocks, 2, (unsigned)g.batch),
-                     dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)ea, (const int*)fb,
-                     Asl, Bsl);
-  prof_record("oz_slice_kernel", s);
-  if ((rc = check_launch("oz_slice_kernel"))) return rc;
+  if ((rc = launch_oz_slice(2, g, o, w, s))) return rc;
   const int64_t tm = o.rb / 2, tn = o.cb / 2;
   const int64_t nblk = tm * tn * g.batch;
   if (nblk > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "grid too large");
@@ -413,24 +238,6 @@ int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
 
 }  // namespace
 
-// Row exponents of A (rows_pad per batch entry, padded rows 1) and column
-// exponents of B (cols_pad per entry; all-zero columns keep the sentinel).
-int launch_oz_exponents(const GemmBatch& g, int64_t rows_pad, int64_t cols_pad, int* ea, int* fb,
-                        hipStream_t s) {
-  const int64_t nfb = cols_pad * g.batch;
-  prof_begin(s);
-  hipLaunchKernelGGL(oz_row_exp_kernel, dim3((unsigned)((rows_pad + 3) / 4), (unsigned)g.batch),
-                     dim3(256), 0, s, g.A, g.m, g.l, rows_pad, ea, fb, nfb);
-  prof_record("oz_row_exp_kernel", s);
-  prof_begin(s);
-  hipLaunchKernelGGL(oz_col_exp_kernel,
-                     dim3((unsigned)((cols_pad + 63) / 64), (unsigned)((g.l + 31) / 32),
-                          (unsigned)g.batch),
-                     dim3(256), 0, s, g.B, g.l, g.n, cols_pad, fb);
-  prof_record("oz_col_exp_kernel", s);
-  return check_launch("oz_exp");
-}
-
 int ozaki_qd_default_slices();
 size_t ozaki_qd_workspace(int64_t m, int64_t n, int64_t l, int64_t batch, int slices);
 int launch_ozaki_qd(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, hipStream_t s);
@@ -445,9 +252,8 @@ bool ozaki_slices_ok(int P, int slices) {
 static size_t ozaki_dd_workspace(int64_t m, int64_t n, int64_t l, int64_t batch, int slices) {
   const int S = slices == 0 ? ozaki_default_slices(2) : slices;
   if (S < kMinS || S > kMaxS || m <= 0 || n <= 0 || l <= 0) return 0;
-  OzLayout o = oz_layout(m, n, l, S);
-  return align256(o.a_bytes * batch) + align256(o.b_bytes * batch) +
-         align256(sizeof(int) * (size_t)(batch * (o.rb + o.cb) * 32));
+  OzLayout o = oz_layout(2, m, n, l, S);
+  return oz_workspace_bytes(o, batch);
 }
 
 size_t ozaki_workspace(int P, int64_t m, int64_t n, int64_t l, int64_t batch, int slices) {

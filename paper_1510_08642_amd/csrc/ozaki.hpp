@@ -1,0 +1,73 @@
+// Shared pieces of the Ozaki-split products (DD: ozaki.hip, QD:
+// ozaki_qd.hip): the workspace layout of the INT8 slice stacks and the two
+// preparation launches (exponents, slicing) in ozaki_split.hip.
+#pragma once
+#include "common.hpp"
+
+namespace ddqd {
+
+constexpr int kOzFrag = 1024;  // bytes of one 32x32 INT8 fragment block
+
+// Slice stacks of one batch entry: for every 32-line block (rows of A,
+// columns of B) and 32-k block, S fragments of 1 KB in the order of the
+// 32x32x32 MFMA (lane l: line l % 32, k = 16 (l / 32) + 0..15).
+struct OzLayout {
+  int64_t m, n, l;
+  int64_t rb, cb, kb;  // 32-blocks: rows of A, columns of B, K
+  int S;
+  int64_t a_bytes, b_bytes;  // per batch entry
+};
+
+// DD products use 64x64 tiles (rb, cb even), QD products 32x32 blocks.
+inline OzLayout oz_layout(int P, int64_t m, int64_t n, int64_t l, int S) {
+  OzLayout o;
+  o.m = m;
+  o.n = n;
+  o.l = l;
+  o.S = S;
+  o.rb = P == 2 ? ((m + 63) / 64) * 2 : (m + 31) / 32;
+  o.cb = P == 2 ? ((n + 63) / 64) * 2 : (n + 31) / 32;
+  o.kb = (l + 31) / 32;
+  o.a_bytes = o.rb * o.kb * S * (int64_t)kOzFrag;
+  o.b_bytes = o.cb * o.kb * S * (int64_t)kOzFrag;
+  return o;
+}
+
+inline size_t oz_align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace of one Ozaki product (batch entries): the slice stacks of A and
+// B, the row exponents of A (rb * 32 ints per entry), the column exponents of
+// B (cb * 32) and the column maxima's exponents per 32-row slab of B
+// (kb * cb * 32).
+struct OzWs {
+  signed char *Asl, *Bsl;
+  int *ea, *fb, *part;
+};
+inline size_t oz_workspace_bytes(const OzLayout& o, int64_t batch) {
+  return oz_align256(o.a_bytes * batch) + oz_align256(o.b_bytes * batch) +
+         oz_align256(sizeof(int) * (size_t)(batch * (o.rb + o.cb) * 32)) +
+         oz_align256(sizeof(int) * (size_t)(batch * o.kb * o.cb * 32));
+}
+inline OzWs oz_ws(char* ws, const OzLayout& o, int64_t batch) {
+  OzWs w;
+  w.Asl = (signed char*)ws;
+  ws += oz_align256(o.a_bytes * batch);
+  w.Bsl = (signed char*)ws;
+  ws += oz_align256(o.b_bytes * batch);
+  w.ea = (int*)ws;
+  w.fb = w.ea + batch * o.rb * 32;
+  ws += oz_align256(sizeof(int) * (size_t)(batch * (o.rb + o.cb) * 32));
+  w.part = (int*)ws;
+  return w;
+}
+
+// Exponents e with max |leading component| < 2^(e - 1) (all-zero lines get a
+// sentinel far below any exponent, padded rows 1): of A's rows into w.ea, and
+// of B's columns per 32-row slab into w.part.  One launch.
+int launch_oz_exponents(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s);
+
+// The S digits of every scaled entry of A and B (P = 2 DD, 4 QD); also
+// reduces the slab exponents of B into w.fb, which the product reads.
+int launch_oz_slice(int P, const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s);
+
+}  // namespace ddqd

@@ -1,17 +1,21 @@
 // QD matrix product on INT8 matrix cores by the Ozaki-style split of the DD
 // form, carried to S (default 31) digits per operand.  A base kernel for the
 // leaves of Sec. 2's algorithms in QD (Sec. 3, Table 2's precision); not in
-// the paper, which predates it.
+// the paper, which predates it.  Steps 1 and 2 run in ozaki_split.hip,
+// steps 3 and 4 here.
 //
 // 1. Scale: the DD form's row exponents of A and column exponents of B (from
 //    the leading components), a'_ik = a_ik 2^-e_i, b'_kj = b_kj 2^-f_j.
 // 2. Slice: each scaled QD value is written as sum_{t=1..S} d_t 2^-7t + r,
-//    d_t = rint(2^7 r_{t-1}) in [-64, 64].  The remainder stays an exact
-//    four-term expansion: after a digit is taken from the leading term, one
-//    bottom-up TwoSum pass (error-free) renormalises the four terms, so the
-//    leading term is the remainder to within a few ulps and the next digit
-//    is its nearest integer.  The digits are stored as INT8 in the fragment
-//    order of the 32x32x32 MFMA (lane l: line l % 32, k = 16 (l / 32) + 0..15).
+//    d_t in [-64, 64].  The remainder stays an exact four-term expansion:
+//    runs of six digits d = rint(2^7 r0), r0 := 2^7 r0 - d are taken from the
+//    leading term alone (exact steps; the lower terms stand for themselves
+//    times 2^(7j)), then the lower terms are scaled by 2^42 and one
+//    bottom-up TwoSum pass (error-free) renormalises the four terms, leaving
+//    the rest within about an ulp of the leading term.  Inside a run the
+//    ignored part is below 2^-12 of a digit unit, so digits stay in
+//    [-64, 64].  The digits are stored as INT8 in the fragment order of the
+//    32x32x32 MFMA (lane l: line l % 32, k = 16 (l / 32) + 0..15).
 // 3. Products: P_d = sum_{t+u=d} A_t B_u for d = 0..S-1, exact INT32 sums
 //    (|P_d| <= S 64^2 l < 2^31 for K chunks of 2^14 and S <= 31).  S 32x32
 //    INT32 accumulators (16 S registers a lane) do not fit one wave, so the
@@ -31,45 +35,22 @@
 #include "common.hpp"
 #include "eft.hpp"
 #include "qd.hpp"
+#include "ozaki.hpp"
 
 #pragma clang fp contract(off)
 
 namespace ddqd {
-
-int launch_oz_exponents(const GemmBatch& g, int64_t rows_pad, int64_t cols_pad, int* ea, int* fb,
-                        hipStream_t s);
 
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kFrag = 1024;          // bytes of one 32x32 INT8 fragment block
+constexpr int kFrag = kOzFrag;
 constexpr int64_t kKChunk = 16384;   // K per exact INT32 accumulation
 constexpr int kMinS = 28, kMaxS = 31;
 
-struct OzqLayout {
-  int64_t m, n, l;
-  int64_t rb, cb, kb;  // 32-blocks: rows of A, columns of B, K
-  int S;
-  int64_t a_bytes, b_bytes;  // per batch entry
-};
-
-OzqLayout ozq_layout(int64_t m, int64_t n, int64_t l, int S) {
-  OzqLayout o;
-  o.m = m;
-  o.n = n;
-  o.l = l;
-  o.S = S;
-  o.rb = (m + 31) / 32;
-  o.cb = (n + 31) / 32;
-  o.kb = (l + 31) / 32;
-  o.a_bytes = o.rb * o.kb * S * (int64_t)kFrag;
-  o.b_bytes = o.cb * o.kb * S * (int64_t)kFrag;
-  return o;
-}
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+size_t align256(size_t x) { return oz_align256(x); }
 
 // ---- the split of the diagonals over the four waves -------------------------
 
@@ -91,92 +72,6 @@ constexpr int slot0(int S, int w) {
   return s;
 }
 constexpr int nslots(int S) { return slot0(S, 4); }
-
-// ---- slicing ----------------------------------------------------------------
-
-// A workgroup takes 32 lines (rows of A or columns of B) by 64 k (two 32-k
-// blocks): the four planes are read with coalesced loads into LDS; wave w
-// then slices k block w / 2, half w % 2 of every lane's 16-k fragment slot
-// (8 values of one line per lane, 8 bytes per digit).
-constexpr int kSliceK = 64;
-
-template <int S>
-__global__ __launch_bounds__(256) void ozq_slice_kernel(CMat A, CMat B, int64_t m, int64_t n,
-                                                        int64_t l, OzqLayout o, const int* ea,
-                                                        const int* fb, signed char* Asl,
-                                                        signed char* Bsl) {
-  __shared__ double tile[4][32][kSliceK + 1];
-  const int side = blockIdx.y;
-  const int64_t b = blockIdx.z;
-  const int64_t nblk32 = side == 0 ? o.rb : o.cb;
-  const int64_t kgroups = (o.kb + 1) / 2;
-  if ((int64_t)blockIdx.x >= nblk32 * kgroups) return;  // uniform per workgroup
-  const int64_t blk = blockIdx.x / kgroups, kg = blockIdx.x % kgroups;
-  const int64_t line0 = blk * 32, kbase = kg * kSliceK;
-  const CMat X = side == 0 ? A : B;
-  const int64_t lines_live = side == 0 ? m : n;
-  const double* base = X.p + b * X.bstride;
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int c = 0; c < 4; c++) {
-    double v[8];
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const int e = t + 256 * j;
-      const int ln = side == 0 ? e / kSliceK : e % 32;
-      const int kk = side == 0 ? e % kSliceK : e / 32;
-      const int64_t line = line0 + ln, k = kbase + kk;
-      const bool in = line < lines_live && k < l;
-      const int64_t idx = in ? (side == 0 ? line * X.ld + k : k * X.ld + line) : 0;
-      v[j] = in ? base[c * X.ps + idx] : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const int e = t + 256 * j;
-      const int ln = side == 0 ? e / kSliceK : e % 32;
-      const int kk = side == 0 ? e % kSliceK : e / 32;
-      tile[c][ln][kk] = v[j];
-    }
-  }
-  __syncthreads();
-  const int w = t / 64, lane = t % 64;
-  const int64_t kb = kg * 2 + w / 2;
-  if (kb >= o.kb) return;
-  const int half = w % 2;
-  const int ln = lane % 32, k0 = (w / 2) * 32 + 16 * (lane / 32) + 8 * half;
-  const int ex = (side == 0 ? ea : fb)[b * (nblk32 * 32) + line0 + ln];
-  double r0[8], r1[8], r2[8], r3[8];
-#pragma unroll
-  for (int q = 0; q < 8; q++) {
-    r0[q] = ldexp(tile[0][ln][k0 + q], -ex);
-    r1[q] = ldexp(tile[1][ln][k0 + q], -ex);
-    r2[q] = ldexp(tile[2][ln][k0 + q], -ex);
-    r3[q] = ldexp(tile[3][ln][k0 + q], -ex);
-  }
-  signed char* dst = (side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
-                     (blk * o.kb + kb) * S * (int64_t)kFrag + lane * 16 + 8 * half;
-#pragma unroll 1
-  for (int s = 0; s < S; s++) {
-    uint32_t x[2] = {0u, 0u};
-#pragma unroll
-    for (int q = 0; q < 8; q++) {
-      const double h = r0[q] * 128.0;
-      const double d = rint(h);
-      x[q / 4] |= (uint32_t)(uint8_t)(signed char)(int)d << (8 * (q % 4));
-      // remainder (h - d) + 128 (r1 + r2 + r3), all terms exact; one
-      // bottom-up TwoSum pass keeps the sum and brings it to the front
-      double a2, a3, a1, b2, a0, b1;
-      two_sum(r2[q] * 128.0, r3[q] * 128.0, a2, a3);
-      two_sum(r1[q] * 128.0, a2, a1, b2);
-      two_sum(h - d, a1, a0, b1);
-      r0[q] = a0;
-      r1[q] = b1;
-      r2[q] = b2;
-      r3[q] = a3;
-    }
-    *reinterpret_cast<uint2*>(dst + s * (int64_t)kFrag) = uint2{x[0], x[1]};
-  }
-}
 
 // ---- products ---------------------------------------------------------------
 
@@ -262,7 +157,7 @@ __device__ __forceinline__ void ozq_wave(const Stage<S>& stage, int lane, int64_
 }
 
 template <int S>
-__global__ __launch_bounds__(256) void ozq_gemm_kernel(GemmBatch g, OzqLayout o,
+__global__ __launch_bounds__(256) void ozq_gemm_kernel(GemmBatch g, OzLayout o,
                                                        const signed char* Asl,
                                                        const signed char* Bsl, const int* ea,
                                                        const int* fb, int64_t kc0, int64_t kc1,
@@ -274,7 +169,8 @@ __global__ __launch_bounds__(256) void ozq_gemm_kernel(GemmBatch g, OzqLayout o,
   const int64_t t = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
   const int64_t per = o.rb * o.cb;
   const int64_t b = t / per;
-  const int64_t rbi = (t % per) / o.cb, cbi = (t % per) % o.cb;
+  int64_t rbi, cbi;
+  banded_tile(t % per, o.rb, o.cb, 4, rbi, cbi);
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int wu = __builtin_amdgcn_readfirstlane(w);
 
@@ -338,23 +234,13 @@ __global__ __launch_bounds__(256) void ozq_gemm_kernel(GemmBatch g, OzqLayout o,
 
 template <int S>
 int run_ozaki_qd(const GemmBatch& g, char* ws, hipStream_t s) {
-  OzqLayout o = ozq_layout(g.m, g.n, g.l, S);
-  signed char* Asl = (signed char*)ws;
-  signed char* Bsl = (signed char*)(ws + align256(o.a_bytes * g.batch));
-  int* ea = (int*)(ws + align256(o.a_bytes * g.batch) + align256(o.b_bytes * g.batch));
-  int* fb = ea + g.batch * o.rb * 32;
-  if (g.batch > 65535) return set_error(DDQD_E_UNSUPPORTED, "batch too large");
-  const int64_t sblocks = (o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 1) / 2);
-  if (sblocks > INT32_MAX || o.kb > 65535)
-    return set_error(DDQD_E_UNSUPPORTED, "matrix too large for one Ozaki launch");
-  int rc = launch_oz_exponents(g, o.rb * 32, o.cb * 32, ea, fb, s);
+  OzLayout o = oz_layout(4, g.m, g.n, g.l, S);
+  const OzWs w = oz_ws(ws, o, g.batch);
+  signed char *Asl = w.Asl, *Bsl = w.Bsl;
+  const int *ea = w.ea, *fb = w.fb;
+  int rc = launch_oz_exponents(g, o, w, s);
   if (rc) return rc;
-  prof_begin(s);
-  hipLaunchKernelGGL(ozq_slice_kernel<S>, dim3((unsigned)sblocks, 2, (unsigned)g.batch),
-                     dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)ea, (const int*)fb,
-                     Asl, Bsl);
-  prof_record("ozq_slice_kernel", s);
-  if ((rc = check_launch("ozq_slice_kernel"))) return rc;
+  if ((rc = launch_oz_slice(4, g, o, w, s))) return rc;
   const int64_t nblk = o.rb * o.cb * g.batch;
   if (nblk > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "grid too large");
   for (int64_t kc0 = 0; kc0 < o.kb; kc0 += kKChunk / 32) {
@@ -376,9 +262,8 @@ int ozaki_qd_default_slices() { return 31; }
 size_t ozaki_qd_workspace(int64_t m, int64_t n, int64_t l, int64_t batch, int slices) {
   const int S = slices == 0 ? ozaki_qd_default_slices() : slices;
   if (S < kMinS || S > kMaxS || m <= 0 || n <= 0 || l <= 0) return 0;
-  OzqLayout o = ozq_layout(m, n, l, S);
-  return align256(o.a_bytes * batch) + align256(o.b_bytes * batch) +
-         align256(sizeof(int) * (size_t)(batch * (o.rb + o.cb) * 32));
+  OzLayout o = oz_layout(4, m, n, l, S);
+  return oz_workspace_bytes(o, batch);
 }
 
 int launch_ozaki_qd(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, hipStream_t s) {

@@ -1,0 +1,387 @@
+// Preparation of the Ozaki-split products (DD and QD): the scaling exponents
+// of A's rows and B's columns, and the slicing of every scaled entry into S
+// signed 7-bit digits stored as INT8 in MFMA fragment order.  The products
+// themselves are in ozaki.hip (DD) and ozaki_qd.hip (QD).
+#include "ddqd.h"
+#include "common.hpp"
+#include "eft.hpp"
+#include "ozaki.hpp"
+
+#pragma clang fp contract(off)
+
+namespace ddqd {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Exponents e with max |leading component| < 2^(e-1), in one launch:
+// workgroups [0, nrow) take four rows of A each (one wave per row, all of a
+// lane's loads in flight before the reduction; padded rows get 1); the others
+// take 64 columns by one 32-row slab of B and store the exponent of each
+// column's slab maximum (kNoExp for an all-zero slab).  Exponents are
+// monotone in |x|, so the maximum over slabs of these is the exponent of the
+// column maximum; the slicing kernel reduces them.
+constexpr int kNoExp = -(1 << 20);
+
+__global__ __launch_bounds__(256) void oz_exp_kernel(CMat A, CMat B, int64_t m, int64_t n,
+                                                     int64_t l, OzLayout o, int64_t nrow,
+                                                     int* ea, int* part) {
+  const int64_t b = blockIdx.y;
+  const int lane = threadIdx.x % 64;
+  if ((int64_t)blockIdx.x < nrow) {
+    const int64_t rows_pad = o.rb * 32;
+    const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    if (r >= rows_pad) return;
+    double mx = 0.0;
+    if (r < m) {
+      const double* p = A.p + b * A.bstride + r * A.ld;
+      int64_t k = lane;
+      for (; k + 960 < l; k += 1024) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) v[q] = p[k + 64 * q];
+#pragma unroll
+        for (int q = 0; q < 16; q++) mx = fmax(mx, fabs(v[q]));
+      }
+      for (; k < l; k += 64) mx = fmax(mx, fabs(p[k]));
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0) {
+      int ex = 0;
+      if (mx > 0.0) frexp(mx, &ex);
+      ea[b * rows_pad + r] = ex + 1;
+    }
+    return;
+  }
+  __shared__ double red[4][64];
+  const int64_t cols_pad = o.cb * 32;
+  const int64_t ncb = (cols_pad + 63) / 64;
+  const int64_t jb = (int64_t)blockIdx.x - nrow;
+  const int64_t slab = jb / ncb;
+  const int c_in = threadIdx.x % 64, r = threadIdx.x / 64;
+  const int64_t c = (jb % ncb) * 64 + c_in;
+  const int64_t k0 = slab * 32 + r * 8;
+  double mx = 0.0;
+  if (c < n) {
+    const double* p = B.p + b * B.bstride + c;
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) v[q] = k0 + q < l ? p[(k0 + q) * B.ld] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; q++) mx = fmax(mx, fabs(v[q]));
+  }
+  red[r][c_in] = mx;
+  __syncthreads();
+  if (r == 0 && c < cols_pad) {
+    mx = fmax(fmax(red[0][c_in], red[1][c_in]), fmax(red[2][c_in], red[3][c_in]));
+    int ex = kNoExp;
+    if (mx > 0.0) {
+      frexp(mx, &ex);
+      ex += 1;
+    }
+    part[(b * o.kb + slab) * cols_pad + c] = ex;
+  }
+}
+
+// Column exponents of B's 32 columns line0.. of batch entry b: the maximum of
+// the slab exponents, into xc[32]; the workgroup with write_fb also stores
+// them for the product kernel.  All 256 threads take part.
+__device__ __forceinline__ void col_exponents(const OzLayout& o, const int* part, int* fb,
+                                              int64_t b, int64_t line0, bool write_fb,
+                                              int* xc /* __shared__ [8][32] */) {
+  const int64_t cols_pad = o.cb * 32;
+  const int c = threadIdx.x % 32, r = threadIdx.x / 32;
+  int ex = kNoExp;
+  for (int64_t sl = r; sl < o.kb; sl += 8) {
+    const int v = part[(b * o.kb + sl) * cols_pad + line0 + c];
+    ex = v > ex ? v : ex;
+  }
+  xc[r * 32 + c] = ex;
+  __syncthreads();
+  if (r == 0) {
+#pragma unroll
+    for (int q = 1; q < 8; q++) ex = xc[q * 32 + c] > ex ? xc[q * 32 + c] : ex;
+    xc[c] = ex;
+    if (write_fb) fb[b * cols_pad + line0 + c] = ex;
+  }
+  __syncthreads();
+}
+
+// Slicing.  A workgroup takes 32 lines (rows of A or columns of B) by 128 k
+// (four 32-k blocks): the DD values are read with coalesced loads (along k
+// for A, along the columns for B) into an LDS tile, then each wave slices one
+// 32x32 block and each lane one fragment slot: 16 consecutive k of one line,
+// exactly what one lane of the 32x32x32 MFMA holds, so each slice is one
+// 16-byte store and a wave writes a whole 1 KB fragment.  Both operands in
+// one launch (blockIdx.y: 0 = A, 1 = B).  Digits of a scaled DD value
+// r = hi + lo (|r| < 1/2, |lo| <= ulp(hi) / 2): runs of kRun digits
+// d = rint(2^7 hi), hi := 2^7 hi - d are taken from the high word alone (each
+// step exact), the low word standing for lo 2^(7j) after j steps; then the
+// run ends with (hi, lo) := FastTwoSum(hi, lo 2^(7 kRun)).  Within a run hi
+// stays 0 or a multiple of 2^(7j) ulp(hi_0) >= 2 |lo 2^(7j)|, so the merge is
+// exact (FastTwoSum's precondition) and the part a digit ignores is below
+// 2^(7 kRun - 54) <= 2^-12 of a digit unit: digits stay in [-64, 64] and the
+// remainder after S digits below (1/2 + 2^-12) 2^-7S.
+constexpr int kSliceK = 128;  // k per slicing workgroup (four 32-k blocks)
+constexpr int kRun = 6;       // digits per run from the high word alone
+static_assert(kRun == 6, "the merge scales by 2^42 = 2^(7 kRun)");
+
+template <int S>
+__global__ __launch_bounds__(256) void oz_slice_kernel(CMat A, CMat B, int64_t m, int64_t n,
+                                                       int64_t l, OzLayout o, const int* ea,
+                                                       const int* part, int* fb,
+                                                       signed char* Asl, signed char* Bsl) {
+  __shared__ double tile[2][32][kSliceK + 1];
+  __shared__ int xc[8 * 32];
+  const int side = blockIdx.y;
+  const int64_t b = blockIdx.z;
+  const int64_t nblk32 = side == 0 ? o.rb : o.cb;
+  const int64_t kgroups = (o.kb + 3) / 4;
+  if ((int64_t)blockIdx.x >= nblk32 * kgroups) return;  // uniform per workgroup
+  const int64_t blk = blockIdx.x / kgroups, kg = blockIdx.x % kgroups;
+  const int64_t line0 = blk * 32, kbase = kg * kSliceK;
+  const CMat X = side == 0 ? A : B;
+  const int64_t lines_live = side == 0 ? m : n;
+  const double* base = X.p + b * X.bstride;
+  const int t = threadIdx.x;
+  // coalesced loads of the 32 x 128 tile (16 values per plane per thread)
+  double vh[16], vl[16];
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const int e = t + 256 * j;
+    const int ln = side == 0 ? e / kSliceK : e % 32;
+    const int kk = side == 0 ? e % kSliceK : e / 32;
+    const int64_t line = line0 + ln, k = kbase + kk;
+    const bool in = line < lines_live && k < l;
+    const int64_t idx = side == 0 ? (in ? line * X.ld + k : 0) : (in ? k * X.ld + line : 0);
+    vh[j] = in ? base[idx] : 0.0;
+    vl[j] = in ? base[X.ps + idx] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const int e = t + 256 * j;
+    const int ln = side == 0 ? e / kSliceK : e % 32;
+    const int kk = side == 0 ? e % kSliceK : e / 32;
+    tile[0][ln][kk] = vh[j];
+    tile[1][ln][kk] = vl[j];
+  }
+  __syncthreads();
+  if (side == 1) col_exponents(o, part, fb, b, line0, kg == 0, xc);  // uniform per workgroup
+  const int w = t / 64, lane = t % 64;
+  const int64_t kb = kg * 4 + w;
+  if (kb >= o.kb) return;
+  const int ln = lane % 32, k0 = w * 32 + 16 * (lane / 32);
+  const int ex = side == 0 ? ea[b * (nblk32 * 32) + line0 + ln] : xc[ln];
+  double rh[16], rl[16];
+#pragma unroll
+  for (int q = 0; q < 16; q++) {
+    rh[q] = ldexp(tile[0][ln][k0 + q], -ex);
+    rl[q] = ldexp(tile[1][ln][k0 + q], -ex);
+  }
+  signed char* dst = (side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
+                     (blk * o.kb + kb) * S * (int64_t)kOzFrag + lane * 16;
+  // a pair whose low word exceeds half an ulp of the high one is brought
+  // into shape first (exact)
+#pragma unroll
+  for (int q = 0; q < 16; q++) two_sum(rh[q], rl[q], rh[q], rl[q]);
+#pragma unroll 1
+  for (int s0 = 0; s0 < S; s0 += kRun) {
+#pragma unroll
+    for (int j = 0; j < kRun; j++) {
+      if (s0 + j < S) {
+        uint32_t x[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+          const double h = rh[q] * 128.0;
+          const double d = rint(h);
+          x[q / 4] |= (uint32_t)(uint8_t)(signed char)(int)d << (8 * (q % 4));
+          rh[q] = h - d;
+        }
+        *reinterpret_cast<v4i*>(dst + (s0 + j) * (int64_t)kOzFrag) =
+            v4i{(int)x[0], (int)x[1], (int)x[2], (int)x[3]};
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; q++) fast_two_sum(rh[q], rl[q] * 0x1p42, rh[q], rl[q]);
+  }
+}
+
+// A workgroup takes 32 lines (rows of A or columns of B) by 64 k (two 32-k
+// blocks): the four planes are read with coalesced loads into LDS; wave w
+// then slices k block w / 2, half w % 2 of every lane's 16-k fragment slot
+// (8 values of one line per lane, 8 bytes per digit).
+constexpr int kSliceKQ = 64;
+
+template <int S>
+__global__ __launch_bounds__(256) void ozq_slice_kernel(CMat A, CMat B, int64_t m, int64_t n,
+                                                        int64_t l, OzLayout o, const int* ea,
+                                                        const int* part, int* fb,
+                                                        signed char* Asl, signed char* Bsl) {
+  __shared__ double tile[4][32][kSliceKQ + 1];
+  __shared__ int xc[8 * 32];
+  const int side = blockIdx.y;
+  const int64_t b = blockIdx.z;
+  const int64_t nblk32 = side == 0 ? o.rb : o.cb;
+  const int64_t kgroups = (o.kb + 1) / 2;
+  if ((int64_t)blockIdx.x >= nblk32 * kgroups) return;  // uniform per workgroup
+  const int64_t blk = blockIdx.x / kgroups, kg = blockIdx.x % kgroups;
+  const int64_t line0 = blk * 32, kbase = kg * kSliceKQ;
+  const CMat X = side == 0 ? A : B;
+  const int64_t lines_live = side == 0 ? m : n;
+  const double* base = X.p + b * X.bstride;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int e = t + 256 * j;
+      const int ln = side == 0 ? e / kSliceKQ : e % 32;
+      const int kk = side == 0 ? e % kSliceKQ : e / 32;
+      const int64_t line = line0 + ln, k = kbase + kk;
+      const bool in = line < lines_live && k < l;
+      const int64_t idx = in ? (side == 0 ? line * X.ld + k : k * X.ld + line) : 0;
+      v[j] = in ? base[c * X.ps + idx] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int e = t + 256 * j;
+      const int ln = side == 0 ? e / kSliceKQ : e % 32;
+      const int kk = side == 0 ? e % kSliceKQ : e / 32;
+      tile[c][ln][kk] = v[j];
+    }
+  }
+  __syncthreads();
+  if (side == 1) col_exponents(o, part, fb, b, line0, kg == 0, xc);  // uniform per workgroup
+  const int w = t / 64, lane = t % 64;
+  const int64_t kb = kg * 2 + w / 2;
+  if (kb >= o.kb) return;
+  const int half = w % 2;
+  const int ln = lane % 32, k0 = (w / 2) * 32 + 16 * (lane / 32) + 8 * half;
+  const int ex = side == 0 ? ea[b * (nblk32 * 32) + line0 + ln] : xc[ln];
+  double r0[8], r1[8], r2[8], r3[8];
+#pragma unroll
+  for (int q = 0; q < 8; q++) {
+    r0[q] = ldexp(tile[0][ln][k0 + q], -ex);
+    r1[q] = ldexp(tile[1][ln][k0 + q], -ex);
+    r2[q] = ldexp(tile[2][ln][k0 + q], -ex);
+    r3[q] = ldexp(tile[3][ln][k0 + q], -ex);
+  }
+  signed char* dst = (side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
+                     (blk * o.kb + kb) * S * (int64_t)kOzFrag + lane * 16 + 8 * half;
+  // the first pass also brings an input whose terms overlap into shape
+#pragma unroll
+  for (int q = 0; q < 8; q++) {
+    double a2, a3, a1, b2, a0, b1;
+    two_sum(r2[q], r3[q], a2, a3);
+    two_sum(r1[q], a2, a1, b2);
+    two_sum(r0[q], a1, a0, b1);
+    r0[q] = a0;
+    r1[q] = b1;
+    r2[q] = b2;
+    r3[q] = a3;
+  }
+#pragma unroll 1
+  for (int s0 = 0; s0 < S; s0 += 6) {
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+      if (s0 + j < S) {
+        uint32_t x[2] = {0u, 0u};
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+          const double h = r0[q] * 128.0;
+          const double d = rint(h);
+          x[q / 4] |= (uint32_t)(uint8_t)(signed char)(int)d << (8 * (q % 4));
+          r0[q] = h - d;
+        }
+        *reinterpret_cast<uint2*>(dst + (s0 + j) * (int64_t)kOzFrag) = uint2{x[0], x[1]};
+      }
+    }
+    // remainder r0 + 2^42 (r1 + r2 + r3), all terms exact; one bottom-up
+    // TwoSum pass keeps the sum and brings it to the front
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      double a2, a3, a1, b2, a0, b1;
+      two_sum(r2[q] * 0x1p42, r3[q] * 0x1p42, a2, a3);
+      two_sum(r1[q] * 0x1p42, a2, a1, b2);
+      two_sum(r0[q], a1, a0, b1);
+      r0[q] = a0;
+      r1[q] = b1;
+      r2[q] = b2;
+      r3[q] = a3;
+    }
+  }
+}
+
+}  // namespace
+
+int launch_oz_exponents(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s) {
+  const int64_t nrow = (o.rb * 32 + 3) / 4;
+  const int64_t ncol = ((o.cb * 32 + 63) / 64) * o.kb;
+  if (nrow + ncol > INT32_MAX || g.batch > 65535)
+    return set_error(DDQD_E_UNSUPPORTED, "matrix too large for one Ozaki launch");
+  prof_begin(s);
+  hipLaunchKernelGGL(oz_exp_kernel, dim3((unsigned)(nrow + ncol), (unsigned)g.batch), dim3(256),
+                     0, s, g.A, g.B, g.m, g.n, g.l, o, nrow, w.ea, w.part);
+  prof_record("oz_exp_kernel", s);
+  return check_launch("oz_exp_kernel");
+}
+
+namespace {
+
+template <int S>
+int slice_dd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s) {
+  const int64_t sblocks = (o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 3) / 4);
+  if (sblocks > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "matrix too large");
+  prof_begin(s);
+  hipLaunchKernelGGL(oz_slice_kernel<S>, dim3((unsigned)sblocks, 2, (unsigned)g.batch),
+                     dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)w.ea,
+                     (const int*)w.part, w.fb, w.Asl, w.Bsl);
+  prof_record("oz_slice_kernel", s);
+  return check_launch("oz_slice_kernel");
+}
+
+template <int S>
+int slice_qd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s) {
+  const int64_t sblocks = (o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 1) / 2);
+  if (sblocks > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "matrix too large");
+  prof_begin(s);
+  hipLaunchKernelGGL(ozq_slice_kernel<S>, dim3((unsigned)sblocks, 2, (unsigned)g.batch),
+                     dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)w.ea,
+                     (const int*)w.part, w.fb, w.Asl, w.Bsl);
+  prof_record("ozq_slice_kernel", s);
+  return check_launch("ozq_slice_kernel");
+}
+
+}  // namespace
+
+int launch_oz_slice(int P, const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s) {
+  if (P == 2) {
+    switch (o.S) {
+      case 8: return slice_dd<8>(g, o, w, s);
+      case 9: return slice_dd<9>(g, o, w, s);
+      case 10: return slice_dd<10>(g, o, w, s);
+      case 11: return slice_dd<11>(g, o, w, s);
+      case 12: return slice_dd<12>(g, o, w, s);
+      case 13: return slice_dd<13>(g, o, w, s);
+      case 14: return slice_dd<14>(g, o, w, s);
+      case 15: return slice_dd<15>(g, o, w, s);
+      case 16: return slice_dd<16>(g, o, w, s);
+      case 17: return slice_dd<17>(g, o, w, s);
+      case 18: return slice_dd<18>(g, o, w, s);
+      case 19: return slice_dd<19>(g, o, w, s);
+      case 20: return slice_dd<20>(g, o, w, s);
+    }
+  } else {
+    switch (o.S) {
+      case 28: return slice_qd<28>(g, o, w, s);
+      case 29: return slice_qd<29>(g, o, w, s);
+      case 30: return slice_qd<30>(g, o, w, s);
+      case 31: return slice_qd<31>(g, o, w, s);
+    }
+  }
+  return set_error(DDQD_E_UNSUPPORTED, "slices");
+}
+
+}  // namespace ddqd
