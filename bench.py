@@ -125,14 +125,32 @@ def roofline(dd, args, n, step, steps):
                     "fma counting one); peak = 256 CU x 2.4 GHz x 64 lanes"}
 
 
-def cpu_baseline(n: int, budget_s: float = 10.0):
-    """The oracle's Block DD product of the n x n workload, repeated on all
-    host threads for about budget_s seconds; plus one thread on a row sample."""
+def roofline_qd_ozaki(dd, step, n, steps, S=31):
+    """The QD Ozaki product kernel at n (Block, one leaf): INT8 MFMA operations
+    of its S(S+1)/2 slice products against the dense INT8 peak."""
+    name = "ozq_gemm_kernel"
+    avg, cnt = kernel_avg_ms(dd, step, steps, name)
+    per = max(1, cnt // steps)
+    ops = 2.0 * n ** 3 * S * (S + 1) / 2 / per
+    ach = ops / (avg * 1e-3) / 1e12
+    return {"bound": "mfma", "kernel": name, "achieved": round(ach, 1), "peak": INT8_PEAK_T,
+            "unit": "TFLOP/s", "frac": round(ach / INT8_PEAK_T, 4),
+            "traffic": measured_traffic(name), "avg_launch_ms": round(avg, 5),
+            "launches_per_step": per,
+            "note": f"qd_gemm base=ozaki, S = {S}: {S * (S + 1) // 2} INT8 slice products "
+                    "per launch"}
+
+
+def cpu_baseline(n: int, budget_s: float = 10.0, P: int = 2):
+    """The oracle's Block product (DD, or QD for P = 4) of the n x n workload,
+    repeated on all host threads for about budget_s seconds; plus one thread on
+    a row sample."""
     import oracle
     from paper_1510_08642_amd import inputs
     g = inputs.rng(0)
-    A = inputs.dd_uniform(n, n, g)
-    B = inputs.dd_uniform(n, n, g)
+    gen = inputs.dd_uniform if P == 2 else inputs.qd_uniform
+    A = gen(n, n, g)
+    B = gen(n, n, g)
     threads = oracle.num_threads()
     reps, t = 0, 0.0
     while t < budget_s or reps == 0:
@@ -160,7 +178,7 @@ def cpu_baseline(n: int, budget_s: float = 10.0):
     except OSError:
         pass
     return {"value": round(gf, 4), "unit": "GFLOPS", "cores": threads, "kind": "oracle",
-            "sample": f"oracle Block DD product of the whole n={n} workload, {reps} times in "
+            "sample": f"oracle Block {'DD' if P == 2 else 'QD'} product of the whole n={n} workload, {reps} times in "
                       f"{t:.1f} s on {threads} OpenMP threads ({model}); one thread on the "
                       f"first {rows} rows: {gf1:.3f} GFLOPS",
             "one_thread_gflops": round(gf1, 4), "cpu_model": model}
@@ -178,22 +196,24 @@ def sampled_error(A, B, C, n, count=64):
     return float(np.max(e / den))
 
 
-def bench_lu(dd, inputs, torch, dev, sizes, configs, stream):
+def bench_lu(dd, inputs, torch, dev, sizes, configs, stream, P=2):
     out = {}
+    getrf = dd.dd_getrf if P == 2 else dd.qd_getrf
+    getrs = dd.dd_getrs if P == 2 else dd.qd_getrs
     for n in sizes:
         g = inputs.rng(0)
-        A0 = torch.from_numpy(inputs.dd_lu_matrix(n, g)).to(dev)
-        b0 = torch.from_numpy(inputs.dd_uniform(n, 16, g)).to(dev)
+        A0 = torch.from_numpy((inputs.dd_lu_matrix if P == 2 else inputs.qd_lu_matrix)(n, g)).to(dev)
+        b0 = torch.from_numpy((inputs.dd_uniform if P == 2 else inputs.qd_uniform)(n, 16, g)).to(dev)
         for (panel, algo, lv, base) in configs:
-            key = f"n{n}_p{panel}_{algo}{lv}_{base}"
-            ws = torch.empty(max(1, dd.getrf_workspace(n, panel, algo, lv, base)),
+            key = ("" if P == 2 else "qd_") + f"n{n}_p{panel}_{algo}{lv}_{base}"
+            ws = torch.empty(max(1, dd.getrf_workspace(n, panel, algo, lv, base, P)),
                              dtype=torch.uint8, device=dev)
             A = A0.clone()
             holder = {}
 
             def f():
                 A.copy_(A0)
-                holder["f"] = dd.dd_getrf(A, panel=panel, algo=algo, levels=lv, base=base, ws=ws)
+                holder["f"] = getrf(A, panel=panel, algo=algo, levels=lv, base=base, ws=ws)
             t_copy = time_steps(lambda: A.copy_(A0), 3, 1, stream)
             t_f = time_steps(f, 2, 1, stream)         # A holds the factors after this
             ipiv, perm, _ = holder["f"]
@@ -203,7 +223,7 @@ def bench_lu(dd, inputs, torch, dev, sizes, configs, stream):
 
                 def s():
                     Xs.copy_(b0[:, :, :nrhs])
-                    dd.dd_getrs(A, ipiv, Xs, perm=perm)
+                    getrs(A, ipiv, Xs, perm=perm)
                 res[nrhs] = time_steps(s, 3, 1, stream)
             t_getrf = t_f - t_copy
             out[key] = {"getrf_ms": round(t_getrf, 3),
@@ -282,38 +302,45 @@ def bench_tuning(dd, inputs, torch, dev, n):
         out[f"dd_{base}_n{n}"] = r
     Aq = torch.from_numpy(inputs.qd_uniform(n, n, g)).to(dev)
     Bq = torch.from_numpy(inputs.qd_uniform(n, n, g)).to(dev)
-    r = dd.tune(Aq, Bq, reps=1)
-    r["gflops"] = round(2.0 * n ** 3 / (r["ms"] * 1e-3) / 1e9, 1)
-    r["ms"] = round(r["ms"], 4)
-    out[f"qd_fma_n{n}"] = r
+    for base in ("fma", "ozaki"):
+        r = dd.tune(Aq, Bq, base=base, reps=1 if base == "fma" else 3)
+        r["gflops"] = round(2.0 * n ** 3 / (r["ms"] * 1e-3) / 1e9, 1)
+        r["ms"] = round(r["ms"], 4)
+        out[f"qd_{base}_n{n}"] = r
     log(f"tuning: {out}")
     return out
 
 
 def bench_equal_accuracy(dd, inputs, torch, dev, n, stream):
-    """Ozaki slice counts against the FMA form: error on sampled entries
-    (exact reference from the oracle) and time, so that the two forms can be
-    compared at equal accuracy."""
+    """Ozaki slice counts against the FMA form, in DD and in QD: error on
+    sampled entries (exact reference from the oracle) and time, so that the
+    two forms can be compared at equal accuracy."""
     g = inputs.rng(11)
-    A = torch.from_numpy(inputs.dd_uniform(n, n, g)).to(dev)
-    B = torch.from_numpy(inputs.dd_uniform(n, n, g)).to(dev)
-    C = torch.empty((2, n, n), dtype=torch.float64, device=dev)
-    Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
     out = {}
-    for base, S in [("fma", 0), ("ozaki", 12), ("ozaki", 13), ("ozaki", 14), ("ozaki", 15),
-                    ("ozaki", 16)]:
-        ws = torch.empty(max(1, dd.gemm_workspace(2, n, n, n, "block", 0, base, S)),
-                         dtype=torch.uint8, device=dev)
+    for P, cases in ((2, [("fma", 0), ("ozaki", 12), ("ozaki", 13), ("ozaki", 14),
+                          ("ozaki", 15), ("ozaki", 16)]),
+                     (4, [("fma", 0), ("ozaki", 28), ("ozaki", 29), ("ozaki", 30),
+                          ("ozaki", 31)])):
+        gen = inputs.dd_uniform if P == 2 else inputs.qd_uniform
+        A = torch.from_numpy(gen(n, n, g)).to(dev)
+        B = torch.from_numpy(gen(n, n, g)).to(dev)
+        C = torch.empty((P, n, n), dtype=torch.float64, device=dev)
+        Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
+        prod = dd.dd_gemm if P == 2 else dd.qd_gemm
+        for base, S in cases:
+            ws = torch.empty(max(1, dd.gemm_workspace(P, n, n, n, "block", 0, base, S)),
+                             dtype=torch.uint8, device=dev)
 
-        def f():
-            dd.dd_gemm(A, B, C, algo="block", base=base, slices=S, ws=ws)
-        t = time_steps(f, 10, 2, stream)
-        f()
-        torch.cuda.synchronize()
-        err = sampled_error(Ah, Bh, C.cpu().numpy(), n)
-        out[f"{base}{S or ''}"] = {"ms": round(t, 4),
-                                   "gflops": round(2.0 * n ** 3 / (t * 1e-3) / 1e9, 1),
-                                   "error_rownorm": err}
+            def f():
+                prod(A, B, C, algo="block", base=base, slices=S, ws=ws)
+            t = time_steps(f, 10 if (P == 2 or base == "ozaki") else 2, 2, stream)
+            f()
+            torch.cuda.synchronize()
+            err = sampled_error(Ah, Bh, C.cpu().numpy(), n)
+            key = ("" if P == 2 else "qd_") + f"{base}{S or ''}"
+            out[key] = {"ms": round(t, 4), "gflops": round(2.0 * n ** 3 / (t * 1e-3) / 1e9, 1),
+                        "error_rownorm": err}
+        del A, B, C
     log(f"equal accuracy: {out}")
     return out
 
@@ -326,11 +353,12 @@ def bench_paper(dd, inputs, torch, dev, stream):
     Strassen and Winograd with the paper's n_min = 32 (5 levels at n = 1024);
     error = max relative error against the closed form sqrt15 n (n-1)
     (n + 3i - 2) / 6 on sampled entries (mpmath, 400 bits).
-    LU (Sec. 4): the random matrix with entries in [-1, 1], no pivoting,
-    n = 1024, block size K = alpha n_min for alpha = 1, 2, 4, 8, trailing
-    update by Block or Winograd (depth down to n_min); x = [0, 1, ..., n-1],
-    b = A x formed by the DD product, and the maximum relative error of the
-    computed x over x_i != 0."""
+    LU (Sec. 4, Fig. 5 upper DD and lower QD): the random matrix with entries
+    in [-1, 1], no pivoting, n = 1024, block size K = alpha n_min for
+    alpha = 1, 2, 4, 8, trailing update by Block or Winograd (depth down to
+    n_min) on the FMA base, and Block on Ozaki leaves; x = [0, 1, ..., n-1],
+    b = A x formed by the library's product, and the maximum relative error of
+    the computed x over x_i != 0."""
     import mpmath
     out = {"products": {}, "lu": {}}
     for P in (2, 4):
@@ -342,16 +370,15 @@ def bench_paper(dd, inputs, torch, dev, stream):
             rows = np.unique(np.concatenate([[0, n // 2, n - 1], rs.integers(0, n, 29)]))
             exact = inputs.paper_product_closed_form(n, rows)
             configs = [("block", 0, "fma"), ("strassen", 5, "fma"), ("winograd", 5, "fma")]
-            if P == 2:
-                configs.append(("block", 0, "ozaki"))
+            configs.append(("block", 0, "ozaki"))
             for algo, lv, base in configs:
                 ws = torch.empty(max(1, dd.gemm_workspace(P, n, n, n, algo, lv, base)),
                                  dtype=torch.uint8, device=dev)
                 if P == 2:
                     f = lambda: dd.dd_gemm(Ad, Bd, C, algo=algo, levels=lv, base=base, ws=ws)
                 else:
-                    f = lambda: dd.qd_gemm(Ad, Bd, C, algo=algo, levels=lv, ws=ws)
-                t = time_steps(f, 3 if P == 2 else 1, 1, stream)
+                    f = lambda: dd.qd_gemm(Ad, Bd, C, algo=algo, levels=lv, base=base, ws=ws)
+                t = time_steps(f, 3 if (P == 2 or base == "ozaki") else 1, 1, stream)
                 Ch = C.cpu().numpy()
                 err = 0.0
                 with mpmath.workprec(400):
@@ -366,36 +393,42 @@ def bench_paper(dd, inputs, torch, dev, stream):
                 log(f"paper {key}: {out['products'][key]}")
             del Ad, Bd, C
     n = 1024
-    A0 = torch.from_numpy(inputs.paper_random_matrix(n, inputs.rng(0))).to(dev)
-    x = np.zeros((2, n, 1))
-    x[0, :, 0] = np.arange(n)
-    b = dd.dd_gemm(A0, torch.from_numpy(x).to(dev))
-    for alpha in (1, 2, 4, 8):
-        K = 32 * alpha
-        for algo in ("block", "winograd"):
-            lv = 0 if algo == "block" else alpha.bit_length() - 1
-            if algo == "winograd" and lv == 0:
-                continue
-            ws = torch.empty(max(1, dd.getrf_workspace(n, K, algo, lv, "fma")),
-                             dtype=torch.uint8, device=dev)
-            A = A0.clone()
-            hold = {}
+    for P in (2, 4):
+        A0 = torch.from_numpy(inputs.paper_random_matrix(n, inputs.rng(0), P)).to(dev)
+        x = np.zeros((P, n, 1))
+        x[0, :, 0] = np.arange(n)
+        prod = dd.dd_gemm if P == 2 else dd.qd_gemm
+        getrf = dd.dd_getrf if P == 2 else dd.qd_getrf
+        getrs = dd.dd_getrs if P == 2 else dd.qd_getrs
+        b = prod(A0, torch.from_numpy(x).to(dev))
+        for alpha in (1, 2, 4, 8):
+            K = 32 * alpha
+            for algo, base in (("block", "fma"), ("winograd", "fma"), ("block", "ozaki")):
+                lv = 0 if algo == "block" else alpha.bit_length() - 1
+                if algo == "winograd" and lv == 0:
+                    continue
+                ws = torch.empty(max(1, dd.getrf_workspace(n, K, algo, lv, base, P)),
+                                 dtype=torch.uint8, device=dev)
+                A = A0.clone()
+                hold = {}
 
-            def f():
-                A.copy_(A0)
-                hold["r"] = dd.dd_getrf(A, panel=K, pivot="none", algo=algo, levels=lv, ws=ws)
-            t_copy = time_steps(lambda: A.copy_(A0), 3, 1, stream)
-            t = time_steps(f, 2, 1, stream) - t_copy      # A holds the factors after this
-            ipiv, perm, info = hold["r"]
-            X = b.clone()
-            dd.dd_getrs(A, ipiv, X, perm=perm)
-            Xh = X.cpu().numpy()[:, :, 0]
-            d = np.abs((Xh[0, 1:] - np.arange(1, n)) + Xh[1, 1:])
-            key = f"lu_n{n}_K{K}_{algo}{lv}"
-            out["lu"][key] = {"getrf_ms": round(t, 3), "info": int(info.cpu()[0]),
-                              "max_rel_error_x": float(np.max(d / np.arange(1, n))),
-                              "normwise_error_x": float(np.max(d) / (n - 1))}
-            log(f"paper {key}: {out['lu'][key]}")
+                def f():
+                    A.copy_(A0)
+                    hold["r"] = getrf(A, panel=K, pivot="none", algo=algo, levels=lv, base=base,
+                                      ws=ws)
+                t_copy = time_steps(lambda: A.copy_(A0), 3, 1, stream)
+                t = time_steps(f, 2, 1, stream) - t_copy  # A holds the factors after this
+                ipiv, perm, info = hold["r"]
+                X = b.clone()
+                getrs(A, ipiv, X, perm=perm)
+                Xh = X.cpu().numpy()[:, :, 0]
+                d = np.abs((Xh[0, 1:] - np.arange(1, n)) + sum(Xh[c, 1:] for c in range(1, P)))
+                key = f"{'dd' if P == 2 else 'qd'}_lu_n{n}_K{K}_{algo}{lv}_{base}"
+                out["lu"][key] = {"getrf_ms": round(t, 3), "info": int(info.cpu()[0]),
+                                  "max_rel_error_x": float(np.max(d / np.arange(1, n))),
+                                  "normwise_error_x": float(np.max(d) / (n - 1))}
+                log(f"paper {key}: {out['lu'][key]}")
+        del A0, b
     return out
 
 
@@ -441,6 +474,9 @@ def main():
     ap.add_argument("--algo", default="block")
     ap.add_argument("--levels", type=int, default=0)
     ap.add_argument("--base", default="ozaki")
+    ap.add_argument("--precision", choices=("dd", "qd"), default="dd",
+                    help="timed product: dd_gemm (default) or qd_gemm (for profiling the QD "
+                         "kernels; the extra legs still run as configured)")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-lu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -475,27 +511,35 @@ def main():
     stream = torch.cuda.current_stream(dev)
     n = args.n
     g = inputs.rng(0)
-    A = torch.from_numpy(inputs.dd_uniform(n, n, g)).to(dev)
-    B = torch.from_numpy(inputs.dd_uniform(n, n, g)).to(dev)
-    C = torch.empty((2, n, n), dtype=torch.float64, device=dev)
+    PM = 2 if args.precision == "dd" else 4
+    gen = inputs.dd_uniform if PM == 2 else inputs.qd_uniform
+    A = torch.from_numpy(gen(n, n, g)).to(dev)
+    B = torch.from_numpy(gen(n, n, g)).to(dev)
+    C = torch.empty((PM, n, n), dtype=torch.float64, device=dev)
 
     def make(algo, levels, base, P=2, X=A, Y=B, Z=C):
         ws = torch.empty(max(1, dd.gemm_workspace(P, n, n, n, algo, levels, base)),
                          dtype=torch.uint8, device=dev)
         if P == 2:
             return lambda: dd.dd_gemm(X, Y, Z, algo=algo, levels=levels, base=base, ws=ws)
-        return lambda: dd.qd_gemm(X, Y, Z, algo=algo, levels=levels, ws=ws)
+        return lambda: dd.qd_gemm(X, Y, Z, algo=algo, levels=levels, base=base, ws=ws)
 
     log(f"bench: n={n} algo={args.algo} levels={args.levels} base={args.base}")
-    step = make(args.algo, args.levels, args.base)
+    step = make(args.algo, args.levels, args.base, PM)
     ms = time_steps(step, args.steps, args.warmup, stream)
     flops = 2.0 * n * n * n
     value = flops / (ms * 1e-3) / 1e9
     log(f"bench: {ms:.4f} ms/step, {value:.1f} GFLOPS effective")
-    roof = roofline(dd, args, n, step, args.steps)
+    if PM == 4:
+        if args.base != "ozaki" or args.algo != "block":
+            sys.exit("--precision qd is for the QD Ozaki Block product (--base ozaki)")
+        roof = roofline_qd_ozaki(dd, step, n, args.steps)
+    else:
+        roof = roofline(dd, args, n, step, args.steps)
     log(f"bench: roofline {roof}")
 
     variants = {}
+    roof_qd = None
     if not args.no_variants:
         for (algo, lv, base) in [("simple", 0, "fma"), ("block", 0, "fma"),
                                  ("strassen", 1, "fma"), ("strassen", 2, "fma"),
@@ -510,11 +554,16 @@ def main():
         Aq = torch.from_numpy(inputs.qd_uniform(n, n, gq)).to(dev)
         Bq = torch.from_numpy(inputs.qd_uniform(n, n, gq)).to(dev)
         Cq = torch.empty((4, n, n), dtype=torch.float64, device=dev)
-        for (algo, lv) in [("block", 0), ("strassen", 1), ("winograd", 1), ("winograd", 2),
-                           ("winograd", 3)]:
-            t = time_steps(make(algo, lv, "fma", 4, Aq, Bq, Cq), 2, 1, stream)
-            variants[f"qd_{algo}{lv}_fma"] = round(flops / (t * 1e-3) / 1e9, 1)
-            log(f"variant qd {algo} L{lv}: {t:.3f} ms")
+        for (algo, lv, base) in [("block", 0, "fma"), ("strassen", 1, "fma"),
+                                 ("winograd", 1, "fma"), ("winograd", 2, "fma"),
+                                 ("winograd", 3, "fma"), ("block", 0, "ozaki"),
+                                 ("winograd", 1, "ozaki")]:
+            t = time_steps(make(algo, lv, base, 4, Aq, Bq, Cq), 2 if base == "fma" else 5, 1,
+                           stream)
+            variants[f"qd_{algo}{lv}_{base}"] = round(flops / (t * 1e-3) / 1e9, 1)
+            log(f"variant qd {algo} L{lv} {base}: {t:.3f} ms")
+        roof_qd = roofline_qd_ozaki(dd, make("block", 0, "ozaki", 4, Aq, Bq, Cq), n, 5)
+        log(f"bench: QD Ozaki roofline {roof_qd}")
         del Aq, Bq, Cq
 
     tuning = equal = None
@@ -544,6 +593,8 @@ def main():
         lu = bench_lu(dd, inputs, torch, dev, [2048, 4096],
                       [(128, "winograd", 1, "fma"), (128, "winograd", 1, "ozaki"),
                        (256, "block", 0, "ozaki")], stream)
+        lu.update(bench_lu(dd, inputs, torch, dev, [1024, 2048],
+                           [(64, "block", 0, "fma"), (128, "block", 0, "ozaki")], stream, P=4))
 
     paper = bench_paper(dd, inputs, torch, dev, stream) if args.paper else None
 
@@ -556,23 +607,26 @@ def main():
     cpu, err = None, None
     if not args.no_cpu:
         log("bench: timing the CPU oracle baseline")
-        cpu = cpu_baseline(n)
+        cpu = cpu_baseline(n, P=PM)
         log(f"bench: cpu baseline {cpu}")
         step()
         torch.cuda.synchronize()
         err = sampled_error(A.cpu().numpy(), B.cpu().numpy(), C.cpu().numpy(), n)
-        log(f"bench: sampled row-normwise error {err:.3e} (tolerance {2.0**-100*n:.3e})")
+        tol = (2.0 ** -100 if PM == 2 else 2.0 ** -200) * n
+        log(f"bench: sampled row-normwise error {err:.3e} (tolerance {tol:.3e})")
 
     out = {
         "metric": "DD/QD GEMM effective GFLOPS (2mnl/t) at n=1024; DD LU-solve p50/p99 latency",
         "value": round(value, 2), "unit": "GFLOPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"dd_gemm m=n=l={n}, DD uniform inputs seed 0",
+        "config": {"workload": f"{args.precision}_gemm m=n=l={n}, "
+                               f"{args.precision.upper()} uniform inputs seed 0",
                    "algo": args.algo, "levels": args.levels, "base": args.base,
-                   "slices": 16 if args.base == "ozaki" else None},
+                   "slices": (16 if PM == 2 else 31) if args.base == "ozaki" else None},
         "error_rownorm": err,
         "roofline": roof,
+        "roofline_qd_ozaki": roof_qd,
         "variants_gflops": variants,
         "tuned": tuning,
         "ozaki_vs_fma_equal_accuracy": equal,

@@ -131,10 +131,10 @@ def paper_product_closed_form(n: int, rows) -> list:
         return [s15 * n * (n - 1) * (n + 3 * (int(r) + 1) - 2) / 6 for r in rows]
 
 
-def paper_random_matrix(n: int, g: np.random.Generator) -> np.ndarray:
-    """The Sec. 4 random matrix: entries uniform in [-1, 1] (DD, low part
-    below half an ulp)."""
-    return dd_uniform(n, n, g)
+def paper_random_matrix(n: int, g: np.random.Generator, P: int = 2) -> np.ndarray:
+    """The Sec. 4 random matrix: entries uniform in [-1, 1] as DD (P = 2) or QD
+    (P = 4) numbers (lower parts below half an ulp of the part above)."""
+    return dd_uniform(n, n, g) if P == 2 else qd_uniform(n, n, g)
 
 
 def serving_trace(nreq: int, rate: float, seed: int = 0, gemm_frac: float = 0.6,
