@@ -170,6 +170,12 @@ size_t qd_gemm_workspace(int64_t m, int64_t n, int64_t l, int algo, int levels, 
  *            exactly zero (the factorisation still completes).
  *   pivot    DDQD_PIVOT_PARTIAL (largest |a_ic| below the diagonal, first row
  *            on ties, compared in DD) or DDQD_PIVOT_NONE (the paper's choice).
+ *   panel    >= 1: the blocked method above.  0: the paper's comparator,
+ *            row-wise parallel elimination without blocking (one launch per
+ *            elimination step, every trailing row updated in parallel; Sec. 4
+ *            compares the blocked LU against it); requires DDQD_PIVOT_NONE
+ *            (else DDQD_E_UNSUPPORTED), ignores algo / levels / base and needs
+ *            no workspace.
  *   ws       workspace of dd_getrf_workspace(...) bytes (the product's).
  * Orders above 8192 return DDQD_E_UNSUPPORTED.
  */

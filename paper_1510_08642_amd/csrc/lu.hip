@@ -15,6 +15,7 @@
 // parts and the TwoSum errors into a second, one rounding at the end); QD
 // uses the order-bucket multiply-add of qd.hpp.
 #include "common.hpp"
+#include "ddqd.h"
 #include "eft.hpp"
 #include "qd.hpp"
 
@@ -782,9 +783,112 @@ __global__ __launch_bounds__(1024) void trsv_block_kernel(const double* T, int64
   }
 }
 
+
+// ---- the paper's row-wise parallel LU (its comparator) --------------------
+//
+// Unblocked elimination without pivoting, one launch per step k (Sec. 4
+// compares its blocked LU against this row-parallel form): a workgroup takes
+// kRwRows rows by kRwCols columns of the trailing matrix, forms its rows'
+// multipliers l_ik = a_ik / a_kk in LDS and updates a_ij -= l_ik a_kj.  Column
+// k keeps the unscaled a_ik (other workgroups of the same step still read
+// it); one last launch divides every sub-diagonal column by its pivot, with
+// the same division, so L is what the steps used.  An exactly zero pivot sets
+// info (first one) and its step is skipped, as in the blocked form.
+constexpr int kRwRows = 16, kRwCols = 256;
+
+template <int P>
+__global__ __launch_bounds__(256) void rowwise_step_kernel(double* A, int64_t lda, int64_t ps,
+                                                           int64_t n, int64_t k,
+                                                           int32_t* info) {
+  using N = LuArith<P>;
+  using V = typename N::T;
+  __shared__ double lsh[P][kRwRows];
+  __shared__ double ush[P][kRwCols];
+  const V u = ld_num<P>(A, ps, k * lda + k);
+  if (N::is_zero(u)) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && *info == 0)
+      *info = (int32_t)(k + 1);
+    return;  // uniform: every thread read the same pivot
+  }
+  const int t = threadIdx.x;
+  const int64_t i0 = k + 1 + (int64_t)blockIdx.y * kRwRows;
+  const int64_t j0 = k + 1 + (int64_t)blockIdx.x * kRwCols;
+  if (t < kRwRows) {
+    const int64_t i = i0 + t;
+    V l = N::zero();
+    if (i < n) l = N::div_digits(ld_num<P>(A, ps, i * lda + k), u, 1.0 / N::get(u, 0));
+#pragma unroll
+    for (int c = 0; c < P; c++) lsh[c][t] = N::get(l, c);
+  }
+  const int64_t j = j0 + t;
+  {
+    V x = N::zero();
+    if (j < n) x = ld_num<P>(A, ps, k * lda + j);
+#pragma unroll
+    for (int c = 0; c < P; c++) ush[c][t] = N::get(x, c);
+  }
+  __syncthreads();
+  if (j >= n) return;
+  V ukj;
+#pragma unroll
+  for (int c = 0; c < P; c++) N::put(ukj, c, ush[c][t]);
+  for (int r = 0; r < kRwRows; r++) {
+    const int64_t i = i0 + r;
+    if (i >= n) break;
+    V l;
+#pragma unroll
+    for (int c = 0; c < P; c++) N::put(l, c, lsh[c][r]);
+    st_num<P>(A, ps, i * lda + j, N::sub(ld_num<P>(A, ps, i * lda + j), N::mul(l, ukj)));
+  }
+}
+
+// L from the unscaled columns: a_ik := a_ik / a_kk for i > k (columns with a
+// zero pivot stay as they are); the last pivot's zero test; ipiv := identity.
+template <int P>
+__global__ __launch_bounds__(256) void rowwise_scale_kernel(double* A, int64_t lda, int64_t ps,
+                                                            int64_t n, int32_t* ipiv,
+                                                            int32_t* info) {
+  using N = LuArith<P>;
+  using V = typename N::T;
+  const int64_t i = blockIdx.y;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i == 0 && k < n) ipiv[k] = (int32_t)k;
+  if (i == n - 1 && k == 0 && N::is_zero(ld_num<P>(A, ps, (n - 1) * lda + n - 1)) && *info == 0)
+    *info = (int32_t)n;
+  if (k >= i) return;
+  const V u = ld_num<P>(A, ps, k * lda + k);
+  if (N::is_zero(u)) return;
+  st_num<P>(A, ps, i * lda + k,
+            N::div_digits(ld_num<P>(A, ps, i * lda + k), u, 1.0 / N::get(u, 0)));
+}
+
 }  // namespace
 
 // ---- launchers ---------------------------------------------------------------
+
+// The row-wise comparator: n - 1 step launches and the scaling launch.
+int launch_rowwise_lu(int P, double* A, int64_t lda, int64_t ps, int64_t n, int32_t* ipiv,
+                      int32_t* info, hipStream_t s) {
+  if (n > 65535) return set_error(DDQD_E_UNSUPPORTED, "row-wise LU of order above 65535");
+  for (int64_t k = 0; k + 1 < n; k++) {
+    const int64_t m = n - k - 1;
+    const dim3 grid((unsigned)((m + kRwCols - 1) / kRwCols), (unsigned)((m + kRwRows - 1) / kRwRows));
+    prof_begin(s);
+    if (P == 2)
+      hipLaunchKernelGGL(rowwise_step_kernel<2>, grid, dim3(256), 0, s, A, lda, ps, n, k, info);
+    else
+      hipLaunchKernelGGL(rowwise_step_kernel<4>, grid, dim3(256), 0, s, A, lda, ps, n, k, info);
+    prof_record("rowwise_step_kernel", s);
+  }
+  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)n);
+  prof_begin(s);
+  if (P == 2)
+    hipLaunchKernelGGL(rowwise_scale_kernel<2>, grid, dim3(256), 0, s, A, lda, ps, n, ipiv, info);
+  else
+    hipLaunchKernelGGL(rowwise_scale_kernel<4>, grid, dim3(256), 0, s, A, lda, ps, n, ipiv, info);
+  prof_record("rowwise_scale_kernel", s);
+  return check_launch("rowwise LU");
+}
 
 int launch_lu_init(int32_t* info, int32_t* perm, int64_t n, hipStream_t s) {
   prof_begin(s);

@@ -35,6 +35,8 @@ bool ranges_overlap(const void* a, int64_t a_len, const void* b, int64_t b_len);
 void clear_error();
 
 int launch_lu_init(int32_t* info, int32_t* perm, int64_t n, hipStream_t s);
+int launch_rowwise_lu(int P, double* A, int64_t lda, int64_t ps, int64_t n, int32_t* ipiv,
+                      int32_t* info, hipStream_t s);
 int getf2_width(int P, int64_t m);
 int trsm_max_rows(int P);
 int launch_getf2(int P, double* A, int64_t lda, int64_t ps, int64_t r0, int64_t m, int64_t c0,
@@ -158,9 +160,10 @@ size_t getrs_ws(int P, int64_t n, int64_t nrhs) {
 }
 
 size_t getrf_workspace_entry(int P, int64_t n, int panel_width, int algo, int levels, int base) {
-  if (n < 0 || panel_width < 1 || algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 ||
+  if (n < 0 || panel_width < 0 || algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 ||
       base > 1)
     return SIZE_MAX;
+  if (panel_width == 0) return 0;  // the row-wise comparator needs none
   return getrf_ws(P, n, panel_width, algo, levels, base);
 }
 
@@ -169,9 +172,11 @@ int getrf_entry(int P, int64_t n, double* A, int64_t lda, int64_t psa, int32_t* 
                 int base, void* ws, size_t ws_bytes, void* stream) {
   clear_error();
   if (n < 0) return set_error(DDQD_E_ARG, "negative order");
-  if (panel_width < 1) return set_error(DDQD_E_ARG, "panel width must be >= 1");
+  if (panel_width < 0) return set_error(DDQD_E_ARG, "panel width must be >= 0");
   if (pivot != DDQD_PIVOT_NONE && pivot != DDQD_PIVOT_PARTIAL)
     return set_error(DDQD_E_ARG, "pivot must be DDQD_PIVOT_NONE or DDQD_PIVOT_PARTIAL");
+  if (panel_width == 0 && pivot != DDQD_PIVOT_NONE)
+    return set_error(DDQD_E_UNSUPPORTED, "the row-wise form (panel width 0) does not pivot");
   if (algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 || base > 1)
     return set_error(DDQD_E_ARG, "bad product algorithm / levels / base");
   if (!info) return set_error(DDQD_E_ARG, "info is NULL");
@@ -180,7 +185,7 @@ int getrf_entry(int P, int64_t n, double* A, int64_t lda, int64_t psa, int32_t* 
     return set_error(DDQD_E_UNSUPPORTED, "LU of order above %lld", (long long)kMaxLuRows);
   int rc;
   if ((rc = check_matrix("A", P, A, n, n, lda, psa))) return rc;
-  const size_t need = getrf_ws(P, n, panel_width, algo, levels, base);
+  const size_t need = panel_width == 0 ? 0 : getrf_ws(P, n, panel_width, algo, levels, base);
   if (need == SIZE_MAX) return set_error(DDQD_E_ARG, "bad product arguments");
   if (need > ws_bytes || (need > 0 && !ws))
     return set_error(DDQD_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
@@ -189,6 +194,10 @@ int getrf_entry(int P, int64_t n, double* A, int64_t lda, int64_t psa, int32_t* 
   Lu c{P, A, lda, psa, n, ipiv, perm, info, pivot, algo, levels, base, ws, ws_bytes,
        (hipStream_t)stream};
   if (n == 0) return launch_lu_init(info, nullptr, 0, c.s);
+  if (panel_width == 0) {
+    if ((rc = launch_lu_init(info, perm, n, c.s))) return rc;
+    return launch_rowwise_lu(P, A, lda, psa, n, ipiv, info, c.s);
+  }
   return getrf(c, panel_width);
 }
 

@@ -191,7 +191,8 @@ def getrf_workspace(n: int, panel=128, algo="winograd", levels=1, base="fma", P:
 def dd_getrf(A, *, panel=128, pivot="partial", algo="winograd", levels=1, base="fma",
              want_perm=True, ws=None, out=None):
     """In-place DD LU of the square (2, n, n) tensor A (blocked right-looking,
-    panel width `panel`, trailing update by `algo`/`levels`/`base`).
+    panel width `panel`, trailing update by `algo`/`levels`/`base`; panel=0
+    is the paper's row-wise parallel comparator, pivot="none" only).
 
     Returns (ipiv, perm, info) as device int32 tensors: LAPACK-style 0-based
     interchanges, the resulting row permutation (or None), and info (0, or the

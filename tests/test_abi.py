@@ -134,7 +134,10 @@ def test_lu_argument_errors(lib):
                             a["panel"], a["pivot"], a["algo"], a["levels"], a["base"], a["ws"],
                             a["wsb"], None)
     assert call(n=-1) == E["ARG"]
-    assert call(panel=0) == E["ARG"]
+    assert call(panel=-1) == E["ARG"]
+    # panel 0 is the row-wise comparator: no pivoting, no workspace
+    assert call(panel=0) == E["UNSUPPORTED"]
+    assert lib.dd_getrf_workspace(1024, 0, 3, 2, 1) == 0
     assert call(pivot=3) == E["ARG"]
     assert call(info=None) == E["ARG"]
     assert call(lda=4) == E["ARG"]

@@ -219,3 +219,50 @@ def test_pivot_decided_by_low_words(dd):
     LUo, ipo, _ = oracle.getrf(A, panel=16, pivot=True, algo="block", levels=0)
     assert ipiv[0] == ipo[0] == 17
     assert np.array_equal(ipiv, ipo)
+
+
+# ---- the paper's row-wise parallel comparator (panel width 0) --------------
+
+@pytest.mark.parametrize("n", [1, 2, 7, 100, 300])
+def test_rowwise_vs_oracle_unblocked(dd, n):
+    """Row-wise elimination without pivoting is the unblocked right-looking LU:
+    the oracle's blocked LU with panel width 1 and no pivoting."""
+    g = inputs.rng(240 + n)
+    A = inputs.dd_lu_matrix(n, g)
+    LU, ipiv, perm, info = factor(dd, A, panel=0, pivot="none")
+    LUo, ipo, info_o = oracle.getrf(A, panel=1, pivot=False, algo="block", levels=0)
+    assert info == info_o == 0
+    assert np.array_equal(ipiv, np.arange(n)) and np.array_equal(perm, np.arange(n))
+    assert np.max(np.abs((LU[0] - LUo[0]) + (LU[1] - LUo[1]))) <= \
+        n * 2.0 ** -96 * np.max(np.abs(LUo[0]))
+    b = inputs.dd_uniform(n, 2, g)
+    x = solve(dd, LU, ipiv, b, perm)
+    assert oracle.lu_residual(A, x, b) <= n * 2.0 ** -100
+
+
+def test_rowwise_integer_factors_exact(dd):
+    g = inputs.rng(250)
+    n = 60
+    L = np.tril(g.integers(-3, 4, (n, n)), -1) + np.eye(n, dtype=np.int64)
+    d = 2.0 ** g.integers(-2, 3, n)
+    U = np.triu(g.integers(-3, 4, (n, n)), 1).astype(np.float64) + np.diag(d)
+    A = np.stack([L.astype(np.float64) @ U, np.zeros((n, n))])
+    LU, _, _, info = factor(dd, A, panel=0, pivot="none")
+    assert info == 0
+    assert np.array_equal(np.tril(LU[0], -1), np.tril(L, -1).astype(np.float64))
+    assert np.array_equal(np.triu(LU[0]), U)
+    assert not LU[1].any()
+
+
+def test_rowwise_zero_pivots_set_info(dd):
+    """An exactly zero pivot: info = its 1-based column, the step is skipped
+    (as the blocked form does); the last pivot is checked too."""
+    n = 5
+    A = np.stack([np.eye(n), np.zeros((n, n))])
+    A[0, 2, 2] = 0.0
+    _, _, _, info = factor(dd, A, panel=0, pivot="none")
+    assert info == 3
+    A = np.stack([np.eye(n), np.zeros((n, n))])
+    A[0, n - 1, n - 1] = 0.0
+    _, _, _, info = factor(dd, A, panel=0, pivot="none")
+    assert info == n

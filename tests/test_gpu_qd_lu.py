@@ -169,3 +169,17 @@ def test_ozaki_trailing_updates(dd):
                              C0=b[:, rows, :])[0]
     normA = np.max(np.sum(np.abs(A[0]), axis=1))
     assert np.max(np.abs(r)) / (normA * np.max(np.abs(x[0]))) <= n * 2.0 ** -200
+
+
+@pytest.mark.parametrize("n", [3, 70, 150])
+def test_rowwise_vs_oracle_unblocked(dd, n):
+    g = inputs.rng(540 + n)
+    A = inputs.qd_lu_matrix(n, g)
+    LU, ipiv, perm, info = factor(dd, A, panel=0, pivot="none")
+    LUo, ipo, info_o = oracle.getrf(A, panel=1, pivot=False, algo="block", levels=0)
+    assert info == info_o == 0
+    assert np.array_equal(ipiv, np.arange(n))
+    assert np.max(vdiff(LU, LUo)) <= n * 2.0 ** -196 * np.max(np.abs(LUo[0]))
+    b = inputs.qd_uniform(n, 1, g)
+    x = solve(dd, LU, ipiv, b, perm)
+    assert oracle.lu_residual(A, x, b) <= n * 2.0 ** -200
