@@ -355,8 +355,9 @@ def bench_paper(dd, inputs, torch, dev, stream):
     (n + 3i - 2) / 6 on sampled entries (mpmath, 400 bits).
     LU (Sec. 4, Fig. 5 upper DD and lower QD): the random matrix with entries
     in [-1, 1], no pivoting, n = 1024, block size K = alpha n_min for
-    alpha = 1, 2, 4, 8, trailing update by Block or Winograd (depth down to
-    n_min) on the FMA base, and Block on Ozaki leaves; x = [0, 1, ..., n-1],
+    alpha = 1, ..., 10, trailing update by Block or Winograd (depth down to
+    n_min) on the FMA base, and Block on Ozaki leaves; the row-wise parallel
+    LU the paper compares against (panel width 0); x = [0, 1, ..., n-1],
     b = A x formed by the library's product, and the maximum relative error of
     the computed x over x_i != 0."""
     import mpmath
@@ -401,33 +402,37 @@ def bench_paper(dd, inputs, torch, dev, stream):
         getrf = dd.dd_getrf if P == 2 else dd.qd_getrf
         getrs = dd.dd_getrs if P == 2 else dd.qd_getrs
         b = prod(A0, torch.from_numpy(x).to(dev))
-        for alpha in (1, 2, 4, 8):
-            K = 32 * alpha
+        runs = [(0, "rowwise", "fma", 0)]   # the paper's row-wise parallel comparator
+        for alpha in range(1, 11):
             for algo, base in (("block", "fma"), ("winograd", "fma"), ("block", "ozaki")):
                 lv = 0 if algo == "block" else alpha.bit_length() - 1
                 if algo == "winograd" and lv == 0:
                     continue
-                ws = torch.empty(max(1, dd.getrf_workspace(n, K, algo, lv, base, P)),
-                                 dtype=torch.uint8, device=dev)
-                A = A0.clone()
-                hold = {}
+                runs.append((32 * alpha, algo, base, lv))
+        for K, algo, base, lv in runs:
+            palgo = "block" if algo == "rowwise" else algo
+            ws = torch.empty(max(1, dd.getrf_workspace(n, K, palgo, lv, base, P)),
+                             dtype=torch.uint8, device=dev)
+            A = A0.clone()
+            hold = {}
 
-                def f():
-                    A.copy_(A0)
-                    hold["r"] = getrf(A, panel=K, pivot="none", algo=algo, levels=lv, base=base,
-                                      ws=ws)
-                t_copy = time_steps(lambda: A.copy_(A0), 3, 1, stream)
-                t = time_steps(f, 2, 1, stream) - t_copy  # A holds the factors after this
-                ipiv, perm, info = hold["r"]
-                X = b.clone()
-                getrs(A, ipiv, X, perm=perm)
-                Xh = X.cpu().numpy()[:, :, 0]
-                d = np.abs((Xh[0, 1:] - np.arange(1, n)) + sum(Xh[c, 1:] for c in range(1, P)))
-                key = f"{'dd' if P == 2 else 'qd'}_lu_n{n}_K{K}_{algo}{lv}_{base}"
-                out["lu"][key] = {"getrf_ms": round(t, 3), "info": int(info.cpu()[0]),
-                                  "max_rel_error_x": float(np.max(d / np.arange(1, n))),
-                                  "normwise_error_x": float(np.max(d) / (n - 1))}
-                log(f"paper {key}: {out['lu'][key]}")
+            def f():
+                A.copy_(A0)
+                hold["r"] = getrf(A, panel=K, pivot="none", algo=palgo, levels=lv, base=base,
+                                  ws=ws)
+            t_copy = time_steps(lambda: A.copy_(A0), 3, 1, stream)
+            t = time_steps(f, 2, 1, stream) - t_copy  # A holds the factors after this
+            ipiv, perm, info = hold["r"]
+            X = b.clone()
+            getrs(A, ipiv, X, perm=perm)
+            Xh = X.cpu().numpy()[:, :, 0]
+            d = np.abs((Xh[0, 1:] - np.arange(1, n)) + sum(Xh[c, 1:] for c in range(1, P)))
+            key = (f"{'dd' if P == 2 else 'qd'}_lu_n{n}_rowwise" if K == 0 else
+                   f"{'dd' if P == 2 else 'qd'}_lu_n{n}_K{K}_{algo}{lv}_{base}")
+            out["lu"][key] = {"getrf_ms": round(t, 3), "info": int(info.cpu()[0]),
+                              "max_rel_error_x": float(np.max(d / np.arange(1, n))),
+                              "normwise_error_x": float(np.max(d) / (n - 1))}
+            log(f"paper {key}: {out['lu'][key]}")
         del A0, b
     return out
 
