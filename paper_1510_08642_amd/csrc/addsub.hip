@@ -29,6 +29,7 @@
 // pre-add moves 4 reads + 7 writes, a post-add 7 reads + 4 writes (+4 reads
 // when beta = 1), P doubles each.
 #include "common.hpp"
+#include "ddqd.h"
 #include "eft.hpp"
 #include "qd.hpp"
 
@@ -187,47 +188,84 @@ int launch_postadd(CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t paren
   return check_launch("postadd_kernel");
 }
 
-// Equilibration exponents: e[r] such that the largest |leading component| of
-// row r of A (rows == true) or column r of B lies in [2^(e-1), 2^e); 0 for an
-// all-zero line.  Rows: one 64-lane wave per row; columns: one lane per
-// column, coalesced across lanes.
-__global__ __launch_bounds__(256) void row_exponent_kernel(CMat A, int64_t m, int64_t l,
-                                                           int* e) {
+// Equilibration exponents: e such that the largest |leading component| of
+// row r of A, or column c of B, lies in [2^(e-1), 2^e); kNoExp, far below any
+// exponent, for an all-zero row or column: its inputs stay zero when scaled,
+// and the rounding residue the recursion leaves in its (exactly zero) row or
+// column of the product is scaled away to zero.
+constexpr int kNoExp = -(1 << 20);
+
+// One wave per row of A, all of a lane's loads in flight before the
+// reduction; the same launch presets B's column exponents to kNoExp.
+__global__ __launch_bounds__(256) void row_exponent_kernel(CMat A, int64_t m, int64_t l, int* e,
+                                                           int* fb, int64_t n) {
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * 256)
+    fb[c] = kNoExp;
   const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (r >= m) return;
+  const double* p = A.p + r * A.ld;
   double mx = 0.0;
-  for (int64_t k = lane; k < l; k += 64) mx = fmax(mx, fabs(A.p[r * A.ld + k]));
+  int64_t k = lane;
+  for (; k + 960 < l; k += 1024) {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) v[q] = p[k + 64 * q];
+#pragma unroll
+    for (int q = 0; q < 16; q++) mx = fmax(mx, fabs(v[q]));
+  }
+  for (; k < l; k += 64) mx = fmax(mx, fabs(p[k]));
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
   if (lane == 0) {
-    int ex = 0;
+    int ex = kNoExp;
     if (mx > 0.0) frexp(mx, &ex);
     e[r] = ex;
   }
 }
 
+// A workgroup takes 64 columns by a 32-row slab of B and raises each column's
+// exponent to its slab maximum's (atomic maximum; exponents are monotone in
+// |x|, so the maximum of the slab exponents is the column maximum's, in any
+// order).  All-zero columns keep kNoExp.
 __global__ __launch_bounds__(256) void col_exponent_kernel(CMat B, int64_t l, int64_t n,
                                                            int* e) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= n) return;
+  __shared__ double red[4][64];
+  const int c_in = threadIdx.x % 64, r = threadIdx.x / 64;
+  const int64_t c = (int64_t)blockIdx.x * 64 + c_in;
+  const int64_t k0 = (int64_t)blockIdx.y * 32 + r * 8;
   double mx = 0.0;
-  for (int64_t k = 0; k < l; k++) mx = fmax(mx, fabs(B.p[k * B.ld + c]));
-  int ex = 0;
-  if (mx > 0.0) frexp(mx, &ex);
-  e[c] = ex;
+  if (c < n) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) v[q] = k0 + q < l ? B.p[(k0 + q) * B.ld + c] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; q++) mx = fmax(mx, fabs(v[q]));
+  }
+  red[r][c_in] = mx;
+  __syncthreads();
+  if (r == 0 && c < n) {
+    mx = fmax(fmax(red[0][c_in], red[1][c_in]), fmax(red[2][c_in], red[3][c_in]));
+    if (mx > 0.0) {
+      int ex;
+      frexp(mx, &ex);
+      atomicMax(&e[c], ex);
+    }
+  }
 }
 
 int launch_exponents(CMat A, CMat B, int64_t m, int64_t n, int64_t l, int* ea, int* fb,
                      hipStream_t stream) {
+  if ((l + 31) / 32 > 65535) return set_error(DDQD_E_UNSUPPORTED, "inner dimension too large");
   prof_begin(stream);
   hipLaunchKernelGGL(row_exponent_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, stream,
-                     A, m, l, ea);
+                     A, m, l, ea, fb, n);
   prof_record("row_exponent_kernel", stream);
   int rc = check_launch("row_exponent_kernel");
   if (rc) return rc;
   prof_begin(stream);
-  hipLaunchKernelGGL(col_exponent_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
-                     B, l, n, fb);
+  hipLaunchKernelGGL(col_exponent_kernel, dim3((unsigned)((n + 63) / 64), (unsigned)((l + 31) / 32)),
+                     dim3(256), 0, stream, B, l, n, fb);
   prof_record("col_exponent_kernel", stream);
   return check_launch("col_exponent_kernel");
 }

@@ -249,3 +249,27 @@ def test_qd_alpha_beta(dd):
         C = run(dd, 4, A, B, C0=C0, alpha=-1, beta=1, algo=algo, levels=lv)
         e = rownorm_error(A, B, C, ii, jj, alpha=-1, C0=C0)
         assert e <= 2.0 ** -200 * l, (algo, e)
+
+
+@pytest.mark.parametrize("P", [2, 4])
+@pytest.mark.parametrize("algo,lv", [("strassen", 1), ("winograd", 2)])
+def test_recursion_with_zero_rows_and_columns(dd, P, algo, lv):
+    """The recursion's equilibration on all-zero rows of A and columns of B:
+    their exponent is far below range, so the rounding residue the recursion
+    leaves in the (exactly zero) row / column of the product is scaled to
+    zero; and a column whose maximum sits in one 32-row slab."""
+    g = inputs.rng(260 + P)
+    m, n, l = 70, 66, 97
+    gen = inputs.dd_uniform if P == 2 else inputs.qd_uniform
+    A = gen(m, l, g)
+    B = gen(l, n, g)
+    A[:, 5, :] = 0.0
+    B[:, :, 9] = 0.0
+    B[:, :, 40] *= 2.0 ** -40
+    B[0, 90, 40] = 3.0
+    C = run(dd, P, A, B, algo=algo, levels=lv)
+    assert not C[:, 5, :].any() and not C[:, :, 9].any()
+    ii, jj = all_entries(m, n)
+    den = np.maximum(rownorm_den(A, B), 1e-300)
+    e = rownorm_error(A, B, C, ii, jj, den=den)
+    assert e <= (2.0 ** -100 if P == 2 else 2.0 ** -200) * l, e
