@@ -108,117 +108,32 @@ __device__ __forceinline__ void col_exponents(const OzLayout& o, const int* part
   __syncthreads();
 }
 
-// Slicing.  A workgroup takes 32 lines (rows of A or columns of B) by 128 k
-// (four 32-k blocks): the DD values are read with coalesced loads (along k
-// for A, along the columns for B) into an LDS tile, then each wave slices one
-// 32x32 block and each lane one fragment slot: 16 consecutive k of one line,
-// exactly what one lane of the 32x32x32 MFMA holds, so each slice is one
-// 16-byte store and a wave writes a whole 1 KB fragment.  Both operands in
-// one launch (blockIdx.y: 0 = A, 1 = B).  Digits of a scaled DD value
-// r = hi + lo (|r| < 1/2, |lo| <= ulp(hi) / 2): runs of kRun digits
-// d = rint(2^7 hi), hi := 2^7 hi - d are taken from the high word alone (each
-// step exact), the low word standing for lo 2^(7j) after j steps; then the
-// run ends with (hi, lo) := FastTwoSum(hi, lo 2^(7 kRun)).  Within a run hi
-// stays 0 or a multiple of 2^(7j) ulp(hi_0) >= 2 |lo 2^(7j)|, so the merge is
-// exact (FastTwoSum's precondition) and the part a digit ignores is below
-// 2^(7 kRun - 54) <= 2^-12 of a digit unit: digits stay in [-64, 64] and the
-// remainder after S digits below (1/2 + 2^-12) 2^-7S.
-constexpr int kSliceK = 128;  // k per slicing workgroup (four 32-k blocks)
-constexpr int kRun = 6;       // digits per run from the high word alone
+// A workgroup takes 32 lines (rows of A or columns of B) by 64 k (two 32-k
+// blocks): the P planes are read with coalesced loads into LDS (along k for
+// A, along the columns for B); wave w then slices k block w / 2, half w % 2
+// of every lane's 16-k fragment slot (8 values of one line per lane, 8 bytes
+// per digit).  Both operands in one launch (blockIdx.y: 0 = A, 1 = B).
+//
+// Digits of a scaled value r (|r| < 1/2) held as an expansion r0 + r1 (+ r2
+// + r3): runs of kRun digits d = rint(2^7 r0), r0 := 2^7 r0 - d are taken
+// from the leading term alone (each step exact; the lower terms stand for
+// themselves times 2^(7j) after j steps), then the lower terms are scaled by
+// 2^(7 kRun) and merged: DD by FastTwoSum(r0, r1) (r0 is 0 or a multiple of
+// 2^(7j) ulp(r0 at the run's start) >= 2 |r1|, its precondition), QD by one
+// bottom-up TwoSum pass, which leaves the rest within about an ulp of the
+// leading term.  Inside a run the part a digit ignores is below
+// 2^(7 kRun - 54) <= 2^-12 of a digit unit, so digits stay in [-64, 64] and
+// the remainder after S digits stays below (1/2 + 2^-12) 2^-7S.
+constexpr int kSliceK = 64;   // k per slicing workgroup (two 32-k blocks)
+constexpr int kRun = 6;       // digits per run from the leading term alone
 static_assert(kRun == 6, "the merge scales by 2^42 = 2^(7 kRun)");
 
-template <int S>
+template <int P, int S>
 __global__ __launch_bounds__(256) void oz_slice_kernel(CMat A, CMat B, int64_t m, int64_t n,
                                                        int64_t l, OzLayout o, const int* ea,
                                                        const int* part, int* fb,
                                                        signed char* Asl, signed char* Bsl) {
-  __shared__ double tile[2][32][kSliceK + 1];
-  __shared__ int xc[8 * 32];
-  const int side = blockIdx.y;
-  const int64_t b = blockIdx.z;
-  const int64_t nblk32 = side == 0 ? o.rb : o.cb;
-  const int64_t kgroups = (o.kb + 3) / 4;
-  if ((int64_t)blockIdx.x >= nblk32 * kgroups) return;  // uniform per workgroup
-  const int64_t blk = blockIdx.x / kgroups, kg = blockIdx.x % kgroups;
-  const int64_t line0 = blk * 32, kbase = kg * kSliceK;
-  const CMat X = side == 0 ? A : B;
-  const int64_t lines_live = side == 0 ? m : n;
-  const double* base = X.p + b * X.bstride;
-  const int t = threadIdx.x;
-  // coalesced loads of the 32 x 128 tile (16 values per plane per thread)
-  double vh[16], vl[16];
-#pragma unroll
-  for (int j = 0; j < 16; j++) {
-    const int e = t + 256 * j;
-    const int ln = side == 0 ? e / kSliceK : e % 32;
-    const int kk = side == 0 ? e % kSliceK : e / 32;
-    const int64_t line = line0 + ln, k = kbase + kk;
-    const bool in = line < lines_live && k < l;
-    const int64_t idx = side == 0 ? (in ? line * X.ld + k : 0) : (in ? k * X.ld + line : 0);
-    vh[j] = in ? base[idx] : 0.0;
-    vl[j] = in ? base[X.ps + idx] : 0.0;
-  }
-#pragma unroll
-  for (int j = 0; j < 16; j++) {
-    const int e = t + 256 * j;
-    const int ln = side == 0 ? e / kSliceK : e % 32;
-    const int kk = side == 0 ? e % kSliceK : e / 32;
-    tile[0][ln][kk] = vh[j];
-    tile[1][ln][kk] = vl[j];
-  }
-  __syncthreads();
-  if (side == 1) col_exponents(o, part, fb, b, line0, kg == 0, xc);  // uniform per workgroup
-  const int w = t / 64, lane = t % 64;
-  const int64_t kb = kg * 4 + w;
-  if (kb >= o.kb) return;
-  const int ln = lane % 32, k0 = w * 32 + 16 * (lane / 32);
-  const int ex = side == 0 ? ea[b * (nblk32 * 32) + line0 + ln] : xc[ln];
-  double rh[16], rl[16];
-#pragma unroll
-  for (int q = 0; q < 16; q++) {
-    rh[q] = ldexp(tile[0][ln][k0 + q], -ex);
-    rl[q] = ldexp(tile[1][ln][k0 + q], -ex);
-  }
-  signed char* dst = (side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
-                     (blk * o.kb + kb) * S * (int64_t)kOzFrag + lane * 16;
-  // a pair whose low word exceeds half an ulp of the high one is brought
-  // into shape first (exact)
-#pragma unroll
-  for (int q = 0; q < 16; q++) two_sum(rh[q], rl[q], rh[q], rl[q]);
-#pragma unroll 1
-  for (int s0 = 0; s0 < S; s0 += kRun) {
-#pragma unroll
-    for (int j = 0; j < kRun; j++) {
-      if (s0 + j < S) {
-        uint32_t x[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int q = 0; q < 16; q++) {
-          const double h = rh[q] * 128.0;
-          const double d = rint(h);
-          x[q / 4] |= (uint32_t)(uint8_t)(signed char)(int)d << (8 * (q % 4));
-          rh[q] = h - d;
-        }
-        *reinterpret_cast<v4i*>(dst + (s0 + j) * (int64_t)kOzFrag) =
-            v4i{(int)x[0], (int)x[1], (int)x[2], (int)x[3]};
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 16; q++) fast_two_sum(rh[q], rl[q] * 0x1p42, rh[q], rl[q]);
-  }
-}
-
-// A workgroup takes 32 lines (rows of A or columns of B) by 64 k (two 32-k
-// blocks): the four planes are read with coalesced loads into LDS; wave w
-// then slices k block w / 2, half w % 2 of every lane's 16-k fragment slot
-// (8 values of one line per lane, 8 bytes per digit).
-constexpr int kSliceKQ = 64;
-
-template <int S>
-__global__ __launch_bounds__(256) void ozq_slice_kernel(CMat A, CMat B, int64_t m, int64_t n,
-                                                        int64_t l, OzLayout o, const int* ea,
-                                                        const int* part, int* fb,
-                                                        signed char* Asl, signed char* Bsl) {
-  __shared__ double tile[4][32][kSliceKQ + 1];
+  __shared__ double tile[P][32][kSliceK + 1];
   __shared__ int xc[8 * 32];
   const int side = blockIdx.y;
   const int64_t b = blockIdx.z;
@@ -226,31 +141,30 @@ __global__ __launch_bounds__(256) void ozq_slice_kernel(CMat A, CMat B, int64_t 
   const int64_t kgroups = (o.kb + 1) / 2;
   if ((int64_t)blockIdx.x >= nblk32 * kgroups) return;  // uniform per workgroup
   const int64_t blk = blockIdx.x / kgroups, kg = blockIdx.x % kgroups;
-  const int64_t line0 = blk * 32, kbase = kg * kSliceKQ;
+  const int64_t line0 = blk * 32, kbase = kg * kSliceK;
   const CMat X = side == 0 ? A : B;
   const int64_t lines_live = side == 0 ? m : n;
   const double* base = X.p + b * X.bstride;
   const int t = threadIdx.x;
+  double v[P][8];
 #pragma unroll
-  for (int c = 0; c < 4; c++) {
-    double v[8];
+  for (int j = 0; j < 8; j++) {  // every load in flight before the first use
+    const int e = t + 256 * j;
+    const int ln = side == 0 ? e / kSliceK : e % 32;
+    const int kk = side == 0 ? e % kSliceK : e / 32;
+    const int64_t line = line0 + ln, k = kbase + kk;
+    const bool in = line < lines_live && k < l;
+    const int64_t idx = in ? (side == 0 ? line * X.ld + k : k * X.ld + line) : 0;
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const int e = t + 256 * j;
-      const int ln = side == 0 ? e / kSliceKQ : e % 32;
-      const int kk = side == 0 ? e % kSliceKQ : e / 32;
-      const int64_t line = line0 + ln, k = kbase + kk;
-      const bool in = line < lines_live && k < l;
-      const int64_t idx = in ? (side == 0 ? line * X.ld + k : k * X.ld + line) : 0;
-      v[j] = in ? base[c * X.ps + idx] : 0.0;
-    }
+    for (int c = 0; c < P; c++) v[c][j] = in ? base[c * X.ps + idx] : 0.0;
+  }
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const int e = t + 256 * j;
-      const int ln = side == 0 ? e / kSliceKQ : e % 32;
-      const int kk = side == 0 ? e % kSliceKQ : e / 32;
-      tile[c][ln][kk] = v[j];
-    }
+  for (int j = 0; j < 8; j++) {
+    const int e = t + 256 * j;
+    const int ln = side == 0 ? e / kSliceK : e % 32;
+    const int kk = side == 0 ? e % kSliceK : e / 32;
+#pragma unroll
+    for (int c = 0; c < P; c++) tile[c][ln][kk] = v[c][j];
   }
   __syncthreads();
   if (side == 1) col_exponents(o, part, fb, b, line0, kg == 0, xc);  // uniform per workgroup
@@ -260,56 +174,61 @@ __global__ __launch_bounds__(256) void ozq_slice_kernel(CMat A, CMat B, int64_t 
   const int half = w % 2;
   const int ln = lane % 32, k0 = (w / 2) * 32 + 16 * (lane / 32) + 8 * half;
   const int ex = side == 0 ? ea[b * (nblk32 * 32) + line0 + ln] : xc[ln];
-  double r0[8], r1[8], r2[8], r3[8];
+  double r[P][8];
+#pragma unroll
+  for (int q = 0; q < 8; q++)
+#pragma unroll
+    for (int c = 0; c < P; c++) r[c][q] = ldexp(tile[c][ln][k0 + q], -ex);
+  // an input whose terms overlap is brought into shape first (exact)
 #pragma unroll
   for (int q = 0; q < 8; q++) {
-    r0[q] = ldexp(tile[0][ln][k0 + q], -ex);
-    r1[q] = ldexp(tile[1][ln][k0 + q], -ex);
-    r2[q] = ldexp(tile[2][ln][k0 + q], -ex);
-    r3[q] = ldexp(tile[3][ln][k0 + q], -ex);
+    if constexpr (P == 2) {
+      two_sum(r[0][q], r[1][q], r[0][q], r[1][q]);
+    } else {
+      double a2, a3, a1, b2, a0, b1;
+      two_sum(r[2][q], r[3][q], a2, a3);
+      two_sum(r[1][q], a2, a1, b2);
+      two_sum(r[0][q], a1, a0, b1);
+      r[0][q] = a0;
+      r[1][q] = b1;
+      r[2][q] = b2;
+      r[3][q] = a3;
+    }
   }
   signed char* dst = (side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
                      (blk * o.kb + kb) * S * (int64_t)kOzFrag + lane * 16 + 8 * half;
-  // the first pass also brings an input whose terms overlap into shape
-#pragma unroll
-  for (int q = 0; q < 8; q++) {
-    double a2, a3, a1, b2, a0, b1;
-    two_sum(r2[q], r3[q], a2, a3);
-    two_sum(r1[q], a2, a1, b2);
-    two_sum(r0[q], a1, a0, b1);
-    r0[q] = a0;
-    r1[q] = b1;
-    r2[q] = b2;
-    r3[q] = a3;
-  }
 #pragma unroll 1
-  for (int s0 = 0; s0 < S; s0 += 6) {
+  for (int s0 = 0; s0 < S; s0 += kRun) {
 #pragma unroll
-    for (int j = 0; j < 6; j++) {
+    for (int j = 0; j < kRun; j++) {
       if (s0 + j < S) {
         uint32_t x[2] = {0u, 0u};
 #pragma unroll
         for (int q = 0; q < 8; q++) {
-          const double h = r0[q] * 128.0;
+          const double h = r[0][q] * 128.0;
           const double d = rint(h);
           x[q / 4] |= (uint32_t)(uint8_t)(signed char)(int)d << (8 * (q % 4));
-          r0[q] = h - d;
+          r[0][q] = h - d;
         }
         *reinterpret_cast<uint2*>(dst + (s0 + j) * (int64_t)kOzFrag) = uint2{x[0], x[1]};
       }
     }
-    // remainder r0 + 2^42 (r1 + r2 + r3), all terms exact; one bottom-up
-    // TwoSum pass keeps the sum and brings it to the front
 #pragma unroll
     for (int q = 0; q < 8; q++) {
-      double a2, a3, a1, b2, a0, b1;
-      two_sum(r2[q] * 0x1p42, r3[q] * 0x1p42, a2, a3);
-      two_sum(r1[q] * 0x1p42, a2, a1, b2);
-      two_sum(r0[q], a1, a0, b1);
-      r0[q] = a0;
-      r1[q] = b1;
-      r2[q] = b2;
-      r3[q] = a3;
+      if constexpr (P == 2) {
+        fast_two_sum(r[0][q], r[1][q] * 0x1p42, r[0][q], r[1][q]);
+      } else {
+        // remainder r0 + 2^42 (r1 + r2 + r3), all terms exact; one bottom-up
+        // TwoSum pass keeps the sum and brings it to the front
+        double a2, a3, a1, b2, a0, b1;
+        two_sum(r[2][q] * 0x1p42, r[3][q] * 0x1p42, a2, a3);
+        two_sum(r[1][q] * 0x1p42, a2, a1, b2);
+        two_sum(r[0][q], a1, a0, b1);
+        r[0][q] = a0;
+        r[1][q] = b1;
+        r[2][q] = b2;
+        r[3][q] = a3;
+      }
     }
   }
 }
@@ -332,10 +251,10 @@ namespace {
 
 template <int S>
 int slice_dd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s) {
-  const int64_t sblocks = (o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 3) / 4);
+  const int64_t sblocks = (o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 1) / 2);
   if (sblocks > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "matrix too large");
   prof_begin(s);
-  hipLaunchKernelGGL(oz_slice_kernel<S>, dim3((unsigned)sblocks, 2, (unsigned)g.batch),
+  hipLaunchKernelGGL((oz_slice_kernel<2, S>), dim3((unsigned)sblocks, 2, (unsigned)g.batch),
                      dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)w.ea,
                      (const int*)w.part, w.fb, w.Asl, w.Bsl);
   prof_record("oz_slice_kernel", s);
@@ -347,11 +266,11 @@ int slice_qd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s
   const int64_t sblocks = (o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 1) / 2);
   if (sblocks > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "matrix too large");
   prof_begin(s);
-  hipLaunchKernelGGL(ozq_slice_kernel<S>, dim3((unsigned)sblocks, 2, (unsigned)g.batch),
+  hipLaunchKernelGGL((oz_slice_kernel<4, S>), dim3((unsigned)sblocks, 2, (unsigned)g.batch),
                      dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)w.ea,
                      (const int*)w.part, w.fb, w.Asl, w.Bsl);
-  prof_record("ozq_slice_kernel", s);
-  return check_launch("ozq_slice_kernel");
+  prof_record("oz_slice_kernel", s);
+  return check_launch("oz_slice_kernel");
 }
 
 }  // namespace
