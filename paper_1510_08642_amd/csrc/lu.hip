@@ -65,6 +65,17 @@ struct LuArith<2> {
     fast_two_sum(q1, q2, q.hi, q.lo);
     return dd_add(q, dd_t{q3, 0.0});
   }
+  // 1 / y: the FP64 reciprocal x0 of y.hi refined by one Newton step,
+  // x0 + x0 (1 - y x0), the residual 1 - y x0 formed by two FMAs (relative
+  // error about 2^-104)
+  __device__ static T recip(T y) {
+    const double x0 = 1.0 / y.hi;
+    double e = fma(-y.hi, x0, 1.0);
+    e = fma(-y.lo, x0, e);
+    T x;
+    fast_two_sum(x0, x0 * e, x.hi, x.lo);
+    return x;
+  }
   __device__ static Acc acc(T x) { return Acc{{x.hi, x.lo}}; }
   // a -= p q
   __device__ static void acc_sub(Acc& a, T p, T q) {
@@ -120,6 +131,17 @@ struct LuArith<4> {
     return q;
   }
   __device__ static T div(T a, T b) { return div_digits(a, b, 1.0 / b.c[0]); }
+  // 1 / y: the DD reciprocal of y's two leading terms (as LuArith<2>),
+  // then one Newton step x + x (1 - y x) in QD (relative error about 2^-207)
+  __device__ static T recip(T y) {
+    const double x0 = 1.0 / y.c[0];
+    double e = fma(-y.c[0], x0, 1.0);
+    e = fma(-y.c[1], x0, e);
+    T x{{0.0, 0.0, 0.0, 0.0}};
+    fast_two_sum(x0, x0 * e, x.c[0], x.c[1]);
+    const T r = qd_sub(one(), qd_mul(y, x));
+    return qd_add(x, qd_mul(x, r));
+  }
   __device__ static Acc acc(T x) { return Acc{{x.c[0], x.c[1], x.c[2], x.c[3]}}; }
   // a -= p q
   __device__ static void acc_sub(Acc& a, T p, T q) {
@@ -307,8 +329,9 @@ __device__ __forceinline__ int wave_argmax(const typename LuArith<P>::T& x, int 
 //   2. after the barrier every wave reduces the wave winners itself and reads
 //      the pivot row p from the winning wave's slot; the owners of rows c and
 //      p exchange them in registers;
-//   3. the column below the pivot is divided by the pivot (long division)
-//      and the remaining strip columns get the rank-1 update.
+//   3. the column below the pivot is multiplied by the pivot's reciprocal
+//      (formed once per column by a Newton step) and the remaining strip
+//      columns get the rank-1 update.
 // The published slots are double-buffered by the parity of c: a slot is
 // rewritten two columns later, after a barrier that every reader of its old
 // contents has passed.
@@ -447,12 +470,17 @@ __global__ __launch_bounds__(T) void getf2_kernel(double* A, int64_t lda, int64_
     const V u = rpv(c);
     if (t == 0 && N::is_zero(u) && *info == 0) *info = (int32_t)(c0 + c + 1);
     if (!N::is_zero(u)) {
-      const double uinv = 1.0 / N::get(u, 0);
+      // multipliers by the pivot's reciprocal (one reciprocal per column, as
+      // LAPACK scales the column); long division where 1 / u.hi would leave
+      // the normal range
+      const bool by_recip = fabs(N::get(u, 0)) >= 0x1p-1000;
+      const V uinv = by_recip ? N::recip(u) : N::zero();
+      const double uinv0 = 1.0 / N::get(u, 0);
 #pragma unroll
       for (int q = 0; q < RPT; q++) {
         const int i = t + T * q;
         if (i > c && i < m) {
-          const V l = N::div_digits(v[q][c], u, uinv);
+          const V l = by_recip ? N::mul(v[q][c], uinv) : N::div_digits(v[q][c], u, uinv0);
           v[q][c] = l;
 #pragma unroll
           for (int k = c + 1; k < W; k++)
