@@ -90,6 +90,15 @@ struct LuArith<2> {
     two_sum(a.w[0], a.w[1], v.hi, v.lo);
     return v;
   }
+  // the same accumulation kept in a number's registers: x -= p q leaves x
+  // as an unnormalised pair (sum, error); norm() restores a DD
+  __device__ static void lazy_sub(T& x, T p, T q) {
+    Acc a{{x.hi, x.lo}};
+    acc_sub(a, p, q);
+    x.hi = a.w[0];
+    x.lo = a.w[1];
+  }
+  __device__ static T norm(T x) { return value(Acc{{x.hi, x.lo}}); }
 };
 
 template <>
@@ -158,6 +167,15 @@ struct LuArith<4> {
     qd_renorm(v.c[0], v.c[1], v.c[2], v.c[3]);
     return v;
   }
+  // the same accumulation kept in a number's registers (order buckets);
+  // norm() restores a QD
+  __device__ static void lazy_sub(T& x, T p, T q) {
+    Acc a{{x.c[0], x.c[1], x.c[2], x.c[3]}};
+    acc_sub(a, p, q);
+#pragma unroll
+    for (int c = 0; c < 4; c++) x.c[c] = a.w[c];
+  }
+  __device__ static T norm(T x) { return value(Acc{{x.c[0], x.c[1], x.c[2], x.c[3]}}); }
 };
 
 template <int P>
@@ -331,7 +349,10 @@ __device__ __forceinline__ int wave_argmax(const typename LuArith<P>::T& x, int 
 //      p exchange them in registers;
 //   3. the column below the pivot is multiplied by the pivot's reciprocal
 //      (formed once per column by a Newton step) and the remaining strip
-//      columns get the rank-1 update.
+//      columns get the rank-1 update, accumulated lazily in the numbers'
+//      own registers (as the products' accumulators: at most W - 1 updates
+//      before a column is normalised at the start of its own step; rows
+//      are normalised when published).
 // The published slots are double-buffered by the parity of c: a slot is
 // rewritten two columns later, after a barrier that every reader of its old
 // contents has passed.
@@ -391,6 +412,9 @@ __global__ __launch_bounds__(T) void getf2_kernel(double* A, int64_t lda, int64_
   for (int c = 0; c < W; c++) {
     if (c >= w) break;
     const int buf = c & 1;
+    // column c has received all its updates (kept unnormalised, see 3.)
+#pragma unroll
+    for (int q = 0; q < RPT; q++) v[q][c] = N::norm(v[q][c]);
     // 1. wave-local pivot search among local rows >= c
     V best = N::zero();
     int bi = -1;
@@ -418,14 +442,18 @@ __global__ __launch_bounds__(T) void getf2_kernel(double* A, int64_t lda, int64_
       const int i = t + T * q;
       if (lane == wl && i == wbi)
 #pragma unroll
-        for (int k = 0; k < W; k++)
+        for (int k = 0; k < W; k++) {
+          const V x = N::norm(v[q][k]);
 #pragma unroll
-          for (int cc = 0; cc < P; cc++) s_row[buf][wave][cc][k] = N::get(v[q][k], cc);
+          for (int cc = 0; cc < P; cc++) s_row[buf][wave][cc][k] = N::get(x, cc);
+        }
       if (i == c)
 #pragma unroll
-        for (int k = 0; k < W; k++)
+        for (int k = 0; k < W; k++) {
+          const V x = N::norm(v[q][k]);
 #pragma unroll
-          for (int cc = 0; cc < P; cc++) s_rowc[buf][cc][k] = N::get(v[q][k], cc);
+          for (int cc = 0; cc < P; cc++) s_rowc[buf][cc][k] = N::get(x, cc);
+        }
     }
     __syncthreads();
     // 2. the winners of all waves, reduced by every wave
@@ -484,7 +512,7 @@ __global__ __launch_bounds__(T) void getf2_kernel(double* A, int64_t lda, int64_
           v[q][c] = l;
 #pragma unroll
           for (int k = c + 1; k < W; k++)
-            if (k < w) v[q][k] = N::sub(v[q][k], N::mul(l, rpv(k)));
+            if (k < w) N::lazy_sub(v[q][k], l, rpv(k));
         }
       }
     }
