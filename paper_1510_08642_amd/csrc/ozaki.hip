@@ -159,6 +159,14 @@ __global__ __launch_bounds__(256) void oz_gemm_kernel(GemmBatch g, OzLayout o,
     const int rb2 = 4 * (ln / 32);
     const int64_t col = cb * 32 + ln % 32;
     const int fexp = col < g.n ? fb[b * (o.cb * 32) + col] : 0;
+    // all sixteen row exponents in flight at once (the fragment registers
+    // are free by now), not one group's latency after another
+    int eaq[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+      const int64_t r = rb * 32 + 8 * (q / 4) + rb2 + q % 4;
+      eaq[q] = r < g.m ? ea[b * (o.rb * 32) + r] : 0;
+    }
 #pragma unroll
     for (int q4 = 0; q4 < 4; q4++) {
       __builtin_amdgcn_sched_barrier(0);
@@ -167,7 +175,7 @@ __global__ __launch_bounds__(256) void oz_gemm_kernel(GemmBatch g, OzLayout o,
 #pragma unroll
       for (int z = 0; z < 4; z++) {
         row[z] = rb * 32 + 8 * q4 + rb2 + z;
-        sc[z] = row[z] < g.m ? ea[b * (o.rb * 32) + row[z]] + fexp : 0;
+        sc[z] = row[z] < g.m ? eaq[4 * q4 + z] + fexp : 0;
       }
       double sh[4], sl[4];
 #pragma unroll

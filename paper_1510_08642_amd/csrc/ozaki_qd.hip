@@ -52,26 +52,85 @@ constexpr int kMinS = 28, kMaxS = 31;
 
 size_t align256(size_t x) { return oz_align256(x); }
 
-// ---- the split of the diagonals over the four waves -------------------------
+// ---- the split of the slice products over the four waves -------------------
+//
+// Products are numbered along the diagonals: product (t, u) of diagonal
+// d = t + u has index tri(d) + t.  Wave 0 takes the whole diagonals [0, c),
+// c the diagonal whose product count before it is nearest a quarter of all
+// (so it keeps at most 16 accumulators); waves 1-3 split the remaining
+// indices into three ranges of equal size, so a diagonal may be shared by two
+// waves: each accumulates its part exactly and the epilogue adds all parts.
 
 constexpr int tri(int d) { return d * (d + 1) / 2; }  // products of the diagonals < d
 constexpr int iabs(int x) { return x < 0 ? -x : x; }
 
-// First diagonal of wave w's range: the d whose product count before it is
-// nearest to w/4 of all S(S+1)/2 products.
-constexpr int cut(int S, int w) {
+constexpr int first_cut(int S) {
   int best = 0;
   for (int d = 0; d <= S; d++)
-    if (iabs(4 * tri(d) - w * tri(S)) < iabs(4 * tri(best) - w * tri(S))) best = d;
+    if (iabs(4 * tri(d) - tri(S)) < iabs(4 * tri(best) - tri(S))) best = d;
   return best;
 }
-constexpr int ngroups(int S, int w) { return (cut(S, w + 1) - cut(S, w) + 3) / 4; }
+// first product index of wave w (w = 4: one past the last)
+constexpr int qstart(int S, int w) {
+  if (w == 0) return 0;
+  if (w >= 4) return tri(S);
+  const int q1 = tri(first_cut(S));
+  return q1 + (2 * (tri(S) - q1) * (w - 1) + 3) / 6;
+}
+constexpr int diag_of(int idx) {
+  int d = 0;
+  while (tri(d + 1) <= idx) d++;
+  return d;
+}
+constexpr int dlo(int S, int w) { return diag_of(qstart(S, w)); }
+constexpr int dhi(int S, int w) { return diag_of(qstart(S, w + 1) - 1); }
+constexpr int ngroups(int S, int w) { return (dhi(S, w) - dlo(S, w) + 1 + 3) / 4; }
 constexpr int slot0(int S, int w) {
   int s = 0;
   for (int v = 0; v < w; v++) s += ngroups(S, v);
   return s;
 }
 constexpr int nslots(int S) { return slot0(S, 4); }
+
+// Row t of wave w's part of the product triangle: slices u in [ulo, uhi].
+struct Rows {
+  int ulo[32], uhi[32];
+  int tmax;
+};
+constexpr Rows rows_of(int S, int w) {
+  Rows r{};
+  r.tmax = -1;
+  const int a = qstart(S, w), b = qstart(S, w + 1);
+  for (int t = 0; t < 32; t++) {
+    r.ulo[t] = 1;
+    r.uhi[t] = 0;
+    int lo = -1, hi = -1;
+    for (int u = 0; t + u < S; u++) {
+      const int idx = tri(t + u) + t;
+      if (idx >= a && idx < b) {
+        if (lo < 0) lo = u;
+        hi = u;
+      }
+    }
+    if (lo >= 0) {
+      r.ulo[t] = lo;
+      r.uhi[t] = hi;
+      r.tmax = t;
+    }
+  }
+  return r;
+}
+// every row up to tmax holds products and the windows only move up as t
+// falls: then each B fragment is read once, when it first enters the window
+constexpr bool rows_ok(int S, int w) {
+  const Rows r = rows_of(S, w);
+  if (r.tmax < 0) return false;
+  for (int t = 0; t <= r.tmax; t++) {
+    if (r.ulo[t] > r.uhi[t]) return false;
+    if (t > 0 && (r.ulo[t - 1] < r.ulo[t] || r.uhi[t - 1] < r.uhi[t])) return false;
+  }
+  return true;
+}
 
 // ---- products ---------------------------------------------------------------
 
@@ -95,16 +154,19 @@ struct Stage {
   }
 };
 
-// Wave with diagonals [D0, D1): rows t of the product triangle from the last
-// down to 0, each row's slices u ascending, so every row brings in one new A
-// and one new B fragment (prefetched during the row before) and consecutive
-// uses of one accumulator are at least a row apart.  Afterwards the
-// diagonals go to LDS as FP64 group values (slots from SL0).
+// Wave W's part of the products: rows t from the last down to 0, each row's
+// slices u ascending, so every row brings in one new A fragment and the B
+// fragments entering its window (prefetched during the row before), and
+// consecutive uses of one accumulator are at least a row apart.  Afterwards
+// its diagonals [D0, D1) go to LDS as FP64 group values (slots from SL0).
 template <int S, int W>
 __device__ __forceinline__ void ozq_wave(const Stage<S>& stage, int lane, int64_t kc0,
                                          int64_t kc1, double (*red)[32][32]) {
-  constexpr int D0 = cut(S, W), D1 = cut(S, W + 1), SL0 = slot0(S, W);
+  constexpr int D0 = dlo(S, W), D1 = dhi(S, W) + 1, SL0 = slot0(S, W);
   constexpr int ND = D1 - D0;
+  constexpr Rows R = rows_of(S, W);
+  constexpr int TM = R.tmax;
+  static_assert(rows_ok(S, W), "wave rows");
   v16i acc[ND];
 #pragma unroll
   for (int d = 0; d < ND; d++)
@@ -118,20 +180,20 @@ __device__ __forceinline__ void ozq_wave(const Stage<S>& stage, int lane, int64_
     if (kb + 1 < kc1) stage.template load<W>(st ^ 1, kb + 1);
     const v4i(*L)[64] = stage.lds[st];
     v4i fb[S];
-    constexpr int t_hi = D1 - 1;  // D1 <= S
-    v4i fa_cur = L[t_hi][lane];
-    fb[0] = L[S + 0][lane];
+    v4i fa_cur = L[TM][lane];
 #pragma unroll
-    for (int t = t_hi; t >= 0; t--) {
-      const int ulo = D0 - t > 0 ? D0 - t : 0, uhi = D1 - 1 - t;
+    for (int u = R.ulo[TM]; u <= R.uhi[TM]; u++) fb[u] = L[S + u][lane];
+#pragma unroll
+    for (int t = TM; t >= 0; t--) {
       v4i fa_next = fa_cur;
       if (t > 0) {
         fa_next = L[t - 1][lane];
-        fb[D1 - t] = L[S + D1 - t][lane];
+#pragma unroll
+        for (int u = R.uhi[t] + 1; u <= R.uhi[t - 1]; u++) fb[u] = L[S + u][lane];
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = ulo; u <= uhi; u++)
+      for (int u = R.ulo[t]; u <= R.uhi[t]; u++)
         acc[t + u - D0] =
             __builtin_amdgcn_mfma_i32_32x32x32_i8(fa_cur, fb[u], acc[t + u - D0], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
@@ -164,7 +226,7 @@ __global__ __launch_bounds__(256) void ozq_gemm_kernel(GemmBatch g, OzLayout o,
                                                        int beta) {
   __shared__ v4i lds[2][2 * S][64];
   static_assert(nslots(S) * 32 * 32 * sizeof(double) <= sizeof(lds), "epilogue LDS");
-  static_assert(cut(S, 1) <= 16, "wave 0 keeps at most 16 accumulators");
+  static_assert(first_cut(S) <= 16, "wave 0 keeps at most 16 accumulators");
 
   const int64_t t = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
   const int64_t per = o.rb * o.cb;
