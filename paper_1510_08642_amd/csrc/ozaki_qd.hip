@@ -95,6 +95,7 @@ constexpr int nslots(int S) { return slot0(S, 4); }
 // Row t of wave w's part of the product triangle: slices u in [ulo, uhi].
 struct Rows {
   int ulo[32], uhi[32];
+  int pre[32];  // products in the rows above t (the wave walks t downwards)
   int tmax;
 };
 constexpr Rows rows_of(int S, int w) {
@@ -118,6 +119,11 @@ constexpr Rows rows_of(int S, int w) {
       r.tmax = t;
     }
   }
+  int n = 0;
+  for (int t = 31; t >= 0; t--) {
+    r.pre[t] = n;
+    if (r.ulo[t] <= r.uhi[t]) n += r.uhi[t] - r.ulo[t] + 1;
+  }
   return r;
 }
 // every row up to tmax holds products and the windows only move up as t
@@ -140,6 +146,18 @@ struct Stage {
   const signed char* asrc;  // this workgroup's A row block, lane offset applied
   const signed char* bsrc;  // its B column block
 
+  // the j-th of wave W's fragments (W + 4 j) of K block kb into buffer st
+  template <int W>
+  __device__ __forceinline__ void load_one(int st, int64_t kb, int j) const {
+    const int f = W + 4 * j;
+    const signed char* src = f < S ? asrc + (kb * S + f) * (int64_t)kFrag
+                                   : bsrc + (kb * S + f - S) * (int64_t)kFrag;
+    __builtin_amdgcn_global_load_lds(
+        (const void*)src, (__attribute__((address_space(3))) void*)&lds[st][f][0], 16, 0, 0);
+  }
+  // how many of the 2S fragments are wave W's
+  template <int W>
+  static constexpr int count() { return (2 * S - W + 3) / 4; }
   // wave W's share (fragments W, W + 4, ...) of the 2S fragments of K block
   // kb into buffer st
   template <int W>
@@ -156,7 +174,7 @@ struct Stage {
 
 // Wave W's part of the products: rows t from the last down to 0, each row's
 // slices u ascending, so every row brings in one new A fragment and the B
-// fragments entering its window (prefetched during the row before), and
+// fragments entering its window (read two rows ahead), and
 // consecutive uses of one accumulator are at least a row apart.  Afterwards
 // its diagonals [D0, D1) go to LDS as FP64 group values (slots from SL0).
 template <int S, int W>
@@ -172,32 +190,50 @@ __device__ __forceinline__ void ozq_wave(const Stage<S>& stage, int lane, int64_
   for (int d = 0; d < ND; d++)
 #pragma unroll
     for (int q = 0; q < 16; q++) acc[d][q] = 0;
+  constexpr int NDMA = Stage<S>::template count<W>();
+  static_assert(NDMA <= tri(S), "one DMA load per MFMA");
   for (int64_t kb = kc0; kb < kc1; kb++) {
     const int st = (int)((kb - kc0) & 1);
     // block kb has landed in buffer st, every wave is done with buffer st ^ 1
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (kb + 1 < kc1) stage.template load<W>(st ^ 1, kb + 1);
+    // block kb + 1 goes into buffer st ^ 1, one fragment after each of the
+    // first MFMAs, so the DMA issue hides behind the matrix cores.  In the
+    // last iteration the last block is loaded again (buffer st ^ 1 is not
+    // read any more, and the loads have landed before the epilogue reuses
+    // LDS), which keeps the MFMA stream free of branches.
+    const int64_t kn = kb + 1 < kc1 ? kb + 1 : kc1 - 1;
     const v4i(*L)[64] = stage.lds[st];
-    v4i fb[S];
-    v4i fa_cur = L[TM][lane];
+    // fragments are read two rows ahead (short rows would not cover the LDS
+    // latency with one)
+    v4i fa[S], fb[S];
+    fa[TM] = L[TM][lane];
 #pragma unroll
     for (int u = R.ulo[TM]; u <= R.uhi[TM]; u++) fb[u] = L[S + u][lane];
+    if (TM > 0) {
+      fa[TM - 1] = L[TM - 1][lane];
+#pragma unroll
+      for (int u = R.uhi[TM] + 1; u <= R.uhi[TM > 0 ? TM - 1 : 0]; u++) fb[u] = L[S + u][lane];
+    }
 #pragma unroll
     for (int t = TM; t >= 0; t--) {
-      v4i fa_next = fa_cur;
-      if (t > 0) {
-        fa_next = L[t - 1][lane];
+      if (t > 1) {
+        fa[t - 2] = L[t - 2][lane];
 #pragma unroll
-        for (int u = R.uhi[t] + 1; u <= R.uhi[t - 1]; u++) fb[u] = L[S + u][lane];
+        for (int u = R.uhi[t - 1] + 1; u <= R.uhi[t - 2]; u++) fb[u] = L[S + u][lane];
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = R.ulo[t]; u <= R.uhi[t]; u++)
+      for (int u = R.ulo[t]; u <= R.uhi[t]; u++) {
         acc[t + u - D0] =
-            __builtin_amdgcn_mfma_i32_32x32x32_i8(fa_cur, fb[u], acc[t + u - D0], 0, 0, 0);
+            __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[t], fb[u], acc[t + u - D0], 0, 0, 0);
+        const int m = R.pre[t] + u - R.ulo[t];
+        if (m < NDMA) {
+          stage.template load_one<W>(st ^ 1, kn, m);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
       __builtin_amdgcn_sched_barrier(0);
-      fa_cur = fa_next;
     }
   }
   __builtin_amdgcn_s_waitcnt(0);
