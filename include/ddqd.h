@@ -97,10 +97,14 @@ int ddqd_profile_query(const char* substr, double* ms, int64_t* count);
  *             C must not overlap A or B (DDQD_E_ALIAS); A and B may overlap.
  *   algo      DDQD_SIMPLE, DDQD_BLOCK, DDQD_STRASSEN or DDQD_WINOGRAD, or
  *             DDQD_AUTO (see dd_gemm_tune; `levels` is then ignored).
- *   levels    recursion depth for Strassen/Winograd (0..6); the depth
+ *   levels    recursion depth L for Strassen/Winograd (0..6); the depth
  *             actually used stops early once a dimension would drop below 2.
- *             Each level splits m, l and n in half; an odd dimension is
- *             peeled (last row / column handled by rank-1 and panel products).
+ *             Each level splits m, l and n in half: a dimension that 2^L
+ *             does not divide is cut down to a multiple (remainder <=
+ *             2^(L-1): the last rows / columns / k become Block products at
+ *             the top level) or padded with zeros up to one inside the
+ *             workspace (the padding is never read from A, B or C, nor
+ *             written to C).
  *   base      DDQD_BASE_FMA or DDQD_BASE_OZAKI_I8 for the leaf products
  *             (ignored by DDQD_SIMPLE).
  *   slices    Ozaki slice count (0 = automatic); ignored for FMA.

@@ -41,9 +41,13 @@ namespace {
 
 // expo (top level only, else NULL): the equilibration exponents, per row of
 // A (side 0) or per column of B (side 1); each input is scaled by 2^-expo.
+// src_rows x src_cols is the part of the 2 rows x 2 cols source that exists
+// (the caller's matrix, padded up to an even split at every level): entries
+// outside it are zeros.
 template <class N>
 __global__ __launch_bounds__(256) void preadd_kernel(CMat src, Mat dst, int64_t rows,
-                                                     int64_t cols, int algo, int side,
+                                                     int64_t cols, int64_t src_rows,
+                                                     int64_t src_cols, int algo, int side,
                                                      const int* expo) {
   using T = typename N::T;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -51,21 +55,24 @@ __global__ __launch_bounds__(256) void preadd_kernel(CMat src, Mat dst, int64_t 
   if (e >= rows * cols) return;
   const int64_t i = e / cols, j = e % cols;
   const double* s = src.p + p * src.bstride;
-  T x11 = N::load(s, src.ps, i * src.ld + j);
-  T x12 = N::load(s, src.ps, i * src.ld + j + cols);
-  T x21 = N::load(s, src.ps, (i + rows) * src.ld + j);
-  T x22 = N::load(s, src.ps, (i + rows) * src.ld + j + cols);
+  const bool r1 = i < src_rows, r2 = i + rows < src_rows;
+  const bool c1 = j < src_cols, c2 = j + cols < src_cols;
+  T x11{}, x12{}, x21{}, x22{};
+  if (r1 && c1) x11 = N::load(s, src.ps, i * src.ld + j);
+  if (r1 && c2) x12 = N::load(s, src.ps, i * src.ld + j + cols);
+  if (r2 && c1) x21 = N::load(s, src.ps, (i + rows) * src.ld + j);
+  if (r2 && c2) x22 = N::load(s, src.ps, (i + rows) * src.ld + j + cols);
   if (expo) {
     if (side == 0) {  // rows i and i + rows
-      x11 = N::scale(x11, -expo[i]);
-      x12 = N::scale(x12, -expo[i]);
-      x21 = N::scale(x21, -expo[i + rows]);
-      x22 = N::scale(x22, -expo[i + rows]);
+      if (r1) x11 = N::scale(x11, -expo[i]);
+      if (r1) x12 = N::scale(x12, -expo[i]);
+      if (r2) x21 = N::scale(x21, -expo[i + rows]);
+      if (r2) x22 = N::scale(x22, -expo[i + rows]);
     } else {  // columns j and j + cols
-      x11 = N::scale(x11, -expo[j]);
-      x21 = N::scale(x21, -expo[j]);
-      x12 = N::scale(x12, -expo[j + cols]);
-      x22 = N::scale(x22, -expo[j + cols]);
+      if (c1) x11 = N::scale(x11, -expo[j]);
+      if (c1) x21 = N::scale(x21, -expo[j]);
+      if (c2) x12 = N::scale(x12, -expo[j + cols]);
+      if (c2) x22 = N::scale(x22, -expo[j + cols]);
     }
   }
   T o[7];
@@ -120,9 +127,12 @@ __global__ __launch_bounds__(256) void preadd_kernel(CMat src, Mat dst, int64_t 
 
 // ea, fb (top level only, else NULL): equilibration exponents of A's rows and
 // B's columns; entry (r, c) of the result is scaled by 2^(ea[r] + fb[c]).
+// Only the dst_rows x dst_cols part of the 2 rows x 2 cols result is written
+// (the rest is the padding's).
 template <class N>
 __global__ __launch_bounds__(256) void postadd_kernel(CMat prod, Mat dst, int64_t rows,
-                                                      int64_t cols, int algo, int alpha,
+                                                      int64_t cols, int64_t dst_rows,
+                                                      int64_t dst_cols, int algo, int alpha,
                                                       int beta, const int* ea, const int* fb) {
   using T = typename N::T;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -153,6 +163,7 @@ __global__ __launch_bounds__(256) void postadd_kernel(CMat prod, Mat dst, int64_
                           (i + rows) * dst.ld + j + cols};
 #pragma unroll
   for (int q = 0; q < 4; q++) {
+    if (i + (q >> 1) * rows >= dst_rows || j + (q & 1) * cols >= dst_cols) continue;
     T v = alpha < 0 ? N::neg(c[q]) : c[q];
     if (ea) v = N::scale(v, ea[i + (q >> 1) * rows] + fb[j + (q & 1) * cols]);
     if (beta) v = N::add(N::load(d, dst.ps, off[q]), v);
@@ -163,27 +174,29 @@ __global__ __launch_bounds__(256) void postadd_kernel(CMat prod, Mat dst, int64_
 }  // namespace
 
 template <class N>
-int launch_preadd(CMat src, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
-                  int side, const int* expo, hipStream_t stream) {
+int launch_preadd(CMat src, Mat dst, int64_t rows, int64_t cols, int64_t src_rows,
+                  int64_t src_cols, int64_t parents, int algo, int side, const int* expo,
+                  hipStream_t stream) {
   if (rows <= 0 || cols <= 0 || parents <= 0) return 0;
   if (parents > 65535) return set_error(4, "too many recursion parents");
   dim3 grid((unsigned)((rows * cols + 255) / 256), (unsigned)parents);
   prof_begin(stream);
-  hipLaunchKernelGGL(preadd_kernel<N>, grid, dim3(256), 0, stream, src, dst, rows, cols, algo,
-                     side, expo);
+  hipLaunchKernelGGL(preadd_kernel<N>, grid, dim3(256), 0, stream, src, dst, rows, cols,
+                     src_rows, src_cols, algo, side, expo);
   prof_record("preadd_kernel", stream);
   return check_launch("preadd_kernel");
 }
 
 template <class N>
-int launch_postadd(CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
-                   int alpha, int beta, const int* ea, const int* fb, hipStream_t stream) {
+int launch_postadd(CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t dst_rows,
+                   int64_t dst_cols, int64_t parents, int algo, int alpha, int beta,
+                   const int* ea, const int* fb, hipStream_t stream) {
   if (rows <= 0 || cols <= 0 || parents <= 0) return 0;
   if (parents > 65535) return set_error(4, "too many recursion parents");
   dim3 grid((unsigned)((rows * cols + 255) / 256), (unsigned)parents);
   prof_begin(stream);
-  hipLaunchKernelGGL(postadd_kernel<N>, grid, dim3(256), 0, stream, prod, dst, rows, cols, algo,
-                     alpha, beta, ea, fb);
+  hipLaunchKernelGGL(postadd_kernel<N>, grid, dim3(256), 0, stream, prod, dst, rows, cols,
+                     dst_rows, dst_cols, algo, alpha, beta, ea, fb);
   prof_record("postadd_kernel", stream);
   return check_launch("postadd_kernel");
 }
@@ -270,13 +283,13 @@ int launch_exponents(CMat A, CMat B, int64_t m, int64_t n, int64_t l, int* ea, i
   return check_launch("col_exponent_kernel");
 }
 
-template int launch_preadd<DDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, const int*,
-                                  hipStream_t);
-template int launch_postadd<DDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, int,
-                                   const int*, const int*, hipStream_t);
-template int launch_preadd<QDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, const int*,
-                                  hipStream_t);
-template int launch_postadd<QDNum>(CMat, Mat, int64_t, int64_t, int64_t, int, int, int,
-                                   const int*, const int*, hipStream_t);
+template int launch_preadd<DDNum>(CMat, Mat, int64_t, int64_t, int64_t, int64_t, int64_t, int,
+                                  int, const int*, hipStream_t);
+template int launch_postadd<DDNum>(CMat, Mat, int64_t, int64_t, int64_t, int64_t, int64_t, int,
+                                   int, int, const int*, const int*, hipStream_t);
+template int launch_preadd<QDNum>(CMat, Mat, int64_t, int64_t, int64_t, int64_t, int64_t, int,
+                                  int, const int*, hipStream_t);
+template int launch_postadd<QDNum>(CMat, Mat, int64_t, int64_t, int64_t, int64_t, int64_t, int,
+                                   int, int, const int*, const int*, hipStream_t);
 
 }  // namespace ddqd

@@ -44,11 +44,13 @@ int launch_dd_grouped(const GroupArgs& ga, int grid, hipStream_t stream);
 int launch_qd_block(const GemmBatch& g, hipStream_t stream);
 int launch_qd_simple(const GemmBatch& g, hipStream_t stream);
 template <class N>
-int launch_preadd(CMat src, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
-                  int side, const int* expo, hipStream_t stream);
+int launch_preadd(CMat src, Mat dst, int64_t rows, int64_t cols, int64_t src_rows,
+                  int64_t src_cols, int64_t parents, int algo, int side, const int* expo,
+                  hipStream_t stream);
 template <class N>
-int launch_postadd(CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
-                   int alpha, int beta, const int* ea, const int* fb, hipStream_t stream);
+int launch_postadd(CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t dst_rows,
+                   int64_t dst_cols, int64_t parents, int algo, int alpha, int beta,
+                   const int* ea, const int* fb, hipStream_t stream);
 int launch_exponents(CMat A, CMat B, int64_t m, int64_t n, int64_t l, int* ea, int* fb,
                      hipStream_t stream);
 size_t ozaki_workspace(int P, int64_t m, int64_t n, int64_t l, int64_t batch, int slices);
@@ -123,6 +125,10 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Plan {
   int P = 2, L = 0;
+  // the recursion's square-split core: each dimension rounded to a multiple
+  // of 2^L, down (the few leftover rows, columns or k peeled off as Block
+  // products) or up (padded with zeros), whichever is nearer
+  int64_t mc = 0, nc = 0, lc = 0;
   int64_t m[kMaxLevels + 1], n[kMaxLevels + 1], l[kMaxLevels + 1];
   size_t offA[kMaxLevels + 1], offB[kMaxLevels + 1], offM[kMaxLevels + 1];
   size_t off_exp = 0;  // int32 equilibration exponents: m for A's rows, n for B's columns
@@ -131,6 +137,19 @@ struct Plan {
 
 // Depth actually used: stop before any dimension of a level's parents drops
 // below 2 (such a parent is a Block product in the paper's scheme too).
+// Orders that 2^L does not divide (Sec. 3 uses n = 1023 and 1025) get a core
+// that it does: a remainder r of at most 2^(L-1) is peeled (the last r rows,
+// columns or k by Block products at the top level only), a larger one is
+// padded with zeros up to the next multiple (the top level's pre-adds read
+// the padding as zeros, its post-adds write only the caller's entries).
+// Either way every level halves exactly and the leaves keep their size.
+int64_t core_dim(int64_t d, int L) {
+  const int64_t q = (int64_t)1 << L, r = d % q;
+  if (r == 0) return d;
+  if (2 * r <= q && d - r >= q) return d - r;
+  return d + (q - r);
+}
+
 Plan make_plan(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
                int slices) {
   Plan pl;
@@ -140,11 +159,20 @@ Plan make_plan(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int
   pl.l[0] = l;
   int L = 0;
   if (algo == DDQD_STRASSEN || algo == DDQD_WINOGRAD) {
-    while (L < levels && pl.m[L] >= 2 && pl.n[L] >= 2 && pl.l[L] >= 2) {
-      pl.m[L + 1] = pl.m[L] / 2;
-      pl.n[L + 1] = pl.n[L] / 2;
-      pl.l[L + 1] = pl.l[L] / 2;
+    int64_t mm = m, nn = n, ll = l;
+    while (L < levels && mm >= 2 && nn >= 2 && ll >= 2) {
+      mm /= 2;
+      nn /= 2;
+      ll /= 2;
       L++;
+    }
+    pl.mc = core_dim(m, L);
+    pl.nc = core_dim(n, L);
+    pl.lc = core_dim(l, L);
+    for (int j = 1; j <= L; j++) {
+      pl.m[j] = pl.mc >> j;
+      pl.n[j] = pl.nc >> j;
+      pl.l[j] = pl.lc >> j;
     }
   }
   pl.L = L;
@@ -193,18 +221,24 @@ int block_fma(int P, const GemmBatch& g, hipStream_t s) {
   return P == 2 ? launch_dd_block(g, 64, s) : launch_qd_block(g, s);
 }
 
-int preadd(int P, CMat src, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
-           int side, const int* expo, hipStream_t s) {
-  return P == 2 ? launch_preadd<DDNum>(src, dst, rows, cols, parents, algo, side, expo, s)
-                : launch_preadd<QDNum>(src, dst, rows, cols, parents, algo, side, expo, s);
+int preadd(int P, CMat src, Mat dst, int64_t rows, int64_t cols, int64_t src_rows,
+           int64_t src_cols, int64_t parents, int algo, int side, const int* expo,
+           hipStream_t s) {
+  return P == 2 ? launch_preadd<DDNum>(src, dst, rows, cols, src_rows, src_cols, parents, algo,
+                                       side, expo, s)
+                : launch_preadd<QDNum>(src, dst, rows, cols, src_rows, src_cols, parents, algo,
+                                       side, expo, s);
 }
 
-int postadd(int P, CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t parents, int algo,
-            int alpha, int beta, const int* ea, const int* fb, hipStream_t s) {
-  return P == 2
-             ? launch_postadd<DDNum>(prod, dst, rows, cols, parents, algo, alpha, beta, ea, fb, s)
-             : launch_postadd<QDNum>(prod, dst, rows, cols, parents, algo, alpha, beta, ea, fb, s);
+int postadd(int P, CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t dst_rows,
+            int64_t dst_cols, int64_t parents, int algo, int alpha, int beta, const int* ea,
+            const int* fb, hipStream_t s) {
+  return P == 2 ? launch_postadd<DDNum>(prod, dst, rows, cols, dst_rows, dst_cols, parents,
+                                        algo, alpha, beta, ea, fb, s)
+                : launch_postadd<QDNum>(prod, dst, rows, cols, dst_rows, dst_cols, parents,
+                                        algo, alpha, beta, ea, fb, s);
 }
+
 
 CMat shift(CMat X, int64_t i, int64_t j) {
   X.p += i * X.ld + j;
@@ -236,38 +270,47 @@ int run_gemm(int P, const GemmBatch& top, int algo, int levels, int base, int sl
     Mat dstB{(double*)dB.p, dB.ld, dB.ps, dB.bstride};
     const int* xa = j == 1 ? ea : nullptr;
     const int* xb = j == 1 ? fb : nullptr;
-    if ((rc = preadd(P, srcA, dstA, pl.m[j], pl.l[j], pow7(j - 1), algo, 0, xa, s))) return rc;
-    if ((rc = preadd(P, srcB, dstB, pl.l[j], pl.n[j], pow7(j - 1), algo, 1, xb, s))) return rc;
+    // the top level reads the caller's matrices (padding reads as zeros,
+    // peeled rows / columns / k are not read)
+    const int64_t am = j == 1 ? std::min(top.m, pl.mc) : 2 * pl.m[j];
+    const int64_t al = j == 1 ? std::min(top.l, pl.lc) : 2 * pl.l[j];
+    const int64_t bl = al, bn = j == 1 ? std::min(top.n, pl.nc) : 2 * pl.n[j];
+    if ((rc = preadd(P, srcA, dstA, pl.m[j], pl.l[j], am, al, pow7(j - 1), algo, 0, xa, s)))
+      return rc;
+    if ((rc = preadd(P, srcB, dstB, pl.l[j], pl.n[j], bl, bn, pow7(j - 1), algo, 1, xb, s)))
+      return rc;
   }
   // all leaf products in one batched launch
   GemmBatch lf{pl.m[L], pl.n[L], pl.l[L], 1, 0, opA(pl, w, L), opB(pl, w, L), prodM(pl, w, L),
                pow7(L)};
   if ((rc = leaf(P, lf, base, slices, tile, w + pl.off_leaf, pl.leaf_bytes, s))) return rc;
-  // post-adds and peeling, level by level back up
+  // post-adds, level by level back up (the root writes only the caller's C)
+  const int64_t mr = std::min(top.m, pl.mc), nr = std::min(top.n, pl.nc);
   for (int j = L; j >= 1; j--) {
     const bool root = j == 1;
     Mat dst = root ? top.C : prodM(pl, w, j - 1);
-    CMat pa = root ? top.A : opA(pl, w, j - 1);
-    CMat pb = root ? top.B : opB(pl, w, j - 1);
     const int alpha = root ? top.alpha : 1, beta = root ? top.beta : 0;
-    const int64_t parents = pow7(j - 1);
-    if ((rc = postadd(P, cview(prodM(pl, w, j)), dst, pl.m[j], pl.n[j], parents, algo, alpha,
-                      beta, root ? ea : nullptr, root ? fb : nullptr, s)))
+    const int64_t dm = root ? mr : 2 * pl.m[j], dn = root ? nr : 2 * pl.n[j];
+    if ((rc = postadd(P, cview(prodM(pl, w, j)), dst, pl.m[j], pl.n[j], dm, dn, pow7(j - 1),
+                      algo, alpha, beta, root ? ea : nullptr, root ? fb : nullptr, s)))
       return rc;
-    const int64_t me = 2 * pl.m[j], ne = 2 * pl.n[j], le = 2 * pl.l[j];
-    const int64_t mp = pl.m[j - 1], np = pl.n[j - 1], lp = pl.l[j - 1];
-    if (lp != le) {  // rank-1: core += A[:, le] B[le, :]
-      GemmBatch g{me, ne, 1, alpha, 1, shift(pa, 0, le), shift(pb, le, 0), dst, parents};
-      if ((rc = block_fma(P, g, s))) return rc;
-    }
-    if (np != ne) {  // last column of C
-      GemmBatch g{me, 1, lp, alpha, beta, pa, shift(pb, 0, ne), shift(dst, 0, ne), parents};
-      if ((rc = block_fma(P, g, s))) return rc;
-    }
-    if (mp != me) {  // last row of C
-      GemmBatch g{1, np, lp, alpha, beta, shift(pa, me, 0), pb, shift(dst, me, 0), parents};
-      if ((rc = block_fma(P, g, s))) return rc;
-    }
+  }
+  // peeled parts: the core's missing k, then the last rows (all columns) and
+  // the last columns (the core's rows), each a Block product
+  if (pl.lc < top.l) {
+    GemmBatch g{mr, nr, top.l - pl.lc, top.alpha, 1, shift(top.A, 0, pl.lc),
+                shift(top.B, pl.lc, 0), top.C, 1};
+    if ((rc = block_fma(P, g, s))) return rc;
+  }
+  if (pl.mc < top.m) {
+    GemmBatch g{top.m - pl.mc, top.n, top.l, top.alpha, top.beta, shift(top.A, pl.mc, 0),
+                top.B, shift(top.C, pl.mc, 0), 1};
+    if ((rc = block_fma(P, g, s))) return rc;
+  }
+  if (pl.nc < top.n) {
+    GemmBatch g{mr, top.n - pl.nc, top.l, top.alpha, top.beta, top.A, shift(top.B, 0, pl.nc),
+                shift(top.C, 0, pl.nc), 1};
+    if ((rc = block_fma(P, g, s))) return rc;
   }
   return DDQD_OK;
 }
