@@ -14,9 +14,11 @@
 //   leaves     one batched launch computes all 7^L leaf products,
 //   post-adds  level L..1: one kernel combines 7 products into each parent,
 //              the top level applying C := beta*C + alpha*result,
-//   peeling    where a parent dimension is odd, the last column of A / row of
-//              B (rank-1 update of the even core), the last column of C and
-//              the last row of C are batched Block products on the parents.
+//   peeling    where an order is not a multiple of 2^L and is cut down, the
+//              few k beyond the core (a rank-r update of C), the last rows
+//              and the last columns of C are products of their own: Simple
+//              for the short K, the thin kernels (K spread over waves) for
+//              the few rows and columns.
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -36,6 +38,8 @@ namespace ddqd {
 int launch_dd_block(const GemmBatch& g, int tile, hipStream_t stream);
 int launch_dd_simple(const GemmBatch& g, hipStream_t stream);
 int64_t dd_block_tiles(int64_t m, int64_t n);
+bool thin_shape(const GemmBatch& g);
+int launch_thin(int P, const GemmBatch& g, hipStream_t stream);
 // autotuning (tune.hip)
 void auto_choice(int P, int64_t m, int64_t n, int64_t l, int base, int slices, int* algo,
                  int* levels, int* tile);
@@ -221,6 +225,16 @@ int block_fma(int P, const GemmBatch& g, hipStream_t s) {
   return P == 2 ? launch_dd_block(g, 64, s) : launch_qd_block(g, s);
 }
 
+// A part peeled off the recursion's core: Simple when K is a few columns
+// (a rank-r update of a large C, r multiply-adds per entry), the thin kernels
+// for a few rows or columns over a long K, Block otherwise.
+int peel_product(int P, const GemmBatch& g, hipStream_t s) {
+  if (g.l <= 16 && (g.m + 15) / 16 <= 65535)
+    return P == 2 ? launch_dd_simple(g, s) : launch_qd_simple(g, s);
+  if (thin_shape(g)) return launch_thin(P, g, s);
+  return block_fma(P, g, s);
+}
+
 int preadd(int P, CMat src, Mat dst, int64_t rows, int64_t cols, int64_t src_rows,
            int64_t src_cols, int64_t parents, int algo, int side, const int* expo,
            hipStream_t s) {
@@ -296,21 +310,21 @@ int run_gemm(int P, const GemmBatch& top, int algo, int levels, int base, int sl
       return rc;
   }
   // peeled parts: the core's missing k, then the last rows (all columns) and
-  // the last columns (the core's rows), each a Block product
+  // the last columns (the core's rows)
   if (pl.lc < top.l) {
     GemmBatch g{mr, nr, top.l - pl.lc, top.alpha, 1, shift(top.A, 0, pl.lc),
                 shift(top.B, pl.lc, 0), top.C, 1};
-    if ((rc = block_fma(P, g, s))) return rc;
+    if ((rc = peel_product(P, g, s))) return rc;
   }
   if (pl.mc < top.m) {
     GemmBatch g{top.m - pl.mc, top.n, top.l, top.alpha, top.beta, shift(top.A, pl.mc, 0),
                 top.B, shift(top.C, pl.mc, 0), 1};
-    if ((rc = block_fma(P, g, s))) return rc;
+    if ((rc = peel_product(P, g, s))) return rc;
   }
   if (pl.nc < top.n) {
     GemmBatch g{mr, top.n - pl.nc, top.l, top.alpha, top.beta, top.A, shift(top.B, 0, pl.nc),
                 shift(top.C, 0, pl.nc), 1};
-    if ((rc = block_fma(P, g, s))) return rc;
+    if ((rc = peel_product(P, g, s))) return rc;
   }
   return DDQD_OK;
 }

@@ -41,6 +41,24 @@ __device__ __forceinline__ void two_prod(double a, double b, double& p, double& 
   p = x;
 }
 
+// Lazy DD multiply-add into a running pair (s, e): the product's leading
+// part p = fl(a_h b_h) joins s by TwoSum; its tail err(a_h b_h) + a_h b_l +
+// a_l b_h (three FMAs; a_l b_l is below 2^-106 relative and dropped) and the
+// TwoSum error join e.  12 FP64 operations; callers renormalise (s, e) with
+// TwoSum every few steps so that e's own rounding stays near u^2 sum |a||b|.
+__device__ __forceinline__ void dd_mac(double& s, double& e, double ah, double al, double bh,
+                                       double bl) {
+  double p = ah * bh;
+  double q = __builtin_fma(ah, bh, -p);
+  q = __builtin_fma(ah, bl, q);
+  q = __builtin_fma(al, bh, q);
+  double t = s + p;
+  double z = t - s;
+  double err = (s - (t - z)) + (p - z);
+  s = t;
+  e = e + (err + q);
+}
+
 // accurate DD + DD, relative error about 3u^2
 __device__ __forceinline__ dd_t dd_add(dd_t x, dd_t y) {
   double sh, sl, th, tl, vh, vl;

@@ -29,19 +29,6 @@ namespace {
 constexpr int kBK = 16, kThreads = 256;
 constexpr int kPad = 2;  // keeps 16-byte rows, spreads banks
 
-__device__ __forceinline__ void dd_mac(double& s, double& e, double ah, double al, double bh,
-                                       double bl) {
-  double p = ah * bh;
-  double q = __builtin_fma(ah, bh, -p);
-  q = __builtin_fma(ah, bl, q);
-  q = __builtin_fma(al, bh, q);
-  double t = s + p;
-  double z = t - s;
-  double err = (s - (t - z)) + (p - z);
-  s = t;
-  e = e + (err + q);
-}
-
 template <int BM>
 using TileBuf = double[2][2][kBK][BM + kPad];
 

@@ -273,3 +273,34 @@ def test_recursion_with_zero_rows_and_columns(dd, P, algo, lv):
     den = np.maximum(rownorm_den(A, B), 1e-300)
     e = rownorm_error(A, B, C, ii, jj, den=den)
     assert e <= (2.0 ** -100 if P == 2 else 2.0 ** -200) * l, e
+
+
+@pytest.mark.parametrize("P", [2, 4])
+@pytest.mark.parametrize("shape,lv,ab", [((68, 67, 66), 3, (1, 0)), ((68, 67, 66), 3, (-1, 1)),
+                                         ((45, 600, 520), 4, (1, 1)),
+                                         ((1040, 1025, 1027), 5, (1, 0))])
+def test_peeled_rows_columns_and_k(dd, P, shape, lv, ab):
+    """Orders cut down to a multiple of 2^L: the last rows, the last columns
+    and the last k are products of their own (few rows or columns over a long
+    K: the thin kernels; a short K: Simple).  Every entry of the peeled rows
+    and columns, and a sample of the core, against the exact product."""
+    m, n, l = shape
+    alpha, beta = ab
+    g = inputs.rng(300 + m + P)
+    gen = inputs.dd_uniform if P == 2 else inputs.qd_uniform
+    A = gen(m, l, g)
+    B = gen(l, n, g)
+    C0 = gen(m, n, g) if beta else None
+    C = run(dd, P, A, B, C0=C0, alpha=alpha, beta=beta, algo="winograd", levels=lv)
+    q = 1 << lv
+    rr = m % q if 2 * (m % q) <= q else 0
+    rc = n % q if 2 * (n % q) <= q else 0
+    rows = np.arange(m - max(rr, 1), m)
+    cols = np.arange(n - max(rc, 1), n)
+    ri, rj = np.meshgrid(rows, np.arange(n), indexing="ij")
+    ci, cj = np.meshgrid(np.arange(0, m, max(1, m // 200)), cols, indexing="ij")
+    si, sj = sample_entries(m, n, 200)
+    ii = np.concatenate([ri.ravel(), ci.ravel(), si])
+    jj = np.concatenate([rj.ravel(), cj.ravel(), sj])
+    e = rownorm_error(A, B, C, ii, jj, alpha=alpha, C0=C0)
+    assert e <= (2.0 ** -100 if P == 2 else 2.0 ** -200) * l, e
