@@ -334,11 +334,14 @@ __device__ __forceinline__ int wave_argmax(const typename LuArith<P>::T& x, int 
   return __builtin_amdgcn_readlane(tag, 0);
 }
 
+typedef double f64x2 __attribute__((ext_vector_type(2)));  // one 16-byte access
+
 // ---- getf2: factor an m x w strip (w <= W) held in registers ---------------
 // One workgroup of T threads; thread t owns local rows t + T q, q < RPT.
 // The strip moves between HBM and registers through an LDS tile, so that
-// global accesses run along the rows (coalesced); all of a thread's loads of a
-// chunk are issued before the first is used.
+// global accesses run along the rows (coalesced); a full-width strip moves in
+// 16-byte chunks with all of a thread's loads in flight before the first is
+// used.
 // Column c, with one barrier:
 //   1. every wave finds its best candidate |a_ic| (rows i >= c; compared in
 //      the working precision, ties to the smaller row; see wave_argmax); it publishes the value, the
@@ -364,10 +367,11 @@ template <int P, int T, int RPT, int W>
 __global__ __launch_bounds__(T) void getf2_kernel(double* A, int64_t lda, int64_t ps,
                                                    int64_t r0, int64_t m, int64_t c0, int w,
                                                    int32_t* ipiv, int32_t* info, int pivot) {
-  constexpr int kLd = W + 1;  // padded LDS row of the staging tile
+  constexpr int kLd = W + 2;  // padded LDS row of the staging tile (16-byte rows)
+  constexpr int kH = W >= 2 ? W / 2 : 1;  // 16-byte chunks in a full strip row
   constexpr int kWaves = T / 64;
   static_assert(kWaves == 4 || kWaves == 8 || kWaves == 16, "T must be 256, 512 or 1024");
-  __shared__ double tile[T * kLd];
+  __shared__ __align__(16) double tile[T * kLd];
   using N = LuArith<P>;
   using V = typename N::T;
   __shared__ double s_val[2][kWaves][P];
@@ -376,35 +380,78 @@ __global__ __launch_bounds__(T) void getf2_kernel(double* A, int64_t lda, int64_
   __shared__ double s_rowc[2][P][W];
   const int t = threadIdx.x, lane = t % 64, wave = t / 64;
   V v[RPT][W];
+  // Full-width strips whose rows start on 16 bytes move in 16-byte chunks,
+  // with the loads of every row block and plane in flight at once; other
+  // strips (the last, narrower one of a panel; odd offsets) by 8-byte words,
+  // one row block at a time.
+  const bool vec = W % 2 == 0 && w == W && ((lda | ps | c0) & 1) == 0 &&
+                   ((uintptr_t)A & 15) == 0;
+  if (vec) {
+    f64x2 xs[RPT][P][kH];
 #pragma unroll
-  for (int q = 0; q < RPT; q++) {
-    const int64_t rows = min((int64_t)T, m - (int64_t)T * q);
-    if (rows <= 0) {
+    for (int q = 0; q < RPT; q++) {
 #pragma unroll
-      for (int k = 0; k < W; k++) v[q][k] = N::zero();
-      continue;
-    }
-    const int n = (int)rows * w;
-    const double* src = A + (r0 + (int64_t)T * q) * lda + c0;
-    double xs[P][W];
+      for (int j = 0; j < kH; j++) {
+        // rows past the strip re-read its last row (the values are not used)
+        const int e = t + T * j, k2 = e % kH;
+        const int64_t row = min((int64_t)T * q + e / kH, m - 1);
+        const double* src = A + (r0 + row) * lda + c0 + 2 * k2;
 #pragma unroll
-    for (int j = 0; j < W; j++) {  // every load in flight before the first use
-      const int e = min(t + T * j, n - 1), r = e / w, k = e - r * w;
-#pragma unroll
-      for (int c = 0; c < P; c++) xs[c][j] = src[c * ps + (int64_t)r * lda + k];
-    }
-#pragma unroll
-    for (int plane = 0; plane < P; plane++) {
-#pragma unroll
-      for (int j = 0; j < W; j++) {
-        const int e = t + T * j, r = e / w, k = e - r * w;
-        if (e < n) tile[r * kLd + k] = xs[plane][j];
+        for (int c = 0; c < P; c++) xs[q][c][j] = *(const f64x2*)(src + c * ps);
       }
-      __syncthreads();
+    }
 #pragma unroll
-      for (int k = 0; k < W; k++)
-        N::put(v[q][k], plane, (t < rows && k < w) ? tile[t * kLd + k] : 0.0);
-      __syncthreads();
+    for (int q = 0; q < RPT; q++) {
+      const int64_t rows = min((int64_t)T, m - (int64_t)T * q);
+      if (rows <= 0) {
+#pragma unroll
+        for (int k = 0; k < W; k++) v[q][k] = N::zero();
+        continue;
+      }
+#pragma unroll
+      for (int plane = 0; plane < P; plane++) {
+#pragma unroll
+        for (int j = 0; j < kH; j++) {
+          const int e = t + T * j, r = e / kH, k2 = e % kH;
+          if (r < rows) *(f64x2*)&tile[r * kLd + 2 * k2] = xs[q][plane][j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < W; k++) N::put(v[q][k], plane, t < rows ? tile[t * kLd + k] : 0.0);
+        __syncthreads();
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < RPT; q++) {
+      const int64_t rows = min((int64_t)T, m - (int64_t)T * q);
+      if (rows <= 0) {
+#pragma unroll
+        for (int k = 0; k < W; k++) v[q][k] = N::zero();
+        continue;
+      }
+      const int n = (int)rows * w;
+      const double* src = A + (r0 + (int64_t)T * q) * lda + c0;
+      double xs[P][W];
+#pragma unroll
+      for (int j = 0; j < W; j++) {  // every load in flight before the first use
+        const int e = min(t + T * j, n - 1), r = e / w, k = e - r * w;
+#pragma unroll
+        for (int c = 0; c < P; c++) xs[c][j] = src[c * ps + (int64_t)r * lda + k];
+      }
+#pragma unroll
+      for (int plane = 0; plane < P; plane++) {
+#pragma unroll
+        for (int j = 0; j < W; j++) {
+          const int e = t + T * j, r = e / w, k = e - r * w;
+          if (e < n) tile[r * kLd + k] = xs[plane][j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < W; k++)
+          N::put(v[q][k], plane, (t < rows && k < w) ? tile[t * kLd + k] : 0.0);
+        __syncthreads();
+      }
     }
   }
   // The column loop is unrolled so that every register index is a constant.
@@ -530,10 +577,20 @@ __global__ __launch_bounds__(T) void getf2_kernel(double* A, int64_t lda, int64_
 #pragma unroll
         for (int k = 0; k < W; k++) tile[t * kLd + k] = N::get(v[q][k], plane);
       __syncthreads();
+      if (vec) {
 #pragma unroll
-      for (int j = 0; j < W; j++) {
-        const int e = t + T * j, r = e / w, k = e - r * w;
-        if (e < n) dst[plane * ps + (int64_t)r * lda + k] = tile[r * kLd + k];
+        for (int j = 0; j < kH; j++) {
+          const int e = t + T * j, r = e / kH, k2 = e % kH;
+          if (r < rows)
+            *(f64x2*)(dst + plane * ps + (int64_t)r * lda + 2 * k2) =
+                *(const f64x2*)&tile[r * kLd + 2 * k2];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < W; j++) {
+          const int e = t + T * j, r = e / w, k = e - r * w;
+          if (e < n) dst[plane * ps + (int64_t)r * lda + k] = tile[r * kLd + k];
+        }
       }
     }
   }
@@ -587,8 +644,20 @@ __global__ __launch_bounds__(256) void lu_update_kernel(const double* A, const d
   if (e >= m * n) return;
   const int64_t i = e / n, j = e - i * n;
   typename N::Acc acc = N::acc(ld_num<P>(C, ps, i * ld + j));
-  for (int64_t k = 0; k < l; k++)
-    N::acc_sub(acc, ld_num<P>(A, ps, i * ld + k), ld_num<P>(B, ps, k * ld + j));
+  int64_t k = 0;
+  // U k at a time with every load in flight before the first product
+  constexpr int U = P == 2 ? 8 : 4;
+  for (; k + U <= l; k += U) {
+    typename N::T a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      a[u] = ld_num<P>(A, ps, i * ld + k + u);
+      b[u] = ld_num<P>(B, ps, (k + u) * ld + j);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) N::acc_sub(acc, a[u], b[u]);
+  }
+  for (; k < l; k++) N::acc_sub(acc, ld_num<P>(A, ps, i * ld + k), ld_num<P>(B, ps, k * ld + j));
   st_num<P>(C, ps, i * ld + j, N::value(acc));
 }
 
@@ -618,15 +687,38 @@ __global__ __launch_bounds__(1024) void trsm_wave_kernel(double* A, int64_t lda,
   const int cpb = nt / 64;  // columns per workgroup
   const int64_t j0 = (int64_t)blockIdx.x * cpb;
   const int nc = (int)min((int64_t)cpb, ncols - j0);
-  for (int e = t; e < nb * nb; e += nt) {
-    const int i = e / nb, k = e - i * nb;
+  // L and X tiles, eight elements per thread in flight at a time
+  for (int e0 = t; e0 < nb * nb; e0 += 8 * nt) {
+    double x[8][P];
 #pragma unroll
-    for (int c = 0; c < P; c++) Ls[c][k][i] = A[c * ps + (r0 + i) * lda + c0 + k];
+    for (int u = 0; u < 8; u++) {
+      const int e = min(e0 + u * nt, nb * nb - 1), i = e / nb, k = e - i * nb;
+#pragma unroll
+      for (int c = 0; c < P; c++) x[u][c] = A[c * ps + (r0 + i) * lda + c0 + k];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int e = e0 + u * nt, i = e / nb, k = e - i * nb;
+      if (e < nb * nb)
+#pragma unroll
+        for (int c = 0; c < P; c++) Ls[c][k][i] = x[u][c];
+    }
   }
-  for (int e = t; e < nb * nc; e += nt) {
-    const int i = e / nc, cc = e - i * nc;
+  for (int e0 = t; e0 < nb * nc; e0 += 8 * nt) {
+    double x[8][P];
 #pragma unroll
-    for (int c = 0; c < P; c++) Xs[c][i][cc] = A[c * ps + (r0 + i) * lda + x0 + j0 + cc];
+    for (int u = 0; u < 8; u++) {
+      const int e = min(e0 + u * nt, nb * nc - 1), i = e / nc, cc = e - i * nc;
+#pragma unroll
+      for (int c = 0; c < P; c++) x[u][c] = A[c * ps + (r0 + i) * lda + x0 + j0 + cc];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int e = e0 + u * nt, i = e / nc, cc = e - i * nc;
+      if (e < nb * nc)
+#pragma unroll
+        for (int c = 0; c < P; c++) Xs[c][i][cc] = x[u][c];
+    }
   }
   __syncthreads();
   if (wave < nc) {
