@@ -495,7 +495,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only (sharding across GPUs is a design, not implemented); --gpus must be 1"}))
         sys.exit(2)
 
     import torch

@@ -48,7 +48,7 @@ extern "C" {
 #define DDQD_E_ARG 1         /* an argument is out of range */
 #define DDQD_E_ALIAS 2       /* an output overlaps an input */
 #define DDQD_E_WORKSPACE 3   /* workspace missing or too small */
-#define DDQD_E_UNSUPPORTED 4 /* a valid combination this build does not do */
+#define DDQD_E_UNSUPPORTED 4 /* a valid combination the library does not implement */
 #define DDQD_E_NODEVICE 5    /* no usable GPU */
 #define DDQD_E_HIP 6         /* a HIP call or launch failed */
 

@@ -2,6 +2,8 @@
 // of A's rows and B's columns, and the slicing of every scaled entry into S
 // signed 7-bit digits stored as INT8 in MFMA fragment order.  The products
 // themselves are in ozaki.hip (DD) and ozaki_qd.hip (QD).
+#include <algorithm>
+
 #include "ddqd.h"
 #include "common.hpp"
 #include "eft.hpp"
@@ -108,25 +110,75 @@ __device__ __forceinline__ void col_exponents(const OzLayout& o, const int* part
   __syncthreads();
 }
 
-// A workgroup takes 32 lines (rows of A or columns of B) by 64 k (two 32-k
-// blocks): the P planes are read with coalesced loads into LDS (along k for
-// A, along the columns for B); wave w then slices k block w / 2, half w % 2
-// of every lane's 16-k fragment slot (8 values of one line per lane, 8 bytes
-// per digit).  Both operands in one launch (blockIdx.y: 0 = A, 1 = B).
+// The work is cut into chunks of 32 lines (rows of A or columns of B) by 64 k
+// (two 32-k blocks), A's chunks first, then B's; workgroup g takes chunks g,
+// g + G, g + 2G, ... (G workgroups per batch entry).  A chunk's P planes are
+// read with coalesced loads into registers (along k for A, along the columns
+// for B) while the workgroup still slices the previous chunk, then pass
+// through LDS; wave w slices k block w / 2, half w % 2 of every lane's 16-k
+// fragment slot (8 values of one line per lane, 8 bytes per digit).
 //
 // Digits of a scaled value r (|r| < 1/2) held as an expansion r0 + r1 (+ r2
-// + r3): runs of kRun digits d = rint(2^7 r0), r0 := 2^7 r0 - d are taken
-// from the leading term alone (each step exact; the lower terms stand for
-// themselves times 2^(7j) after j steps), then the lower terms are scaled by
-// 2^(7 kRun) and merged: DD by FastTwoSum(r0, r1) (r0 is 0 or a multiple of
-// 2^(7j) ulp(r0 at the run's start) >= 2 |r1|, its precondition), QD by one
-// bottom-up TwoSum pass, which leaves the rest within about an ulp of the
-// leading term.  Inside a run the part a digit ignores is below
-// 2^(7 kRun - 54) <= 2^-12 of a digit unit, so digits stay in [-64, 64] and
-// the remainder after S digits stays below (1/2 + 2^-12) 2^-7S.
-constexpr int kSliceK = 64;   // k per slicing workgroup (two 32-k blocks)
+// + r3): runs of kRun digits are taken from the leading term alone, then the
+// lower terms are scaled by 2^(7 kRun) and merged: DD by FastTwoSum(r0, r1)
+// (r0 is 0 or a multiple of 2^(7 kRun) ulp(r0 at the run's start) >= 2 |r1|,
+// its precondition), QD by one bottom-up TwoSum pass, which leaves the rest
+// within about an ulp of the leading term.  Inside a run the part a digit
+// ignores is below 2^(7 kRun - 54) <= 2^-12 of a digit unit, so digits stay in
+// [-64, 64] and the remainder after S digits stays below (1/2 + 2^-12) 2^-7S.
+//
+// Within a run, N_j = rint(2^(7j) r0) is read from t_j = r0 + 1.5 2^(52-7j):
+// that sum lies in a binade whose ulp is 2^(-7j), so it is r0 rounded to a
+// multiple of 2^(-7j) (nearest, ties to even), and the low 32 bits of its
+// encoding are N_j modulo 2^32.  Digit j is N_j - 2^7 N_(j-1) (N_0 = 0), the
+// same digit as rint(2^7 x) of the remainder x left by digits 1..j-1 (shifting
+// by the even integer 2^7 N_(j-1) keeps ties to even), and |digit| <= 64.
+// After kRun digits the remainder 2^(7 kRun) (r0 - (t_kRun - 1.5 2^(52 - 7 kRun)))
+// is exact (Sterbenz for the subtraction, a power of two for the scaling).
+constexpr int kSliceK = 64;   // k per chunk (two 32-k blocks)
 constexpr int kRun = 6;       // digits per run from the leading term alone
 static_assert(kRun == 6, "the merge scales by 2^42 = 2^(7 kRun)");
+constexpr int kSliceWgs = 512;  // workgroups of one slicing launch (two per CU)
+// 1.5 2^(52 - 7j), j = 1..kRun: r0 + kMagic[j - 1] rounds r0 to a multiple of 2^(-7j)
+constexpr double kMagic[kRun] = {0x1.8p45, 0x1.8p38, 0x1.8p31, 0x1.8p24, 0x1.8p17, 0x1.8p10};
+
+struct SliceChunk {
+  int side;            // 0: rows of A, 1: columns of B
+  int64_t blk, kg;     // 32-line block, 64-k group
+};
+
+__device__ __forceinline__ SliceChunk slice_chunk(const OzLayout& o, int64_t ch, int64_t kgroups) {
+  const int64_t na = o.rb * kgroups;
+  SliceChunk c;
+  c.side = ch < na ? 0 : 1;
+  const int64_t x = c.side == 0 ? ch : ch - na;
+  c.blk = x / kgroups;
+  c.kg = x % kgroups;
+  return c;
+}
+
+// Issues the loads of one chunk's 32 x 64 values, every load in flight before
+// the first use; values outside the matrix read as zero.
+template <int P>
+__device__ __forceinline__ void slice_load(const CMat& A, const CMat& B, int64_t m, int64_t n,
+                                           int64_t l, int64_t b, const SliceChunk& c,
+                                           double (&v)[P][8]) {
+  const CMat X = c.side == 0 ? A : B;
+  const int64_t lines_live = c.side == 0 ? m : n;
+  const double* base = X.p + b * X.bstride;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    const int e = t + 256 * j;
+    const int ln = c.side == 0 ? e / kSliceK : e % 32;
+    const int kk = c.side == 0 ? e % kSliceK : e / 32;
+    const int64_t line = c.blk * 32 + ln, k = c.kg * kSliceK + kk;
+    const bool in = line < lines_live && k < l;
+    const int64_t idx = in ? (c.side == 0 ? line * X.ld + k : k * X.ld + line) : 0;
+#pragma unroll
+    for (int q = 0; q < P; q++) v[q][j] = in ? base[q * X.ps + idx] : 0.0;
+  }
+}
 
 template <int P, int S>
 __global__ __launch_bounds__(256) void oz_slice_kernel(CMat A, CMat B, int64_t m, int64_t n,
@@ -135,99 +187,103 @@ __global__ __launch_bounds__(256) void oz_slice_kernel(CMat A, CMat B, int64_t m
                                                        signed char* Asl, signed char* Bsl) {
   __shared__ double tile[P][32][kSliceK + 1];
   __shared__ int xc[8 * 32];
-  const int side = blockIdx.y;
   const int64_t b = blockIdx.z;
-  const int64_t nblk32 = side == 0 ? o.rb : o.cb;
   const int64_t kgroups = (o.kb + 1) / 2;
-  if ((int64_t)blockIdx.x >= nblk32 * kgroups) return;  // uniform per workgroup
-  const int64_t blk = blockIdx.x / kgroups, kg = blockIdx.x % kgroups;
-  const int64_t line0 = blk * 32, kbase = kg * kSliceK;
-  const CMat X = side == 0 ? A : B;
-  const int64_t lines_live = side == 0 ? m : n;
-  const double* base = X.p + b * X.bstride;
-  const int t = threadIdx.x;
+  const int64_t nchunks = (o.rb + o.cb) * kgroups;
+  const int t = threadIdx.x, w = t / 64, lane = t % 64;
+  int64_t ch = blockIdx.x;
+  if (ch >= nchunks) return;  // uniform per workgroup
   double v[P][8];
+  SliceChunk c = slice_chunk(o, ch, kgroups);
+  slice_load<P>(A, B, m, n, l, b, c, v);
+  for (; ch < nchunks; ch += gridDim.x) {
+    __syncthreads();  // the previous chunk's readers of tile and xc are done
 #pragma unroll
-  for (int j = 0; j < 8; j++) {  // every load in flight before the first use
-    const int e = t + 256 * j;
-    const int ln = side == 0 ? e / kSliceK : e % 32;
-    const int kk = side == 0 ? e % kSliceK : e / 32;
-    const int64_t line = line0 + ln, k = kbase + kk;
-    const bool in = line < lines_live && k < l;
-    const int64_t idx = in ? (side == 0 ? line * X.ld + k : k * X.ld + line) : 0;
+    for (int j = 0; j < 8; j++) {
+      const int e = t + 256 * j;
+      const int ln = c.side == 0 ? e / kSliceK : e % 32;
+      const int kk = c.side == 0 ? e % kSliceK : e / 32;
 #pragma unroll
-    for (int c = 0; c < P; c++) v[c][j] = in ? base[c * X.ps + idx] : 0.0;
-  }
-#pragma unroll
-  for (int j = 0; j < 8; j++) {
-    const int e = t + 256 * j;
-    const int ln = side == 0 ? e / kSliceK : e % 32;
-    const int kk = side == 0 ? e % kSliceK : e / 32;
-#pragma unroll
-    for (int c = 0; c < P; c++) tile[c][ln][kk] = v[c][j];
-  }
-  __syncthreads();
-  if (side == 1) col_exponents(o, part, fb, b, line0, kg == 0, xc);  // uniform per workgroup
-  const int w = t / 64, lane = t % 64;
-  const int64_t kb = kg * 2 + w / 2;
-  if (kb >= o.kb) return;
-  const int half = w % 2;
-  const int ln = lane % 32, k0 = (w / 2) * 32 + 16 * (lane / 32) + 8 * half;
-  const int ex = side == 0 ? ea[b * (nblk32 * 32) + line0 + ln] : xc[ln];
-  double r[P][8];
-#pragma unroll
-  for (int q = 0; q < 8; q++)
-#pragma unroll
-    for (int c = 0; c < P; c++) r[c][q] = ldexp(tile[c][ln][k0 + q], -ex);
-  // an input whose terms overlap is brought into shape first (exact)
-#pragma unroll
-  for (int q = 0; q < 8; q++) {
-    if constexpr (P == 2) {
-      two_sum(r[0][q], r[1][q], r[0][q], r[1][q]);
-    } else {
-      double a2, a3, a1, b2, a0, b1;
-      two_sum(r[2][q], r[3][q], a2, a3);
-      two_sum(r[1][q], a2, a1, b2);
-      two_sum(r[0][q], a1, a0, b1);
-      r[0][q] = a0;
-      r[1][q] = b1;
-      r[2][q] = b2;
-      r[3][q] = a3;
+      for (int q = 0; q < P; q++) tile[q][ln][kk] = v[q][j];
     }
-  }
-  signed char* dst = (side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
-                     (blk * o.kb + kb) * S * (int64_t)kOzFrag + lane * 16 + 8 * half;
-#pragma unroll 1
-  for (int s0 = 0; s0 < S; s0 += kRun) {
-#pragma unroll
-    for (int j = 0; j < kRun; j++) {
-      if (s0 + j < S) {
-        uint32_t x[2] = {0u, 0u};
-#pragma unroll
-        for (int q = 0; q < 8; q++) {
-          const double h = r[0][q] * 128.0;
-          const double d = rint(h);
-          x[q / 4] |= (uint32_t)(uint8_t)(signed char)(int)d << (8 * (q % 4));
-          r[0][q] = h - d;
-        }
-        *reinterpret_cast<uint2*>(dst + (s0 + j) * (int64_t)kOzFrag) = uint2{x[0], x[1]};
-      }
+    __syncthreads();
+    const SliceChunk cur = c;
+    if (ch + gridDim.x < nchunks) {  // the next chunk's loads fly during the slicing
+      c = slice_chunk(o, ch + gridDim.x, kgroups);
+      slice_load<P>(A, B, m, n, l, b, c, v);
     }
+    const int64_t line0 = cur.blk * 32;
+    // uniform per workgroup
+    if (cur.side == 1) col_exponents(o, part, fb, b, line0, cur.kg == 0, xc);
+    const int64_t kb = cur.kg * 2 + w / 2;
+    if (kb >= o.kb) continue;  // past the last K block (no barrier follows in this pass)
+    const int half = w % 2;
+    const int ln = lane % 32, k0 = (w / 2) * 32 + 16 * (lane / 32) + 8 * half;
+    const int ex = cur.side == 0 ? ea[b * (o.rb * 32) + line0 + ln] : xc[ln];
+    double r[P][8];
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+#pragma unroll
+      for (int p = 0; p < P; p++) r[p][q] = ldexp(tile[p][ln][k0 + q], -ex);
+    // an input whose terms overlap is brought into shape first (exact)
 #pragma unroll
     for (int q = 0; q < 8; q++) {
       if constexpr (P == 2) {
-        fast_two_sum(r[0][q], r[1][q] * 0x1p42, r[0][q], r[1][q]);
+        two_sum(r[0][q], r[1][q], r[0][q], r[1][q]);
       } else {
-        // remainder r0 + 2^42 (r1 + r2 + r3), all terms exact; one bottom-up
-        // TwoSum pass keeps the sum and brings it to the front
         double a2, a3, a1, b2, a0, b1;
-        two_sum(r[2][q] * 0x1p42, r[3][q] * 0x1p42, a2, a3);
-        two_sum(r[1][q] * 0x1p42, a2, a1, b2);
+        two_sum(r[2][q], r[3][q], a2, a3);
+        two_sum(r[1][q], a2, a1, b2);
         two_sum(r[0][q], a1, a0, b1);
         r[0][q] = a0;
         r[1][q] = b1;
         r[2][q] = b2;
         r[3][q] = a3;
+      }
+    }
+    signed char* dst = (cur.side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
+                       (cur.blk * o.kb + kb) * S * (int64_t)kOzFrag + lane * 16 + 8 * half;
+#pragma unroll 1
+    for (int s0 = 0; s0 < S; s0 += kRun) {
+      uint32_t prev[8];
+      double tl[8];  // t_j of the run's last digit
+#pragma unroll
+      for (int q = 0; q < 8; q++) prev[q] = 0u;
+#pragma unroll
+      for (int j = 0; j < kRun; j++) {
+        if (s0 + j < S) {
+          const double magic = kMagic[j];
+          uint32_t x[2] = {0u, 0u};
+#pragma unroll
+          for (int q = 0; q < 8; q++) {
+            const double tq = r[0][q] + magic;
+            const uint32_t nj = (uint32_t)__builtin_bit_cast(uint64_t, tq);
+            const uint32_t d = nj - (prev[q] << 7);
+            prev[q] = nj;
+            tl[q] = tq;
+            x[q / 4] |= (d & 0xffu) << (8 * (q % 4));
+          }
+          *reinterpret_cast<uint2*>(dst + (s0 + j) * (int64_t)kOzFrag) = uint2{x[0], x[1]};
+        }
+      }
+      if (s0 + kRun >= S) break;  // no digits left: the remainder is not needed
+#pragma unroll
+      for (int q = 0; q < 8; q++) {
+        const double rem = (r[0][q] - (tl[q] - kMagic[kRun - 1])) * 0x1p42;
+        if constexpr (P == 2) {
+          fast_two_sum(rem, r[1][q] * 0x1p42, r[0][q], r[1][q]);
+        } else {
+          // remainder rem + 2^42 (r1 + r2 + r3), all terms exact; one bottom-up
+          // TwoSum pass keeps the sum and brings it to the front
+          double a2, a3, a1, b2, a0, b1;
+          two_sum(r[2][q] * 0x1p42, r[3][q] * 0x1p42, a2, a3);
+          two_sum(r[1][q] * 0x1p42, a2, a1, b2);
+          two_sum(rem, a1, a0, b1);
+          r[0][q] = a0;
+          r[1][q] = b1;
+          r[2][q] = b2;
+          r[3][q] = a3;
+        }
       }
     }
   }
@@ -249,12 +305,18 @@ int launch_oz_exponents(const GemmBatch& g, const OzLayout& o, const OzWs& w, hi
 
 namespace {
 
+// Workgroups per batch entry: kSliceWgs over the batch, at most one per chunk.
+inline int64_t slice_grid(const GemmBatch& g, const OzLayout& o) {
+  const int64_t nchunks = (o.rb + o.cb) * ((o.kb + 1) / 2);
+  const int64_t per = std::max<int64_t>(1, kSliceWgs / std::max<int64_t>(1, g.batch));
+  return std::min(nchunks, per);
+}
+
 template <int S>
 int slice_dd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s) {
-  const int64_t sblocks = (o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 1) / 2);
-  if (sblocks > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "matrix too large");
+  const int64_t grid = slice_grid(g, o);
   prof_begin(s);
-  hipLaunchKernelGGL((oz_slice_kernel<2, S>), dim3((unsigned)sblocks, 2, (unsigned)g.batch),
+  hipLaunchKernelGGL((oz_slice_kernel<2, S>), dim3((unsigned)grid, 1, (unsigned)g.batch),
                      dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)w.ea,
                      (const int*)w.part, w.fb, w.Asl, w.Bsl);
   prof_record("oz_slice_kernel", s);
@@ -263,10 +325,9 @@ int slice_dd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s
 
 template <int S>
 int slice_qd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s) {
-  const int64_t sblocks = (o.rb > o.cb ? o.rb : o.cb) * ((o.kb + 1) / 2);
-  if (sblocks > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "matrix too large");
+  const int64_t grid = slice_grid(g, o);
   prof_begin(s);
-  hipLaunchKernelGGL((oz_slice_kernel<4, S>), dim3((unsigned)sblocks, 2, (unsigned)g.batch),
+  hipLaunchKernelGGL((oz_slice_kernel<4, S>), dim3((unsigned)grid, 1, (unsigned)g.batch),
                      dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)w.ea,
                      (const int*)w.part, w.fb, w.Asl, w.Bsl);
   prof_record("oz_slice_kernel", s);
