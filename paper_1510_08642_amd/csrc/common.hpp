@@ -37,6 +37,15 @@ struct GroupArgs {
   int64_t start[kMaxGroup + 1];
 };
 
+// Steps of a factored panel whose triangular solve X := L^-1 X is still to be
+// stored (kernel argument): L at (r0[q], r0[q]), nb[q] rows; X = those rows of
+// columns [x0[q], x0[q] + nc[q]).
+constexpr int kTrsmNodesMax = 64;
+struct TrsmNodes {
+  int count;
+  int r0[kTrsmNodesMax], nb[kTrsmNodesMax], x0[kTrsmNodesMax], nc[kTrsmNodesMax];
+};
+
 // Round-robin dispatch places workgroup b on XCD b % 8.  This permutation
 // gives each XCD one contiguous range of logical tiles, so tiles that share
 // operand panels share an L2.

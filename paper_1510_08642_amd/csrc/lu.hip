@@ -675,18 +675,15 @@ constexpr int trsm_rows() {
   return P == 2 ? 64 : 32;
 }
 
+// Stages L and the X tile of columns [x0 + j0, x0 + j0 + nc) in LDS and solves
+// (waves < nc, one column each); Xs then holds X = L^-1 X.
 template <int P>
-__global__ __launch_bounds__(1024) void trsm_wave_kernel(double* A, int64_t lda, int64_t ps,
-                                                         int64_t r0, int64_t c0, int nb,
-                                                         int64_t x0, int64_t ncols) {
+__device__ __forceinline__ void trsm_tile(const double* A, int64_t lda, int64_t ps, int64_t r0,
+                                          int64_t c0, int nb, int64_t x0, int64_t j0, int nc,
+                                          double (&Ls)[P][trsm_rows<P>()][trsm_rows<P>() + 1],
+                                          double (&Xs)[P][trsm_rows<P>()][kTrsmCols + 1]) {
   using N = LuArith<P>;
-  constexpr int R = trsm_rows<P>();
-  __shared__ double Ls[P][R][R + 1];
-  __shared__ double Xs[P][R][kTrsmCols + 1];
   const int t = threadIdx.x, lane = t % 64, wave = t / 64, nt = blockDim.x;
-  const int cpb = nt / 64;  // columns per workgroup
-  const int64_t j0 = (int64_t)blockIdx.x * cpb;
-  const int nc = (int)min((int64_t)cpb, ncols - j0);
   // L and X tiles, eight elements per thread in flight at a time
   for (int e0 = t; e0 < nb * nb; e0 += 8 * nt) {
     double x[8][P];
@@ -743,11 +740,107 @@ __global__ __launch_bounds__(1024) void trsm_wave_kernel(double* A, int64_t lda,
     }
   }
   __syncthreads();
-  for (int e = t; e < nb * nc; e += nt) {
+}
+
+template <int P>
+__device__ __forceinline__ void store_x_tile(double* A, int64_t lda, int64_t ps, int64_t r0,
+                                             int nb, int64_t x0, int64_t j0, int nc,
+                                             const double (&Xs)[P][trsm_rows<P>()]
+                                                                [kTrsmCols + 1]) {
+  for (int e = threadIdx.x; e < nb * nc; e += blockDim.x) {
     const int i = e / nc, cc = e - i * nc;
 #pragma unroll
     for (int c = 0; c < P; c++) A[c * ps + (r0 + i) * lda + x0 + j0 + cc] = Xs[c][i][cc];
   }
+}
+
+template <int P>
+__global__ __launch_bounds__(1024) void trsm_wave_kernel(double* A, int64_t lda, int64_t ps,
+                                                         int64_t r0, int64_t c0, int nb,
+                                                         int64_t x0, int64_t ncols) {
+  constexpr int R = trsm_rows<P>();
+  __shared__ double Ls[P][R][R + 1];
+  __shared__ double Xs[P][R][kTrsmCols + 1];
+  const int cpb = blockDim.x / 64;  // columns per workgroup
+  const int64_t j0 = (int64_t)blockIdx.x * cpb;
+  const int nc = (int)min((int64_t)cpb, ncols - j0);
+  trsm_tile<P>(A, lda, ps, r0, c0, nb, x0, j0, nc, Ls, Xs);
+  store_x_tile<P>(A, lda, ps, r0, nb, x0, j0, nc, Xs);
+}
+
+// ---- the solve and the thin product of one panel step in one launch --------
+// X := L^-1 X as trsm_wave_kernel (L at (r0, r0), nb <= R rows, columns
+// [x0, x0 + ncols)), then rows [r0 + nb, r0 + nb + mb) of the same columns
+// -= A[those rows, r0 .. r0 + nb) X, each entry accumulated from its value
+// down with k ascending, as lu_update_kernel does (the same values as the
+// two launches, bit for bit).  Workgroup (g, h) takes column group g and the
+// kTrsmUpdRows rows of block h; every row block solves its group's X itself in
+// LDS from the unsolved values in A (the solve is small and saves a launch and
+// the trip of X through memory).  X is not stored here: a row block could
+// still be reading the unsolved values.  Inside a panel nothing else reads
+// those rows of those columns (later interchanges only move rows below them),
+// so trsm_nodes_kernel solves and stores the X of all such steps of a panel
+// once the panel is factored.
+constexpr int kTrsmUpdRows = 64;
+
+template <int P>
+__global__ __launch_bounds__(1024) void trsm_update_kernel(double* A, int64_t lda, int64_t ps,
+                                                           int64_t r0, int nb, int64_t x0,
+                                                           int64_t ncols, int64_t mb) {
+  using N = LuArith<P>;
+  constexpr int R = trsm_rows<P>();
+  __shared__ double Ls[P][R][R + 1];
+  __shared__ double Xs[P][R][kTrsmCols + 1];
+  const int cpb = blockDim.x / 64;
+  const int64_t j0 = (int64_t)blockIdx.x * cpb;
+  const int nc = (int)min((int64_t)cpb, ncols - j0);
+  trsm_tile<P>(A, lda, ps, r0, r0, nb, x0, j0, nc, Ls, Xs);
+  const int64_t i0 = r0 + nb + (int64_t)blockIdx.y * kTrsmUpdRows;
+  const int64_t rows = min((int64_t)kTrsmUpdRows, r0 + nb + mb - i0);
+  constexpr int U = P == 2 ? 8 : 4;
+  for (int e = threadIdx.x; e < rows * nc; e += blockDim.x) {
+    const int il = e / nc, cc = e - il * nc;
+    const int64_t i = i0 + il, j = x0 + j0 + cc;
+    typename N::Acc acc = N::acc(ld_num<P>(A, ps, i * lda + j));
+    const double* arow = A + i * lda + r0;
+    int k = 0;
+    for (; k + U <= nb; k += U) {
+      typename N::T a[U], b[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        a[u] = ld_num<P>(arow, ps, k + u);
+#pragma unroll
+        for (int c = 0; c < P; c++) N::put(b[u], c, Xs[c][k + u][cc]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) N::acc_sub(acc, a[u], b[u]);
+    }
+    for (; k < nb; k++) {
+      typename N::T b;
+#pragma unroll
+      for (int c = 0; c < P; c++) N::put(b, c, Xs[c][k][cc]);
+      N::acc_sub(acc, ld_num<P>(arow, ps, k), b);
+    }
+    st_num<P>(A, ps, i * lda + j, N::value(acc));
+  }
+}
+
+// X := L^-1 X for the steps recorded by the panel (their tiles are disjoint
+// and lie above the diagonal, where no L is read): workgroup (g, q) solves
+// column group g of step q and stores it.
+template <int P>
+__global__ __launch_bounds__(1024) void trsm_nodes_kernel(double* A, int64_t lda, int64_t ps,
+                                                          TrsmNodes nodes) {
+  constexpr int R = trsm_rows<P>();
+  __shared__ double Ls[P][R][R + 1];
+  __shared__ double Xs[P][R][kTrsmCols + 1];
+  const int q = blockIdx.y;
+  const int cpb = blockDim.x / 64;
+  const int64_t j0 = (int64_t)blockIdx.x * cpb;
+  if (j0 >= nodes.nc[q]) return;  // uniform per workgroup
+  const int nc = (int)min((int64_t)cpb, nodes.nc[q] - j0);
+  trsm_tile<P>(A, lda, ps, nodes.r0[q], nodes.r0[q], nodes.nb[q], nodes.x0[q], j0, nc, Ls, Xs);
+  store_x_tile<P>(A, lda, ps, nodes.r0[q], nodes.nb[q], nodes.x0[q], j0, nc, Xs);
 }
 
 __global__ void lu_init_kernel(int32_t* info, int32_t* perm, int64_t n) {
@@ -1117,6 +1210,48 @@ int launch_trsm_wave(int P, double* A, int64_t lda, int64_t ps, int64_t r0, int6
                        s, A, lda, ps, r0, c0, nb, x0, ncols);
   prof_record("trsm_wave_kernel", s);
   return check_launch("trsm_wave_kernel");
+}
+
+int launch_trsm_update(int P, double* A, int64_t lda, int64_t ps, int64_t r0, int nb,
+                       int64_t x0, int64_t ncols, int64_t mb, hipStream_t s) {
+  if (nb <= 0 || ncols <= 0) return 0;
+  if (nb > trsm_max_rows(P)) return set_error(4, "trsm_update: block too large");
+  if (mb <= 0) return set_error(4, "trsm_update: no rows to update");
+  const int64_t cpb = ncols < kTrsmCols ? ncols : kTrsmCols;
+  const int64_t gx = (ncols + cpb - 1) / cpb, gy = (mb + kTrsmUpdRows - 1) / kTrsmUpdRows;
+  if (gx > INT32_MAX || gy > 65535) return set_error(4, "trsm_update: grid too large");
+  prof_begin(s);
+  if (P == 2)
+    hipLaunchKernelGGL(trsm_update_kernel<2>, dim3((unsigned)gx, (unsigned)gy),
+                       dim3((unsigned)(64 * cpb)), 0, s, A, lda, ps, r0, nb, x0, ncols, mb);
+  else
+    hipLaunchKernelGGL(trsm_update_kernel<4>, dim3((unsigned)gx, (unsigned)gy),
+                       dim3((unsigned)(64 * cpb)), 0, s, A, lda, ps, r0, nb, x0, ncols, mb);
+  prof_record("trsm_update_kernel", s);
+  return check_launch("trsm_update_kernel");
+}
+
+int launch_trsm_nodes(int P, double* A, int64_t lda, int64_t ps, const TrsmNodes& nodes,
+                      hipStream_t s) {
+  if (nodes.count <= 0) return 0;
+  if (nodes.count > kTrsmNodesMax) return set_error(4, "trsm_nodes: too many steps");
+  int maxnc = 0;
+  for (int q = 0; q < nodes.count; q++) {
+    if (nodes.nb[q] > trsm_max_rows(P) || nodes.nb[q] <= 0 || nodes.nc[q] <= 0)
+      return set_error(4, "trsm_nodes: bad step");
+    if (nodes.nc[q] > maxnc) maxnc = nodes.nc[q];
+  }
+  const int cpb = maxnc < kTrsmCols ? maxnc : kTrsmCols;
+  const int gx = (maxnc + cpb - 1) / cpb;
+  prof_begin(s);
+  if (P == 2)
+    hipLaunchKernelGGL(trsm_nodes_kernel<2>, dim3((unsigned)gx, (unsigned)nodes.count),
+                       dim3((unsigned)(64 * cpb)), 0, s, A, lda, ps, nodes);
+  else
+    hipLaunchKernelGGL(trsm_nodes_kernel<4>, dim3((unsigned)gx, (unsigned)nodes.count),
+                       dim3((unsigned)(64 * cpb)), 0, s, A, lda, ps, nodes);
+  prof_record("trsm_nodes_kernel", s);
+  return check_launch("trsm_nodes_kernel");
 }
 
 int launch_lu_update(int P, const double* A, const double* B, double* C, int64_t ld, int64_t ps,
