@@ -195,7 +195,9 @@ size_t dd_getrf_workspace(int64_t n, int panel, int algo, int levels, int base);
  *            its permutation or NULL (then it is rebuilt from ipiv, serially).
  *   B        device DD n x nrhs (ldb >= nrhs), overwritten by X; must not
  *            overlap LU.
- *   ws       workspace of dd_getrs_workspace(n, nrhs) bytes.
+ *   ws       workspace of dd_getrs_workspace(n, nrhs) bytes (the gathered
+ *            right-hand sides and a counter of the block solves); calls
+ *            that share one workspace must not run at the same time.
  */
 int dd_getrs(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t pslu,
              const int32_t* ipiv, const int32_t* perm, double* B, int64_t ldb, int64_t psb,

@@ -869,8 +869,10 @@ __global__ void perm_from_ipiv_kernel(const int32_t* ipiv, int64_t n, int32_t* p
 // X[i][:] = B[perm[i]][:] (X tight, n x nrhs, P planes)
 __global__ __launch_bounds__(256) void gather_rows_kernel(const double* B, int64_t ldb,
                                                           int64_t psb, int P, const int32_t* perm,
-                                                          int64_t n, int64_t nrhs, double* X) {
+                                                          int64_t n, int64_t nrhs, double* X,
+                                                          int* done) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e == 0) atomicExch(done, 0);  // trsv_block_kernel's counter starts at zero
   if (e >= n * nrhs) return;
   const int64_t i = e / nrhs, c = e % nrhs;
   const int64_t src = (int64_t)perm[i] * ldb + c;
@@ -894,8 +896,12 @@ constexpr int trsv_block() {
 
 // Forward (lower, unit) or backward (upper) step for block I of X (n x nrhs,
 // nrhs <= 16).  Every workgroup solves the diagonal block redundantly (one
-// wave per right-hand side, lane = row); the workgroup of block I stores it,
-// every other workgroup W updates its rows X_W -= T_WI X_I.  The diagonal
+// wave per right-hand side, lane = row) from X_I as it is in memory, and every
+// workgroup W != I updates its rows X_W -= T_WI X_I.  X_I is stored by the
+// last workgroup to have read it: each one counts itself in *done once its
+// loads of X_I have returned, and the one that completes the count stores and
+// resets it (a workgroup dispatched late, behind other work on the device,
+// must not find X_I already solved).  The diagonal
 // block, T_WI, X_I and X_W are all requested from memory before any of them
 // is used (one round trip), and staged in LDS.  In the solve, lane i keeps
 // x_i as an accumulator; step k finishes x_k, broadcasts it with readlane,
@@ -906,13 +912,15 @@ constexpr int trsv_block() {
 template <int P>
 __global__ __launch_bounds__(1024) void trsv_block_kernel(const double* T, int64_t ldt,
                                                           int64_t pst, double* X, int64_t n,
-                                                          int64_t nrhs, int64_t I, int upper) {
+                                                          int64_t nrhs, int64_t I, int upper,
+                                                          int* done) {
   using N = LuArith<P>;
   using V = typename N::T;
   constexpr int TB = trsv_block<P>();
   __shared__ double Ts[P][TB][TB + 1];
   __shared__ double Ws[P][TB][TB + 1];
   __shared__ double Xs[P][TB][17];
+  __shared__ int s_last;
   const int64_t nb = (n + TB - 1) / TB;
   const int64_t Wb = upper ? (I - (int64_t)blockIdx.x) : (I + (int64_t)blockIdx.x);
   if (Wb < 0 || Wb >= nb) return;
@@ -965,6 +973,8 @@ __global__ __launch_bounds__(1024) void trsv_block_kernel(const double* T, int64
 #pragma unroll
     for (int c = 0; c < P; c++) Xs[c][xi][xc] = xiv[c];
   __syncthreads();
+  // every load of X_I has returned (its value is in LDS)
+  if (t == 0) s_last = atomicAdd(done, 1) == (int)gridDim.x - 1;
   if (wave < nr) {
     V xinit = N::zero();
     if (lane < TB)
@@ -1000,12 +1010,13 @@ __global__ __launch_bounds__(1024) void trsv_block_kernel(const double* T, int64
     }
   }
   __syncthreads();
-  if (!upd) {
+  if (s_last) {
     if (xin)
 #pragma unroll
       for (int c = 0; c < P; c++) X[c * psx + (i0 + xi) * nrhs + xc] = Xs[c][xi][xc];
-    return;
+    if (t == 0) atomicExch(done, 0);
   }
+  if (!upd) return;
   // update rows of block Wb: X_W -= T_W,I X_I (one thread per entry)
   if (uin) {
     typename N::Acc acc = N::acc(xw);
@@ -1278,10 +1289,10 @@ int launch_perm_from_ipiv(const int32_t* ipiv, int64_t n, int32_t* perm, hipStre
 }
 
 int launch_gather_rows(int P, const double* B, int64_t ldb, int64_t psb, const int32_t* perm,
-                       int64_t n, int64_t nrhs, double* X, hipStream_t s) {
+                       int64_t n, int64_t nrhs, double* X, int* done, hipStream_t s) {
   prof_begin(s);
   hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0,
-                     s, B, ldb, psb, P, perm, n, nrhs, X);
+                     s, B, ldb, psb, P, perm, n, nrhs, X, done);
   prof_record("gather_rows_kernel", s);
   return check_launch("gather_rows_kernel");
 }
@@ -1296,7 +1307,7 @@ int launch_scatter_rows(int P, const double* X, int64_t n, int64_t nrhs, double*
 }
 
 int launch_trsv_blocks(int P, const double* T, int64_t ldt, int64_t pst, double* X, int64_t n,
-                       int64_t nrhs, int upper, hipStream_t s) {
+                       int64_t nrhs, int upper, int* done, hipStream_t s) {
   const int TB = P == 2 ? trsv_block<2>() : trsv_block<4>();
   const int64_t nb = (n + TB - 1) / TB;
   if (nrhs > 16) return set_error(4, "at most 16 right-hand sides per solve call");
@@ -1306,10 +1317,10 @@ int launch_trsv_blocks(int P, const double* T, int64_t ldt, int64_t pst, double*
     prof_begin(s);
     if (P == 2)
       hipLaunchKernelGGL(trsv_block_kernel<2>, dim3((unsigned)blocks), dim3(1024), 0, s, T, ldt,
-                         pst, X, n, nrhs, I, upper);
+                         pst, X, n, nrhs, I, upper, done);
     else
       hipLaunchKernelGGL(trsv_block_kernel<4>, dim3((unsigned)blocks), dim3(1024), 0, s, T, ldt,
-                         pst, X, n, nrhs, I, upper);
+                         pst, X, n, nrhs, I, upper, done);
     prof_record("trsv_block_kernel", s);
     int rc = check_launch("trsv_block_kernel");
     if (rc) return rc;

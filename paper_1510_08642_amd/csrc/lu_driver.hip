@@ -54,11 +54,11 @@ int launch_trsm_nodes(int P, double* A, int64_t lda, int64_t ps, const TrsmNodes
                       hipStream_t s);
 int launch_perm_from_ipiv(const int32_t* ipiv, int64_t n, int32_t* perm, hipStream_t s);
 int launch_gather_rows(int P, const double* B, int64_t ldb, int64_t psb, const int32_t* perm,
-                       int64_t n, int64_t nrhs, double* X, hipStream_t s);
+                       int64_t n, int64_t nrhs, double* X, int* done, hipStream_t s);
 int launch_scatter_rows(int P, const double* X, int64_t n, int64_t nrhs, double* B, int64_t ldb,
                         int64_t psb, hipStream_t s);
 int launch_trsv_blocks(int P, const double* T, int64_t ldt, int64_t pst, double* X, int64_t n,
-                       int64_t nrhs, int upper, hipStream_t s);
+                       int64_t nrhs, int upper, int* done, hipStream_t s);
 
 namespace {
 
@@ -187,10 +187,16 @@ size_t getrf_ws(int P, int64_t n, int64_t K, int algo, int levels, int base) {
   return mx;
 }
 
-size_t getrs_ws(int P, int64_t n, int64_t nrhs) {
+// getrs workspace: the gathered right-hand sides (P x n x min(nrhs, 16)
+// doubles), the block solves' counter, the permutation (n int32) if only
+// ipiv is given.
+size_t getrs_x_bytes(int P, int64_t n, int64_t nrhs) {
   const int64_t c = nrhs < 16 ? nrhs : 16;
-  return ((sizeof(double) * P * (size_t)(n * c) + 255) & ~(size_t)255) +
-         sizeof(int32_t) * (size_t)n;
+  return (sizeof(double) * P * (size_t)(n * c) + 255) & ~(size_t)255;
+}
+
+size_t getrs_ws(int P, int64_t n, int64_t nrhs) {
+  return getrs_x_bytes(P, n, nrhs) + 256 + sizeof(int32_t) * (size_t)n;
 }
 
 size_t getrf_workspace_entry(int P, int64_t n, int panel_width, int algo, int levels, int base) {
@@ -262,17 +268,17 @@ int getrs_entry(int P, int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, 
   hipStream_t s = (hipStream_t)stream;
   const int64_t chunk = nrhs < 16 ? nrhs : 16;
   double* X = (double*)ws;
-  int32_t* pm = (int32_t*)((char*)ws + (((sizeof(double) * P * (size_t)(n * chunk)) + 255) &
-                                        ~(size_t)255));
+  int* done = (int*)((char*)ws + getrs_x_bytes(P, n, nrhs));
+  int32_t* pm = (int32_t*)((char*)done + 256);
   if (!perm) {
     if ((rc = launch_perm_from_ipiv(ipiv, n, pm, s))) return rc;
     perm = pm;
   }
   for (int64_t c0 = 0; c0 < nrhs; c0 += chunk) {
     const int64_t nc = nrhs - c0 < chunk ? nrhs - c0 : chunk;
-    if ((rc = launch_gather_rows(P, B + c0, ldb, psb, perm, n, nc, X, s))) return rc;
-    if ((rc = launch_trsv_blocks(P, LU, ldlu, pslu, X, n, nc, 0, s))) return rc;
-    if ((rc = launch_trsv_blocks(P, LU, ldlu, pslu, X, n, nc, 1, s))) return rc;
+    if ((rc = launch_gather_rows(P, B + c0, ldb, psb, perm, n, nc, X, done, s))) return rc;
+    if ((rc = launch_trsv_blocks(P, LU, ldlu, pslu, X, n, nc, 0, done, s))) return rc;
+    if ((rc = launch_trsv_blocks(P, LU, ldlu, pslu, X, n, nc, 1, done, s))) return rc;
     if ((rc = launch_scatter_rows(P, X, n, nc, B + c0, ldb, psb, s))) return rc;
   }
   return DDQD_OK;

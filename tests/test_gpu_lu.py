@@ -266,3 +266,42 @@ def test_rowwise_zero_pivots_set_info(dd):
     A[0, n - 1, n - 1] = 0.0
     _, _, _, info = factor(dd, A, panel=0, pivot="none")
     assert info == n
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_getrs_with_the_device_busy_is_bit_identical(dd, P):
+    """A block step of the solve is one launch whose workgroups all read the
+    diagonal block as it is in memory; while a large product keeps the device
+    busy on another stream, workgroups of the step start late, and the solve
+    must still give the result of the quiet device, bit for bit."""
+    import torch
+    print(f"case getrs busy P={P}", flush=True)
+    n, nrhs = 300, 3
+    g = inputs.rng(21)
+    gen = inputs.dd_lu_matrix if P == 2 else inputs.qd_lu_matrix
+    LU = to_dev(gen(n, g))
+    getrf = dd.dd_getrf if P == 2 else dd.qd_getrf
+    getrs = dd.dd_getrs if P == 2 else dd.qd_getrs
+    ipiv, perm, info = getrf(LU, panel=64)
+    B = to_dev((inputs.dd_uniform if P == 2 else inputs.qd_uniform)(n, nrhs, g))
+    ref = B.clone()
+    getrs(LU, ipiv, ref, perm=perm)
+    torch.cuda.synchronize()
+    m = 2048
+    A2 = to_dev(inputs.dd_uniform(m, m, g))
+    B2 = to_dev(inputs.dd_uniform(m, m, g))
+    C2 = torch.empty_like(A2)
+    ws2 = torch.empty(dd.gemm_workspace(2, m, m, m, "block", 0, "ozaki"), dtype=torch.uint8,
+                      device=A2.device)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for rep in range(6):
+        s1.wait_stream(torch.cuda.current_stream())
+        s2.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s1):
+            for _ in range(2):
+                dd.dd_gemm(A2, B2, C2, base="ozaki", ws=ws2)
+        with torch.cuda.stream(s2):
+            X = B.clone()
+            getrs(LU, ipiv, X, perm=perm)
+        torch.cuda.synchronize()
+        assert torch.equal(X, ref), rep
