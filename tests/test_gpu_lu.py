@@ -273,7 +273,9 @@ def test_getrs_with_the_device_busy_is_bit_identical(dd, P):
     """A block step of the solve is one launch whose workgroups all read the
     diagonal block as it is in memory; while a large product keeps the device
     busy on another stream, workgroups of the step start late, and the solve
-    must still give the result of the quiet device, bit for bit."""
+    must still give the result of the quiet device, bit for bit.  The same for
+    the factorisation (whose panel steps also read, in one launch, values
+    that later launches overwrite)."""
     import torch
     print(f"case getrs busy P={P}", flush=True)
     n, nrhs = 300, 3
@@ -282,6 +284,7 @@ def test_getrs_with_the_device_busy_is_bit_identical(dd, P):
     LU = to_dev(gen(n, g))
     getrf = dd.dd_getrf if P == 2 else dd.qd_getrf
     getrs = dd.dd_getrs if P == 2 else dd.qd_getrs
+    A0 = LU.clone()
     ipiv, perm, info = getrf(LU, panel=64)
     B = to_dev((inputs.dd_uniform if P == 2 else inputs.qd_uniform)(n, nrhs, g))
     ref = B.clone()
@@ -303,5 +306,8 @@ def test_getrs_with_the_device_busy_is_bit_identical(dd, P):
         with torch.cuda.stream(s2):
             X = B.clone()
             getrs(LU, ipiv, X, perm=perm)
+            LU2 = A0.clone()
+            ipiv2, _, _ = getrf(LU2, panel=64)
         torch.cuda.synchronize()
         assert torch.equal(X, ref), rep
+        assert torch.equal(LU2, LU) and torch.equal(ipiv2, ipiv), rep
