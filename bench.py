@@ -489,6 +489,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--paper", action="store_true",
                     help="also run the paper's experiment shapes (Sec. 3 tables, Sec. 4 LU)")
+    ap.add_argument("--lu-only", type=int, default=0, metavar="N",
+                    help="only time the DD LU factor-and-solve of order N (panel 128, Winograd 1 "
+                         "on Ozaki leaves), for kernel traces of the LU")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB, 5 times "
                          "(reference kernel for scaling HBM byte counters)")
@@ -514,6 +517,11 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    if args.lu_only:
+        out = bench_lu(dd, inputs, torch, dev, [args.lu_only], [(128, "winograd", 1, "ozaki")],
+                       stream)
+        print(json.dumps({"lu": out}))
+        return
     n = args.n
     g = inputs.rng(0)
     PM = 2 if args.precision == "dd" else 4
