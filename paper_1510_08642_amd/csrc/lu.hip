@@ -298,30 +298,28 @@ __device__ __forceinline__ typename LuArith<P>::T readlane_acc(const typename Lu
 
 // The lane holding the best candidate of a wave (largest |x|, then the
 // smallest index; idx < 0 marks "no candidate"), the same in every lane, or
-// -1 if no lane has one.  FP64 maxima of the leading terms and of the tails
-// find the leader; a lane can equal or beat it only if the gap between its
-// leading term and the largest is within the tails' bound, and when that
-// holds for one lane alone it is the winner.  Otherwise the comparison in the
-// working precision decides among those lanes.  kRow0: candidates only in
-// lanes 0..15.
+// -1 if no lane has one.  The FP64 maximum M of the leading terms finds the
+// leader.  Candidates are normalized, so the trailing terms of each add at
+// most about 2^-52 of its leading term (or a few units of the smallest
+// subnormal): a lane can equal or beat the leader only if its leading term is
+// within 2^-48 M + 2^-1060 of M, and when that holds for one lane alone it is
+// the winner.  Otherwise the comparison in the working precision decides
+// among those lanes.  kRow0: candidates only in lanes 0..15.
 template <int P, bool kRow0>
 __device__ __forceinline__ int wave_argmax(const typename LuArith<P>::T& x, int idx) {
   using N = LuArith<P>;
   const int lane = threadIdx.x % 64;
   const bool valid = idx >= 0;
-  const double h = valid ? fabs(N::get(x, 0)) : -1.0, l = valid ? N::tail(x) : -1.0;
-  double M = row16_max(h), L = row16_max(l);
+  const double h = valid ? fabs(N::get(x, 0)) : -1.0;
+  double M = row16_max(h);
   if (kRow0) {
     M = readlane_f64(M, 0);
-    L = readlane_f64(L, 0);
   } else {
     M = fmax(fmax(readlane_f64(M, 0), readlane_f64(M, 16)),
              fmax(readlane_f64(M, 32), readlane_f64(M, 48)));
-    L = fmax(fmax(readlane_f64(L, 0), readlane_f64(L, 16)),
-             fmax(readlane_f64(L, 32), readlane_f64(L, 48)));
   }
   if (!(M >= 0.0)) return -1;
-  const bool close = valid && (M - h) <= 2.0 * (L + l);
+  const bool close = valid && (M - h) <= 0x1p-48 * M + 0x1p-1060;
   const uint64_t mask = __ballot(close);
   if (__popcll(mask) == 1) return __ffsll((unsigned long long)mask) - 1;
   typename N::T b = close ? x : N::zero();
