@@ -485,17 +485,19 @@ __global__ __launch_bounds__(T) void getf2_kernel(double* A, int64_t lda, int64_
 #pragma unroll
     for (int q = 0; q < RPT; q++) {
       const int i = t + T * q;
+      // columns before c hold multipliers and column c was normalized at the
+      // start of this step; only the lazily updated columns after c need it
       if (lane == wl && i == wbi)
 #pragma unroll
         for (int k = 0; k < W; k++) {
-          const V x = N::norm(v[q][k]);
+          const V x = k > c ? N::norm(v[q][k]) : v[q][k];
 #pragma unroll
           for (int cc = 0; cc < P; cc++) s_row[buf][wave][cc][k] = N::get(x, cc);
         }
       if (i == c)
 #pragma unroll
         for (int k = 0; k < W; k++) {
-          const V x = N::norm(v[q][k]);
+          const V x = k > c ? N::norm(v[q][k]) : v[q][k];
 #pragma unroll
           for (int cc = 0; cc < P; cc++) s_rowc[buf][cc][k] = N::get(x, cc);
         }
