@@ -475,19 +475,19 @@ __global__ __launch_bounds__(T) void getf2_kernel(double* A, int64_t lda, int64_
       }
     }
     const int wl = wave_argmax<P, false>(best, bi);
-    const int wbi = wl >= 0 ? __builtin_amdgcn_readlane(bi, wl) : -1;
-    if (lane == 0) {
+    // the winning lane publishes its own candidate (lane 0 "none" if no lane
+    // has one)
+    if (lane == (wl >= 0 ? wl : 0)) {
 #pragma unroll
-      for (int cc = 0; cc < P; cc++)
-        s_val[buf][wave][cc] = wl >= 0 ? readlane_f64(N::get(best, cc), wl) : 0.0;
-      s_idx[buf][wave] = wbi;
+      for (int cc = 0; cc < P; cc++) s_val[buf][wave][cc] = wl >= 0 ? N::get(best, cc) : 0.0;
+      s_idx[buf][wave] = wl >= 0 ? bi : -1;
     }
 #pragma unroll
     for (int q = 0; q < RPT; q++) {
       const int i = t + T * q;
       // columns before c hold multipliers and column c was normalized at the
       // start of this step; only the lazily updated columns after c need it
-      if (lane == wl && i == wbi)
+      if (lane == wl && i == bi)
 #pragma unroll
         for (int k = 0; k < W; k++) {
           const V x = k > c ? N::norm(v[q][k]) : v[q][k];
