@@ -781,7 +781,7 @@ __global__ __launch_bounds__(1024) void trsm_wave_kernel(double* A, int64_t lda,
 // those rows of those columns (later interchanges only move rows below them),
 // so trsm_nodes_kernel solves and stores the X of all such steps of a panel
 // once the panel is factored.
-constexpr int kTrsmUpdRows = 64;
+constexpr int kTrsmUpdRows = 32;
 
 template <int P>
 __global__ __launch_bounds__(1024) void trsm_update_kernel(double* A, int64_t lda, int64_t ps,
