@@ -66,7 +66,7 @@ extern "C" {
  * of two per row of A / column of B and cut into `slices` signed 7-bit digits;
  * the digit products run exactly on v_mfma_i32_32x32x32_i8 and are recombined
  * in FP64.  Leaf error at most about l (S+3) 2^(-7S-2) max|a_i.| max|b_.j|
- * times 4, S the slice count.) */
+ * times 16, S the slice count.) */
 
 /* pivoting for dd_getrf */
 #define DDQD_PIVOT_NONE 0
@@ -149,7 +149,7 @@ int dd_gemm_grouped(int count, const ddqd_gemm_desc* descs, void* stream);
 /* As dd_gemm, in QD (4 planes per matrix; Sec. 3, Table 2's precision).
  * With DDQD_BASE_OZAKI_I8 the slice count is 0 = 31 or 28..31 (else
  * DDQD_E_UNSUPPORTED); 31 slices keep the leaf error below about
- * 2^-211 l max|a_i.| max|b_.j|, QD's accuracy class. */
+ * 2^-209 l max|a_i.| max|b_.j|, QD's accuracy class. */
 int qd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
             int64_t psa, const double* B, int64_t ldb, int64_t psb, int beta, double* C,
             int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,

@@ -24,8 +24,9 @@
 //    summed by TwoSum into a DD, then C := beta C + alpha value.
 //
 // Error: slicing and the dropped diagonals d > S + 1 contribute at most about
-// l (S + 3) 2^(-7S-2) 2^(e_i + f_j) to entry (i, j); with S = 16 that is below
-// 2^-103 l max|a_i.| max|b_.j| -- the same accuracy class as the FMA kernel.
+// l (S + 3) 2^(-7S-2) 2^(e_i + f_j) to entry (i, j); as 2^(e_i + f_j) <= 16
+// max|a_i.| max|b_.j|, with S = 16 that is below 2^-105 l max|a_i.| max|b_.j|
+// -- the same accuracy class as the FMA kernel.
 #include "ddqd.h"
 #include "common.hpp"
 #include "eft.hpp"

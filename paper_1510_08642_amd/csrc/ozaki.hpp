@@ -61,9 +61,11 @@ inline OzWs oz_ws(char* ws, const OzLayout& o, int64_t batch) {
   return w;
 }
 
-// Exponents e with max |leading component| < 2^(e - 1) (all-zero lines get a
-// sentinel far below any exponent, padded rows 1): of A's rows into w.ea, and
-// of B's columns per 32-row slab into w.part.  One launch.
+// Exponents e with max |leading component| < 2^(e - 1): of A's rows into
+// w.ea (an all-zero row, and every padded row, gets 1: its digits are all
+// zero, so any exponent gives the same result), and of B's columns per 32-row
+// slab into w.part (an all-zero slab gets a sentinel far below any exponent,
+// so the column's maximum over slabs ignores it).  One launch.
 int launch_oz_exponents(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s);
 
 // The S digits of every scaled entry of A and B (P = 2 DD, 4 QD); also

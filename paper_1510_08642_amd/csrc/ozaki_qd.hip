@@ -29,8 +29,10 @@
 //    scaled by 2^(e_i + f_j); then C := beta C + alpha value in QD.
 //
 // Error: the slicing remainders and the dropped diagonals d >= S contribute at
-// most about l (S + 3) 2^(-7S-2) 2^(e_i + f_j) to entry (i, j); with S = 31
-// that is below 2^-213 l max|a_i.| max|b_.j| -- QD's accuracy class.
+// most about l (S + 3) 2^(-7S-2) 2^(e_i + f_j) to entry (i, j).  Since
+// max|a_i.| >= 2^(e_i - 2) and max|b_.j| >= 2^(f_j - 2), 2^(e_i + f_j) is at
+// most 16 max|a_i.| max|b_.j|; with S = 31 the bound is below
+// 2^-209 l max|a_i.| max|b_.j| -- QD's accuracy class.
 #include "ddqd.h"
 #include "common.hpp"
 #include "eft.hpp"

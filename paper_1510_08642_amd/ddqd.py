@@ -148,6 +148,8 @@ def gemm_workspace(P: int, m: int, n: int, l: int, algo="block", levels=0, base=
 
 
 def _gemm(P, A, B, C, alpha, beta, algo, levels, base, slices, ws):
+    if A.dim() != 3 or B.dim() != 3:
+        raise ValueError(f"A and B must have shape ({P}, rows, cols)")
     m, l = A.shape[1], A.shape[2]
     n = B.shape[2]
     if B.shape[1] != l:
@@ -155,6 +157,10 @@ def _gemm(P, A, B, C, alpha, beta, algo, levels, base, slices, ws):
     if C is None:
         C = torch.empty((P, m, n), dtype=torch.float64, device=A.device)
         beta = 0
+    elif tuple(C.shape) != (P, m, n):
+        # the C ABI sees only pointers and strides: a C of another shape would
+        # be written only in part, or beyond its storage
+        raise ValueError(f"C must have shape ({P}, {m}, {n}), got {tuple(C.shape)}")
     pa, lda, psa = _mat(A, P, "A")
     pb, ldb, psb = _mat(B, P, "B")
     pc, ldc, psc = _mat(C, P, "C")
@@ -209,7 +215,7 @@ def qd_getrf(A, *, panel=128, pivot="partial", algo="winograd", levels=1, base="
 
 def _getrf(P, A, panel, pivot, algo, levels, base, want_perm, ws, out):
     n = A.shape[1]
-    if A.shape[2] != n:
+    if A.dim() != 3 or A.shape[2] != n:
         raise ValueError("A must be square")
     pa, lda, psa = _mat(A, P, "A")
     dev = A.device
@@ -247,6 +253,13 @@ def qd_getrs(LU, ipiv, B, *, perm=None, ws=None):
 
 def _getrs(P, LU, ipiv, B, perm, ws):
     n, nrhs = B.shape[1], B.shape[2]
+    if tuple(LU.shape) != (P, n, n):
+        raise ValueError(f"LU must have shape ({P}, {n}, {n}), got {tuple(LU.shape)}")
+    for name, v in (("ipiv", ipiv), ("perm", perm)):
+        if v is not None and (v.dtype != torch.int32 or not v.is_contiguous() or v.numel() < n):
+            raise ValueError(f"{name} must be a contiguous int32 tensor of at least {n} entries")
+    if ipiv is None and perm is None:
+        raise ValueError("ipiv and perm are both None")
     pl, ldl, psl = _mat(LU, P, "LU")
     pb, ldb, psb = _mat(B, P, "B")
     need = getattr(_lib, f"{_PREC[P]}_getrs_workspace")(n, nrhs)
