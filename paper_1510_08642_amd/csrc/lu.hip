@@ -923,6 +923,11 @@ __global__ __launch_bounds__(1024) void trsv_block_kernel(const double* T, int64
   __shared__ int s_last;
   const int64_t nb = (n + TB - 1) / TB;
   const int64_t Wb = upper ? (I - (int64_t)blockIdx.x) : (I + (int64_t)blockIdx.x);
+  // The workgroups that take part (and count themselves in *done) are those
+  // whose block Wb exists: blockIdx.x < I + 1 (upper) or < nb - I (lower).
+  // Any further workgroups of a larger grid return here without counting.
+  const int64_t in_range = upper ? I + 1 : nb - I;
+  const int members = (int)(in_range < (int64_t)gridDim.x ? in_range : (int64_t)gridDim.x);
   if (Wb < 0 || Wb >= nb) return;
   const int64_t i0 = I * TB, w0 = Wb * TB;
   const int rows = (int)(n - i0 < TB ? n - i0 : TB);
@@ -974,7 +979,7 @@ __global__ __launch_bounds__(1024) void trsv_block_kernel(const double* T, int64
     for (int c = 0; c < P; c++) Xs[c][xi][xc] = xiv[c];
   __syncthreads();
   // every load of X_I has returned (its value is in LDS)
-  if (t == 0) s_last = atomicAdd(done, 1) == (int)gridDim.x - 1;
+  if (t == 0) s_last = atomicAdd(done, 1) == members - 1;
   if (wave < nr) {
     V xinit = N::zero();
     if (lane < TB)
@@ -1310,10 +1315,13 @@ int launch_trsv_blocks(int P, const double* T, int64_t ldt, int64_t pst, double*
                        int64_t nrhs, int upper, int* done, hipStream_t s) {
   const int TB = P == 2 ? trsv_block<2>() : trsv_block<4>();
   const int64_t nb = (n + TB - 1) / TB;
-  if (nrhs > 16) return set_error(4, "at most 16 right-hand sides per solve call");
+  if (nrhs > 16) return set_error(DDQD_E_UNSUPPORTED, "at most 16 right-hand sides per solve call");
   for (int64_t step = 0; step < nb; step++) {
     const int64_t I = upper ? nb - 1 - step : step;
+    // one workgroup per block row the step updates, the diagonal one included
+    // (all of them must run: a smaller grid would leave rows unsolved)
     const int64_t blocks = upper ? I + 1 : nb - I;
+    if (blocks < 1 || blocks > nb) return set_error(DDQD_E_HIP, "trsv grid out of range");
     prof_begin(s);
     if (P == 2)
       hipLaunchKernelGGL(trsv_block_kernel<2>, dim3((unsigned)blocks), dim3(1024), 0, s, T, ldt,

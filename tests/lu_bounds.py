@@ -1,0 +1,44 @@
+"""Bounds for comparing two LU factorizations computed in different rounding
+orders (used by the LU parity tests): the backward error elimination
+guarantees, and the first-order perturbation bound of the factors."""
+import numpy as np
+
+
+def split(LU):
+    """Unit lower L and upper U of a plane-layout factorization."""
+    P, n = LU.shape[0], LU.shape[1]
+    low = np.tril(np.ones((n, n), dtype=bool), -1)
+    L = np.where(low[None], LU, 0.0)
+    L[0][np.arange(n), np.arange(n)] = 1.0
+    U = np.where(~low[None], LU, 0.0)
+    return L, U
+
+
+def da_bound(L, U, u):
+    """Entrywise bound on the backward error of factors L, U (leading parts)."""
+    n = L.shape[1]
+    aL, aU = np.abs(L[0]), np.abs(U[0])
+    comp = aL @ aU
+    rowcol = aL.max(axis=1)[:, None] * aU.max(axis=0)[None, :]
+    return n * u * np.maximum(comp, rowcol)
+
+
+def first_order_bound(L, U, dA):
+    from scipy.linalg import solve_triangular
+    n = L.shape[1]
+    Li = np.abs(solve_triangular(L[0], np.eye(n), lower=True, unit_diagonal=True))
+    Ui = np.abs(solve_triangular(U[0], np.eye(n), lower=False))
+    X = Li @ dA @ Ui
+    upper = np.triu(np.ones((n, n), dtype=bool))
+    return np.where(upper, np.triu(X) @ np.abs(U[0]), np.abs(L[0]) @ np.tril(X, -1))
+
+
+def samples(n, count, seed):
+    g = np.random.default_rng(seed)
+    ii = np.concatenate([np.arange(n), [0, n - 1], g.integers(0, n, count)])
+    jj = np.concatenate([np.arange(n), [n - 1, 0], g.integers(0, n, count)])
+    return ii, jj
+
+
+def vsum(X):
+    return sum(X[c] for c in range(X.shape[0]))
