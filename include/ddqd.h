@@ -206,6 +206,28 @@ int dd_getrs(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t ps
 size_t dd_getrs_workspace(int64_t n, int64_t nrhs);
 
 /*
+ * dd_getrs without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation): the same kernels and the same result, bit for bit,
+ * as dd_getrs, with the workspace taken from a fixed buffer that the library
+ * holds on each GPU until the process ends (about 2 MiB: the gathered
+ * right-hand sides, 16 at a time, the block solves' counter and the
+ * permutation for orders up to 8192).  The call allocates and frees nothing.
+ *   n        order, at most 8192 (else DDQD_E_UNSUPPORTED, nothing enqueued);
+ *            nrhs any (solved 16 at a time).
+ *   other arguments and errors as dd_getrs.
+ * The buffer's device address is looked up once per device (on that device's
+ * first call; DDQD_E_HIP if the lookup fails).  Every call on one GPU uses
+ * the same buffer, which keeps the last call's contents (the counter is
+ * reset by the call's own kernels): calls that overlap on one GPU (on
+ * different streams, or from several threads, with no ordering between them)
+ * race and give wrong results; calls ordered on one stream are safe.
+ */
+int dd_getrs_noalloc(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t pslu,
+                     const int32_t* ipiv, const int32_t* perm, double* B, int64_t ldb,
+                     int64_t psb, void* stream);
+
+/*
  * The same factorisation and solve in QD (4 planes per matrix; the paper's
  * second LU workload, Sec. 4): arguments, layouts, ipiv / perm / info and
  * errors as dd_getrf / dd_getrs.  Pivots are compared, and the panel is

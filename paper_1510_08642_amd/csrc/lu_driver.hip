@@ -18,6 +18,8 @@
 // the row permutation in `perm`.  U12 = L11^-1 A12 is a recursive triangular
 // solve (diagonal solves of up to 64 rows in DD, 32 in QD, one wave per
 // column; products for the off-diagonal parts).
+#include <mutex>
+
 #include "common.hpp"
 #include "ddqd.h"
 
@@ -190,12 +192,11 @@ size_t getrf_ws(int P, int64_t n, int64_t K, int algo, int levels, int base) {
 // getrs workspace: the gathered right-hand sides (P x n x min(nrhs, 16)
 // doubles), the block solves' counter, the permutation (n int32) if only
 // ipiv is given.
-size_t getrs_x_bytes(int P, int64_t n, int64_t nrhs) {
-  const int64_t c = nrhs < 16 ? nrhs : 16;
-  return (sizeof(double) * P * (size_t)(n * c) + 255) & ~(size_t)255;
+constexpr size_t getrs_x_bytes(int P, int64_t n, int64_t nrhs) {
+  return (sizeof(double) * P * (size_t)(n * (nrhs < 16 ? nrhs : 16)) + 255) & ~(size_t)255;
 }
 
-size_t getrs_ws(int P, int64_t n, int64_t nrhs) {
+constexpr size_t getrs_ws(int P, int64_t n, int64_t nrhs) {
   return getrs_x_bytes(P, n, nrhs) + 256 + sizeof(int32_t) * (size_t)n;
 }
 
@@ -284,6 +285,79 @@ int getrs_entry(int P, int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, 
   return DDQD_OK;
 }
 
+// ---- allocation-free solve (dd_getrs_noalloc) --------------------------
+//
+// The workspace of a DD solve of order up to kMaxLuRows (any number of
+// right-hand sides: they are solved 16 at a time in the same buffer) lives in
+// a file-scope device array.  In host code `scratch` names a host-side stand-in;
+// the device address of each GPU's copy is looked up once per device with
+// hipGetSymbolAddress and only that address is passed to kernels.
+constexpr size_t kNoAllocBytes = getrs_ws(2, kMaxLuRows, 16);
+
+}  // namespace
+}  // namespace ddqd
+
+static __device__ __align__(256) unsigned char scratch[ddqd::kNoAllocBytes];
+
+namespace ddqd {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device, once known
+
+// The device address of this device's `scratch`, looked up on first use with
+// the device current.
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(DDQD_E_UNSUPPORTED, "device %d above the %d the library tracks", dev,
+                     kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess)
+      return set_error(DDQD_E_HIP, "hipGetDevice failed");
+    if (cur != dev && hipSetDevice(dev) != hipSuccess)
+      return set_error(DDQD_E_HIP, "hipSetDevice(%d) failed", dev);
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      return set_error(DDQD_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                       hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DDQD_OK;
+}
+
+int getrs_noalloc_entry(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t pslu,
+                        const int32_t* ipiv, const int32_t* perm, double* B, int64_t ldb,
+                        int64_t psb, void* stream) {
+  clear_error();
+  if (n < 0 || nrhs < 0) return set_error(DDQD_E_ARG, "negative dimension");
+  if (n == 0 || nrhs == 0) return DDQD_OK;
+  if (n > kMaxLuRows)
+    return set_error(DDQD_E_UNSUPPORTED,
+                     "dd_getrs_noalloc: order %lld above its scratch limit of %lld",
+                     (long long)n, (long long)kMaxLuRows);
+  static_assert(getrs_ws(2, kMaxLuRows, 16) <= kNoAllocBytes, "scratch too small");
+  int rc;
+  if ((rc = check_device())) return rc;
+  int dev = -1;
+  hipStream_t s = (hipStream_t)stream;
+  if (s) {
+    if (hipStreamGetDevice(s, &dev) != hipSuccess)
+      return set_error(DDQD_E_ARG, "stream has no device");
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    return set_error(DDQD_E_HIP, "hipGetDevice failed");
+  }
+  void* ws = nullptr;
+  if ((rc = scratch_address(dev, &ws))) return rc;
+  return getrs_entry(2, n, nrhs, LU, ldlu, pslu, ipiv, perm, B, ldb, psb, ws, kNoAllocBytes,
+                     stream);
+}
+
 }  // namespace
 }  // namespace ddqd
 
@@ -319,6 +393,12 @@ int qd_getrf(int64_t n, double* A, int64_t lda, int64_t psa, int32_t* ipiv, int3
              size_t ws_bytes, void* stream) {
   return getrf_entry(4, n, A, lda, psa, ipiv, perm, info, panel_width, pivot, algo, levels, base,
                      ws, ws_bytes, stream);
+}
+
+int dd_getrs_noalloc(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, int64_t pslu,
+                     const int32_t* ipiv, const int32_t* perm, double* B, int64_t ldb,
+                     int64_t psb, void* stream) {
+  return getrs_noalloc_entry(n, nrhs, LU, ldlu, pslu, ipiv, perm, B, ldb, psb, stream);
 }
 
 size_t qd_getrs_workspace(int64_t n, int64_t nrhs) { return getrs_workspace_entry(4, n, nrhs); }

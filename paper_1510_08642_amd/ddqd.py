@@ -51,6 +51,8 @@ for _p in ("dd", "qd"):
     getattr(_lib, f"{_p}_getrs").argtypes = [_i64, _i64, _vp, _i64, _i64, _vp, _vp, _vp, _i64,
                                              _i64, _vp, _sz, _vp]
     getattr(_lib, f"{_p}_getrs").restype = _int
+_lib.dd_getrs_noalloc.argtypes = [_i64, _i64, _vp, _i64, _i64, _vp, _vp, _vp, _i64, _i64, _vp]
+_lib.dd_getrs_noalloc.restype = _int
 _PREC = {2: "dd", 4: "qd"}
 
 
@@ -272,6 +274,27 @@ def _getrs(P, LU, ipiv, B, perm, ws):
         perm.data_ptr() if perm is not None else None, pb, ldb, psb, ws.data_ptr(), ws.numel(),
         _stream_of(B))
     _check(st, f"{_PREC[P]}_getrs")
+    return B
+
+
+def dd_getrs_noalloc(LU, ipiv, B, *, perm=None):
+    """As dd_getrs, with no workspace: the library's fixed per-GPU buffer
+    (orders up to 8192).  Calls that overlap on one GPU race."""
+    n, nrhs = B.shape[1], B.shape[2]
+    if tuple(LU.shape) != (2, n, n):
+        raise ValueError(f"LU must have shape (2, {n}, {n}), got {tuple(LU.shape)}")
+    for name, v in (("ipiv", ipiv), ("perm", perm)):
+        if v is not None and (v.dtype != torch.int32 or not v.is_contiguous() or v.numel() < n):
+            raise ValueError(f"{name} must be a contiguous int32 tensor of at least {n} entries")
+    if ipiv is None and perm is None:
+        raise ValueError("ipiv and perm are both None")
+    pl, ldl, psl = _mat(LU, 2, "LU")
+    pb, ldb, psb = _mat(B, 2, "B")
+    st = _lib.dd_getrs_noalloc(n, nrhs, pl, ldl, psl,
+                               ipiv.data_ptr() if ipiv is not None else None,
+                               perm.data_ptr() if perm is not None else None, pb, ldb, psb,
+                               _stream_of(B))
+    _check(st, "dd_getrs_noalloc")
     return B
 
 

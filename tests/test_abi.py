@@ -226,3 +226,17 @@ def test_qd_lu_argument_errors(lib):
     assert lib.qd_getrf_workspace(1024, 128, 3, 1, 1) > lib.qd_getrf_workspace(1024, 128, 3, 1, 0)
     assert lib.qd_getrs_workspace(100, 3) >= 4 * 8 * 100 * 3
     assert lib.qd_getrs_workspace(100, 3) > lib.dd_getrs_workspace(100, 3)
+
+
+def test_getrs_noalloc_argument_errors(lib):
+    f = lib.dd_getrs_noalloc
+    f.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+    assert f(-1, 1, 0x10000, 4, 16, 0x20000, None, 0x30000, 1, 4, None) == E["ARG"]
+    assert f(0, 1, None, 1, 1, None, None, None, 1, 1, None) == E["OK"]
+    assert f(5, 0, None, 1, 1, None, None, None, 1, 1, None) == E["OK"]
+    # orders beyond the fixed buffer are refused before any device call
+    assert f(8193, 1, 0x10000, 8193, 8193 * 8193, 0x20000, None, 0x30000, 1, 8193,
+             None) == E["UNSUPPORTED"]
+    assert b"scratch limit" in lib.ddqd_last_error()
