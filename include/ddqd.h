@@ -122,10 +122,13 @@ int dd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t
 size_t dd_gemm_workspace(int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
                          int slices);
 
-/* One problem of a grouped launch: C := beta*C + alpha*(A B), as in dd_gemm. */
+/* One problem of a grouped launch: C := beta*C + alpha*(A B), as in dd_gemm
+ * with DDQD_BLOCK and the given base (DDQD_BASE_FMA or DDQD_BASE_OZAKI_I8)
+ * and Ozaki slice count (0 = 16, else 8..20; ignored for FMA). */
 typedef struct {
   int64_t m, n, l;
   int alpha, beta;
+  int base, slices;
   const double* A;
   int64_t lda, psa;
   const double* B;
@@ -135,16 +138,27 @@ typedef struct {
 } ddqd_gemm_desc;
 
 /*
- * `count` unrelated DD products of any shapes (host array of descriptors,
- * read before the call returns) in persistent Block-FMA launches of up to 24
- * problems each: one launch instead of one per problem, for the uneven small
- * products of a serving batch or of the 7 sub-products of a recursion level
- * (the paper runs those as parallel sections, Sec. 2).  Each problem's result
- * is bit-identical to the same dd_gemm call with DDQD_BLOCK and the FMA base.
- * No output may overlap any input or another output of the group
- * (DDQD_E_ALIAS).  No workspace.
+ * `count` unrelated DD products of any shapes and bases (host array of
+ * descriptors, read before the call returns) in grouped launches instead of
+ * one per problem, for the uneven small products of a serving batch or of
+ * an LU step (the paper runs independent products as parallel sections,
+ * Sec. 2): FMA problems in persistent Block launches of up to 24 problems
+ * each; Ozaki problems, per slice count, in launches of up to 12 problems
+ * (one exponent, one slicing and one product launch per group; a problem
+ * with l > 16384 runs as a product of its own).  Each problem's result is
+ * bit-identical to the same dd_gemm call with DDQD_BLOCK and its base and
+ * slices.  No output may overlap any input or another output of the group
+ * (DDQD_E_ALIAS).
+ *   ws     device workspace of ws_bytes >= dd_gemm_grouped_workspace(count,
+ *          descs) bytes, 8-byte aligned (may be NULL when that size is 0:
+ *          a group of FMA problems needs none).
  */
-int dd_gemm_grouped(int count, const ddqd_gemm_desc* descs, void* stream);
+int dd_gemm_grouped(int count, const ddqd_gemm_desc* descs, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* Workspace bytes dd_gemm_grouped needs for these descriptors (SIZE_MAX if
+ * one of them is invalid). */
+size_t dd_gemm_grouped_workspace(int count, const ddqd_gemm_desc* descs);
 
 /* As dd_gemm, in QD (4 planes per matrix; Sec. 3, Table 2's precision).
  * With DDQD_BASE_OZAKI_I8 the slice count is 0 = 31 or 28..31 (else

@@ -58,6 +58,10 @@ int launch_postadd(CMat prod, Mat dst, int64_t rows, int64_t cols, int64_t dst_r
 int launch_exponents(CMat A, CMat B, int64_t m, int64_t n, int64_t l, int* ea, int* fb,
                      hipStream_t stream);
 size_t ozaki_workspace(int P, int64_t m, int64_t n, int64_t l, int64_t batch, int slices);
+int ozaki_default_slices(int P);
+size_t ozaki_grouped_bytes(const GemmBatch& g, int S);
+int launch_ozaki_grouped(const GemmBatch* probs, int count, int S, char* ws, size_t ws_bytes,
+                         hipStream_t s);
 int launch_ozaki(int P, const GemmBatch& g, int slices, void* ws, size_t ws_bytes,
                  hipStream_t stream);
 bool ozaki_slices_ok(int P, int slices);
@@ -512,11 +516,43 @@ int ddqd_profile_query(const char* substr, double* ms, int64_t* count) {
   return DDQD_OK;
 }
 
-int dd_gemm_grouped(int count, const ddqd_gemm_desc* d, void* stream) {
-  g_msg[0] = 0;
+}  // extern "C"
+
+namespace ddqd {
+namespace {
+
+// Problems of a grouped call that run on Ozaki leaves (m, n, l > 0), and the
+// workspace each needs: the grouped launches take l <= 16384 (one exact INT32
+// accumulation), longer K runs as a product of its own.
+constexpr int64_t kGroupedOzakiMaxL = 16384;
+
+GemmBatch desc_batch(const ddqd_gemm_desc& x) {
+  GemmBatch g{x.m, x.n, x.l, x.alpha, x.beta, CMat{x.A, x.lda, x.psa, 0},
+              CMat{x.B, x.ldb, x.psb, 0}, Mat{x.C, x.ldc, x.psc, 0}, 1};
+  if (x.l == 0) {  // C := beta C: the empty K loop reads nothing from A or B
+    g.A = CMat{x.C, x.ldc, x.psc, 0};
+    g.B = g.A;
+  }
+  return g;
+}
+
+bool desc_ozaki(const ddqd_gemm_desc& x) {
+  return x.base == DDQD_BASE_OZAKI_I8 && x.m > 0 && x.n > 0 && x.l > 0;
+}
+
+int desc_slices(const ddqd_gemm_desc& x) {
+  return x.slices == 0 ? ozaki_default_slices(2) : x.slices;
+}
+
+size_t desc_ozaki_bytes(const ddqd_gemm_desc& x) {
+  const GemmBatch g = desc_batch(x);
+  if (x.l <= kGroupedOzakiMaxL) return ozaki_grouped_bytes(g, desc_slices(x));
+  return align_up(ozaki_workspace(2, x.m, x.n, x.l, 1, desc_slices(x)));
+}
+
+int check_descs(int count, const ddqd_gemm_desc* d) {
   if (count < 0) return set_error(DDQD_E_ARG, "negative count");
-  if (count == 0) return DDQD_OK;
-  if (!d) return set_error(DDQD_E_ARG, "descriptor array is NULL");
+  if (count > 0 && !d) return set_error(DDQD_E_ARG, "descriptor array is NULL");
   int rc;
   for (int i = 0; i < count; i++) {
     const ddqd_gemm_desc& x = d[i];
@@ -524,12 +560,45 @@ int dd_gemm_grouped(int count, const ddqd_gemm_desc* d, void* stream) {
       return set_error(DDQD_E_ARG, "problem %d: negative dimension", i);
     if ((x.alpha != 1 && x.alpha != -1) || (x.beta != 0 && x.beta != 1))
       return set_error(DDQD_E_ARG, "problem %d: alpha must be +-1 and beta 0 or 1", i);
+    if (x.base != DDQD_BASE_FMA && x.base != DDQD_BASE_OZAKI_I8)
+      return set_error(DDQD_E_ARG, "problem %d: unknown base %d", i, x.base);
+    if (x.slices < 0 || x.slices > 40)
+      return set_error(DDQD_E_ARG, "problem %d: slices must be in 0..40", i);
+    if (x.base == DDQD_BASE_OZAKI_I8 && !ozaki_slices_ok(2, x.slices))
+      return set_error(DDQD_E_UNSUPPORTED, "problem %d: %d slices not supported (DD 8..20)", i,
+                       x.slices);
     if ((rc = check_mat("C", 2, x.C, x.m, x.n, x.ldc, x.psc))) return rc;
     if (x.l > 0 && x.m > 0 && x.n > 0) {
       if ((rc = check_mat("A", 2, x.A, x.m, x.l, x.lda, x.psa))) return rc;
       if ((rc = check_mat("B", 2, x.B, x.l, x.n, x.ldb, x.psb))) return rc;
     }
   }
+  return DDQD_OK;
+}
+
+size_t grouped_ws(int count, const ddqd_gemm_desc* d) {
+  size_t need = 0;
+  for (int i = 0; i < count; i++)
+    if (desc_ozaki(d[i])) need += desc_ozaki_bytes(d[i]);
+  return need;
+}
+
+}  // namespace
+}  // namespace ddqd
+
+extern "C" {
+
+size_t dd_gemm_grouped_workspace(int count, const ddqd_gemm_desc* d) {
+  if (check_descs(count, d)) return SIZE_MAX;
+  return grouped_ws(count, d);
+}
+
+int dd_gemm_grouped(int count, const ddqd_gemm_desc* d, void* ws, size_t ws_bytes,
+                    void* stream) {
+  g_msg[0] = 0;
+  int rc;
+  if ((rc = check_descs(count, d))) return rc;
+  if (count == 0) return DDQD_OK;
   // no output may overlap any input or any other output of the group
   for (int i = 0; i < count; i++) {
     const ddqd_gemm_desc& x = d[i];
@@ -544,27 +613,60 @@ int dd_gemm_grouped(int count, const ddqd_gemm_desc* d, void* stream) {
         return set_error(DDQD_E_ALIAS, "outputs of problems %d and %d overlap", i, j);
     }
   }
+  const size_t need = grouped_ws(count, d);
+  if (need > ws_bytes || (need > 0 && !ws))
+    return set_error(DDQD_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
+                     ws_bytes);
+  if (need > 0 && (uintptr_t)ws % 8) return set_error(DDQD_E_WORKSPACE, "workspace misaligned");
   if ((rc = device_ok())) return rc;
-  for (int c0 = 0; c0 < count; c0 += kMaxGroup) {
+  hipStream_t s = (hipStream_t)stream;
+  // FMA problems (and every C := beta C): persistent Block launches of up to
+  // kMaxGroup problems
+  std::vector<GemmBatch> fma;
+  for (int i = 0; i < count; i++)
+    if (d[i].m > 0 && d[i].n > 0 && !desc_ozaki(d[i])) fma.push_back(desc_batch(d[i]));
+  for (size_t c0 = 0; c0 < fma.size(); c0 += kMaxGroup) {
     GroupArgs ga;
     ga.count = 0;
     ga.start[0] = 0;
-    for (int i = c0; i < count && i < c0 + kMaxGroup; i++) {
-      const ddqd_gemm_desc& x = d[i];
-      if (x.m == 0 || x.n == 0) continue;
-      GemmBatch g{x.m, x.n, x.l, x.alpha, x.beta, CMat{x.A, x.lda, x.psa, 0},
-                  CMat{x.B, x.ldb, x.psb, 0}, Mat{x.C, x.ldc, x.psc, 0}, 1};
-      if (x.l == 0) {  // C := beta C: the empty K loop reads nothing from A or B
-        g.A = CMat{x.C, x.ldc, x.psc, 0};
-        g.B = g.A;
-      }
-      ga.g[ga.count] = g;
-      ga.start[ga.count + 1] = ga.start[ga.count] + dd_block_tiles(x.m, x.n);
+    for (size_t i = c0; i < fma.size() && i < c0 + kMaxGroup; i++) {
+      ga.g[ga.count] = fma[i];
+      ga.start[ga.count + 1] = ga.start[ga.count] + dd_block_tiles(fma[i].m, fma[i].n);
       ga.count++;
     }
     const int64_t tiles = ga.start[ga.count];
     const int grid = (int)(tiles < 512 ? tiles : 512);
-    if ((rc = launch_dd_grouped(ga, grid, (hipStream_t)stream))) return rc;
+    if ((rc = launch_dd_grouped(ga, grid, s))) return rc;
+  }
+  // Ozaki problems: grouped launches per slice count, each problem with its
+  // own part of the workspace (laid out slice count by slice count, in the
+  // order of the descriptors); longer K as products of their own
+  char* w = (char*)ws;
+  size_t off = 0;
+  std::vector<int> done(count, 0);
+  for (int i = 0; i < count; i++) {
+    if (!desc_ozaki(d[i]) || done[i]) continue;
+    const int S = desc_slices(d[i]);
+    std::vector<GemmBatch> grp;
+    const size_t off0 = off;
+    for (int j = i; j < count; j++) {
+      if (!desc_ozaki(d[j]) || done[j] || desc_slices(d[j]) != S ||
+          d[j].l > kGroupedOzakiMaxL)
+        continue;
+      grp.push_back(desc_batch(d[j]));
+      off += desc_ozaki_bytes(d[j]);
+      done[j] = 1;
+    }
+    if (!grp.empty() &&
+        (rc = launch_ozaki_grouped(grp.data(), (int)grp.size(), S, w + off0, off - off0, s)))
+      return rc;
+  }
+  for (int i = 0; i < count; i++) {
+    if (!desc_ozaki(d[i]) || done[i]) continue;
+    const size_t b = desc_ozaki_bytes(d[i]);
+    GemmBatch g = desc_batch(d[i]);
+    if ((rc = launch_ozaki(2, g, d[i].slices, w + off, b, s))) return rc;
+    off += b;
   }
   return DDQD_OK;
 }

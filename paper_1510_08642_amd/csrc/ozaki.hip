@@ -54,20 +54,13 @@ size_t align256(size_t x) { return oz_align256(x); }
 // slices of its two row blocks of A and two column blocks of B; wave w loads
 // group w), double-buffered.  Each wave then holds its S B fragments in
 // registers and reads one A fragment at a time from LDS.
+// Tile (tm, tn) of batch entry b (the kernels below pick the tile).
 template <int S>
-__global__ __launch_bounds__(256) void oz_gemm_kernel(GemmBatch g, OzLayout o,
-                                                      const signed char* Asl,
-                                                      const signed char* Bsl, const int* ea,
-                                                      const int* fb, int64_t tiles_m,
-                                                      int64_t tiles_n, int64_t kc0, int64_t kc1,
-                                                      int beta) {
-  __shared__ v4i lds[2][4 * S][64];
-
-  const int64_t t = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
-  const int64_t per = tiles_m * tiles_n;
-  const int64_t b = t / per;
-  int64_t tm, tn;
-  banded_tile(t % per, tiles_m, tiles_n, 4, tm, tn);
+__device__ __forceinline__ void oz_gemm_tile(const GemmBatch& g, const OzLayout& o,
+                                             const signed char* Asl, const signed char* Bsl,
+                                             const int* ea, const int* fb, int64_t b,
+                                             int64_t tm, int64_t tn, int64_t kc0, int64_t kc1,
+                                             int beta, v4i (&lds)[2][4 * S][64]) {
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int wr = w / 2, wc = w % 2;
   const int64_t rb = 2 * tm + wr, cb = 2 * tn + wc;
@@ -222,6 +215,51 @@ __global__ __launch_bounds__(256) void oz_gemm_kernel(GemmBatch g, OzLayout o,
 }
 
 template <int S>
+__global__ __launch_bounds__(256) void oz_gemm_kernel(GemmBatch g, OzLayout o,
+                                                      const signed char* Asl,
+                                                      const signed char* Bsl, const int* ea,
+                                                      const int* fb, int64_t tiles_m,
+                                                      int64_t tiles_n, int64_t kc0, int64_t kc1,
+                                                      int beta) {
+  __shared__ v4i lds[2][4 * S][64];
+  const int64_t t = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
+  const int64_t per = tiles_m * tiles_n;
+  int64_t tm, tn;
+  banded_tile(t % per, tiles_m, tiles_n, 4, tm, tn);
+  oz_gemm_tile<S>(g, o, Asl, Bsl, ea, fb, t / per, tm, tn, kc0, kc1, beta, lds);
+}
+
+// The products of a group: problem q owns tiles [ga.tile[q], ga.tile[q+1])
+// of the concatenated list, each computed exactly as by oz_gemm_kernel (one
+// K chunk: every problem of a group has l <= 16384).
+template <int S>
+__global__ __launch_bounds__(256) void oz_gemm_grouped_kernel(OzGroupArgs ga) {
+  __shared__ v4i lds[2][4 * S][64];
+  const int64_t t = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
+  const int q = oz_group_find(ga.tile, ga.count, t);
+  const OzProb& p = ga.p[q];
+  const int64_t tiles_m = p.o.rb / 2, tiles_n = p.o.cb / 2;
+  int64_t tm, tn;
+  banded_tile(t - ga.tile[q], tiles_m, tiles_n, 4, tm, tn);
+  oz_gemm_tile<S>(p.g, p.o, p.w.Asl, p.w.Bsl, p.w.ea, p.w.fb, 0, tm, tn, 0, p.o.kb, p.g.beta,
+                  lds);
+}
+
+template <int S>
+int run_ozaki_grouped(const OzGroupArgs& ga, hipStream_t s) {
+  int rc;
+  if ((rc = launch_oz_exponents_grouped(ga, s))) return rc;
+  if ((rc = launch_oz_slice_grouped(ga, S, s))) return rc;
+  const int64_t nblk = ga.tile[ga.count];
+  if (nblk <= 0) return DDQD_OK;
+  if (nblk > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "group too large");
+  prof_begin(s);
+  hipLaunchKernelGGL(oz_gemm_grouped_kernel<S>, dim3((unsigned)nblk), dim3(256), 0, s, ga);
+  prof_record("oz_gemm_grouped_kernel", s);
+  return check_launch("oz_gemm_grouped_kernel");
+}
+
+template <int S>
 int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
   OzLayout o = oz_layout(2, g.m, g.n, g.l, S);
   const OzWs w = oz_ws(ws, o, g.batch);
@@ -268,6 +306,62 @@ static size_t ozaki_dd_workspace(int64_t m, int64_t n, int64_t l, int64_t batch,
 size_t ozaki_workspace(int P, int64_t m, int64_t n, int64_t l, int64_t batch, int slices) {
   return P == 4 ? ozaki_qd_workspace(m, n, l, batch, slices)
                 : ozaki_dd_workspace(m, n, l, batch, slices);
+}
+
+// Workspace of the grouped form for one problem (DD, one K chunk) at S slices.
+size_t ozaki_grouped_bytes(const GemmBatch& g, int S) {
+  return oz_align256(oz_workspace_bytes(oz_layout(2, g.m, g.n, g.l, S), 1));
+}
+
+// Unrelated DD products (batch = 1 each, 0 < l <= 16384) at S slices in
+// launches of up to kOzGroup problems: one exponent, one slicing and one
+// product launch per group.  ws holds ozaki_grouped_bytes of every problem,
+// in order.
+int launch_ozaki_grouped(const GemmBatch* probs, int count, int S, char* ws, size_t ws_bytes,
+                         hipStream_t s) {
+  if (S < kMinS || S > kMaxS)
+    return set_error(DDQD_E_UNSUPPORTED, "Ozaki slices must be in %d..%d", kMinS, kMaxS);
+  size_t off = 0;
+  for (int c0 = 0; c0 < count; c0 += kOzGroup) {
+    OzGroupArgs ga;
+    ga.count = 0;
+    ga.wg[0] = ga.chunk[0] = ga.tile[0] = 0;
+    for (int i = c0; i < count && i < c0 + kOzGroup; i++) {
+      const GemmBatch& g = probs[i];
+      if (g.l > kKChunk) return set_error(DDQD_E_UNSUPPORTED, "grouped Ozaki product with l > %lld",
+                                          (long long)kKChunk);
+      OzProb& p = ga.p[ga.count];
+      p.g = g;
+      p.o = oz_layout(2, g.m, g.n, g.l, S);
+      const size_t need = ozaki_grouped_bytes(g, S);
+      if (off + need > ws_bytes) return set_error(DDQD_E_WORKSPACE, "grouped Ozaki workspace");
+      p.w = oz_ws((char*)ws + off, p.o, 1);
+      off += need;
+      const int c = ga.count++;
+      ga.wg[c + 1] = ga.wg[c] + oz_exp_wgs(p.o);
+      ga.chunk[c + 1] = ga.chunk[c] + oz_slice_chunks(p.o);
+      ga.tile[c + 1] = ga.tile[c] + (p.o.rb / 2) * (p.o.cb / 2);
+    }
+    if (ga.count == 0) continue;
+    int rc;
+    switch (S) {
+      case 8: rc = run_ozaki_grouped<8>(ga, s); break;
+      case 9: rc = run_ozaki_grouped<9>(ga, s); break;
+      case 10: rc = run_ozaki_grouped<10>(ga, s); break;
+      case 11: rc = run_ozaki_grouped<11>(ga, s); break;
+      case 12: rc = run_ozaki_grouped<12>(ga, s); break;
+      case 13: rc = run_ozaki_grouped<13>(ga, s); break;
+      case 14: rc = run_ozaki_grouped<14>(ga, s); break;
+      case 15: rc = run_ozaki_grouped<15>(ga, s); break;
+      case 16: rc = run_ozaki_grouped<16>(ga, s); break;
+      case 17: rc = run_ozaki_grouped<17>(ga, s); break;
+      case 18: rc = run_ozaki_grouped<18>(ga, s); break;
+      case 19: rc = run_ozaki_grouped<19>(ga, s); break;
+      default: rc = run_ozaki_grouped<20>(ga, s); break;
+    }
+    if (rc) return rc;
+  }
+  return DDQD_OK;
 }
 
 int launch_ozaki(int P, const GemmBatch& g, int slices, void* ws, size_t ws_bytes,

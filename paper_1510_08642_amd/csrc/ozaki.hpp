@@ -61,6 +61,41 @@ inline OzWs oz_ws(char* ws, const OzLayout& o, int64_t batch) {
   return w;
 }
 
+// Unrelated DD Ozaki products of one grouped launch (kernel argument, under
+// the 4 KB limit): each problem with its own layout and workspace; the
+// prefix sums give problem p the exponent workgroups [wg[p], wg[p+1]), the
+// slicing chunks [chunk[p], chunk[p+1]) and the product tiles
+// [tile[p], tile[p+1]) of the concatenated lists.
+constexpr int kOzGroup = 12;
+struct OzProb {
+  GemmBatch g;  // batch = 1
+  OzLayout o;
+  OzWs w;
+};
+struct OzGroupArgs {
+  int count;
+  OzProb p[kOzGroup];
+  int64_t wg[kOzGroup + 1], chunk[kOzGroup + 1], tile[kOzGroup + 1];
+};
+static_assert(sizeof(OzGroupArgs) <= 4096, "kernel argument limit");
+
+// Problem q of a grouped launch owning item x of the prefix sums `start`.
+__device__ __forceinline__ int oz_group_find(const int64_t* start, int count, int64_t x) {
+  int q = 0;
+  while (q + 1 < count && x >= start[q + 1]) q++;
+  return q;
+}
+
+// Exponent workgroups and slicing chunks of one product (grouped launches).
+inline int64_t oz_exp_wgs(const OzLayout& o) {
+  return (o.rb * 32 + 3) / 4 + ((o.cb * 32 + 63) / 64) * o.kb;
+}
+inline int64_t oz_slice_chunks(const OzLayout& o) { return (o.rb + o.cb) * ((o.kb + 1) / 2); }
+
+// The three launches of a group (exponents, slicing, products), P = 2.
+int launch_oz_exponents_grouped(const OzGroupArgs& ga, hipStream_t s);
+int launch_oz_slice_grouped(const OzGroupArgs& ga, int S, hipStream_t s);
+
 // Exponents e with max |leading component| < 2^(e - 1): of A's rows into
 // w.ea (an all-zero row, and every padded row, gets 1: its digits are all
 // zero, so any exponent gives the same result), and of B's columns per 32-row

@@ -26,14 +26,15 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 // column maximum; the slicing kernel reduces them.
 constexpr int kNoExp = -(1 << 20);
 
-__global__ __launch_bounds__(256) void oz_exp_kernel(CMat A, CMat B, int64_t m, int64_t n,
-                                                     int64_t l, OzLayout o, int64_t nrow,
-                                                     int* ea, int* part) {
-  const int64_t b = blockIdx.y;
+// Workgroup `bid` of the exponent pass of batch entry b (see oz_exp_kernel).
+__device__ __forceinline__ void oz_exp_body(const CMat& A, const CMat& B, int64_t m, int64_t n,
+                                            int64_t l, const OzLayout& o, int64_t nrow, int* ea,
+                                            int* part, int64_t b, int64_t bid,
+                                            double (&red)[4][64]) {
   const int lane = threadIdx.x % 64;
-  if ((int64_t)blockIdx.x < nrow) {
+  if (bid < nrow) {
     const int64_t rows_pad = o.rb * 32;
-    const int64_t r = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    const int64_t r = bid * 4 + threadIdx.x / 64;
     if (r >= rows_pad) return;
     double mx = 0.0;
     if (r < m) {
@@ -56,10 +57,9 @@ __global__ __launch_bounds__(256) void oz_exp_kernel(CMat A, CMat B, int64_t m, 
     }
     return;
   }
-  __shared__ double red[4][64];
   const int64_t cols_pad = o.cb * 32;
   const int64_t ncb = (cols_pad + 63) / 64;
-  const int64_t jb = (int64_t)blockIdx.x - nrow;
+  const int64_t jb = bid - nrow;
   const int64_t slab = jb / ncb;
   const int c_in = threadIdx.x % 64, r = threadIdx.x / 64;
   const int64_t c = (jb % ncb) * 64 + c_in;
@@ -84,6 +84,23 @@ __global__ __launch_bounds__(256) void oz_exp_kernel(CMat A, CMat B, int64_t m, 
     }
     part[(b * o.kb + slab) * cols_pad + c] = ex;
   }
+}
+
+__global__ __launch_bounds__(256) void oz_exp_kernel(CMat A, CMat B, int64_t m, int64_t n,
+                                                     int64_t l, OzLayout o, int64_t nrow,
+                                                     int* ea, int* part) {
+  __shared__ double red[4][64];
+  oz_exp_body(A, B, m, n, l, o, nrow, ea, part, blockIdx.y, blockIdx.x, red);
+}
+
+// The exponent passes of a group's problems: problem q takes workgroups
+// [ga.wg[q], ga.wg[q+1]).
+__global__ __launch_bounds__(256) void oz_exp_grouped_kernel(OzGroupArgs ga) {
+  __shared__ double red[4][64];
+  const int q = oz_group_find(ga.wg, ga.count, blockIdx.x);
+  const OzProb& p = ga.p[q];
+  oz_exp_body(p.g.A, p.g.B, p.g.m, p.g.n, p.g.l, p.o, (p.o.rb * 32 + 3) / 4, p.w.ea, p.w.part,
+              0, (int64_t)blockIdx.x - ga.wg[q], red);
 }
 
 // Column exponents of B's 32 columns line0.. of batch entry b: the maximum of
@@ -180,6 +197,106 @@ __device__ __forceinline__ void slice_load(const CMat& A, const CMat& B, int64_t
   }
 }
 
+// The digits of chunk `cur` of batch entry b, whose values (unscaled) are in
+// `tile`; xc is scratch for B's column exponents.  All 256 threads take part.
+template <int P, int S>
+__device__ __forceinline__ void slice_digits(const OzLayout& o, const int* ea, const int* part,
+                                             int* fb, signed char* Asl, signed char* Bsl,
+                                             int64_t b, const SliceChunk& cur,
+                                             double (&tile)[P][32][kSliceK + 1], int* xc) {
+  const int t = threadIdx.x, w = t / 64, lane = t % 64;
+  const int64_t line0 = cur.blk * 32;
+  // uniform per workgroup
+  if (cur.side == 1) col_exponents(o, part, fb, b, line0, cur.kg == 0, xc);
+  const int64_t kb = cur.kg * 2 + w / 2;
+  if (kb >= o.kb) return;  // past the last K block (no barrier follows in this pass)
+  const int half = w % 2;
+  const int ln = lane % 32, k0 = (w / 2) * 32 + 16 * (lane / 32) + 8 * half;
+  const int ex = cur.side == 0 ? ea[b * (o.rb * 32) + line0 + ln] : xc[ln];
+  double r[P][8];
+#pragma unroll
+  for (int q = 0; q < 8; q++)
+#pragma unroll
+    for (int p = 0; p < P; p++) r[p][q] = ldexp(tile[p][ln][k0 + q], -ex);
+  // an input whose terms overlap is brought into shape first (exact)
+#pragma unroll
+  for (int q = 0; q < 8; q++) {
+    if constexpr (P == 2) {
+      two_sum(r[0][q], r[1][q], r[0][q], r[1][q]);
+    } else {
+      double a2, a3, a1, b2, a0, b1;
+      two_sum(r[2][q], r[3][q], a2, a3);
+      two_sum(r[1][q], a2, a1, b2);
+      two_sum(r[0][q], a1, a0, b1);
+      r[0][q] = a0;
+      r[1][q] = b1;
+      r[2][q] = b2;
+      r[3][q] = a3;
+    }
+  }
+  signed char* dst = (cur.side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
+                     (cur.blk * o.kb + kb) * S * (int64_t)kOzFrag + lane * 16 + 8 * half;
+#pragma unroll 1
+  for (int s0 = 0; s0 < S; s0 += kRun) {
+    uint32_t prev[8];
+    double tl[8];  // t_j of the run's last digit
+#pragma unroll
+    for (int q = 0; q < 8; q++) prev[q] = 0u;
+#pragma unroll
+    for (int j = 0; j < kRun; j++) {
+      if (s0 + j < S) {
+        const double magic = kMagic[j];
+        uint32_t x[2] = {0u, 0u};
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+          const double tq = r[0][q] + magic;
+          const uint32_t nj = (uint32_t)__builtin_bit_cast(uint64_t, tq);
+          const uint32_t d = nj - (prev[q] << 7);
+          prev[q] = nj;
+          tl[q] = tq;
+          x[q / 4] |= (d & 0xffu) << (8 * (q % 4));
+        }
+        *reinterpret_cast<uint2*>(dst + (s0 + j) * (int64_t)kOzFrag) = uint2{x[0], x[1]};
+      }
+    }
+    if (s0 + kRun >= S) break;  // no digits left: the remainder is not needed
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      const double rem = (r[0][q] - (tl[q] - kMagic[kRun - 1])) * 0x1p42;
+      if constexpr (P == 2) {
+        fast_two_sum(rem, r[1][q] * 0x1p42, r[0][q], r[1][q]);
+      } else {
+        // remainder rem + 2^42 (r1 + r2 + r3), all terms exact; one bottom-up
+        // TwoSum pass keeps the sum and brings it to the front
+        double a2, a3, a1, b2, a0, b1;
+        two_sum(r[2][q] * 0x1p42, r[3][q] * 0x1p42, a2, a3);
+        two_sum(r[1][q] * 0x1p42, a2, a1, b2);
+        two_sum(rem, a1, a0, b1);
+        r[0][q] = a0;
+        r[1][q] = b1;
+        r[2][q] = b2;
+        r[3][q] = a3;
+      }
+    }
+  }
+}
+
+// The loaded values of a chunk into the LDS tile (after a barrier that every
+// reader of the previous chunk has passed).
+template <int P>
+__device__ __forceinline__ void slice_to_tile(const SliceChunk& c, const double (&v)[P][8],
+                                              double (&tile)[P][32][kSliceK + 1]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    const int e = t + 256 * j;
+    const int ln = c.side == 0 ? e / kSliceK : e % 32;
+    const int kk = c.side == 0 ? e % kSliceK : e / 32;
+#pragma unroll
+    for (int q = 0; q < P; q++) tile[q][ln][kk] = v[q][j];
+  }
+}
+
 template <int P, int S>
 __global__ __launch_bounds__(256) void oz_slice_kernel(CMat A, CMat B, int64_t m, int64_t n,
                                                        int64_t l, OzLayout o, const int* ea,
@@ -190,7 +307,6 @@ __global__ __launch_bounds__(256) void oz_slice_kernel(CMat A, CMat B, int64_t m
   const int64_t b = blockIdx.z;
   const int64_t kgroups = (o.kb + 1) / 2;
   const int64_t nchunks = (o.rb + o.cb) * kgroups;
-  const int t = threadIdx.x, w = t / 64, lane = t % 64;
   int64_t ch = blockIdx.x;
   if (ch >= nchunks) return;  // uniform per workgroup
   double v[P][8];
@@ -198,94 +314,48 @@ __global__ __launch_bounds__(256) void oz_slice_kernel(CMat A, CMat B, int64_t m
   slice_load<P>(A, B, m, n, l, b, c, v);
   for (; ch < nchunks; ch += gridDim.x) {
     __syncthreads();  // the previous chunk's readers of tile and xc are done
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const int e = t + 256 * j;
-      const int ln = c.side == 0 ? e / kSliceK : e % 32;
-      const int kk = c.side == 0 ? e % kSliceK : e / 32;
-#pragma unroll
-      for (int q = 0; q < P; q++) tile[q][ln][kk] = v[q][j];
-    }
+    slice_to_tile<P>(c, v, tile);
     __syncthreads();
     const SliceChunk cur = c;
     if (ch + gridDim.x < nchunks) {  // the next chunk's loads fly during the slicing
       c = slice_chunk(o, ch + gridDim.x, kgroups);
       slice_load<P>(A, B, m, n, l, b, c, v);
     }
-    const int64_t line0 = cur.blk * 32;
-    // uniform per workgroup
-    if (cur.side == 1) col_exponents(o, part, fb, b, line0, cur.kg == 0, xc);
-    const int64_t kb = cur.kg * 2 + w / 2;
-    if (kb >= o.kb) continue;  // past the last K block (no barrier follows in this pass)
-    const int half = w % 2;
-    const int ln = lane % 32, k0 = (w / 2) * 32 + 16 * (lane / 32) + 8 * half;
-    const int ex = cur.side == 0 ? ea[b * (o.rb * 32) + line0 + ln] : xc[ln];
-    double r[P][8];
-#pragma unroll
-    for (int q = 0; q < 8; q++)
-#pragma unroll
-      for (int p = 0; p < P; p++) r[p][q] = ldexp(tile[p][ln][k0 + q], -ex);
-    // an input whose terms overlap is brought into shape first (exact)
-#pragma unroll
-    for (int q = 0; q < 8; q++) {
-      if constexpr (P == 2) {
-        two_sum(r[0][q], r[1][q], r[0][q], r[1][q]);
-      } else {
-        double a2, a3, a1, b2, a0, b1;
-        two_sum(r[2][q], r[3][q], a2, a3);
-        two_sum(r[1][q], a2, a1, b2);
-        two_sum(r[0][q], a1, a0, b1);
-        r[0][q] = a0;
-        r[1][q] = b1;
-        r[2][q] = b2;
-        r[3][q] = a3;
-      }
+    slice_digits<P, S>(o, ea, part, fb, Asl, Bsl, b, cur, tile, xc);
+  }
+}
+
+// The slicing of a group's problems (DD): one persistent grid over the
+// concatenated chunk lists, problem q owning chunks [ga.chunk[q],
+// ga.chunk[q+1]); the same digits as the single product's launch.
+template <int S>
+__global__ __launch_bounds__(256) void oz_slice_grouped_kernel(OzGroupArgs ga) {
+  __shared__ double tile[2][32][kSliceK + 1];
+  __shared__ int xc[8 * 32];
+  const int64_t total = ga.chunk[ga.count];
+  int64_t G = blockIdx.x;
+  if (G >= total) return;  // uniform per workgroup
+  double v[2][8];
+  int q = oz_group_find(ga.chunk, ga.count, G);
+  SliceChunk c = slice_chunk(ga.p[q].o, G - ga.chunk[q], (ga.p[q].o.kb + 1) / 2);
+  {
+    const GemmBatch& g = ga.p[q].g;
+    slice_load<2>(g.A, g.B, g.m, g.n, g.l, 0, c, v);
+  }
+  for (; G < total; G += gridDim.x) {
+    __syncthreads();
+    slice_to_tile<2>(c, v, tile);
+    __syncthreads();
+    const SliceChunk cur = c;
+    const int qc = q;
+    if (G + gridDim.x < total) {
+      q = oz_group_find(ga.chunk, ga.count, G + gridDim.x);
+      c = slice_chunk(ga.p[q].o, G + gridDim.x - ga.chunk[q], (ga.p[q].o.kb + 1) / 2);
+      const GemmBatch& g = ga.p[q].g;
+      slice_load<2>(g.A, g.B, g.m, g.n, g.l, 0, c, v);
     }
-    signed char* dst = (cur.side == 0 ? Asl + b * o.a_bytes : Bsl + b * o.b_bytes) +
-                       (cur.blk * o.kb + kb) * S * (int64_t)kOzFrag + lane * 16 + 8 * half;
-#pragma unroll 1
-    for (int s0 = 0; s0 < S; s0 += kRun) {
-      uint32_t prev[8];
-      double tl[8];  // t_j of the run's last digit
-#pragma unroll
-      for (int q = 0; q < 8; q++) prev[q] = 0u;
-#pragma unroll
-      for (int j = 0; j < kRun; j++) {
-        if (s0 + j < S) {
-          const double magic = kMagic[j];
-          uint32_t x[2] = {0u, 0u};
-#pragma unroll
-          for (int q = 0; q < 8; q++) {
-            const double tq = r[0][q] + magic;
-            const uint32_t nj = (uint32_t)__builtin_bit_cast(uint64_t, tq);
-            const uint32_t d = nj - (prev[q] << 7);
-            prev[q] = nj;
-            tl[q] = tq;
-            x[q / 4] |= (d & 0xffu) << (8 * (q % 4));
-          }
-          *reinterpret_cast<uint2*>(dst + (s0 + j) * (int64_t)kOzFrag) = uint2{x[0], x[1]};
-        }
-      }
-      if (s0 + kRun >= S) break;  // no digits left: the remainder is not needed
-#pragma unroll
-      for (int q = 0; q < 8; q++) {
-        const double rem = (r[0][q] - (tl[q] - kMagic[kRun - 1])) * 0x1p42;
-        if constexpr (P == 2) {
-          fast_two_sum(rem, r[1][q] * 0x1p42, r[0][q], r[1][q]);
-        } else {
-          // remainder rem + 2^42 (r1 + r2 + r3), all terms exact; one bottom-up
-          // TwoSum pass keeps the sum and brings it to the front
-          double a2, a3, a1, b2, a0, b1;
-          two_sum(r[2][q] * 0x1p42, r[3][q] * 0x1p42, a2, a3);
-          two_sum(r[1][q] * 0x1p42, a2, a1, b2);
-          two_sum(rem, a1, a0, b1);
-          r[0][q] = a0;
-          r[1][q] = b1;
-          r[2][q] = b2;
-          r[3][q] = a3;
-        }
-      }
-    }
+    const OzProb& p = ga.p[qc];
+    slice_digits<2, S>(p.o, p.w.ea, p.w.part, p.w.fb, p.w.Asl, p.w.Bsl, 0, cur, tile, xc);
   }
 }
 
@@ -334,7 +404,46 @@ int slice_qd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s
   return check_launch("oz_slice_kernel");
 }
 
+template <int S>
+int slice_grouped(const OzGroupArgs& ga, hipStream_t s) {
+  const int64_t grid = std::min<int64_t>(ga.chunk[ga.count], kSliceWgs);
+  prof_begin(s);
+  hipLaunchKernelGGL((oz_slice_grouped_kernel<S>), dim3((unsigned)grid), dim3(256), 0, s, ga);
+  prof_record("oz_slice_grouped_kernel", s);
+  return check_launch("oz_slice_grouped_kernel");
+}
+
 }  // namespace
+
+int launch_oz_exponents_grouped(const OzGroupArgs& ga, hipStream_t s) {
+  const int64_t grid = ga.wg[ga.count];
+  if (grid <= 0) return DDQD_OK;
+  if (grid > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "group too large");
+  prof_begin(s);
+  hipLaunchKernelGGL(oz_exp_grouped_kernel, dim3((unsigned)grid), dim3(256), 0, s, ga);
+  prof_record("oz_exp_grouped_kernel", s);
+  return check_launch("oz_exp_grouped_kernel");
+}
+
+int launch_oz_slice_grouped(const OzGroupArgs& ga, int S, hipStream_t s) {
+  if (ga.chunk[ga.count] <= 0) return DDQD_OK;
+  switch (S) {
+    case 8: return slice_grouped<8>(ga, s);
+    case 9: return slice_grouped<9>(ga, s);
+    case 10: return slice_grouped<10>(ga, s);
+    case 11: return slice_grouped<11>(ga, s);
+    case 12: return slice_grouped<12>(ga, s);
+    case 13: return slice_grouped<13>(ga, s);
+    case 14: return slice_grouped<14>(ga, s);
+    case 15: return slice_grouped<15>(ga, s);
+    case 16: return slice_grouped<16>(ga, s);
+    case 17: return slice_grouped<17>(ga, s);
+    case 18: return slice_grouped<18>(ga, s);
+    case 19: return slice_grouped<19>(ga, s);
+    case 20: return slice_grouped<20>(ga, s);
+  }
+  return set_error(DDQD_E_UNSUPPORTED, "slices");
+}
 
 int launch_oz_slice(int P, const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s) {
   if (P == 2) {

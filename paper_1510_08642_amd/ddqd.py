@@ -59,12 +59,15 @@ _PREC = {2: "dd", 4: "qd"}
 class GemmDesc(ctypes.Structure):
     """ddqd_gemm_desc of include/ddqd.h."""
     _fields_ = [("m", _i64), ("n", _i64), ("l", _i64), ("alpha", _int), ("beta", _int),
+                ("base", _int), ("slices", _int),
                 ("A", _vp), ("lda", _i64), ("psa", _i64), ("B", _vp), ("ldb", _i64),
                 ("psb", _i64), ("C", _vp), ("ldc", _i64), ("psc", _i64)]
 
 
-_lib.dd_gemm_grouped.argtypes = [_int, ctypes.POINTER(GemmDesc), _vp]
+_lib.dd_gemm_grouped.argtypes = [_int, ctypes.POINTER(GemmDesc), _vp, _sz, _vp]
 _lib.dd_gemm_grouped.restype = _int
+_lib.dd_gemm_grouped_workspace.argtypes = [_int, ctypes.POINTER(GemmDesc)]
+_lib.dd_gemm_grouped_workspace.restype = _sz
 _lib.ddqd_profile_enable.argtypes = [_int]
 _lib.ddqd_profile_enable.restype = None
 _lib.ddqd_profile_reset.argtypes = []
@@ -298,23 +301,34 @@ def dd_getrs_noalloc(LU, ipiv, B, *, perm=None):
     return B
 
 
-def dd_gemm_grouped(problems, stream_of=None):
+def dd_gemm_grouped(problems, *, base="fma", slices=0, ws=None, stream_of=None):
     """Several unrelated DD products in grouped launches.
 
-    problems: list of (A, B, C, alpha, beta) with C preallocated.  Results are
-    bit-identical to dd_gemm(A, B, C, algo="block", base="fma")."""
+    problems: list of (A, B, C, alpha, beta) with C preallocated, or
+    (A, B, C, alpha, beta, base, slices) to give a problem its own base.
+    Each result is bit-identical to dd_gemm(A, B, C, algo="block", base=...,
+    slices=...)."""
     if not problems:
         return
     arr = (GemmDesc * len(problems))()
-    for i, (A, B, C, alpha, beta) in enumerate(problems):
+    for i, pr in enumerate(problems):
+        A, B, C, alpha, beta = pr[:5]
+        pbase, psl = (pr[5], pr[6]) if len(pr) > 5 else (base, slices)
         pa, lda, psa = _mat(A, 2, "A")
         pb, ldb, psb = _mat(B, 2, "B")
         pc, ldc, psc = _mat(C, 2, "C")
         if A.shape[2] != B.shape[1] or C.shape[1] != A.shape[1] or C.shape[2] != B.shape[2]:
             raise ValueError(f"problem {i}: shapes do not match")
-        arr[i] = GemmDesc(A.shape[1], B.shape[2], A.shape[2], alpha, beta, pa, lda, psa, pb, ldb,
-                          psb, pc, ldc, psc)
-    st = _lib.dd_gemm_grouped(len(problems), arr,
+        arr[i] = GemmDesc(A.shape[1], B.shape[2], A.shape[2], alpha, beta, BASE[pbase], psl,
+                          pa, lda, psa, pb, ldb, psb, pc, ldc, psc)
+    need = _lib.dd_gemm_grouped_workspace(len(problems), arr)
+    if need == SIZE_MAX:
+        raise ValueError("invalid grouped gemm arguments")
+    dev = problems[0][2].device
+    if need > 0 and (ws is None or ws.numel() < need):
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    st = _lib.dd_gemm_grouped(len(problems), arr, ws.data_ptr() if need > 0 else None,
+                              ws.numel() if need > 0 else 0,
                               _stream_of(problems[0][2]) if stream_of is None else stream_of)
     _check(st, "dd_gemm_grouped")
 

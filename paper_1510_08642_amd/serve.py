@@ -321,6 +321,11 @@ class OnlineServer:
 class GpuExecutor:
     """Runs requests with the HIP library on one GPU, one stream per slot.
 
+    Small products waiting together are merged into one grouped call on
+    either base (FMA: persistent Block launches; Ozaki: one exponent, one
+    slicing and one product launch per group), each result bit-identical to
+    the product run alone.
+
     Request inputs are views into device-resident pools (so a request's
     latency is queueing plus device work, not PCIe).  payload of a "gemm"
     request: (A, B) device DD tensors; of an "lu" request: (A, B) with A
@@ -342,7 +347,6 @@ class GpuExecutor:
         self.lu_panel, self.lu_algo, self.lu_levels = lu_panel, lu_algo, lu_levels
         self.keep_factors = keep_factors
         self.factors = {}
-        self.can_group = base == "fma"
         self._t0 = None
 
     # -- memory accounting -------------------------------------------------
@@ -380,7 +384,7 @@ class GpuExecutor:
                     C = torch.empty((2, r.n, r.n), dtype=torch.float64, device=self.dev)
                     probs.append((A, B, C, 1, 0))
                     outs.append(C)
-                dd.dd_gemm_grouped(probs)
+                dd.dd_gemm_grouped(probs, base=self.base)
             elif batch[0].kind == "gemm":
                 r = batch[0]
                 A, B = r.payload

@@ -240,3 +240,32 @@ def test_getrs_noalloc_argument_errors(lib):
     assert f(8193, 1, 0x10000, 8193, 8193 * 8193, 0x20000, None, 0x30000, 1, 8193,
              None) == E["UNSUPPORTED"]
     assert b"scratch limit" in lib.ddqd_last_error()
+
+
+def test_grouped_descriptor_errors_and_workspace(lib):
+    from paper_1510_08642_amd import ddqd
+    D = ddqd.GemmDesc
+    lib.dd_gemm_grouped_workspace.argtypes = [ctypes.c_int, ctypes.POINTER(D)]
+    lib.dd_gemm_grouped_workspace.restype = ctypes.c_size_t
+    lib.dd_gemm_grouped.argtypes = [ctypes.c_int, ctypes.POINTER(D), ctypes.c_void_p,
+                                    ctypes.c_size_t, ctypes.c_void_p]
+    SIZE_MAX = ctypes.c_size_t(-1).value
+
+    def desc(base=0, slices=0, m=64, n=64, l=64, A=0x100000, B=0x200000, C=0x300000):
+        return D(m, n, l, 1, 0, base, slices, A, l, m * l, B, n, l * n, C, n, m * n)
+    arr = (D * 2)(desc(), desc(base=1, A=0x400000, B=0x500000, C=0x600000))
+    # FMA problems need no workspace; an Ozaki one needs its slices
+    assert lib.dd_gemm_grouped_workspace(1, arr) == 0
+    need = lib.dd_gemm_grouped_workspace(2, arr)
+    assert need >= 2 * 16 * 64 * 64
+    assert lib.dd_gemm_grouped(2, arr, None, 0, None) == E["WORKSPACE"]
+    bad = (D * 1)(desc(base=3))
+    assert lib.dd_gemm_grouped_workspace(1, bad) == SIZE_MAX
+    assert lib.dd_gemm_grouped(1, bad, None, 0, None) == E["ARG"]
+    bad = (D * 1)(desc(base=1, slices=30))
+    assert lib.dd_gemm_grouped(1, bad, None, 0, None) == E["UNSUPPORTED"]
+    # an output overlapping another problem's input
+    alias = (D * 2)(desc(), desc(A=0x300000 + 64, C=0x700000))
+    assert lib.dd_gemm_grouped(2, alias, None, 0, None) == E["ALIAS"]
+    assert lib.dd_gemm_grouped(0, None, None, 0, None) == E["OK"]
+    assert lib.dd_gemm_grouped(-1, None, None, 0, None) == E["ARG"]

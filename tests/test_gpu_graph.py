@@ -124,3 +124,36 @@ def test_grouped_replay_matches_eager(dd):
             assert np.array_equal(to_host(p[2]), r), rep
         _noise(dd, g)
     graph.release()
+
+
+def test_grouped_ozaki_replay_matches_eager(dd):
+    """Grouped Ozaki products (exponents, slicing and products of several
+    problems) recorded with their workspace and replayed: every replay gives
+    the eager bits."""
+    import torch
+    print("case graph grouped ozaki", flush=True)
+    g = inputs.rng(321)
+    shapes = [(64, 80, 96), (130, 70, 33), (200, 200, 200), (1, 1, 1)]
+    probs = []
+    for m, n, l in shapes:
+        A = to_dev(inputs.dd_uniform(m, l, g))
+        B = to_dev(inputs.dd_uniform(l, n, g))
+        C = torch.empty((2, m, n), dtype=torch.float64, device="cuda")
+        probs.append((A, B, C, 1, 0, "ozaki", 0))
+    ws = torch.empty(1 << 22, dtype=torch.uint8, device="cuda")
+    dd.dd_gemm_grouped(probs, ws=ws)
+    torch.cuda.synchronize()
+    refs = [to_host(p[2]) for p in probs]
+    s = torch.cuda.Stream()
+    graph = dd.capture(lambda: dd.dd_gemm_grouped(probs, ws=ws, stream_of=s.cuda_stream), s)
+    for rep in range(3):
+        for p in probs:
+            p[2].fill_(float("nan"))
+        ws.fill_(7)
+        torch.cuda.synchronize()
+        graph.replay(s.cuda_stream)
+        s.synchronize()
+        for p, r in zip(probs, refs):
+            assert np.array_equal(to_host(p[2]), r), rep
+        _noise(dd, g)
+    graph.release()
