@@ -46,6 +46,12 @@ struct TrsmNodes {
   int r0[kTrsmNodesMax], nb[kTrsmNodesMax], x0[kTrsmNodesMax], nc[kTrsmNodesMax];
 };
 
+// Block rows of the triangular solves of getrs (DD, QD), and the flag words
+// their chained launches use: one per block row of the smaller block, and
+// one for the wait-limit record.
+constexpr int kTrsvBlockDD = 64, kTrsvBlockQD = 32;
+constexpr int64_t trsv_flag_words(int64_t n) { return (n + kTrsvBlockQD - 1) / kTrsvBlockQD + 1; }
+
 // Round-robin dispatch places workgroup b on XCD b % 8.  This permutation
 // gives each XCD one contiguous range of logical tiles, so tiles that share
 // operand panels share an L2.

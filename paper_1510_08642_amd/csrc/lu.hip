@@ -49,6 +49,7 @@ struct LuArith<2> {
   // bound on |x - leading term|
   __device__ static double tail(const T& x) { return fabs(x.lo); }
   __device__ static int abs_cmp(T x, T y) { return dd_abs_cmp(x, y); }
+  __device__ static T add(T a, T b) { return dd_add(a, b); }
   __device__ static T sub(T a, T b) { return dd_sub(a, b); }
   __device__ static T mul(T a, T b) { return dd_mul(a, b); }
   __device__ static T div(T a, T b) { return dd_div(a, b); }
@@ -123,6 +124,7 @@ struct LuArith<4> {
     const qd_t d = qd_sub(abs(x), abs(y));
     return (d.c[0] > 0.0) - (d.c[0] < 0.0);
   }
+  __device__ static T add(T a, T b) { return qd_add(a, b); }
   __device__ static T sub(T a, T b) { return qd_sub(a, b); }
   __device__ static T mul(T a, T b) { return qd_mul(a, b); }
   __device__ static T mul_d(T a, double q) { return qd_mul(a, T{{q, 0.0, 0.0, 0.0}}); }
@@ -285,6 +287,27 @@ __device__ __forceinline__ typename LuArith<P>::T readlane_num(const typename Lu
 #pragma unroll
   for (int c = 0; c < P; c++) LuArith<P>::put(r, c, readlane_f64(LuArith<P>::get(v, c), k));
   return r;
+}
+// lane k's accumulator as a number, in every lane, for a triangular solve's
+// next step.  DD: the pair (w0, w1) as it is, unnormalised (its sum is the
+// value; a product with it drops only the low word's cross term with the
+// other factor's low part, which leaves it accurate relative to the partial
+// sums), keeping the normalisation off the step-to-step chain.  QD: the
+// normalised value (a product reads the components as terms of decreasing
+// order).
+template <int P>
+__device__ __forceinline__ typename LuArith<P>::T readlane_words(const typename LuArith<P>::Acc& a,
+                                                                 int k);
+template <int P>
+__device__ __forceinline__ typename LuArith<P>::T readlane_acc(const typename LuArith<P>::Acc& a,
+                                                               int k);
+template <>
+__device__ __forceinline__ dd_t readlane_words<2>(const LuArith<2>::Acc& a, int k) {
+  return dd_t{readlane_f64(a.w[0], k), readlane_f64(a.w[1], k)};
+}
+template <>
+__device__ __forceinline__ qd_t readlane_words<4>(const LuArith<4>::Acc& a, int k) {
+  return readlane_acc<4>(a, k);
 }
 // the value held by lane k's accumulator, in every lane
 template <int P>
@@ -866,13 +889,14 @@ __global__ void perm_from_ipiv_kernel(const int32_t* ipiv, int64_t n, int32_t* p
   }
 }
 
-// X[i][:] = B[perm[i]][:] (X tight, n x nrhs, P planes)
+// X[i][:] = B[perm[i]][:] (X tight, n x nrhs, P planes); also clears the
+// nflags block flags of the two triangular solves that follow.
 __global__ __launch_bounds__(256) void gather_rows_kernel(const double* B, int64_t ldb,
                                                           int64_t psb, int P, const int32_t* perm,
                                                           int64_t n, int64_t nrhs, double* X,
-                                                          int* done) {
+                                                          int* flags, int nflags) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e == 0) atomicExch(done, 0);  // trsv_block_kernel's counter starts at zero
+  if (e < nflags) flags[e] = 0;
   if (e >= n * nrhs) return;
   const int64_t i = e / nrhs, c = e % nrhs;
   const int64_t src = (int64_t)perm[i] * ldb + c;
@@ -888,155 +912,190 @@ __global__ __launch_bounds__(256) void scatter_rows_kernel(const double* X, int6
   for (int q = 0; q < P; q++) B[q * psb + i * ldb + c] = X[q * n * nrhs + e];
 }
 
-// block size of the blocked triangular solves (LDS: two tiles per plane)
+// block size of the blocked triangular solves
 template <int P>
 constexpr int trsv_block() {
-  return P == 2 ? 64 : 32;
+  return P == 2 ? kTrsvBlockDD : kTrsvBlockQD;
 }
 
-// Forward (lower, unit) or backward (upper) step for block I of X (n x nrhs,
-// nrhs <= 16).  Every workgroup solves the diagonal block redundantly (one
-// wave per right-hand side, lane = row) from X_I as it is in memory, and every
-// workgroup W != I updates its rows X_W -= T_WI X_I.  X_I is stored by the
-// last workgroup to have read it: each one counts itself in *done once its
-// loads of X_I have returned, and the one that completes the count stores and
-// resets it (a workgroup dispatched late, behind other work on the device,
-// must not find X_I already solved).  The diagonal
-// block, T_WI, X_I and X_W are all requested from memory before any of them
-// is used (one round trip), and staged in LDS.  In the solve, lane i keeps
-// x_i as an accumulator; step k finishes x_k, broadcasts it with readlane,
-// and the other lanes subtract T_ik x_k.  The backward solve multiplies by
-// the diagonal's reciprocals, formed by all lanes at once before the
-// sequential steps begin.
-// Lower: blocks W > I are blockIdx.x + 1 + I; upper: W = blockIdx.x - 1 ... .
+// Longest wait for a block another workgroup solves (100 MHz ticks: 2 s).
+// Reached only if that workgroup never runs; the solve then finishes with
+// wrong values instead of hanging, and records it in the flag word after the
+// block flags.
+constexpr uint64_t kTrsvWaitTicks = 200000000ull;
+constexpr int kTrsvWgs = 32;  // workgroups of one triangular solve launch
+
+// One triangle of X := T^-1 X (unit lower, or upper with its diagonal; X is
+// n x nrhs, nrhs <= 16, tight) in one launch of G <= kTrsvWgs workgroups:
+// workgroup w solves the block rows of TB rows in steps s = w, w + G, ...,
+// step s being block row I = s (lower) or nb - 1 - s (upper).  It first applies, in the
+// order they are solved, every block J it depends on (J < I lower, J > I
+// upper): it stages T_IJ while it waits for J's flag, then forms
+// sum_k T_IJ[i][k] X_J[k][c] with tpe threads per entry (each a slice of k
+// accumulated lazily, the slices summed in a fixed butterfly) and subtracts
+// it from its entry of X_I.  Then it solves the diagonal block (one wave per
+// right-hand side, lane = row: step k finishes x_k, broadcasts it with
+// readlane, the other lanes subtract T_ik x_k; the upper solve multiplies by
+// reciprocals of the diagonal formed by all lanes at once), stores X_I and
+// publishes it: flag[I] := tag (1 lower, 2 upper) with release semantics at
+// device scope, after the values were stored with device-coherent stores;
+// readers acquire the flag and load the values device-coherently.  Step s
+// waits only for earlier steps, so the chain progresses once every
+// workgroup of the launch has been dispatched (a few dozen workgroups: a
+// handful of concurrent solves cannot fill the device with waiting ones).
+// The accumulation order is fixed: the result does not depend on timing.
 template <int P>
-__global__ __launch_bounds__(1024) void trsv_block_kernel(const double* T, int64_t ldt,
+__global__ __launch_bounds__(1024) void trsv_chain_kernel(const double* T, int64_t ldt,
                                                           int64_t pst, double* X, int64_t n,
-                                                          int64_t nrhs, int64_t I, int upper,
-                                                          int* done) {
+                                                          int64_t nrhs, int upper, int* flags) {
   using N = LuArith<P>;
   using V = typename N::T;
   constexpr int TB = trsv_block<P>();
-  __shared__ double Ts[P][TB][TB + 1];
-  __shared__ double Ws[P][TB][TB + 1];
-  __shared__ double Xs[P][TB][17];
-  __shared__ int s_last;
-  const int64_t nb = (n + TB - 1) / TB;
-  const int64_t Wb = upper ? (I - (int64_t)blockIdx.x) : (I + (int64_t)blockIdx.x);
-  // The workgroups that take part (and count themselves in *done) are those
-  // whose block Wb exists: blockIdx.x < I + 1 (upper) or < nb - I (lower).
-  // Any further workgroups of a larger grid return here without counting.
-  const int64_t in_range = upper ? I + 1 : nb - I;
-  const int members = (int)(in_range < (int64_t)gridDim.x ? in_range : (int64_t)gridDim.x);
-  if (Wb < 0 || Wb >= nb) return;
-  const int64_t i0 = I * TB, w0 = Wb * TB;
-  const int rows = (int)(n - i0 < TB ? n - i0 : TB);
-  const int wrows = (int)(n - w0 < TB ? n - w0 : TB);
-  const bool upd = Wb != I;
-  const int t = threadIdx.x, lane = t % 64, wave = t / 64;
-  const int nr = (int)nrhs;
-  const int64_t psx = n * nrhs;
   constexpr int kPer = (TB * TB + 1023) / 1024;  // tile elements per thread
-  double dv[kPer][P], ov[kPer][P];
+  __shared__ double Ws[P][TB][TB + 1];            // T_IJ, then the diagonal block
+  __shared__ double Ys[P][TB][17];                // X_J, then X_I
+  const int64_t nb = (n + TB - 1) / TB;
+  for (int64_t s = blockIdx.x; s < nb; s += gridDim.x) {
+    const int64_t I = upper ? nb - 1 - s : s;
+    const int tag = upper ? 2 : 1;
+    const int64_t i0 = I * TB;
+    const int rows = (int)(n - i0 < TB ? n - i0 : TB);
+    const int t = threadIdx.x, lane = t % 64, wave = t / 64;
+    const int nr = (int)nrhs;
+    const int64_t psx = n * nrhs;
+    // threads per entry of X_I in the updates: a power of two <= 16 (lanes of
+    // one wave) with rows * nr * tpe <= 1024
+    int tpe = 1;
+    while (tpe < 16 && rows * nr * tpe * 2 <= 1024) tpe *= 2;
+    const int ent = t / tpe, slice = t % tpe;
+    const int ui = nr > 0 ? ent / nr : 0, uc = nr > 0 ? ent % nr : 0;
+    const bool uin = ent < rows * nr;
+    V x = N::zero();
+    if (uin)
 #pragma unroll
-  for (int j = 0; j < kPer; j++) {
-    const int e = t + 1024 * j, i = e / TB, k = e % TB;
-    const bool in = e < TB * TB && i < rows && k < rows;
-    const int64_t o = (i0 + (in ? i : 0)) * ldt + i0 + (in ? k : 0);
-    const bool win = e < TB * TB && upd && i < wrows && k < rows;
-    const int64_t ow = (w0 + (win ? i : 0)) * ldt + i0 + (win ? k : 0);
+      for (int c = 0; c < P; c++) N::put(x, c, X[c * psx + (i0 + ui) * nrhs + uc]);
+
+    auto stage = [&](int64_t J, double (&v)[kPer][P]) {
+      const int64_t j0 = J * TB;
+      const int cols = (int)(n - j0 < TB ? n - j0 : TB);
 #pragma unroll
-    for (int c = 0; c < P; c++) {
-      dv[j][c] = in ? T[c * pst + o] : ((c == 0 && i == k) ? 1.0 : 0.0);
-      ov[j][c] = win ? T[c * pst + ow] : 0.0;
-    }
-  }
-  // X_I (as staged) and this thread's entry of X_W
-  const int xi = t / 16, xc = t % 16;
-  const bool xin = xi < rows && xc < nr;
-  double xiv[P];
+      for (int q = 0; q < kPer; q++) {
+        const int e = t + 1024 * q, i = e / TB, k = e % TB;
+        const bool in = e < TB * TB && i < rows && k < cols;
+        const int64_t o = (i0 + (in ? i : 0)) * ldt + j0 + (in ? k : 0);
 #pragma unroll
-  for (int c = 0; c < P; c++) xiv[c] = xin ? X[c * psx + (i0 + xi) * nrhs + xc] : 0.0;
-  const int ui = nr > 0 ? t / nr : 0, uc = nr > 0 ? t % nr : 0;
-  const bool uin = upd && t < wrows * nr;
-  const int64_t xo = (w0 + (uin ? ui : 0)) * nrhs + (uin ? uc : 0);
-  V xw = N::zero();
-  if (uin)
-#pragma unroll
-    for (int c = 0; c < P; c++) N::put(xw, c, X[c * psx + xo]);
-#pragma unroll
-  for (int j = 0; j < kPer; j++) {
-    const int e = t + 1024 * j, i = e / TB, k = e % TB;
-    if (e < TB * TB)
-#pragma unroll
-      for (int c = 0; c < P; c++) {
-        Ts[c][i][k] = dv[j][c];
-        Ws[c][i][k] = ov[j][c];
+        for (int c = 0; c < P; c++)
+          v[q][c] = in ? T[c * pst + o] : ((J == I && c == 0 && i == k) ? 1.0 : 0.0);
       }
-  }
-  if (xi < TB)
-#pragma unroll
-    for (int c = 0; c < P; c++) Xs[c][xi][xc] = xiv[c];
-  __syncthreads();
-  // every load of X_I has returned (its value is in LDS)
-  if (t == 0) s_last = atomicAdd(done, 1) == members - 1;
-  if (wave < nr) {
-    V xinit = N::zero();
-    if (lane < TB)
-#pragma unroll
-      for (int c = 0; c < P; c++) N::put(xinit, c, Xs[c][lane][wave]);
-    typename N::Acc acc = N::acc(xinit);
-    auto tval = [&](int i, int k) {
-      V r;
-#pragma unroll
-      for (int c = 0; c < P; c++) N::put(r, c, Ts[c][i][k]);
-      return r;
     };
-    if (!upper) {
-      for (int k = 0; k < rows - 1; k++) {
-        const V xk = readlane_acc<P>(acc, k);
-        if (lane > k && lane < rows) N::acc_sub(acc, tval(lane, k), xk);
+    auto to_lds = [&](const double (&v)[kPer][P]) {
+#pragma unroll
+      for (int q = 0; q < kPer; q++) {
+        const int e = t + 1024 * q, i = e / TB, k = e % TB;
+        if (e < TB * TB)
+#pragma unroll
+          for (int c = 0; c < P; c++) Ws[c][i][k] = v[q][c];
       }
-    } else {
-      // reciprocals of the diagonal, all lanes at once
-      const V inv = lane < rows ? N::div(N::one(), tval(lane, lane)) : N::zero();
-      for (int k = rows - 1; k >= 0; k--) {
-        const V xk = N::mul(readlane_acc<P>(acc, k), readlane_num<P>(inv, k));
-        if (lane == k)
-          acc = N::acc(xk);
-        else if (lane < k)
-          N::acc_sub(acc, tval(lane, k), xk);
+    };
+    double v[kPer][P], vd[kPer][P];
+    stage(I, vd);  // the diagonal block, needed last, requested first
+    for (int64_t d = 0; d < s; d++) {
+      const int64_t J = upper ? nb - 1 - d : d;
+      stage(J, v);  // the tile's loads fly while this workgroup waits for J
+      if (t == 0) {
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(flags + J, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != tag) {
+          __builtin_amdgcn_s_sleep(2);
+          if (__builtin_amdgcn_s_memrealtime() - t0 > kTrsvWaitTicks) {
+            __hip_atomic_fetch_or(flags + nb, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+        }
       }
-    }
-    if (lane < TB) {
-      const V x = N::value(acc);
+      __syncthreads();  // J is published (and every reader of Ws / Ys of the last step is done)
+      const int64_t j0 = J * TB;
+      const int cols = (int)(n - j0 < TB ? n - j0 : TB);
+      {
+        const int yi = t / 16, yc = t % 16;
+        if (yi < cols && yc < nr)
 #pragma unroll
-      for (int c = 0; c < P; c++) Xs[c][lane][wave] = N::get(x, c);
-    }
-  }
-  __syncthreads();
-  if (s_last) {
-    if (xin)
-#pragma unroll
-      for (int c = 0; c < P; c++) X[c * psx + (i0 + xi) * nrhs + xc] = Xs[c][xi][xc];
-    if (t == 0) atomicExch(done, 0);
-  }
-  if (!upd) return;
-  // update rows of block Wb: X_W -= T_W,I X_I (one thread per entry)
-  if (uin) {
-    typename N::Acc acc = N::acc(xw);
-    for (int k = 0; k < rows; k++) {
-      V a, b;
-#pragma unroll
-      for (int c = 0; c < P; c++) {
-        N::put(a, c, Ws[c][ui][k]);
-        N::put(b, c, Xs[c][k][uc]);
+          for (int c = 0; c < P; c++)
+            Ys[c][yi][yc] = __hip_atomic_load(X + c * psx + (j0 + yi) * nrhs + yc,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      N::acc_sub(acc, a, b);
-    }
-    const V x = N::value(acc);
+      to_lds(v);
+      __syncthreads();
+      // sum over this thread's slice of k, then the slices of an entry summed
+      // by a butterfly inside the wave
+      typename N::Acc a = N::acc(N::zero());
+      if (uin)
+        for (int k = slice; k < cols; k += tpe) {
+          V tv, yv;
 #pragma unroll
-    for (int c = 0; c < P; c++) X[c * psx + xo] = N::get(x, c);
+          for (int c = 0; c < P; c++) {
+            N::put(tv, c, Ws[c][ui][k]);
+            N::put(yv, c, Ys[c][k][uc]);
+          }
+          N::acc_sub(a, tv, yv);
+        }
+      V part = N::value(a);  // minus the slice's sum
+      for (int off = 1; off < tpe; off <<= 1) {
+        V o;
+#pragma unroll
+        for (int c = 0; c < P; c++) N::put(o, c, __shfl_xor(N::get(part, c), off, 64));
+        part = (slice & off) ? N::add(o, part) : N::add(part, o);
+      }
+      if (uin) x = N::add(x, part);
+      __syncthreads();  // Ws and Ys are rewritten by the next step
+    }
+    // the diagonal block and this block's values
+    to_lds(vd);
+    if (uin && slice == 0)
+#pragma unroll
+      for (int c = 0; c < P; c++) Ys[c][ui][uc] = N::get(x, c);
+    __syncthreads();
+    if (wave < nr) {
+      V xinit = N::zero();
+      if (lane < rows)
+#pragma unroll
+        for (int c = 0; c < P; c++) N::put(xinit, c, Ys[c][lane][wave]);
+      typename N::Acc acc = N::acc(xinit);
+      auto tval = [&](int i, int k) {
+        V r;
+#pragma unroll
+        for (int c = 0; c < P; c++) N::put(r, c, Ws[c][i][k]);
+        return r;
+      };
+      // a finished x_k is broadcast by readlane_words (DD: unnormalised)
+      if (!upper) {
+        for (int k = 0; k < rows - 1; k++) {
+          const V xk = readlane_words<P>(acc, k);
+          if (lane > k && lane < rows) N::acc_sub(acc, tval(lane, k), xk);
+        }
+      } else {
+        // reciprocals of the diagonal, all lanes at once
+        const V inv = lane < rows ? N::div(N::one(), tval(lane, lane)) : N::zero();
+        for (int k = rows - 1; k >= 0; k--) {
+          const V xk = N::mul(readlane_words<P>(acc, k), readlane_num<P>(inv, k));
+          if (lane == k)
+            acc = N::acc(xk);
+          else if (lane < k)
+            N::acc_sub(acc, tval(lane, k), xk);
+        }
+      }
+      if (lane < rows) {
+        const V xs = N::value(acc);
+#pragma unroll
+        for (int c = 0; c < P; c++)
+          __hip_atomic_store(X + c * psx + (i0 + lane) * nrhs + wave, N::get(xs, c),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      // this wave's stores are complete and visible at device scope
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    }
+    __syncthreads();  // every value of X_I is stored
+    if (t == 0) __hip_atomic_store(flags + I, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();  // Ws and Ys are reused by the next step
   }
 }
 
@@ -1294,10 +1353,12 @@ int launch_perm_from_ipiv(const int32_t* ipiv, int64_t n, int32_t* perm, hipStre
 }
 
 int launch_gather_rows(int P, const double* B, int64_t ldb, int64_t psb, const int32_t* perm,
-                       int64_t n, int64_t nrhs, double* X, int* done, hipStream_t s) {
+                       int64_t n, int64_t nrhs, double* X, int* flags, int nflags,
+                       hipStream_t s) {
+  const int64_t items = n * nrhs > nflags ? n * nrhs : nflags;
   prof_begin(s);
-  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((n * nrhs + 255) / 256)), dim3(256), 0,
-                     s, B, ldb, psb, P, perm, n, nrhs, X, done);
+  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s,
+                     B, ldb, psb, P, perm, n, nrhs, X, flags, nflags);
   prof_record("gather_rows_kernel", s);
   return check_launch("gather_rows_kernel");
 }
@@ -1311,29 +1372,22 @@ int launch_scatter_rows(int P, const double* X, int64_t n, int64_t nrhs, double*
   return check_launch("scatter_rows_kernel");
 }
 
-int launch_trsv_blocks(int P, const double* T, int64_t ldt, int64_t pst, double* X, int64_t n,
-                       int64_t nrhs, int upper, int* done, hipStream_t s) {
+int launch_trsv_chain(int P, const double* T, int64_t ldt, int64_t pst, double* X, int64_t n,
+                      int64_t nrhs, int upper, int* flags, hipStream_t s) {
   const int TB = P == 2 ? trsv_block<2>() : trsv_block<4>();
   const int64_t nb = (n + TB - 1) / TB;
   if (nrhs > 16) return set_error(DDQD_E_UNSUPPORTED, "at most 16 right-hand sides per solve call");
-  for (int64_t step = 0; step < nb; step++) {
-    const int64_t I = upper ? nb - 1 - step : step;
-    // one workgroup per block row the step updates, the diagonal one included
-    // (all of them must run: a smaller grid would leave rows unsolved)
-    const int64_t blocks = upper ? I + 1 : nb - I;
-    if (blocks < 1 || blocks > nb) return set_error(DDQD_E_HIP, "trsv grid out of range");
-    prof_begin(s);
-    if (P == 2)
-      hipLaunchKernelGGL(trsv_block_kernel<2>, dim3((unsigned)blocks), dim3(1024), 0, s, T, ldt,
-                         pst, X, n, nrhs, I, upper, done);
-    else
-      hipLaunchKernelGGL(trsv_block_kernel<4>, dim3((unsigned)blocks), dim3(1024), 0, s, T, ldt,
-                         pst, X, n, nrhs, I, upper, done);
-    prof_record("trsv_block_kernel", s);
-    int rc = check_launch("trsv_block_kernel");
-    if (rc) return rc;
-  }
-  return 0;
+  if (nb + 1 > trsv_flag_words(n)) return set_error(DDQD_E_HIP, "trsv flags out of range");
+  const unsigned grid = (unsigned)(nb < kTrsvWgs ? nb : kTrsvWgs);
+  prof_begin(s);
+  if (P == 2)
+    hipLaunchKernelGGL(trsv_chain_kernel<2>, dim3(grid), dim3(1024), 0, s, T, ldt, pst, X, n,
+                       nrhs, upper, flags);
+  else
+    hipLaunchKernelGGL(trsv_chain_kernel<4>, dim3(grid), dim3(1024), 0, s, T, ldt, pst, X, n,
+                       nrhs, upper, flags);
+  prof_record("trsv_chain_kernel", s);
+  return check_launch("trsv_chain_kernel");
 }
 
 }  // namespace ddqd

@@ -56,11 +56,12 @@ int launch_trsm_nodes(int P, double* A, int64_t lda, int64_t ps, const TrsmNodes
                       hipStream_t s);
 int launch_perm_from_ipiv(const int32_t* ipiv, int64_t n, int32_t* perm, hipStream_t s);
 int launch_gather_rows(int P, const double* B, int64_t ldb, int64_t psb, const int32_t* perm,
-                       int64_t n, int64_t nrhs, double* X, int* done, hipStream_t s);
+                       int64_t n, int64_t nrhs, double* X, int* flags, int nflags,
+                       hipStream_t s);
 int launch_scatter_rows(int P, const double* X, int64_t n, int64_t nrhs, double* B, int64_t ldb,
                         int64_t psb, hipStream_t s);
-int launch_trsv_blocks(int P, const double* T, int64_t ldt, int64_t pst, double* X, int64_t n,
-                       int64_t nrhs, int upper, int* done, hipStream_t s);
+int launch_trsv_chain(int P, const double* T, int64_t ldt, int64_t pst, double* X, int64_t n,
+                      int64_t nrhs, int upper, int* flags, hipStream_t s);
 
 namespace {
 
@@ -190,14 +191,18 @@ size_t getrf_ws(int P, int64_t n, int64_t K, int algo, int levels, int base) {
 }
 
 // getrs workspace: the gathered right-hand sides (P x n x min(nrhs, 16)
-// doubles), the block solves' counter, the permutation (n int32) if only
-// ipiv is given.
+// doubles), the triangular solves' block flags, the permutation (n int32) if
+// only ipiv is given.
 constexpr size_t getrs_x_bytes(int P, int64_t n, int64_t nrhs) {
   return (sizeof(double) * P * (size_t)(n * (nrhs < 16 ? nrhs : 16)) + 255) & ~(size_t)255;
 }
 
+constexpr size_t getrs_flag_bytes(int64_t n) {
+  return (sizeof(int) * (size_t)trsv_flag_words(n) + 255) & ~(size_t)255;
+}
+
 constexpr size_t getrs_ws(int P, int64_t n, int64_t nrhs) {
-  return getrs_x_bytes(P, n, nrhs) + 256 + sizeof(int32_t) * (size_t)n;
+  return getrs_x_bytes(P, n, nrhs) + getrs_flag_bytes(n) + sizeof(int32_t) * (size_t)n;
 }
 
 size_t getrf_workspace_entry(int P, int64_t n, int panel_width, int algo, int levels, int base) {
@@ -269,17 +274,19 @@ int getrs_entry(int P, int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, 
   hipStream_t s = (hipStream_t)stream;
   const int64_t chunk = nrhs < 16 ? nrhs : 16;
   double* X = (double*)ws;
-  int* done = (int*)((char*)ws + getrs_x_bytes(P, n, nrhs));
-  int32_t* pm = (int32_t*)((char*)done + 256);
+  int* flags = (int*)((char*)ws + getrs_x_bytes(P, n, nrhs));
+  int32_t* pm = (int32_t*)((char*)flags + getrs_flag_bytes(n));
   if (!perm) {
     if ((rc = launch_perm_from_ipiv(ipiv, n, pm, s))) return rc;
     perm = pm;
   }
   for (int64_t c0 = 0; c0 < nrhs; c0 += chunk) {
     const int64_t nc = nrhs - c0 < chunk ? nrhs - c0 : chunk;
-    if ((rc = launch_gather_rows(P, B + c0, ldb, psb, perm, n, nc, X, done, s))) return rc;
-    if ((rc = launch_trsv_blocks(P, LU, ldlu, pslu, X, n, nc, 0, done, s))) return rc;
-    if ((rc = launch_trsv_blocks(P, LU, ldlu, pslu, X, n, nc, 1, done, s))) return rc;
+    if ((rc = launch_gather_rows(P, B + c0, ldb, psb, perm, n, nc, X, flags,
+                                 (int)trsv_flag_words(n), s)))
+      return rc;
+    if ((rc = launch_trsv_chain(P, LU, ldlu, pslu, X, n, nc, 0, flags, s))) return rc;
+    if ((rc = launch_trsv_chain(P, LU, ldlu, pslu, X, n, nc, 1, flags, s))) return rc;
     if ((rc = launch_scatter_rows(P, X, n, nc, B + c0, ldb, psb, s))) return rc;
   }
   return DDQD_OK;
