@@ -262,13 +262,15 @@ size_t qd_getrs_workspace(int64_t n, int64_t nrhs);
  * per shape as future work (Sec. 5); here the library times the candidate
  * configurations of one shape on the device and keeps the fastest in a
  * process-wide, thread-safe cache that algo = DDQD_AUTO then uses.
- * Candidates: Block (FMA leaves: 64x64 and 32x32 tiles, which give
- * bit-identical results), and Strassen and Winograd with 1..3 levels while
- * the leaves keep at least 16 rows and columns.  The base and the slice
- * count are the caller's: they set the accuracy, the tuner only the speed.
- * Without a cache entry DDQD_AUTO takes a default: Block for DD (32x32 tiles
- * when 64x64 would leave compute units idle), Winograd for QD with levels
- * while the leaves stay >= 128.
+ * Candidates: Block (FMA leaves: two tiles, DD 64x64 and 32x32, QD 32x32
+ * and 16x16, which give bit-identical results; Ozaki leaves: tile orders in
+ * bands of 2, 4, 8 or 16 tile rows, bit-identical too), and Strassen and
+ * Winograd with 1..3 levels while the leaves keep at least 16 rows and
+ * columns.  The base and the slice count are the caller's: they set the
+ * accuracy, the tuner only the speed.  Without a cache entry DDQD_AUTO takes
+ * a default: Block for DD (the smaller tile when the larger would leave
+ * compute units idle), Winograd for QD with levels while the leaves stay
+ * >= 128.
  *   A, B, C  as dd_gemm with alpha = 1, beta = 0; C receives A B (computed
  *            by every candidate in turn).
  *   reps     timed calls per candidate (>= 1; one untimed call precedes).
@@ -281,7 +283,8 @@ size_t qd_getrs_workspace(int64_t n, int64_t nrhs);
 typedef struct {
   int algo;       /* DDQD_BLOCK, DDQD_STRASSEN or DDQD_WINOGRAD */
   int levels;     /* recursion depth */
-  int tile;       /* Block FMA leaf tile edge (64 or 32), 0 for other leaves */
+  int tile;       /* Block FMA leaf tile edge (DD 64 or 32, QD 32 or 16), 0 for Ozaki */
+  int band;       /* Ozaki leaves: tile rows per band of the tile order, 0 = default */
   int candidates; /* configurations timed; 0 = not tuned, default shown */
   double ms;      /* time per call of the chosen configuration (0 if not tuned) */
 } ddqd_tune_result;

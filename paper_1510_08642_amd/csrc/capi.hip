@@ -42,10 +42,10 @@ bool thin_shape(const GemmBatch& g);
 int launch_thin(int P, const GemmBatch& g, hipStream_t stream);
 // autotuning (tune.hip)
 void auto_choice(int P, int64_t m, int64_t n, int64_t l, int base, int slices, int* algo,
-                 int* levels, int* tile);
+                 int* levels, int* tile, int* band);
 size_t auto_workspace(int P, int64_t m, int64_t n, int64_t l, int base, int slices);
 int launch_dd_grouped(const GroupArgs& ga, int grid, hipStream_t stream);
-int launch_qd_block(const GemmBatch& g, hipStream_t stream);
+int launch_qd_block(const GemmBatch& g, int tile, hipStream_t stream);
 int launch_qd_simple(const GemmBatch& g, hipStream_t stream);
 template <class N>
 int launch_preadd(CMat src, Mat dst, int64_t rows, int64_t cols, int64_t src_rows,
@@ -63,7 +63,7 @@ size_t ozaki_grouped_bytes(const GemmBatch& g, int S);
 int launch_ozaki_grouped(const GemmBatch* probs, int count, int S, char* ws, size_t ws_bytes,
                          hipStream_t s);
 int launch_ozaki(int P, const GemmBatch& g, int slices, void* ws, size_t ws_bytes,
-                 hipStream_t stream);
+                 hipStream_t stream, int band = 0);
 bool ozaki_slices_ok(int P, int slices);
 
 static thread_local char g_msg[512];
@@ -219,14 +219,16 @@ Mat prodM(const Plan& pl, char* ws, int j) {
   return Mat{(double*)(ws + pl.offM[j]), c, r * c, pl.P * r * c};
 }
 
-int leaf(int P, const GemmBatch& g, int base, int slices, int tile, void* ws, size_t ws_bytes,
-         hipStream_t s) {
-  if (base == DDQD_BASE_OZAKI_I8) return launch_ozaki(P, g, slices, ws, ws_bytes, s);
-  return P == 2 ? launch_dd_block(g, tile, s) : launch_qd_block(g, s);
+// tile: the FMA Block tile (DD 64 or 32, QD 32 or 16; 0 = the larger);
+// band: the Ozaki tile order's band of tile rows (0 = 4)
+int leaf(int P, const GemmBatch& g, int base, int slices, int tile, int band, void* ws,
+         size_t ws_bytes, hipStream_t s) {
+  if (base == DDQD_BASE_OZAKI_I8) return launch_ozaki(P, g, slices, ws, ws_bytes, s, band);
+  return P == 2 ? launch_dd_block(g, tile ? tile : 64, s) : launch_qd_block(g, tile, s);
 }
 
 int block_fma(int P, const GemmBatch& g, hipStream_t s) {
-  return P == 2 ? launch_dd_block(g, 64, s) : launch_qd_block(g, s);
+  return P == 2 ? launch_dd_block(g, 64, s) : launch_qd_block(g, 32, s);
 }
 
 // A part peeled off the recursion's core: Simple when K is a few columns
@@ -268,12 +270,12 @@ Mat shift(Mat X, int64_t i, int64_t j) {
 }
 
 int run_gemm(int P, const GemmBatch& top, int algo, int levels, int base, int slices, void* ws,
-             size_t ws_bytes, hipStream_t s, int tile = 64) {
+             size_t ws_bytes, hipStream_t s, int tile = 0, int band = 0) {
   if (algo == DDQD_SIMPLE) return P == 2 ? launch_dd_simple(top, s) : launch_qd_simple(top, s);
   Plan pl = make_plan(P, top.m, top.n, top.l, algo, levels, base, slices);
   char* w = (char*)ws;
   const int L = pl.L;
-  if (L == 0) return leaf(P, top, base, slices, tile, w, ws_bytes, s);
+  if (L == 0) return leaf(P, top, base, slices, tile, band, w, ws_bytes, s);
   int rc;
   // equilibration exponents of A's rows and B's columns (top level only)
   int* ea = (int*)(w + pl.off_exp);
@@ -301,7 +303,8 @@ int run_gemm(int P, const GemmBatch& top, int algo, int levels, int base, int sl
   // all leaf products in one batched launch
   GemmBatch lf{pl.m[L], pl.n[L], pl.l[L], 1, 0, opA(pl, w, L), opB(pl, w, L), prodM(pl, w, L),
                pow7(L)};
-  if ((rc = leaf(P, lf, base, slices, tile, w + pl.off_leaf, pl.leaf_bytes, s))) return rc;
+  if ((rc = leaf(P, lf, base, slices, tile, band, w + pl.off_leaf, pl.leaf_bytes, s)))
+    return rc;
   // post-adds, level by level back up (the root writes only the caller's C)
   const int64_t mr = std::min(top.m, pl.mc), nr = std::min(top.n, pl.nc);
   for (int j = L; j >= 1; j--) {
@@ -382,18 +385,21 @@ size_t plan_workspace(int P, int64_t m, int64_t n, int64_t l, int algo, int leve
   return gemm_ws(P, m, n, l, algo, levels, base, slices);
 }
 
-// tile: Block FMA leaf tile (0 = 64); algo DDQD_AUTO takes the tuned or
+// tile: Block FMA leaf tile (DD 64 or 32, QD 32 or 16; 0 = the larger);
+// band: Ozaki tile order band (0 = 4); algo DDQD_AUTO takes the tuned or
 // default configuration of this shape.
 int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
                int64_t psa, const double* B, int64_t ldb, int64_t psb, int beta, double* C,
                int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
-               size_t ws_bytes, void* stream, int tile) {
+               size_t ws_bytes, void* stream, int tile, int band) {
   g_msg[0] = 0;
   if (m < 0 || n < 0 || l < 0) return set_error(DDQD_E_ARG, "negative dimension");
   if (alpha != 1 && alpha != -1) return set_error(DDQD_E_ARG, "alpha must be +1 or -1");
   if (beta != 0 && beta != 1) return set_error(DDQD_E_ARG, "beta must be 0 or 1");
   if (algo < 0 || algo > DDQD_AUTO) return set_error(DDQD_E_ARG, "unknown algo %d", algo);
-  if (tile != 0 && tile != 32 && tile != 64) return set_error(DDQD_E_ARG, "tile must be 32 or 64");
+  if (tile != 0 && tile != 32 && tile != (P == 2 ? 64 : 16))
+    return set_error(DDQD_E_ARG, P == 2 ? "tile must be 32 or 64" : "tile must be 16 or 32");
+  if (band < 0 || band > 64) return set_error(DDQD_E_ARG, "band must be in 0..64");
   if (levels < 0 || levels > kMaxLevels)
     return set_error(DDQD_E_ARG, "levels must be in 0..%d", kMaxLevels);
   if (base != DDQD_BASE_FMA && base != DDQD_BASE_OZAKI_I8)
@@ -419,8 +425,7 @@ int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* 
                      ws_bytes);
   if (need > 0 && (uintptr_t)ws % 8) return set_error(DDQD_E_WORKSPACE, "workspace misaligned");
   if ((rc = device_ok())) return rc;
-  if (algo == DDQD_AUTO) auto_choice(P, m, n, l, base, slices, &algo, &levels, &tile);
-  if (tile == 0) tile = 64;
+  if (algo == DDQD_AUTO) auto_choice(P, m, n, l, base, slices, &algo, &levels, &tile, &band);
   hipStream_t s = (hipStream_t)stream;
   GemmBatch top{m, n, l, alpha, beta, CMat{A, lda, psa, 0}, CMat{B, ldb, psb, 0},
                 Mat{C, ldc, psc, 0}, 1};
@@ -429,7 +434,7 @@ int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* 
     top.B = CMat{C, ldc, psc, 0};
     return block_fma(P, top, s);
   }
-  return run_gemm(P, top, algo, levels, base, slices, ws, ws_bytes, s, tile);
+  return run_gemm(P, top, algo, levels, base, slices, ws, ws_bytes, s, tile, band);
 }
 
 // Internal entry points for other drivers (LU): no validation, no alias checks.
@@ -686,7 +691,7 @@ int dd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t
             int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
             size_t ws_bytes, void* stream) {
   return gemm_entry(2, m, n, l, alpha, A, lda, psa, B, ldb, psb, beta, C, ldc, psc, algo,
-                    levels, base, slices, ws, ws_bytes, stream, 0);
+                    levels, base, slices, ws, ws_bytes, stream, 0, 0);
 }
 
 int qd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
@@ -694,7 +699,7 @@ int qd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t
             int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
             size_t ws_bytes, void* stream) {
   return gemm_entry(4, m, n, l, alpha, A, lda, psa, B, ldb, psb, beta, C, ldc, psc, algo,
-                    levels, base, slices, ws, ws_bytes, stream, 0);
+                    levels, base, slices, ws, ws_bytes, stream, 0, 0);
 }
 
 }  // extern "C"

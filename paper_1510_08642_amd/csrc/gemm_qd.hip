@@ -2,11 +2,14 @@
 // paper, in the quad-double precision of its Table 2).
 //
 // Block kernel.  A 256-thread workgroup owns a 32x32 tile of C, each thread a
-// 2x2 micro-tile held as four order buckets per entry (see qd_mac).  K moves
-// in steps of 16 with the four planes of the A tile (k-major) and B tile
-// double-buffered in LDS.  The buckets are renormalised after every K step.
-// About 113 FP64 operations per QD multiply-add make the kernel VALU-bound;
-// LDS traffic is 16 doubles per 4 multiply-adds.
+// 2x2 micro-tile held as four order buckets per entry (see qd_mac); the
+// 16x16 variant (one entry per thread) gives small products four times the
+// workgroups.  K moves in steps of 16 with the four planes of the A tile
+// (k-major) and B tile double-buffered in LDS.  The buckets are renormalised
+// after every K step.  Every entry sees the same operations in the same order
+// in both variants, so their results are identical.  About 113 FP64
+// operations per QD multiply-add make the kernel VALU-bound; LDS traffic is
+// 16 doubles per 4 multiply-adds (32x32).
 #include "common.hpp"
 #include "qd.hpp"
 
@@ -16,12 +19,14 @@ namespace ddqd {
 
 namespace {
 
-constexpr int kBM = 32, kBN = 32, kBK = 16, kTM = 2, kTN = 2;
-constexpr int kThreads = (kBM / kTM) * (kBN / kTN);  // 256
+constexpr int kBK = 16, kThreads = 256;
 constexpr int kPad = 2;
 
+// kT x kT micro-tiles per thread, tile edge 16 kT
+template <int kT>
 __global__ __launch_bounds__(kThreads) void qd_gemm_block_kernel(GemmBatch g, int64_t tiles_m,
                                                                  int64_t tiles_n) {
+  constexpr int kBM = 16 * kT, kBN = 16 * kT, kTM = kT, kTN = kT;
   __shared__ __attribute__((aligned(16))) double As[2][4][kBK][kBM + kPad];
   __shared__ __attribute__((aligned(16))) double Bs[2][4][kBK][kBN + kPad];
 
@@ -52,7 +57,7 @@ __global__ __launch_bounds__(kThreads) void qd_gemm_block_kernel(GemmBatch g, in
       }
     }
 
-  constexpr int kPer = kBM * kBK / kThreads;  // 2
+  constexpr int kPer = (kBM * kBK + kThreads - 1) / kThreads;  // 2 (32x32) or 1 (16x16)
   double ra[4][kPer], rb[4][kPer];
   auto load_tiles = [&](int64_t k0) {
 #pragma unroll
@@ -99,12 +104,20 @@ __global__ __launch_bounds__(kThreads) void qd_gemm_block_kernel(GemmBatch g, in
       double a[kTM][4], bv[kTN][4];
 #pragma unroll
       for (int c = 0; c < 4; c++) {
-        double2 x = *reinterpret_cast<const double2*>(&As[buf][c][kk][ty * kTM]);
-        double2 y = *reinterpret_cast<const double2*>(&Bs[buf][c][kk][tx * kTN]);
-        a[0][c] = x.x;
-        a[1][c] = x.y;
-        bv[0][c] = y.x;
-        bv[1][c] = y.y;
+        if constexpr (kT == 2) {
+          double2 x = *reinterpret_cast<const double2*>(&As[buf][c][kk][ty * kTM]);
+          double2 y = *reinterpret_cast<const double2*>(&Bs[buf][c][kk][tx * kTN]);
+          a[0][c] = x.x;
+          a[1][c] = x.y;
+          bv[0][c] = y.x;
+          bv[1][c] = y.y;
+        } else {
+#pragma unroll
+          for (int r = 0; r < kT; r++) {
+            a[r][c] = As[buf][c][kk][ty * kTM + r];
+            bv[r][c] = Bs[buf][c][kk][tx * kTN + r];
+          }
+        }
       }
 #pragma unroll
       for (int r = 0; r < kTM; r++)
@@ -160,15 +173,24 @@ __global__ __launch_bounds__(256) void qd_gemm_simple_kernel(GemmBatch g) {
 
 }  // namespace
 
-int launch_qd_block(const GemmBatch& g, hipStream_t stream) {
+// tile: 32 or 16 (the same results), 0 = 32
+int launch_qd_block(const GemmBatch& g, int tile, hipStream_t stream) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return 0;
-  int64_t tm = (g.m + kBM - 1) / kBM, tn = (g.n + kBN - 1) / kBN;
+  if (tile == 0) tile = 32;
+  if (tile != 32 && tile != 16) return set_error(1 /*DDQD_E_ARG*/, "QD tile must be 32 or 16");
+  int64_t tm = (g.m + tile - 1) / tile, tn = (g.n + tile - 1) / tile;
   int64_t nblk = tm * tn * g.batch;
   if (nblk > INT32_MAX) return set_error(4, "grid too large");
   prof_begin(stream);
-  hipLaunchKernelGGL(qd_gemm_block_kernel, dim3((unsigned)nblk), dim3(kThreads), 0, stream, g,
-                     tm, tn);
-  prof_record("qd_gemm_block_kernel", stream);
+  if (tile == 32) {
+    hipLaunchKernelGGL(qd_gemm_block_kernel<2>, dim3((unsigned)nblk), dim3(kThreads), 0, stream,
+                       g, tm, tn);
+    prof_record("qd_gemm_block_kernel", stream);
+  } else {
+    hipLaunchKernelGGL(qd_gemm_block_kernel<1>, dim3((unsigned)nblk), dim3(kThreads), 0, stream,
+                       g, tm, tn);
+    prof_record("qd_gemm_block_kernel<16>", stream);
+  }
   return check_launch("qd_gemm_block_kernel");
 }
 

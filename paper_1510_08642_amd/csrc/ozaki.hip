@@ -220,12 +220,12 @@ __global__ __launch_bounds__(256) void oz_gemm_kernel(GemmBatch g, OzLayout o,
                                                       const signed char* Bsl, const int* ea,
                                                       const int* fb, int64_t tiles_m,
                                                       int64_t tiles_n, int64_t kc0, int64_t kc1,
-                                                      int beta) {
+                                                      int beta, int band) {
   __shared__ v4i lds[2][4 * S][64];
   const int64_t t = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
   const int64_t per = tiles_m * tiles_n;
   int64_t tm, tn;
-  banded_tile(t % per, tiles_m, tiles_n, 4, tm, tn);
+  banded_tile(t % per, tiles_m, tiles_n, band, tm, tn);
   oz_gemm_tile<S>(g, o, Asl, Bsl, ea, fb, t / per, tm, tn, kc0, kc1, beta, lds);
 }
 
@@ -260,7 +260,7 @@ int run_ozaki_grouped(const OzGroupArgs& ga, hipStream_t s) {
 }
 
 template <int S>
-int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
+int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s, int band) {
   OzLayout o = oz_layout(2, g.m, g.n, g.l, S);
   const OzWs w = oz_ws(ws, o, g.batch);
   signed char *Asl = w.Asl, *Bsl = w.Bsl;
@@ -276,7 +276,7 @@ int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
     prof_begin(s);
     hipLaunchKernelGGL(oz_gemm_kernel<S>, dim3((unsigned)nblk), dim3(256), 0, s, g, o,
                        (const signed char*)Asl, (const signed char*)Bsl, (const int*)ea,
-                       (const int*)fb, tm, tn, kc0, kc1, kc0 == 0 ? g.beta : 1);
+                       (const int*)fb, tm, tn, kc0, kc1, kc0 == 0 ? g.beta : 1, band);
     prof_record("oz_gemm_kernel", s);
     if ((rc = check_launch("oz_gemm_kernel"))) return rc;
   }
@@ -287,7 +287,8 @@ int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s) {
 
 int ozaki_qd_default_slices();
 size_t ozaki_qd_workspace(int64_t m, int64_t n, int64_t l, int64_t batch, int slices);
-int launch_ozaki_qd(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, hipStream_t s);
+int launch_ozaki_qd(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, hipStream_t s,
+                    int band);
 
 int ozaki_default_slices(int P) { return P == 4 ? ozaki_qd_default_slices() : 16; }
 
@@ -364,9 +365,12 @@ int launch_ozaki_grouped(const GemmBatch* probs, int count, int S, char* ws, siz
   return DDQD_OK;
 }
 
+// band: tile rows per band of the product's tile order (0 = 4); the order
+// changes only which workgroups share L2, never a result bit.
 int launch_ozaki(int P, const GemmBatch& g, int slices, void* ws, size_t ws_bytes,
-                 hipStream_t s) {
-  if (P == 4) return launch_ozaki_qd(g, slices, ws, ws_bytes, s);
+                 hipStream_t s, int band) {
+  if (P == 4) return launch_ozaki_qd(g, slices, ws, ws_bytes, s, band);
+  if (band == 0) band = 4;
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return DDQD_OK;
   const int S = slices == 0 ? ozaki_default_slices(2) : slices;
   if (S < kMinS || S > kMaxS)
@@ -375,19 +379,19 @@ int launch_ozaki(int P, const GemmBatch& g, int slices, void* ws, size_t ws_byte
     return set_error(DDQD_E_WORKSPACE, "Ozaki workspace too small");
   char* w = (char*)ws;
   switch (S) {
-    case 8: return run_ozaki<8>(g, w, s);
-    case 9: return run_ozaki<9>(g, w, s);
-    case 10: return run_ozaki<10>(g, w, s);
-    case 11: return run_ozaki<11>(g, w, s);
-    case 12: return run_ozaki<12>(g, w, s);
-    case 13: return run_ozaki<13>(g, w, s);
-    case 14: return run_ozaki<14>(g, w, s);
-    case 15: return run_ozaki<15>(g, w, s);
-    case 16: return run_ozaki<16>(g, w, s);
-    case 17: return run_ozaki<17>(g, w, s);
-    case 18: return run_ozaki<18>(g, w, s);
-    case 19: return run_ozaki<19>(g, w, s);
-    case 20: return run_ozaki<20>(g, w, s);
+    case 8: return run_ozaki<8>(g, w, s, band);
+    case 9: return run_ozaki<9>(g, w, s, band);
+    case 10: return run_ozaki<10>(g, w, s, band);
+    case 11: return run_ozaki<11>(g, w, s, band);
+    case 12: return run_ozaki<12>(g, w, s, band);
+    case 13: return run_ozaki<13>(g, w, s, band);
+    case 14: return run_ozaki<14>(g, w, s, band);
+    case 15: return run_ozaki<15>(g, w, s, band);
+    case 16: return run_ozaki<16>(g, w, s, band);
+    case 17: return run_ozaki<17>(g, w, s, band);
+    case 18: return run_ozaki<18>(g, w, s, band);
+    case 19: return run_ozaki<19>(g, w, s, band);
+    case 20: return run_ozaki<20>(g, w, s, band);
   }
   return set_error(DDQD_E_UNSUPPORTED, "slices");
 }

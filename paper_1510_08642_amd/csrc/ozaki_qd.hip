@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256) void ozq_gemm_kernel(GemmBatch g, OzLayout o,
                                                        const signed char* Asl,
                                                        const signed char* Bsl, const int* ea,
                                                        const int* fb, int64_t kc0, int64_t kc1,
-                                                       int beta) {
+                                                       int beta, int band) {
   __shared__ v4i lds[2][2 * S][64];
   static_assert(nslots(S) * 32 * 32 * sizeof(double) <= sizeof(lds), "epilogue LDS");
   static_assert(first_cut(S) <= 16, "wave 0 keeps at most 16 accumulators");
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(256) void ozq_gemm_kernel(GemmBatch g, OzLayout o,
   const int64_t per = o.rb * o.cb;
   const int64_t b = t / per;
   int64_t rbi, cbi;
-  banded_tile(t % per, o.rb, o.cb, 4, rbi, cbi);
+  banded_tile(t % per, o.rb, o.cb, band, rbi, cbi);
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int wu = __builtin_amdgcn_readfirstlane(w);
 
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(256) void ozq_gemm_kernel(GemmBatch g, OzLayout o,
 }
 
 template <int S>
-int run_ozaki_qd(const GemmBatch& g, char* ws, hipStream_t s) {
+int run_ozaki_qd(const GemmBatch& g, char* ws, hipStream_t s, int band) {
   OzLayout o = oz_layout(4, g.m, g.n, g.l, S);
   const OzWs w = oz_ws(ws, o, g.batch);
   signed char *Asl = w.Asl, *Bsl = w.Bsl;
@@ -348,7 +348,7 @@ int run_ozaki_qd(const GemmBatch& g, char* ws, hipStream_t s) {
     prof_begin(s);
     hipLaunchKernelGGL(ozq_gemm_kernel<S>, dim3((unsigned)nblk), dim3(256), 0, s, g, o,
                        (const signed char*)Asl, (const signed char*)Bsl, (const int*)ea,
-                       (const int*)fb, kc0, kc1, kc0 == 0 ? g.beta : 1);
+                       (const int*)fb, kc0, kc1, kc0 == 0 ? g.beta : 1, band);
     prof_record("ozq_gemm_kernel", s);
     if ((rc = check_launch("ozq_gemm_kernel"))) return rc;
   }
@@ -366,7 +366,8 @@ size_t ozaki_qd_workspace(int64_t m, int64_t n, int64_t l, int64_t batch, int sl
   return oz_workspace_bytes(o, batch);
 }
 
-int launch_ozaki_qd(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, hipStream_t s) {
+int launch_ozaki_qd(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, hipStream_t s,
+                    int band) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return DDQD_OK;
   const int S = slices == 0 ? ozaki_qd_default_slices() : slices;
   if (S < kMinS || S > kMaxS)
@@ -375,10 +376,10 @@ int launch_ozaki_qd(const GemmBatch& g, int slices, void* ws, size_t ws_bytes, h
     return set_error(DDQD_E_WORKSPACE, "Ozaki workspace too small");
   char* w = (char*)ws;
   switch (S) {
-    case 28: return run_ozaki_qd<28>(g, w, s);
-    case 29: return run_ozaki_qd<29>(g, w, s);
-    case 30: return run_ozaki_qd<30>(g, w, s);
-    case 31: return run_ozaki_qd<31>(g, w, s);
+    case 28: return run_ozaki_qd<28>(g, w, s, band ? band : 4);
+    case 29: return run_ozaki_qd<29>(g, w, s, band ? band : 4);
+    case 30: return run_ozaki_qd<30>(g, w, s, band ? band : 4);
+    case 31: return run_ozaki_qd<31>(g, w, s, band ? band : 4);
   }
   return set_error(DDQD_E_UNSUPPORTED, "slices");
 }

@@ -1,5 +1,6 @@
-// Autotuner: per-shape choice of product algorithm, recursion depth and
-// Block tile, timed on the device and cached process-wide (DDQD_AUTO).
+// Autotuner: per-shape choice of product algorithm, recursion depth, Block
+// tile (FMA leaves) and tile-order band (Ozaki leaves), timed on the device
+// and cached process-wide (DDQD_AUTO).
 //
 // The paper names the block size and the recursion depth as the tuning
 // parameters left open (Sec. 5).  The candidates of one shape all compute a
@@ -18,7 +19,7 @@ namespace ddqd {
 int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
                int64_t psa, const double* B, int64_t ldb, int64_t psb, int beta, double* C,
                int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
-               size_t ws_bytes, void* stream, int tile);
+               size_t ws_bytes, void* stream, int tile, int band);
 size_t plan_workspace(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
                       int slices);
 void clear_error();
@@ -35,7 +36,7 @@ struct Key {
 };
 
 struct Choice {
-  int algo, levels, tile, candidates;
+  int algo, levels, tile, band, candidates;
   double ms;
 };
 
@@ -46,21 +47,24 @@ constexpr int kMaxTuneLevels = 3, kMinLeaf = 16;
 
 int64_t min3(int64_t a, int64_t b, int64_t c) { return std::min(a, std::min(b, c)); }
 
-// Block FMA leaves: 32x32 tiles when 64x64 tiles would not give every compute
-// unit one workgroup.
+// Block FMA leaves: the smaller tile (DD 32x32, QD 16x16) when the larger
+// one would not give every compute unit one workgroup; 0 for Ozaki leaves.
 int leaf_tile(int P, int base, int64_t m, int64_t n, int64_t batch) {
-  if (P != 2 || base != DDQD_BASE_FMA) return 0;
-  const int64_t tiles64 = ((m + 63) / 64) * ((n + 63) / 64) * batch;
-  return tiles64 < 256 ? 32 : 64;
+  if (base != DDQD_BASE_FMA) return 0;
+  const int big = P == 2 ? 64 : 32;
+  const int64_t tiles = ((m + big - 1) / big) * ((n + big - 1) / big) * batch;
+  return tiles < 256 ? big / 2 : big;
 }
 
 std::vector<Choice> candidates(int P, int64_t m, int64_t n, int64_t l, int base) {
   std::vector<Choice> c;
-  if (P == 2 && base == DDQD_BASE_FMA) {
-    c.push_back(Choice{DDQD_BLOCK, 0, 64, 0, 0.0});
-    c.push_back(Choice{DDQD_BLOCK, 0, 32, 0, 0.0});
+  if (base == DDQD_BASE_FMA) {
+    const int big = P == 2 ? 64 : 32;
+    c.push_back(Choice{DDQD_BLOCK, 0, big, 0, 0, 0.0});
+    c.push_back(Choice{DDQD_BLOCK, 0, big / 2, 0, 0, 0.0});
   } else {
-    c.push_back(Choice{DDQD_BLOCK, 0, 0, 0, 0.0});
+    // Ozaki leaves: the band of tile rows an XCD's consecutive tiles span
+    for (int band : {2, 4, 8, 16}) c.push_back(Choice{DDQD_BLOCK, 0, 0, band, 0, 0.0});
   }
   int64_t batch = 1;
   for (int L = 1; L <= kMaxTuneLevels; L++) {
@@ -68,8 +72,8 @@ std::vector<Choice> candidates(int P, int64_t m, int64_t n, int64_t l, int base)
     const int64_t d = min3(m, n, l) >> L;
     if (d < kMinLeaf) break;
     const int t = leaf_tile(P, base, m >> L, n >> L, batch);
-    c.push_back(Choice{DDQD_STRASSEN, L, t, 0, 0.0});
-    c.push_back(Choice{DDQD_WINOGRAD, L, t, 0, 0.0});
+    c.push_back(Choice{DDQD_STRASSEN, L, t, 0, 0, 0.0});
+    c.push_back(Choice{DDQD_WINOGRAD, L, t, 0, 0, 0.0});
   }
   return c;
 }
@@ -78,9 +82,12 @@ Choice default_choice(int P, int64_t m, int64_t n, int64_t l, int base) {
   if (P == 4 && base == DDQD_BASE_FMA) {
     int L = 0;
     while (L < kMaxTuneLevels && (min3(m, n, l) >> (L + 1)) >= 128) L++;
-    return Choice{L ? DDQD_WINOGRAD : DDQD_BLOCK, L, 0, 0, 0.0};
+    int64_t batch = 1;
+    for (int j = 0; j < L; j++) batch *= 7;
+    return Choice{L ? DDQD_WINOGRAD : DDQD_BLOCK, L, leaf_tile(P, base, m >> L, n >> L, batch),
+                  0, 0, 0.0};
   }
-  return Choice{DDQD_BLOCK, 0, leaf_tile(P, base, m, n, 1), 0, 0.0};
+  return Choice{DDQD_BLOCK, 0, leaf_tile(P, base, m, n, 1), 0, 0, 0.0};
 }
 
 int tune(int P, int64_t m, int64_t n, int64_t l, const double* A, int64_t lda, int64_t psa,
@@ -90,10 +97,10 @@ int tune(int P, int64_t m, int64_t n, int64_t l, const double* A, int64_t lda, i
   if (reps < 1 || reps > 1000) return set_error(DDQD_E_ARG, "reps must be in 1..1000");
   // validation (and the no-op cases) exactly as the product itself
   int rc = gemm_entry(P, m, n, l, 1, A, lda, psa, B, ldb, psb, 0, C, ldc, psc, DDQD_AUTO, 0, base,
-                      slices, ws, ws_bytes, stream, 0);
+                      slices, ws, ws_bytes, stream, 0, 0);
   if (rc) return rc;
   if (m == 0 || n == 0 || l == 0) {
-    if (out) *out = ddqd_tune_result{DDQD_BLOCK, 0, 0, 0, 0.0};
+    if (out) *out = ddqd_tune_result{DDQD_BLOCK, 0, 0, 0, 0, 0.0};
     return DDQD_OK;
   }
   hipStream_t s = (hipStream_t)stream;
@@ -104,12 +111,12 @@ int tune(int P, int64_t m, int64_t n, int64_t l, const double* A, int64_t lda, i
     return set_error(DDQD_E_HIP, "hipEventCreate failed");
   }
   std::vector<Choice> cs = candidates(P, m, n, l, base);
-  Choice best{0, 0, 0, 0, 0.0};
+  Choice best{0, 0, 0, 0, 0, 0.0};
   bool have = false;
   for (const Choice& c : cs) {
     auto run = [&]() {
       return gemm_entry(P, m, n, l, 1, A, lda, psa, B, ldb, psb, 0, C, ldc, psc, c.algo, c.levels,
-                        base, slices, ws, ws_bytes, stream, c.tile);
+                        base, slices, ws, ws_bytes, stream, c.tile, c.band);
     };
     if ((rc = run())) break;
     if (hipEventRecord(e0, s) != hipSuccess) {
@@ -139,14 +146,16 @@ int tune(int P, int64_t m, int64_t n, int64_t l, const double* A, int64_t lda, i
     std::lock_guard<std::mutex> lk(g_mu);
     g_cache[Key{P, m, n, l, base, slices}] = best;
   }
-  if (out) *out = ddqd_tune_result{best.algo, best.levels, best.tile, best.candidates, best.ms};
+  if (out)
+    *out = ddqd_tune_result{best.algo, best.levels, best.tile, best.band, best.candidates,
+                            best.ms};
   return DDQD_OK;
 }
 
 }  // namespace
 
 void auto_choice(int P, int64_t m, int64_t n, int64_t l, int base, int slices, int* algo,
-                 int* levels, int* tile) {
+                 int* levels, int* tile, int* band) {
   Choice c = default_choice(P, m, n, l, base);
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -156,6 +165,7 @@ void auto_choice(int P, int64_t m, int64_t n, int64_t l, int base, int slices, i
   *algo = c.algo;
   *levels = c.levels;
   *tile = c.tile;
+  *band = c.band;
 }
 
 size_t auto_workspace(int P, int64_t m, int64_t n, int64_t l, int base, int slices) {
@@ -201,7 +211,7 @@ int ddqd_tune_lookup(int precision, int64_t m, int64_t n, int64_t l, int base, i
     auto it = g_cache.find(Key{precision, m, n, l, base, slices});
     if (it != g_cache.end()) c = it->second;
   }
-  *out = ddqd_tune_result{c.algo, c.levels, c.tile, c.candidates, c.ms};
+  *out = ddqd_tune_result{c.algo, c.levels, c.tile, c.band, c.candidates, c.ms};
   return DDQD_OK;
 }
 

@@ -83,8 +83,8 @@ _lib.ddqd_last_error.restype = ctypes.c_char_p
 
 class TuneResult(ctypes.Structure):
     """ddqd_tune_result of include/ddqd.h."""
-    _fields_ = [("algo", _int), ("levels", _int), ("tile", _int), ("candidates", _int),
-                ("ms", ctypes.c_double)]
+    _fields_ = [("algo", _int), ("levels", _int), ("tile", _int), ("band", _int),
+                ("candidates", _int), ("ms", ctypes.c_double)]
 
 
 for _name in ("dd_gemm_tune", "qd_gemm_tune"):
@@ -389,8 +389,8 @@ def capture(fn, stream):
 
 
 def _tune_dict(r: TuneResult):
-    return dict(algo=ALGO_NAME[r.algo], levels=r.levels, tile=r.tile, candidates=r.candidates,
-                ms=r.ms)
+    return dict(algo=ALGO_NAME[r.algo], levels=r.levels, tile=r.tile, band=r.band,
+                candidates=r.candidates, ms=r.ms)
 
 
 def tune(A, B, C=None, *, base="fma", slices=0, reps=3, ws=None):

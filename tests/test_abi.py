@@ -178,6 +178,9 @@ def test_tune_defaults_and_errors(lib):
     q = ddqd.tune_lookup(4, 1024, 1024, 1024)
     assert (q["algo"], q["levels"]) == ("winograd", 3)
     assert ddqd.tune_lookup(4, 200, 200, 200)["algo"] == "block"
+    assert ddqd.tune_lookup(4, 200, 200, 200)["tile"] == 16       # 32x32 tiles would idle CUs
+    assert ddqd.tune_lookup(4, 2048, 2048, 2048)["tile"] == 32
+    assert ddqd.tune_lookup(2, 1024, 1024, 1024, base="ozaki")["band"] == 0
     import ctypes as C
     r = ddqd.TuneResult()
     assert lib.ddqd_tune_lookup(3, 8, 8, 8, 0, 0, C.byref(r)) == E["ARG"]

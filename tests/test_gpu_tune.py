@@ -66,3 +66,43 @@ def test_default_small_tile_is_bit_identical_to_64(dd):
     Cc = to_host(dd.dd_gemm(Ad, Bd, C0.clone(), alpha=-1, beta=1, algo="auto"))
     Cd = to_host(dd.dd_gemm(Ad, Bd, C0.clone(), alpha=-1, beta=1, algo="block"))
     assert np.array_equal(Cc, Cd)
+
+
+def test_qd_small_tile_is_bit_identical_to_32(dd):
+    """The QD Block kernel's 16x16 tile (the default for small products)
+    gives the 32x32 tile's bits, with and without beta."""
+    import torch
+    dd.tune_clear()
+    g = inputs.rng(411)
+    A, B = inputs.qd_uniform(100, 90, g), inputs.qd_uniform(90, 110, g)
+    Ad, Bd = to_dev(A), to_dev(B)
+    assert dd.tune_lookup(4, 100, 110, 90)["tile"] == 16
+    Ca = to_host(dd.qd_gemm(Ad, Bd, algo="auto"))
+    Cb = to_host(dd.qd_gemm(Ad, Bd, algo="block"))
+    torch.cuda.synchronize()
+    assert np.array_equal(Ca, Cb)
+    assert _err_ok(A, B, Ca, 4, 90)
+    C0 = to_dev(inputs.qd_uniform(100, 110, g))
+    Cc = to_host(dd.qd_gemm(Ad, Bd, C0.clone(), alpha=-1, beta=1, algo="auto"))
+    Cd = to_host(dd.qd_gemm(Ad, Bd, C0.clone(), alpha=-1, beta=1, algo="block"))
+    assert np.array_equal(Cc, Cd)
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_tuned_ozaki_band_is_bit_identical(dd, P):
+    """Ozaki leaves: the tuner times tile orders in bands of 2..16 tile rows;
+    the chosen order gives the default order's bits."""
+    import torch
+    print(f"case tune ozaki band P={P}", flush=True)
+    dd.tune_clear()
+    g = inputs.rng(412 + P)
+    mk = inputs.dd_uniform if P == 2 else inputs.qd_uniform
+    m, n, l = 520, 390, 300
+    Ad, Bd = to_dev(mk(m, l, g)), to_dev(mk(l, n, g))
+    r = dd.tune(Ad, Bd, base="ozaki", reps=2)
+    assert r["candidates"] >= 4
+    gem = dd.dd_gemm if P == 2 else dd.qd_gemm
+    Ca = gem(Ad, Bd, algo="auto", base="ozaki")
+    Ce = gem(Ad, Bd, algo=r["algo"], levels=r["levels"], base="ozaki")
+    torch.cuda.synchronize()
+    assert torch.equal(Ca, Ce), r
