@@ -47,6 +47,10 @@ INT8_PEAK_T = 5000.0
 # FP64 operations per DD multiply-add of the Block FMA kernel (1 mul + 3 fma +
 # 8 add, and a 6-operation TwoSum every 16) -- confirmed by SQ_INSTS_VALU_*_F64
 DD_OPS_PER_MAC = 12 + 6 / 16
+# FP64 operations per QD multiply-add of the QD Block FMA kernel (six
+# TwoProducts, four order-3 products, 14 TwoSums and 13 adds = 113, and a
+# 30-operation renormalisation every 16)
+QD_OPS_PER_MAC = 113 + 30 / 16
 
 
 def measured_traffic(kernel: str):
@@ -141,10 +145,29 @@ def roofline_qd_ozaki(dd, step, n, steps, S=31):
                     "per launch"}
 
 
-def cpu_baseline(n: int, budget_s: float = 10.0, P: int = 2):
-    """The oracle's Block product (DD, or QD for P = 4) of the n x n workload,
-    repeated on all host threads for about budget_s seconds; plus one thread on
-    a row sample."""
+def roofline_qd_fma(dd, step, n, steps):
+    """The QD Block FMA product kernel at n: FP64 VALU operations of its
+    multiply-adds against the FP64 issue peak."""
+    name = "qd_gemm_block_kernel"
+    avg, cnt = kernel_avg_ms(dd, step, steps, name)
+    per = max(1, cnt // steps)
+    ach = float(n) ** 3 / per * QD_OPS_PER_MAC / (avg * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": name, "achieved": round(ach, 3),
+            "peak": round(FP64_OPS_PEAK_T, 2), "unit": "TFLOP/s",
+            "frac": round(ach / FP64_OPS_PEAK_T, 4), "traffic": measured_traffic(name),
+            "avg_launch_ms": round(avg, 5), "launches_per_step": per,
+            "note": f"qd_gemm base=fma: FP64 VALU operations ({QD_OPS_PER_MAC} per QD "
+                    "multiply-add, each add/mul/fma counting one); peak = 256 CU x 2.4 GHz x "
+                    "64 lanes"}
+
+
+def cpu_baseline(n: int, budget_s: float = 8.0, P: int = 2):
+    """The oracle (as it stands) on this host, on bounded samples of the
+    workloads: the Block product (DD, or QD for P = 4) of the n x n step
+    repeated on all threads for about budget_s seconds (the reported value);
+    one thread on a 64-row sample (median of 3); the QD Block product on row
+    samples (all threads, one thread); the blocked LU with partial pivoting
+    (DD n = 512, QD n = 128; all threads and one thread)."""
     import oracle
     from paper_1510_08642_amd import inputs
     g = inputs.rng(0)
@@ -152,22 +175,48 @@ def cpu_baseline(n: int, budget_s: float = 10.0, P: int = 2):
     A = gen(n, n, g)
     B = gen(n, n, g)
     threads = oracle.num_threads()
+
+    def timed(fn, reps=1):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    def one_thread(fn, reps=1):
+        oracle.set_threads(1)
+        try:
+            return timed(fn, reps)
+        finally:
+            oracle.set_threads(threads)
+
     reps, t = 0, 0.0
     while t < budget_s or reps == 0:
-        t0 = time.perf_counter()
-        oracle.gemm(A, B, "block")
-        t += time.perf_counter() - t0
+        t += timed(lambda: oracle.gemm(A, B, "block"))
         reps += 1
     gf = 2.0 * n ** 3 * reps / t / 1e9
     rows = 64
-    oracle.set_threads(1)
-    try:
-        t0 = time.perf_counter()
-        oracle.gemm(A[:, :rows], B, "block")
-        t1 = time.perf_counter() - t0
-    finally:
-        oracle.set_threads(threads)
+    t1 = one_thread(lambda: oracle.gemm(A[:, :rows], B, "block"), reps=3)
     gf1 = 2.0 * rows * n * n / t1 / 1e9
+    # QD: the oracle's exact-expansion arithmetic is slow, so row samples
+    # (block size 4 so that every thread gets rows)
+    Aq = inputs.qd_uniform(32, n, g)
+    Bq = inputs.qd_uniform(n, n, g)
+    tq = timed(lambda: oracle.gemm(Aq, Bq, "block", bs=4))
+    tq1 = one_thread(lambda: oracle.gemm(Aq[:, :4], Bq, "block", bs=4))
+    qd = {"gflops_all_threads": round(2.0 * 32 * n * n / tq / 1e9, 5),
+          "gflops_one_thread": round(2.0 * 4 * n * n / tq1 / 1e9, 5),
+          "sample": f"QD Block, 32 rows x {n} x {n} on {threads} threads ({tq:.1f} s), "
+                    f"4 rows on one thread ({tq1:.1f} s)"}
+    lu = {}
+    for Pl, nl in ((2, 512), (4, 128)):
+        Al = (inputs.dd_lu_matrix if Pl == 2 else inputs.qd_lu_matrix)(nl, g)
+        f = lambda: oracle.getrf(Al, panel=64, pivot=True, algo="block", levels=0)
+        ta, t1l = timed(f), one_thread(f)
+        lu[f"{'dd' if Pl == 2 else 'qd'}_getrf_n{nl}"] = {
+            "ms_all_threads": round(ta * 1e3, 1), "ms_one_thread": round(t1l * 1e3, 1),
+            "gflops_all_threads": round(2.0 / 3.0 * nl ** 3 / ta / 1e9, 5)}
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
@@ -178,10 +227,11 @@ def cpu_baseline(n: int, budget_s: float = 10.0, P: int = 2):
     except OSError:
         pass
     return {"value": round(gf, 4), "unit": "GFLOPS", "cores": threads, "kind": "oracle",
-            "sample": f"oracle Block {'DD' if P == 2 else 'QD'} product of the whole n={n} workload, {reps} times in "
-                      f"{t:.1f} s on {threads} OpenMP threads ({model}); one thread on the "
-                      f"first {rows} rows: {gf1:.3f} GFLOPS",
-            "one_thread_gflops": round(gf1, 4), "cpu_model": model}
+            "sample": f"oracle Block {'DD' if P == 2 else 'QD'} product of the whole n={n} "
+                      f"workload, {reps} times in {t:.1f} s on {threads} OpenMP threads "
+                      f"({model}); one thread on the first {rows} rows: {gf1:.3f} GFLOPS "
+                      "(median of 3)",
+            "one_thread_gflops": round(gf1, 4), "cpu_model": model, "qd": qd, "lu": lu}
 
 
 def sampled_error(A, B, C, n, count=64):
@@ -194,6 +244,30 @@ def sampled_error(A, B, C, n, count=64):
     e = np.abs(oracle.exact_error(A, B, C, ii, jj))
     den = (np.abs(A[0]) @ np.abs(B[0])).max(axis=1)[ii]
     return float(np.max(e / den))
+
+
+def qd_residual(dd, torch, A, x, b):
+    """||b - A x||_inf / (||A||_inf ||x||_inf) with the residual evaluated by
+    the library's QD product (A, x, b widened to four planes exactly): for a
+    DD solve the evaluation's own rounding (about n 2^-212) is far below the
+    residual; for a QD solve it is of the residual's order, so the figure is
+    an estimate within a small factor."""
+    P, n = A.shape[0], A.shape[1]
+
+    def q(X):
+        if P == 4:
+            return X.contiguous()
+        Z = torch.zeros((4,) + tuple(X.shape[1:]), dtype=torch.float64, device=X.device)
+        Z[:P] = X
+        return Z
+    Aq = q(A)
+    r = q(b)
+    dd.qd_gemm(Aq, q(x), r, alpha=-1, beta=1)
+    rh = r[0].abs().max().item()
+    normA = A[0].abs().sum(dim=1).max().item()
+    normx = x[0].abs().max().item()
+    del Aq, r
+    return rh / (normA * normx)
 
 
 def bench_lu(dd, inputs, torch, dev, sizes, configs, stream, P=2):
@@ -226,9 +300,15 @@ def bench_lu(dd, inputs, torch, dev, sizes, configs, stream, P=2):
                     getrs(A, ipiv, Xs, perm=perm)
                 res[nrhs] = time_steps(s, 3, 1, stream)
             t_getrf = t_f - t_copy
+            # Eq. 2's solve for one right-hand side, and its residual
+            x1 = b0[:, :, :1].contiguous()
+            getrs(A, ipiv, x1, perm=perm)
+            resid = qd_residual(dd, torch, A0, x1, b0[:, :, :1].contiguous())
             out[key] = {"getrf_ms": round(t_getrf, 3),
                         "getrf_gflops": round(2.0 / 3.0 * n ** 3 / (t_getrf * 1e-3) / 1e9, 1),
-                        "getrs_ms_nrhs1": round(res[1], 3), "getrs_ms_nrhs16": round(res[16], 3)}
+                        "getrs_ms_nrhs1": round(res[1], 3), "getrs_ms_nrhs16": round(res[16], 3),
+                        "residual_nrhs1": float(f"{resid:.3e}"),
+                        "residual_bound": float(f"{n * (2.0 ** -100 if P == 2 else 2.0 ** -200):.3e}")}
             log(f"lu {key}: {out[key]}")
     return out
 
@@ -345,8 +425,9 @@ def bench_equal_accuracy(dd, inputs, torch, dev, n, stream):
     return out
 
 
-def bench_paper(dd, inputs, torch, dev, stream):
-    """The paper's own experiment shapes on this GPU.
+def bench_paper(dd, inputs, torch, dev, stream, full=False):
+    """The paper's own experiment shapes on this GPU (a few seconds; full=True
+    adds Strassen products and the Winograd / Ozaki LU updates).
 
     Products (Sec. 3, Tables 1-2): the Sec. 3 matrices A = [sqrt5 (i+j-1)],
     B = [sqrt3 (n-i)] at n = 1023, 1024, 1025 in DD and QD, Block against
@@ -370,8 +451,9 @@ def bench_paper(dd, inputs, torch, dev, stream):
             rs = np.random.default_rng(n)
             rows = np.unique(np.concatenate([[0, n // 2, n - 1], rs.integers(0, n, 29)]))
             exact = inputs.paper_product_closed_form(n, rows)
-            configs = [("block", 0, "fma"), ("strassen", 5, "fma"), ("winograd", 5, "fma")]
-            configs.append(("block", 0, "ozaki"))
+            configs = [("block", 0, "fma"), ("winograd", 5, "fma"), ("block", 0, "ozaki")]
+            if full:
+                configs.insert(1, ("strassen", 5, "fma"))
             for algo, lv, base in configs:
                 ws = torch.empty(max(1, dd.gemm_workspace(P, n, n, n, algo, lv, base)),
                                  dtype=torch.uint8, device=dev)
@@ -404,7 +486,9 @@ def bench_paper(dd, inputs, torch, dev, stream):
         b = prod(A0, torch.from_numpy(x).to(dev))
         runs = [(0, "rowwise", "fma", 0)]   # the paper's row-wise parallel comparator
         for alpha in range(1, 11):
-            for algo, base in (("block", "fma"), ("winograd", "fma"), ("block", "ozaki")):
+            updates = (("block", "fma"), ("winograd", "fma"), ("block", "ozaki")) if full else \
+                (("block", "fma"),)
+            for algo, base in updates:
                 lv = 0 if algo == "block" else alpha.bit_length() - 1
                 if algo == "winograd" and lv == 0:
                     continue
@@ -488,7 +572,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--paper", action="store_true",
-                    help="also run the paper's experiment shapes (Sec. 3 tables, Sec. 4 LU)")
+                    help="the paper's experiment shapes in full (Sec. 3 tables with Strassen, "
+                         "Sec. 4 LU with every update); by default a few-second subset runs")
+    ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--lu-only", type=int, default=0, metavar="N",
                     help="only time the DD LU factor-and-solve of order N (panel 128, Winograd 1 "
                          "on Ozaki leaves), for kernel traces of the LU")
@@ -544,15 +630,16 @@ def main():
     value = flops / (ms * 1e-3) / 1e9
     log(f"bench: {ms:.4f} ms/step, {value:.1f} GFLOPS effective")
     if PM == 4:
-        if args.base != "ozaki" or args.algo != "block":
-            sys.exit("--precision qd is for the QD Ozaki Block product (--base ozaki)")
-        roof = roofline_qd_ozaki(dd, step, n, args.steps)
+        if args.algo != "block":
+            sys.exit("--precision qd times the QD Block product (either base)")
+        roof = (roofline_qd_ozaki(dd, step, n, args.steps) if args.base == "ozaki" else
+                roofline_qd_fma(dd, step, n, min(args.steps, 5)))
     else:
         roof = roofline(dd, args, n, step, args.steps)
     log(f"bench: roofline {roof}")
 
     variants = {}
-    roof_qd = None
+    roof_qd = roof_qd_fma = None
     if not args.no_variants:
         for (algo, lv, base) in [("simple", 0, "fma"), ("block", 0, "fma"),
                                  ("strassen", 1, "fma"), ("strassen", 2, "fma"),
@@ -577,27 +664,67 @@ def main():
             log(f"variant qd {algo} L{lv} {base}: {t:.3f} ms")
         roof_qd = roofline_qd_ozaki(dd, make("block", 0, "ozaki", 4, Aq, Bq, Cq), n, 5)
         log(f"bench: QD Ozaki roofline {roof_qd}")
+        roof_qd_fma = roofline_qd_fma(dd, make("block", 0, "fma", 4, Aq, Bq, Cq), n, 2)
+        log(f"bench: QD FMA roofline {roof_qd_fma}")
         del Aq, Bq, Cq
 
     tuning = equal = None
+    row_scaled = None
     if not args.no_variants:
         tuning = bench_tuning(dd, inputs, torch, dev, n)
         if not args.no_cpu:
             equal = bench_equal_accuracy(dd, inputs, torch, dev, n, stream)
+        # the DD product at n = 2048: Block, Strassen and Winograd at 1-3
+        # levels, FMA against Ozaki leaves
         n2 = 2 * n
         g2 = inputs.rng(3)
         A2 = torch.from_numpy(inputs.dd_uniform(n2, n2, g2)).to(dev)
         B2 = torch.from_numpy(inputs.dd_uniform(n2, n2, g2)).to(dev)
         C2 = torch.empty((2, n2, n2), dtype=torch.float64, device=dev)
-        for (algo, lv, base) in [("block", 0, "fma"), ("block", 0, "ozaki"),
-                                 ("winograd", 1, "ozaki")]:
-            ws2 = torch.empty(max(1, dd.gemm_workspace(2, n2, n2, n2, algo, lv, base)),
-                              dtype=torch.uint8, device=dev)
-            t = time_steps(lambda: dd.dd_gemm(A2, B2, C2, algo=algo, levels=lv, base=base,
-                                              ws=ws2), 3, 1, stream)
-            variants[f"dd_{algo}{lv}_{base}_n{n2}"] = round(2.0 * n2 ** 3 / (t * 1e-3) / 1e9, 1)
-            log(f"variant dd {algo} L{lv} {base} n={n2}: {t:.3f} ms")
+        recursive = [("block", 0)] + [(a, lv) for a in ("strassen", "winograd") for lv in (1, 2, 3)]
+        for base in ("fma", "ozaki"):
+            for (algo, lv) in recursive:
+                ws2 = torch.empty(max(1, dd.gemm_workspace(2, n2, n2, n2, algo, lv, base)),
+                                  dtype=torch.uint8, device=dev)
+                t = time_steps(lambda: dd.dd_gemm(A2, B2, C2, algo=algo, levels=lv, base=base,
+                                                  ws=ws2), 3, 1, stream)
+                variants[f"dd_{algo}{lv}_{base}_n{n2}"] = round(2.0 * n2 ** 3 / (t * 1e-3) / 1e9, 1)
+                log(f"variant dd {algo} L{lv} {base} n={n2}: {t:.3f} ms")
+                del ws2
         del A2, B2, C2
+        # the QD product at n = 512 (FMA: Block, Strassen, Winograd at 1-3
+        # levels; Block on Ozaki leaves)
+        n5 = n // 2
+        g5 = inputs.rng(4)
+        A5 = torch.from_numpy(inputs.qd_uniform(n5, n5, g5)).to(dev)
+        B5 = torch.from_numpy(inputs.qd_uniform(n5, n5, g5)).to(dev)
+        C5 = torch.empty((4, n5, n5), dtype=torch.float64, device=dev)
+        for (algo, lv, base) in [(a, l, "fma") for (a, l) in recursive] + [("block", 0, "ozaki")]:
+            ws5 = torch.empty(max(1, dd.gemm_workspace(4, n5, n5, n5, algo, lv, base)),
+                              dtype=torch.uint8, device=dev)
+            t = time_steps(lambda: dd.qd_gemm(A5, B5, C5, algo=algo, levels=lv, base=base,
+                                              ws=ws5), 3, 1, stream)
+            variants[f"qd_{algo}{lv}_{base}_n{n5}"] = round(2.0 * n5 ** 3 / (t * 1e-3) / 1e9, 1)
+            log(f"variant qd {algo} L{lv} {base} n={n5}: {t:.3f} ms")
+        del A5, B5, C5
+        # the row-scaled variant (row i of A times 2^r_i, r_i in [-30, 30]):
+        # time here, error in the CPU leg
+        As = torch.from_numpy(inputs.row_scaled(A.cpu().numpy() if PM == 2 else
+                                                inputs.dd_uniform(n, n, inputs.rng(0)),
+                                                inputs.rng(1))[0]).to(dev)
+        Cs = torch.empty((2, n, n), dtype=torch.float64, device=dev)
+        Bs = B if PM == 2 else torch.from_numpy(inputs.dd_uniform(n, n, inputs.rng(2))).to(dev)
+        row_scaled = {}
+        for (algo, lv, base) in [("block", 0, "fma"), ("winograd", 1, "fma"),
+                                 ("block", 0, "ozaki"), ("winograd", 1, "ozaki")]:
+            wss = torch.empty(max(1, dd.gemm_workspace(2, n, n, n, algo, lv, base)),
+                              dtype=torch.uint8, device=dev)
+            t = time_steps(lambda: dd.dd_gemm(As, Bs, Cs, algo=algo, levels=lv, base=base,
+                                              ws=wss), 5, 1, stream)
+            row_scaled[f"{algo}{lv}_{base}"] = {"ms": round(t, 4),
+                                                "gflops": round(flops / (t * 1e-3) / 1e9, 1),
+                                                "C": Cs.clone() if not args.no_cpu else None}
+            log(f"row-scaled 2^+-30 dd {algo} L{lv} {base}: {t:.3f} ms")
 
     graphs = None if args.no_lu else bench_graphs(dd, inputs, torch, dev)
 
@@ -609,7 +736,7 @@ def main():
         lu.update(bench_lu(dd, inputs, torch, dev, [1024, 2048],
                            [(64, "block", 0, "fma"), (128, "block", 0, "ozaki")], stream, P=4))
 
-    paper = bench_paper(dd, inputs, torch, dev, stream) if args.paper else None
+    paper = None if args.no_paper else bench_paper(dd, inputs, torch, dev, stream, full=args.paper)
 
     serving = None
     if not args.no_serving and args.serving_requests > 0:
@@ -627,12 +754,22 @@ def main():
         err = sampled_error(A.cpu().numpy(), B.cpu().numpy(), C.cpu().numpy(), n)
         tol = (2.0 ** -100 if PM == 2 else 2.0 ** -200) * n
         log(f"bench: sampled row-normwise error {err:.3e} (tolerance {tol:.3e})")
+        if row_scaled:
+            Ash, Bsh = As.cpu().numpy(), Bs.cpu().numpy()
+            for k, v in row_scaled.items():
+                v["error_rownorm"] = sampled_error(Ash, Bsh, v.pop("C").cpu().numpy(), n)
+            log(f"bench: row-scaled variant {row_scaled}")
+    elif row_scaled:
+        for v in row_scaled.values():
+            v.pop("C", None)
 
     out = {
         "metric": "DD/QD GEMM effective GFLOPS (2mnl/t) at n=1024; DD LU-solve p50/p99 latency",
         "value": round(value, 2), "unit": "GFLOPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": ("i8 mfma (i32 sums) + f64 recombination" if args.base == "ozaki" else "f64"),
+        "data": "synthetic",
         "config": {"workload": f"{args.precision}_gemm m=n=l={n}, "
                                f"{args.precision.upper()} uniform inputs seed 0",
                    "algo": args.algo, "levels": args.levels, "base": args.base,
@@ -640,9 +777,11 @@ def main():
         "error_rownorm": err,
         "roofline": roof,
         "roofline_qd_ozaki": roof_qd,
+        "roofline_qd_fma": roof_qd_fma,
         "variants_gflops": variants,
         "tuned": tuning,
         "ozaki_vs_fma_equal_accuracy": equal,
+        "row_scaled_2pm30": row_scaled,
         "graphs": graphs,
         "lu": lu,
         "serving": serving,
