@@ -340,7 +340,7 @@ int launch_ozaki_grouped(const GemmBatch* probs, int count, int S, char* ws, siz
       off += need;
       const int c = ga.count++;
       ga.wg[c + 1] = ga.wg[c] + oz_exp_wgs(p.o);
-      ga.chunk[c + 1] = ga.chunk[c] + oz_slice_chunks(p.o);
+      ga.chunk[c + 1] = ga.chunk[c] + oz_slice_chunks(p.o, 2);
       ga.tile[c + 1] = ga.tile[c] + (p.o.rb / 2) * (p.o.cb / 2);
     }
     if (ga.count == 0) continue;

@@ -90,7 +90,12 @@ __device__ __forceinline__ int oz_group_find(const int64_t* start, int count, in
 inline int64_t oz_exp_wgs(const OzLayout& o) {
   return (o.rb * 32 + 3) / 4 + ((o.cb * 32 + 63) / 64) * o.kb;
 }
-inline int64_t oz_slice_chunks(const OzLayout& o) { return (o.rb + o.cb) * ((o.kb + 1) / 2); }
+// 32-k blocks per slicing chunk (DD: four, QD: two) and chunks per product.
+constexpr int oz_slice_kb(int P) { return P == 2 ? 4 : 2; }
+inline int64_t oz_slice_chunks(const OzLayout& o, int P) {
+  const int kb = oz_slice_kb(P);
+  return (o.rb + o.cb) * ((o.kb + kb - 1) / kb);
+}
 
 // The three launches of a group (exponents, slicing, products), P = 2.
 int launch_oz_exponents_grouped(const OzGroupArgs& ga, hipStream_t s);

@@ -3,6 +3,7 @@
 // signed 7-bit digits stored as INT8 in MFMA fragment order.  The products
 // themselves are in ozaki.hip (DD) and ozaki_qd.hip (QD).
 #include <algorithm>
+#include <type_traits>
 
 #include "ddqd.h"
 #include "common.hpp"
@@ -127,13 +128,15 @@ __device__ __forceinline__ void col_exponents(const OzLayout& o, const int* part
   __syncthreads();
 }
 
-// The work is cut into chunks of 32 lines (rows of A or columns of B) by 64 k
-// (two 32-k blocks), A's chunks first, then B's; workgroup g takes chunks g,
-// g + G, g + 2G, ... (G workgroups per batch entry).  A chunk's P planes are
-// read with coalesced loads into registers (along k for A, along the columns
-// for B) while the workgroup still slices the previous chunk, then pass
-// through LDS; wave w slices k block w / 2, half w % 2 of every lane's 16-k
-// fragment slot (8 values of one line per lane, 8 bytes per digit).
+// The work is cut into chunks of 32 lines (rows of A or columns of B) by KB
+// 32-k blocks (DD: 4, QD: 2), A's chunks first, then B's; workgroup g takes
+// chunks g, g + G, g + 2G, ... (G workgroups per batch entry).  A chunk's P
+// planes are read with coalesced loads into registers (along k for A, along
+// the columns for B) while the workgroup still slices the previous chunk,
+// then pass through LDS.  DD: wave w slices k block w, every lane its whole
+// 16-k fragment slot (16 bytes per digit: each store instruction writes a
+// whole 1 KB fragment); QD: wave w slices k block w / 2, half w % 2 of the
+// slot (8 values, 8 bytes per digit).
 //
 // Digits of a scaled value r (|r| < 1/2) held as an expansion r0 + r1 (+ r2
 // + r3): runs of kRun digits are taken from the leading term alone, then the
@@ -152,7 +155,6 @@ __device__ __forceinline__ void col_exponents(const OzLayout& o, const int* part
 // by the even integer 2^7 N_(j-1) keeps ties to even), and |digit| <= 64.
 // After kRun digits the remainder 2^(7 kRun) (r0 - (t_kRun - 1.5 2^(52 - 7 kRun)))
 // is exact (Sterbenz for the subtraction, a power of two for the scaling).
-constexpr int kSliceK = 64;   // k per chunk (two 32-k blocks)
 constexpr int kRun = 6;       // digits per run from the leading term alone
 static_assert(kRun == 6, "the merge scales by 2^42 = 2^(7 kRun)");
 constexpr int kSliceWgs = 512;  // workgroups of one slicing launch (two per CU)
@@ -161,7 +163,7 @@ constexpr double kMagic[kRun] = {0x1.8p45, 0x1.8p38, 0x1.8p31, 0x1.8p24, 0x1.8p1
 
 struct SliceChunk {
   int side;            // 0: rows of A, 1: columns of B
-  int64_t blk, kg;     // 32-line block, 64-k group
+  int64_t blk, kg;     // 32-line block, group of KB k blocks
 };
 
 __device__ __forceinline__ SliceChunk slice_chunk(const OzLayout& o, int64_t ch, int64_t kgroups) {
@@ -174,22 +176,24 @@ __device__ __forceinline__ SliceChunk slice_chunk(const OzLayout& o, int64_t ch,
   return c;
 }
 
-// Issues the loads of one chunk's 32 x 64 values, every load in flight before
-// the first use; values outside the matrix read as zero.
-template <int P>
+// Issues the loads of one chunk's 32 x 32 KB values (4 KB per thread and
+// plane), every load in flight before the first use; values outside the
+// matrix read as zero.
+template <int P, int KB>
 __device__ __forceinline__ void slice_load(const CMat& A, const CMat& B, int64_t m, int64_t n,
                                            int64_t l, int64_t b, const SliceChunk& c,
-                                           double (&v)[P][8]) {
+                                           double (&v)[P][4 * KB]) {
+  constexpr int K = 32 * KB;
   const CMat X = c.side == 0 ? A : B;
   const int64_t lines_live = c.side == 0 ? m : n;
   const double* base = X.p + b * X.bstride;
   const int t = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < 8; j++) {
+  for (int j = 0; j < 4 * KB; j++) {
     const int e = t + 256 * j;
-    const int ln = c.side == 0 ? e / kSliceK : e % 32;
-    const int kk = c.side == 0 ? e % kSliceK : e / 32;
-    const int64_t line = c.blk * 32 + ln, k = c.kg * kSliceK + kk;
+    const int ln = c.side == 0 ? e / K : e % 32;
+    const int kk = c.side == 0 ? e % K : e / 32;
+    const int64_t line = c.blk * 32 + ln, k = c.kg * K + kk;
     const bool in = line < lines_live && k < l;
     const int64_t idx = in ? (c.side == 0 ? line * X.ld + k : k * X.ld + line) : 0;
 #pragma unroll
@@ -199,28 +203,31 @@ __device__ __forceinline__ void slice_load(const CMat& A, const CMat& B, int64_t
 
 // The digits of chunk `cur` of batch entry b, whose values (unscaled) are in
 // `tile`; xc is scratch for B's column exponents.  All 256 threads take part.
-template <int P, int S>
+template <int P, int S, int KB>
 __device__ __forceinline__ void slice_digits(const OzLayout& o, const int* ea, const int* part,
                                              int* fb, signed char* Asl, signed char* Bsl,
                                              int64_t b, const SliceChunk& cur,
-                                             double (&tile)[P][32][kSliceK + 1], int* xc) {
+                                             double (&tile)[P][32][32 * KB + 1], int* xc) {
+  constexpr int V = 4 * KB;  // values per lane: the whole 16-k slot (KB = 4) or half of it
+  static_assert(KB == 4 || KB == 2, "four waves cover KB k blocks");
+  using Word = typename std::conditional<V == 16, uint4, uint2>::type;
   const int t = threadIdx.x, w = t / 64, lane = t % 64;
   const int64_t line0 = cur.blk * 32;
   // uniform per workgroup
   if (cur.side == 1) col_exponents(o, part, fb, b, line0, cur.kg == 0, xc);
-  const int64_t kb = cur.kg * 2 + w / 2;
+  const int wk = KB == 4 ? w : w / 2, half = KB == 4 ? 0 : w % 2;
+  const int64_t kb = cur.kg * KB + wk;
   if (kb >= o.kb) return;  // past the last K block (no barrier follows in this pass)
-  const int half = w % 2;
-  const int ln = lane % 32, k0 = (w / 2) * 32 + 16 * (lane / 32) + 8 * half;
+  const int ln = lane % 32, k0 = wk * 32 + 16 * (lane / 32) + 8 * half;
   const int ex = cur.side == 0 ? ea[b * (o.rb * 32) + line0 + ln] : xc[ln];
-  double r[P][8];
+  double r[P][V];
 #pragma unroll
-  for (int q = 0; q < 8; q++)
+  for (int q = 0; q < V; q++)
 #pragma unroll
     for (int p = 0; p < P; p++) r[p][q] = ldexp(tile[p][ln][k0 + q], -ex);
   // an input whose terms overlap is brought into shape first (exact)
 #pragma unroll
-  for (int q = 0; q < 8; q++) {
+  for (int q = 0; q < V; q++) {
     if constexpr (P == 2) {
       two_sum(r[0][q], r[1][q], r[0][q], r[1][q]);
     } else {
@@ -238,17 +245,19 @@ __device__ __forceinline__ void slice_digits(const OzLayout& o, const int* ea, c
                      (cur.blk * o.kb + kb) * S * (int64_t)kOzFrag + lane * 16 + 8 * half;
 #pragma unroll 1
   for (int s0 = 0; s0 < S; s0 += kRun) {
-    uint32_t prev[8];
-    double tl[8];  // t_j of the run's last digit
+    uint32_t prev[V];
+    double tl[V];  // t_j of the run's last digit
 #pragma unroll
-    for (int q = 0; q < 8; q++) prev[q] = 0u;
+    for (int q = 0; q < V; q++) prev[q] = 0u;
 #pragma unroll
     for (int j = 0; j < kRun; j++) {
       if (s0 + j < S) {
         const double magic = kMagic[j];
-        uint32_t x[2] = {0u, 0u};
+        uint32_t x[V / 4];
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
+        for (int q = 0; q < V / 4; q++) x[q] = 0u;
+#pragma unroll
+        for (int q = 0; q < V; q++) {
           const double tq = r[0][q] + magic;
           const uint32_t nj = (uint32_t)__builtin_bit_cast(uint64_t, tq);
           const uint32_t d = nj - (prev[q] << 7);
@@ -256,12 +265,12 @@ __device__ __forceinline__ void slice_digits(const OzLayout& o, const int* ea, c
           tl[q] = tq;
           x[q / 4] |= (d & 0xffu) << (8 * (q % 4));
         }
-        *reinterpret_cast<uint2*>(dst + (s0 + j) * (int64_t)kOzFrag) = uint2{x[0], x[1]};
+        *reinterpret_cast<Word*>(dst + (s0 + j) * (int64_t)kOzFrag) = __builtin_bit_cast(Word, x);
       }
     }
     if (s0 + kRun >= S) break;  // no digits left: the remainder is not needed
 #pragma unroll
-    for (int q = 0; q < 8; q++) {
+    for (int q = 0; q < V; q++) {
       const double rem = (r[0][q] - (tl[q] - kMagic[kRun - 1])) * 0x1p42;
       if constexpr (P == 2) {
         fast_two_sum(rem, r[1][q] * 0x1p42, r[0][q], r[1][q]);
@@ -283,15 +292,16 @@ __device__ __forceinline__ void slice_digits(const OzLayout& o, const int* ea, c
 
 // The loaded values of a chunk into the LDS tile (after a barrier that every
 // reader of the previous chunk has passed).
-template <int P>
-__device__ __forceinline__ void slice_to_tile(const SliceChunk& c, const double (&v)[P][8],
-                                              double (&tile)[P][32][kSliceK + 1]) {
+template <int P, int KB>
+__device__ __forceinline__ void slice_to_tile(const SliceChunk& c, const double (&v)[P][4 * KB],
+                                              double (&tile)[P][32][32 * KB + 1]) {
+  constexpr int K = 32 * KB;
   const int t = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < 8; j++) {
+  for (int j = 0; j < 4 * KB; j++) {
     const int e = t + 256 * j;
-    const int ln = c.side == 0 ? e / kSliceK : e % 32;
-    const int kk = c.side == 0 ? e % kSliceK : e / 32;
+    const int ln = c.side == 0 ? e / K : e % 32;
+    const int kk = c.side == 0 ? e % K : e / 32;
 #pragma unroll
     for (int q = 0; q < P; q++) tile[q][ln][kk] = v[q][j];
   }
@@ -302,26 +312,27 @@ __global__ __launch_bounds__(256) void oz_slice_kernel(CMat A, CMat B, int64_t m
                                                        int64_t l, OzLayout o, const int* ea,
                                                        const int* part, int* fb,
                                                        signed char* Asl, signed char* Bsl) {
-  __shared__ double tile[P][32][kSliceK + 1];
+  constexpr int KB = oz_slice_kb(P);
+  __shared__ double tile[P][32][32 * KB + 1];
   __shared__ int xc[8 * 32];
   const int64_t b = blockIdx.z;
-  const int64_t kgroups = (o.kb + 1) / 2;
+  const int64_t kgroups = (o.kb + KB - 1) / KB;
   const int64_t nchunks = (o.rb + o.cb) * kgroups;
   int64_t ch = blockIdx.x;
   if (ch >= nchunks) return;  // uniform per workgroup
-  double v[P][8];
+  double v[P][4 * KB];
   SliceChunk c = slice_chunk(o, ch, kgroups);
-  slice_load<P>(A, B, m, n, l, b, c, v);
+  slice_load<P, KB>(A, B, m, n, l, b, c, v);
   for (; ch < nchunks; ch += gridDim.x) {
     __syncthreads();  // the previous chunk's readers of tile and xc are done
-    slice_to_tile<P>(c, v, tile);
+    slice_to_tile<P, KB>(c, v, tile);
     __syncthreads();
     const SliceChunk cur = c;
     if (ch + gridDim.x < nchunks) {  // the next chunk's loads fly during the slicing
       c = slice_chunk(o, ch + gridDim.x, kgroups);
-      slice_load<P>(A, B, m, n, l, b, c, v);
+      slice_load<P, KB>(A, B, m, n, l, b, c, v);
     }
-    slice_digits<P, S>(o, ea, part, fb, Asl, Bsl, b, cur, tile, xc);
+    slice_digits<P, S, KB>(o, ea, part, fb, Asl, Bsl, b, cur, tile, xc);
   }
 }
 
@@ -330,32 +341,33 @@ __global__ __launch_bounds__(256) void oz_slice_kernel(CMat A, CMat B, int64_t m
 // ga.chunk[q+1]); the same digits as the single product's launch.
 template <int S>
 __global__ __launch_bounds__(256) void oz_slice_grouped_kernel(OzGroupArgs ga) {
-  __shared__ double tile[2][32][kSliceK + 1];
+  constexpr int KB = oz_slice_kb(2);
+  __shared__ double tile[2][32][32 * KB + 1];
   __shared__ int xc[8 * 32];
   const int64_t total = ga.chunk[ga.count];
   int64_t G = blockIdx.x;
   if (G >= total) return;  // uniform per workgroup
-  double v[2][8];
+  double v[2][4 * KB];
   int q = oz_group_find(ga.chunk, ga.count, G);
-  SliceChunk c = slice_chunk(ga.p[q].o, G - ga.chunk[q], (ga.p[q].o.kb + 1) / 2);
+  SliceChunk c = slice_chunk(ga.p[q].o, G - ga.chunk[q], (ga.p[q].o.kb + KB - 1) / KB);
   {
     const GemmBatch& g = ga.p[q].g;
-    slice_load<2>(g.A, g.B, g.m, g.n, g.l, 0, c, v);
+    slice_load<2, KB>(g.A, g.B, g.m, g.n, g.l, 0, c, v);
   }
   for (; G < total; G += gridDim.x) {
     __syncthreads();
-    slice_to_tile<2>(c, v, tile);
+    slice_to_tile<2, KB>(c, v, tile);
     __syncthreads();
     const SliceChunk cur = c;
     const int qc = q;
     if (G + gridDim.x < total) {
       q = oz_group_find(ga.chunk, ga.count, G + gridDim.x);
-      c = slice_chunk(ga.p[q].o, G + gridDim.x - ga.chunk[q], (ga.p[q].o.kb + 1) / 2);
+      c = slice_chunk(ga.p[q].o, G + gridDim.x - ga.chunk[q], (ga.p[q].o.kb + KB - 1) / KB);
       const GemmBatch& g = ga.p[q].g;
-      slice_load<2>(g.A, g.B, g.m, g.n, g.l, 0, c, v);
+      slice_load<2, KB>(g.A, g.B, g.m, g.n, g.l, 0, c, v);
     }
     const OzProb& p = ga.p[qc];
-    slice_digits<2, S>(p.o, p.w.ea, p.w.part, p.w.fb, p.w.Asl, p.w.Bsl, 0, cur, tile, xc);
+    slice_digits<2, S, KB>(p.o, p.w.ea, p.w.part, p.w.fb, p.w.Asl, p.w.Bsl, 0, cur, tile, xc);
   }
 }
 
@@ -376,15 +388,15 @@ int launch_oz_exponents(const GemmBatch& g, const OzLayout& o, const OzWs& w, hi
 namespace {
 
 // Workgroups per batch entry: kSliceWgs over the batch, at most one per chunk.
-inline int64_t slice_grid(const GemmBatch& g, const OzLayout& o) {
-  const int64_t nchunks = (o.rb + o.cb) * ((o.kb + 1) / 2);
+inline int64_t slice_grid(int P, const GemmBatch& g, const OzLayout& o) {
+  const int64_t nchunks = oz_slice_chunks(o, P);
   const int64_t per = std::max<int64_t>(1, kSliceWgs / std::max<int64_t>(1, g.batch));
   return std::min(nchunks, per);
 }
 
 template <int S>
 int slice_dd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s) {
-  const int64_t grid = slice_grid(g, o);
+  const int64_t grid = slice_grid(2, g, o);
   prof_begin(s);
   hipLaunchKernelGGL((oz_slice_kernel<2, S>), dim3((unsigned)grid, 1, (unsigned)g.batch),
                      dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)w.ea,
@@ -395,7 +407,7 @@ int slice_dd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s
 
 template <int S>
 int slice_qd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s) {
-  const int64_t grid = slice_grid(g, o);
+  const int64_t grid = slice_grid(4, g, o);
   prof_begin(s);
   hipLaunchKernelGGL((oz_slice_kernel<4, S>), dim3((unsigned)grid, 1, (unsigned)g.batch),
                      dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)w.ea,
