@@ -38,6 +38,7 @@ class Request:
     result: Any = None
     error: Optional[str] = None
     batch_size: int = 1
+    bypassed: int = 0          # later requests admitted while this one was the head
 
     @property
     def latency(self) -> Optional[float]:
@@ -71,25 +72,45 @@ def request_flops(r: Request) -> float:
 
 
 class Server:
-    """Admission by memory footprint, FIFO order, continuous batching.
+    """Admission by memory footprint, oldest first, continuous batching.
 
     budget_bytes  device memory the in-flight requests may use together
     slots         concurrent launch streams
     small_n       products with n <= small_n are merged into grouped launches
     max_batch     at most this many products per grouped launch
+    reserve_small slots kept for small requests (work <= small_flops): large
+                  requests start only while more slots than this are free, so
+                  a burst of large factorizations cannot hold every slot
+    max_bypass    a head that does not fit (memory, or a slot held back for
+                  small requests) lets later requests that fit go first, at
+                  most this many times; then it waits alone (no starvation)
+    window        how far behind the head admission looks for such requests
     """
 
     def __init__(self, executor, budget_bytes: int, slots: int = 4, small_n: int = 256,
-                 max_batch: int = 24, poll_sleep_s: float = 0.0):
+                 max_batch: int = 24, poll_sleep_s: float = 0.0, reserve_small: int = 0,
+                 small_flops: float = 2.0 * 512 ** 3, max_bypass: int = 32, window: int = 64):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.slots = int(slots)
         self.small_n = small_n
         self.max_batch = max_batch
         self.poll_sleep_s = poll_sleep_s
+        self.reserve_small = int(reserve_small)
+        self.small_flops = small_flops
+        self.max_bypass = max_bypass
+        self.window = window
 
     def _batchable(self, r: Request) -> bool:
         return r.kind == "gemm" and r.n <= self.small_n and self.ex.can_group
+
+    def _small(self, r: Request) -> bool:
+        return request_flops(r) <= self.small_flops
+
+    def _fits(self, r: Request, fp: int) -> bool:
+        if fp > self._free_bytes:
+            return False
+        return self._small(r) or len(self._free_slots) > self.reserve_small
 
     # -- the loop's state and one scheduling pass (shared with OnlineServer) --
     def _reset(self):
@@ -129,14 +150,31 @@ class Server:
                 if on_done:
                     on_done([head])
                 continue
-            if fp > self._free_bytes:
-                break                           # back-pressure: FIFO, the head waits
-            batch = [queue.popleft()]
+            pick = 0
+            if not self._fits(head, fp):
+                # back-pressure: the head waits; a later request that fits may
+                # go first while the head has been passed fewer than
+                # max_bypass times
+                pick = -1
+                if head.bypassed < self.max_bypass:
+                    for k in range(1, min(len(queue), self.window)):
+                        f = self.ex.footprint(queue[k])
+                        if f <= self.budget and self._fits(queue[k], f):
+                            pick, fp = k, f
+                            break
+                if pick < 0:
+                    break
+                head.bypassed += 1
+            first = queue[pick]
+            del queue[pick]
+            batch = [first]
             used = fp
-            if self._batchable(head):
+            if self._batchable(first):
                 keep = collections.deque()
-                while queue and len(batch) < self.max_batch:
+                scanned = 0
+                while queue and len(batch) < self.max_batch and scanned < self.window:
                     r = queue.popleft()
+                    scanned += 1
                     f = self.ex.footprint(r)
                     if self._batchable(r) and used + f <= self._free_bytes:
                         batch.append(r)

@@ -138,3 +138,53 @@ def test_online_server_futures_from_threads():
     srv.close(timeout=30)
     st = srv.stats()
     assert st.completed == 4 and st.failed == 2
+
+
+def test_blocked_head_is_bypassed_by_requests_that_fit():
+    """A head that does not fit the free memory lets a later small request go
+    first (the loop stays busy); with max_bypass = 0 admission is strictly
+    oldest first."""
+    fp_big = 16 * 300 * 300 + 16 * 300
+    for max_bypass, expect_small_first in ((8, True), (0, False)):
+        clock = VirtualClock()
+        ex = FakeExecutor(clock)
+        reqs = reqs_from([("gemm", 300, 0, 0.0), ("gemm", 300, 0, 0.0), ("gemm", 10, 0, 0.0)])
+        Server(ex, budget_bytes=fp_big + 5000, slots=4, small_n=0,
+               max_bypass=max_bypass).run(reqs, clock=clock)
+        assert all(r.error is None for r in reqs)
+        small_first = reqs[2].t_admit < reqs[1].t_admit
+        assert small_first == expect_small_first, max_bypass
+        if expect_small_first:
+            assert reqs[1].bypassed >= 1
+
+
+def test_bypass_is_bounded():
+    """A head passed max_bypass times waits until it fits: no starvation by a
+    stream of small requests."""
+    clock = VirtualClock()
+    ex = FakeExecutor(clock)
+    fp_big = 16 * 300 * 300 + 16 * 300
+    spec = [("gemm", 300, 0, 0.0), ("gemm", 300, 0, 0.0)] + [("gemm", 10, 0, 0.0)] * 40
+    reqs = reqs_from(spec)
+    Server(ex, budget_bytes=fp_big + 5000, slots=4, small_n=0, max_bypass=5).run(reqs,
+                                                                            clock=clock)
+    head = reqs[1]
+    assert head.bypassed == 5
+    passed = [r for r in reqs[2:] if r.t_admit < head.t_admit]
+    assert len(passed) == 5
+
+
+def test_reserved_slot_keeps_small_requests_flowing():
+    """With one of two slots reserved for small requests, two large
+    factorizations run one at a time and the small products use the other
+    slot meanwhile."""
+    clock = VirtualClock()
+    ex = FakeExecutor(clock)
+    reqs = reqs_from([("lu", 600, 4, 0.0), ("lu", 600, 4, 0.0)] +
+                     [("gemm", 20, 0, 0.0)] * 6)
+    Server(ex, budget_bytes=10 ** 9, slots=2, small_n=0, reserve_small=1,
+           small_flops=2.0 * 64 ** 3).run(reqs, clock=clock)
+    big0, big1 = reqs[0], reqs[1]
+    assert big1.t_admit >= big0.t_done - 1e-9        # never both large ones at once
+    smalls = reqs[2:]
+    assert all(r.t_done <= big0.t_done for r in smalls)   # they ran beside the first
