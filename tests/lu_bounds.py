@@ -42,3 +42,21 @@ def samples(n, count, seed):
 
 def vsum(X):
     return sum(X[c] for c in range(X.shape[0]))
+
+
+def solve_diff_bound(LU, x, u):
+    """Componentwise bound on the difference of two solutions of L U x = P b
+    by triangular solves on the same factors, each backward stable with
+    |dL| <= n u |L|, |dU| <= n u |U| (any summation order): to first order
+    |x_hat - x| <= n u (|U^-1| |U| |x| + |U^-1| |L^-1| |L| |U x|) for each, so
+    twice that for two (FP64 inverses; a further factor 2 covers their
+    relative error)."""
+    from scipy.linalg import solve_triangular
+    L, U = split(LU)
+    n = L.shape[1]
+    x0 = vsum(x) if x.ndim == 3 else x
+    Li = np.abs(solve_triangular(L[0], np.eye(n), lower=True, unit_diagonal=True))
+    Ui = np.abs(solve_triangular(U[0], np.eye(n), lower=False))
+    aL, aU = np.abs(L[0]), np.abs(U[0])
+    one = Ui @ (aU @ np.abs(x0)) + Ui @ (Li @ (aL @ np.abs(U[0] @ x0)))
+    return 4 * n * u * one

@@ -2,13 +2,17 @@
 the oracle's own unpivoted factorizations of the paper's Sec. 4 matrix, in
 different rounding orders (blocked and unblocked), meet the backward-error
 bound and agree within the first-order bound; a factor entry changed in its
-last bits breaks the backward-error bound."""
+last bits breaks the backward-error bound.  The solve bound: the oracle's
+triangular solves on given factors stay within it of the exact solution of
+those factors' systems (rational arithmetic), and a solve that drops L's
+low-order plane does not."""
+from fractions import Fraction
 import numpy as np
 import pytest
 
 import oracle
 from paper_1510_08642_amd import inputs
-from tests.lu_bounds import da_bound, first_order_bound, split, vsum
+from tests.lu_bounds import da_bound, first_order_bound, solve_diff_bound, split, vsum
 
 UNIT = {2: 2.0 ** -100, 4: 2.0 ** -200}
 
@@ -48,3 +52,44 @@ def test_a_wrong_factor_entry_breaks_the_backward_bound(P):
         G[P - 1, i, j] = G[P - 1, i, j] + np.ldexp(abs(G[0, i, j]), -70 if P == 2 else -160)
         back, bound = backward_error(A, G)
         assert np.any(back > bound), (i, j)
+
+
+def exact_lu_solve(LU, ipiv, b):
+    """x with L U x = P b exactly (rationals): the interchanges replayed on b,
+    then forward and back substitution."""
+    P, n = LU.shape[0], LU.shape[1]
+    F = [[sum(Fraction(float(LU[c, i, j])) for c in range(P)) for j in range(n)] for i in range(n)]
+    y = [sum(Fraction(float(b[c, i, 0])) for c in range(P)) for i in range(n)]
+    for k in range(n):
+        p = int(ipiv[k])
+        y[k], y[p] = y[p], y[k]
+    for i in range(n):
+        y[i] -= sum(F[i][j] * y[j] for j in range(i))
+    x = [Fraction(0)] * n
+    for i in reversed(range(n)):
+        x[i] = (y[i] - sum(F[i][j] * x[j] for j in range(i + 1, n))) / F[i][i]
+    return x
+
+
+@pytest.mark.parametrize("P,u", [(2, 2.0 ** -104), (4, 2.0 ** -208)])
+def test_solve_bound_holds_for_the_oracle_solve_and_fails_without_a_plane(P, u):
+    n = 16
+    g = inputs.rng(5)
+    A = inputs.paper_random_matrix(n, g, P)
+    LU, ipiv, _ = oracle.getrf(A, panel=4, pivot=True, algo="block", levels=0)
+    b = np.zeros((P, n, 1))
+    b[0, :, 0] = g.uniform(-1, 1, n)
+    x = exact_lu_solve(LU, ipiv, b)
+    xg = oracle.getrs(LU, ipiv, b)
+    bound = solve_diff_bound(LU, xg, u)[:, 0]
+    err = np.array([float(sum(Fraction(float(xg[c, i, 0])) for c in range(P)) - x[i])
+                    for i in range(n)])
+    assert np.all(np.abs(err) <= bound / 2)      # one solve: half of the two-solve bound
+    assert np.any(bound > 0)
+    # the same solve with the low-order planes of L's multipliers dropped
+    bad = LU.copy()
+    low = np.tril(np.ones((n, n), dtype=bool), -1)
+    bad[1:, low] = 0.0
+    xb = oracle.getrs(bad, ipiv, b)
+    diff = np.abs(vsum(xb - xg))[:, 0]
+    assert np.any(diff > solve_diff_bound(LU, xg, u)[:, 0])
