@@ -49,7 +49,7 @@ INT8_PEAK_T = 5000.0
 DD_OPS_PER_MAC = 12 + 6 / 16
 # FP64 operations per QD multiply-add of the QD Block FMA kernel (six
 # TwoProducts, four order-3 products, 14 TwoSums and 13 adds = 113, and a
-# 30-operation renormalisation every 16)
+# 30-operation renormalisation every 16) -- SQ_INSTS_VALU_*_F64 counts 114.91
 QD_OPS_PER_MAC = 113 + 30 / 16
 
 
@@ -370,7 +370,8 @@ def bench_graphs(dd, inputs, torch, dev):
 
 
 def bench_tuning(dd, inputs, torch, dev, n):
-    """Autotuned configuration per product kind at n (dd_gemm_tune / qd_gemm_tune)."""
+    """Autotuned configuration per product kind at n (dd_gemm_tune / qd_gemm_tune)
+    and LU panel width at n and 2n (ddqd_getrf_tune)."""
     out = {}
     g = inputs.rng(7)
     A = torch.from_numpy(inputs.dd_uniform(n, n, g)).to(dev)
@@ -387,6 +388,14 @@ def bench_tuning(dd, inputs, torch, dev, n):
         r["gflops"] = round(2.0 * n ** 3 / (r["ms"] * 1e-3) / 1e9, 1)
         r["ms"] = round(r["ms"], 4)
         out[f"qd_{base}_n{n}"] = r
+    # LU panel width per order (Sec. 4's K = 32 alpha sweep), Winograd-1 on Ozaki leaves
+    for nl in (n, 2 * n):
+        Al = torch.from_numpy(inputs.dd_lu_matrix(nl, inputs.rng(0))).to(dev)
+        r = dd.getrf_tune(Al, algo="winograd", levels=1, base="ozaki", reps=2)
+        r["gflops"] = round(2.0 / 3.0 * nl ** 3 / (r["ms"] * 1e-3) / 1e9, 1)
+        r["ms"] = round(r["ms"], 3)
+        out[f"lu_dd_winograd1_ozaki_n{nl}"] = r
+        del Al
     log(f"tuning: {out}")
     return out
 

@@ -72,6 +72,9 @@ extern "C" {
 #define DDQD_PIVOT_NONE 0
 #define DDQD_PIVOT_PARTIAL 1
 
+/* panel width for dd_getrf / qd_getrf: the tuned width (ddqd_getrf_tune) */
+#define DDQD_PANEL_AUTO (-1)
+
 /* Human-readable name of a status code. */
 const char* ddqd_status_string(int status);
 
@@ -193,8 +196,10 @@ size_t qd_gemm_workspace(int64_t m, int64_t n, int64_t l, int algo, int levels, 
  *            elimination step, every trailing row updated in parallel; Sec. 4
  *            compares the blocked LU against it); requires DDQD_PIVOT_NONE
  *            (else DDQD_E_UNSUPPORTED), ignores algo / levels / base and needs
- *            no workspace.
- *   ws       workspace of dd_getrf_workspace(...) bytes (the product's).
+ *            no workspace.  DDQD_PANEL_AUTO: the width ddqd_getrf_tune chose
+ *            for this order, pivoting and product, else 128.
+ *   ws       workspace of dd_getrf_workspace(...) bytes (the product's; with
+ *            DDQD_PANEL_AUTO, enough for every width the tuner may choose).
  * Orders above 8192 return DDQD_E_UNSUPPORTED.
  */
 int dd_getrf(int64_t n, double* A, int64_t lda, int64_t psa, int32_t* ipiv, int32_t* perm,
@@ -301,8 +306,40 @@ int qd_gemm_tune(int64_t m, int64_t n, int64_t l, const double* A, int64_t lda, 
  * DDQD_E_ARG for bad arguments. */
 int ddqd_tune_lookup(int precision, int64_t m, int64_t n, int64_t l, int base, int slices,
                      ddqd_tune_result* out);
-/* Empties the cache. */
+/* Empties the caches (products and LU panel widths). */
 void ddqd_tune_clear(void);
+
+/*
+ * LU panel width per order.  Sec. 4 runs the blocked LU with panel widths
+ * K = 32 alpha, alpha = 1..10; the fastest K depends on the order and on the
+ * product that updates the trailing matrix (Sec. 5 leaves the block size
+ * open).  ddqd_getrf_tune factors a copy of A with every such K <= n (K = n
+ * for n < 32), each `reps` times after one untimed run, and keeps the fastest
+ * in a process-wide, thread-safe cache keyed by (precision, n, pivot, algo,
+ * levels, base) that DDQD_PANEL_AUTO then uses.  Every width gives a correct
+ * factorization; only the speed is compared.
+ *   precision  2 (DD, dd_getrf) or 4 (QD, qd_getrf).
+ *   A          device plane-layout n x n matrix (lda, psa); not modified.
+ *   pivot, algo, levels, base  as dd_getrf.
+ *   reps       timed factorizations per width (1..100).
+ *   ws         ddqd_getrf_tune_workspace(precision, n, algo, levels, base)
+ *              bytes: the copy of A, its pivots and the factorization's
+ *              workspace for every width.
+ *   panel, ms  the chosen width and its time per factorization (either may
+ *              be NULL).
+ * Blocks the calling thread until the timing on `stream` is done; cannot be
+ * recorded in a graph.  Errors as dd_getrf (DDQD_E_ARG for a bad precision or
+ * reps; SIZE_MAX from the workspace query for bad arguments).
+ */
+int ddqd_getrf_tune(int precision, int64_t n, const double* A, int64_t lda, int64_t psa,
+                    int pivot, int algo, int levels, int base, int reps, void* ws,
+                    size_t ws_bytes, void* stream, int* panel, double* ms);
+size_t ddqd_getrf_tune_workspace(int precision, int64_t n, int algo, int levels, int base);
+/* The width DDQD_PANEL_AUTO uses (tuned, else 128); candidates = widths
+ * timed (0 if not tuned), ms = the chosen width's time (0 if not tuned); the
+ * last two may be NULL.  DDQD_E_ARG for bad arguments. */
+int ddqd_getrf_panel_lookup(int precision, int64_t n, int pivot, int algo, int levels, int base,
+                            int* panel, int* candidates, double* ms);
 
 /*
  * Captured launch sequences.  The calls above, issued on one non-null stream

@@ -18,7 +18,11 @@
 // the row permutation in `perm`.  U12 = L11^-1 A12 is a recursive triangular
 // solve (diagonal solves of up to 64 rows in DD, 32 in QD, one wave per
 // column; products for the off-diagonal parts).
+#include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
+#include <vector>
 
 #include "common.hpp"
 #include "ddqd.h"
@@ -205,11 +209,61 @@ constexpr size_t getrs_ws(int P, int64_t n, int64_t nrhs) {
   return getrs_x_bytes(P, n, nrhs) + getrs_flag_bytes(n) + sizeof(int32_t) * (size_t)n;
 }
 
+// ---- panel width per order (DDQD_PANEL_AUTO, ddqd_getrf_tune) -----------
+// Sec. 4 factors with panel widths K = 32 alpha, alpha = 1..10, and Sec. 5
+// leaves the block size open; the tuner times those widths (the ones not
+// above n; n itself for orders below 32) and keeps the fastest per order,
+// pivoting and trailing-update product.  Untuned orders use 128.
+constexpr int kDefaultPanel = 128;
+
+std::vector<int> panel_candidates(int64_t n) {
+  std::vector<int> c;
+  for (int a = 1; a <= 10; a++)
+    if (32 * a <= n) c.push_back(32 * a);
+  if (c.empty()) c.push_back((int)std::max<int64_t>(n, 1));
+  return c;
+}
+
+struct PanelKey {
+  int P;
+  int64_t n;
+  int pivot, algo, levels, base;
+  bool operator<(const PanelKey& o) const {
+    return std::tie(P, n, pivot, algo, levels, base) <
+           std::tie(o.P, o.n, o.pivot, o.algo, o.levels, o.base);
+  }
+};
+struct PanelChoice {
+  int panel, candidates;
+  double ms;
+};
+std::mutex g_panel_mu;
+std::map<PanelKey, PanelChoice> g_panel_cache;
+
+PanelChoice panel_choice(int P, int64_t n, int pivot, int algo, int levels, int base) {
+  std::lock_guard<std::mutex> lk(g_panel_mu);
+  auto it = g_panel_cache.find(PanelKey{P, n, pivot, algo, levels, base});
+  if (it != g_panel_cache.end()) return it->second;
+  return PanelChoice{kDefaultPanel, 0, 0.0};
+}
+
+// the product workspace of every width DDQD_PANEL_AUTO may resolve to
+size_t auto_panel_ws(int P, int64_t n, int algo, int levels, int base) {
+  size_t w = getrf_ws(P, n, kDefaultPanel, algo, levels, base);
+  for (int K : panel_candidates(n)) {
+    const size_t k = getrf_ws(P, n, K, algo, levels, base);
+    if (k == SIZE_MAX || w == SIZE_MAX) return SIZE_MAX;
+    w = std::max(w, k);
+  }
+  return w;
+}
+
 size_t getrf_workspace_entry(int P, int64_t n, int panel_width, int algo, int levels, int base) {
-  if (n < 0 || panel_width < 0 || algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 ||
-      base > 1)
+  if (n < 0 || panel_width < DDQD_PANEL_AUTO || algo < 0 || algo > 3 || levels < 0 ||
+      levels > 6 || base < 0 || base > 1)
     return SIZE_MAX;
   if (panel_width == 0) return 0;  // the row-wise comparator needs none
+  if (panel_width == DDQD_PANEL_AUTO) return auto_panel_ws(P, n, algo, levels, base);
   return getrf_ws(P, n, panel_width, algo, levels, base);
 }
 
@@ -218,9 +272,13 @@ int getrf_entry(int P, int64_t n, double* A, int64_t lda, int64_t psa, int32_t* 
                 int base, void* ws, size_t ws_bytes, void* stream) {
   clear_error();
   if (n < 0) return set_error(DDQD_E_ARG, "negative order");
-  if (panel_width < 0) return set_error(DDQD_E_ARG, "panel width must be >= 0");
+  if (panel_width < DDQD_PANEL_AUTO)
+    return set_error(DDQD_E_ARG, "panel width must be >= 0 or DDQD_PANEL_AUTO");
   if (pivot != DDQD_PIVOT_NONE && pivot != DDQD_PIVOT_PARTIAL)
     return set_error(DDQD_E_ARG, "pivot must be DDQD_PIVOT_NONE or DDQD_PIVOT_PARTIAL");
+  if (panel_width == DDQD_PANEL_AUTO && algo >= 0 && algo <= 3 && levels >= 0 && levels <= 6 &&
+      base >= 0 && base <= 1)
+    panel_width = panel_choice(P, n, pivot, algo, levels, base).panel;
   if (panel_width == 0 && pivot != DDQD_PIVOT_NONE)
     return set_error(DDQD_E_UNSUPPORTED, "the row-wise form (panel width 0) does not pivot");
   if (algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 || base > 1)
@@ -289,6 +347,104 @@ int getrs_entry(int P, int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, 
     if ((rc = launch_trsv_chain(P, LU, ldlu, pslu, X, n, nc, 1, flags, s))) return rc;
     if ((rc = launch_scatter_rows(P, X, n, nc, B + c0, ldb, psb, s))) return rc;
   }
+  return DDQD_OK;
+}
+
+// Tuning workspace: a copy of A, the pivots (ipiv, perm, info) and the
+// factorization's workspace for every candidate width.
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t getrf_tune_ws(int P, int64_t n, int algo, int levels, int base) {
+  if (n < 0 || n > kMaxLuRows || algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 ||
+      base > 1)
+    return SIZE_MAX;
+  const size_t prod = auto_panel_ws(P, n, algo, levels, base);
+  if (prod == SIZE_MAX) return SIZE_MAX;
+  return align256(sizeof(double) * P * (size_t)(n * n)) +
+         align256(sizeof(int32_t) * (size_t)(2 * n + 1)) + prod;
+}
+
+int getrf_tune(int P, int64_t n, const double* A, int64_t lda, int64_t psa, int pivot, int algo,
+               int levels, int base, int reps, void* ws, size_t ws_bytes, void* stream,
+               int* panel_out, double* ms_out) {
+  clear_error();
+  if (reps < 1 || reps > 100) return set_error(DDQD_E_ARG, "reps must be in 1..100");
+  if (n < 0) return set_error(DDQD_E_ARG, "negative order");
+  if (n > kMaxLuRows)
+    return set_error(DDQD_E_UNSUPPORTED, "LU of order above %lld", (long long)kMaxLuRows);
+  if (pivot != DDQD_PIVOT_NONE && pivot != DDQD_PIVOT_PARTIAL)
+    return set_error(DDQD_E_ARG, "pivot must be DDQD_PIVOT_NONE or DDQD_PIVOT_PARTIAL");
+  if (algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 || base > 1)
+    return set_error(DDQD_E_ARG, "bad product algorithm / levels / base");
+  int rc;
+  if ((rc = check_matrix("A", P, A, n, n, lda, psa))) return rc;
+  const size_t need = getrf_tune_ws(P, n, algo, levels, base);
+  if (need == SIZE_MAX) return set_error(DDQD_E_ARG, "bad product arguments");
+  if (need > ws_bytes || (need > 0 && !ws))
+    return set_error(DDQD_E_WORKSPACE, "workspace of %zu bytes needed, %zu given", need,
+                     ws_bytes);
+  if ((rc = check_device())) return rc;
+  if (n == 0) {
+    if (panel_out) *panel_out = kDefaultPanel;
+    if (ms_out) *ms_out = 0.0;
+    return DDQD_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double* Ac = (double*)ws;
+  int32_t* ipiv = (int32_t*)((char*)ws + align256(sizeof(double) * P * (size_t)(n * n)));
+  int32_t* perm = ipiv + n;
+  int32_t* info = perm + n;
+  char* pw = (char*)ipiv + align256(sizeof(int32_t) * (size_t)(2 * n + 1));
+  const size_t pw_bytes = need - (size_t)(pw - (char*)ws);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return set_error(DDQD_E_HIP, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return set_error(DDQD_E_HIP, "hipEventCreate failed");
+  }
+  const std::vector<int> cs = panel_candidates(n);
+  PanelChoice best{kDefaultPanel, (int)cs.size(), 0.0};
+  bool have = false;
+  for (int K : cs) {
+    double total = 0.0;
+    for (int r = 0; r <= reps && !rc; r++) {  // the first factorization is not timed
+      for (int c = 0; c < P && !rc; c++)
+        if (hipMemcpy2DAsync(Ac + c * n * n, sizeof(double) * n, A + c * psa, sizeof(double) * lda,
+                             sizeof(double) * n, n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+          rc = set_error(DDQD_E_HIP, "copy of A failed");
+      if (rc) break;
+      float ms = 0.0f;
+      if (hipEventRecord(e0, s) != hipSuccess) {
+        rc = set_error(DDQD_E_HIP, "hipEventRecord failed");
+        break;
+      }
+      if ((rc = getrf_entry(P, n, Ac, n, n * n, ipiv, perm, info, K, pivot, algo, levels, base, pw,
+                            pw_bytes, stream)))
+        break;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = set_error(DDQD_E_HIP, "timing events failed");
+        break;
+      }
+      if (r > 0) total += ms;
+    }
+    if (rc) break;
+    const double per = total / reps;
+    if (!have || per < best.ms) {
+      best.panel = K;
+      best.ms = per;
+      have = true;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_panel_mu);
+    g_panel_cache[PanelKey{P, n, pivot, algo, levels, base}] = best;
+  }
+  if (panel_out) *panel_out = best.panel;
+  if (ms_out) *ms_out = best.ms;
   return DDQD_OK;
 }
 
@@ -368,9 +524,47 @@ int getrs_noalloc_entry(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu,
 }  // namespace
 }  // namespace ddqd
 
+namespace ddqd {
+void lu_tune_clear() {
+  std::lock_guard<std::mutex> lk(g_panel_mu);
+  g_panel_cache.clear();
+}
+}  // namespace ddqd
+
 using namespace ddqd;
 
 extern "C" {
+
+int ddqd_getrf_tune(int precision, int64_t n, const double* A, int64_t lda, int64_t psa,
+                    int pivot, int algo, int levels, int base, int reps, void* ws,
+                    size_t ws_bytes, void* stream, int* panel, double* ms) {
+  if (precision != 2 && precision != 4) {
+    clear_error();
+    return set_error(DDQD_E_ARG, "precision must be 2 (DD) or 4 (QD)");
+  }
+  return getrf_tune(precision, n, A, lda, psa, pivot, algo, levels, base, reps, ws, ws_bytes,
+                    stream, panel, ms);
+}
+
+size_t ddqd_getrf_tune_workspace(int precision, int64_t n, int algo, int levels, int base) {
+  if (precision != 2 && precision != 4) return SIZE_MAX;
+  return getrf_tune_ws(precision, n, algo, levels, base);
+}
+
+int ddqd_getrf_panel_lookup(int precision, int64_t n, int pivot, int algo, int levels, int base,
+                            int* panel, int* candidates, double* ms) {
+  clear_error();
+  if (!panel) return set_error(DDQD_E_ARG, "panel is NULL");
+  if ((precision != 2 && precision != 4) || n < 0 ||
+      (pivot != DDQD_PIVOT_NONE && pivot != DDQD_PIVOT_PARTIAL) || algo < 0 || algo > 3 ||
+      levels < 0 || levels > 6 || base < 0 || base > 1)
+    return set_error(DDQD_E_ARG, "invalid panel lookup arguments");
+  const PanelChoice c = panel_choice(precision, n, pivot, algo, levels, base);
+  *panel = c.panel;
+  if (candidates) *candidates = c.candidates;
+  if (ms) *ms = c.ms;
+  return DDQD_OK;
+}
 
 size_t dd_getrf_workspace(int64_t n, int panel_width, int algo, int levels, int base) {
   return getrf_workspace_entry(2, n, panel_width, algo, levels, base);

@@ -23,6 +23,7 @@ int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* 
 size_t plan_workspace(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
                       int slices);
 void clear_error();
+void lu_tune_clear();
 
 namespace {
 
@@ -216,8 +217,11 @@ int ddqd_tune_lookup(int precision, int64_t m, int64_t n, int64_t l, int base, i
 }
 
 void ddqd_tune_clear(void) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  g_cache.clear();
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache.clear();
+  }
+  lu_tune_clear();
 }
 
 }  // extern "C"

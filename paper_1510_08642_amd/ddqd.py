@@ -96,6 +96,14 @@ _lib.ddqd_tune_lookup.argtypes = [_int, _i64, _i64, _i64, _int, _int, ctypes.POI
 _lib.ddqd_tune_lookup.restype = _int
 _lib.ddqd_tune_clear.argtypes = []
 _lib.ddqd_tune_clear.restype = None
+_lib.ddqd_getrf_tune.argtypes = [_int, _i64, _vp, _i64, _i64, _int, _int, _int, _int, _int, _vp,
+                                 _sz, _vp, ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)]
+_lib.ddqd_getrf_tune.restype = _int
+_lib.ddqd_getrf_tune_workspace.argtypes = [_int, _i64, _int, _int, _int]
+_lib.ddqd_getrf_tune_workspace.restype = _sz
+_lib.ddqd_getrf_panel_lookup.argtypes = [_int, _i64, _int, _int, _int, _int, ctypes.POINTER(_int),
+                                         ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)]
+_lib.ddqd_getrf_panel_lookup.restype = _int
 _lib.ddqd_graph_begin.argtypes = [_vp]
 _lib.ddqd_graph_begin.restype = _int
 _lib.ddqd_graph_end.argtypes = [_vp, ctypes.POINTER(_vp)]
@@ -106,6 +114,11 @@ _lib.ddqd_graph_destroy.argtypes = [_vp]
 _lib.ddqd_graph_destroy.restype = _int
 
 SIZE_MAX = ctypes.c_size_t(-1).value
+PANEL_AUTO = -1     # DDQD_PANEL_AUTO
+
+
+def _panel(panel):
+    return PANEL_AUTO if panel == "auto" else int(panel)
 
 
 class DDQDError(RuntimeError):
@@ -193,7 +206,8 @@ def qd_gemm(A, B, C=None, *, alpha=1, beta=0, algo="block", levels=0, base="fma"
 
 
 def getrf_workspace(n: int, panel=128, algo="winograd", levels=1, base="fma", P: int = 2) -> int:
-    ws = getattr(_lib, f"{_PREC[P]}_getrf_workspace")(n, panel, ALGO[algo], levels, BASE[base])
+    ws = getattr(_lib, f"{_PREC[P]}_getrf_workspace")(n, _panel(panel), ALGO[algo], levels,
+                                                      BASE[base])
     if ws == SIZE_MAX:
         raise ValueError("invalid getrf arguments")
     return ws
@@ -203,7 +217,8 @@ def dd_getrf(A, *, panel=128, pivot="partial", algo="winograd", levels=1, base="
              want_perm=True, ws=None, out=None):
     """In-place DD LU of the square (2, n, n) tensor A (blocked right-looking,
     panel width `panel`, trailing update by `algo`/`levels`/`base`; panel=0
-    is the paper's row-wise parallel comparator, pivot="none" only).
+    is the paper's row-wise parallel comparator, pivot="none" only;
+    panel="auto" the width getrf_tune chose for this order, else 128).
 
     Returns (ipiv, perm, info) as device int32 tensors: LAPACK-style 0-based
     interchanges, the resulting row permutation (or None), and info (0, or the
@@ -240,7 +255,7 @@ def _getrf(P, A, panel, pivot, algo, levels, base, want_perm, ws, out):
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     st = getattr(_lib, f"{_PREC[P]}_getrf")(
         n, pa, lda, psa, ipiv.data_ptr(), perm.data_ptr() if perm is not None else None,
-        info.data_ptr(), panel, PIVOT[pivot], ALGO[algo], levels, BASE[base], ws.data_ptr(),
+        info.data_ptr(), _panel(panel), PIVOT[pivot], ALGO[algo], levels, BASE[base], ws.data_ptr(),
         ws.numel(), _stream_of(A))
     _check(st, f"{_PREC[P]}_getrf")
     return ipiv[:n], (perm[:n] if perm is not None else None), info
@@ -426,3 +441,34 @@ def tune_lookup(P: int, m: int, n: int, l: int, base="fma", slices=0):
 
 def tune_clear() -> None:
     _lib.ddqd_tune_clear()
+
+
+def getrf_tune(A, *, pivot="partial", algo="winograd", levels=1, base="fma", reps=2, ws=None):
+    """Times dd_getrf / qd_getrf (by the number of planes) of a copy of A
+    with the panel widths K = 32, 64, ..., 320 (those <= n) and caches the
+    fastest for panel="auto"; A is not modified.  Returns
+    dict(panel, ms, candidates)."""
+    P, n = A.shape[0], A.shape[1]
+    if P not in (2, 4) or A.dim() != 3 or A.shape[2] != n:
+        raise ValueError("A must be a square (2 | 4, n, n) tensor")
+    pa, lda, psa = _mat(A, P, "A")
+    need = _lib.ddqd_getrf_tune_workspace(P, n, ALGO[algo], levels, BASE[base])
+    if need == SIZE_MAX:
+        raise ValueError("invalid getrf_tune arguments")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    panel, ms = _int(0), ctypes.c_double(0.0)
+    _check(_lib.ddqd_getrf_tune(P, n, pa, lda, psa, PIVOT[pivot], ALGO[algo], levels, BASE[base],
+                                reps, ws.data_ptr(), ws.numel(), _stream_of(A),
+                                ctypes.byref(panel), ctypes.byref(ms)), "ddqd_getrf_tune")
+    return getrf_panel_lookup(P, n, pivot=pivot, algo=algo, levels=levels, base=base)
+
+
+def getrf_panel_lookup(P: int, n: int, *, pivot="partial", algo="winograd", levels=1,
+                       base="fma"):
+    """The panel width panel="auto" uses for this order and product."""
+    panel, cands, ms = _int(0), _int(0), ctypes.c_double(0.0)
+    _check(_lib.ddqd_getrf_panel_lookup(P, n, PIVOT[pivot], ALGO[algo], levels, BASE[base],
+                                        ctypes.byref(panel), ctypes.byref(cands),
+                                        ctypes.byref(ms)), "ddqd_getrf_panel_lookup")
+    return dict(panel=panel.value, candidates=cands.value, ms=ms.value)

@@ -134,7 +134,8 @@ def test_lu_argument_errors(lib):
                             a["panel"], a["pivot"], a["algo"], a["levels"], a["base"], a["ws"],
                             a["wsb"], None)
     assert call(n=-1) == E["ARG"]
-    assert call(panel=-1) == E["ARG"]
+    assert call(panel=-2) == E["ARG"]
+    assert call(panel=-1) == E["NODEVICE"]      # DDQD_PANEL_AUTO: a valid width
     # panel 0 is the row-wise comparator: no pivoting, no workspace
     assert call(panel=0) == E["UNSUPPORTED"]
     assert lib.dd_getrf_workspace(1024, 0, 3, 2, 1) == 0
@@ -190,6 +191,47 @@ def test_tune_defaults_and_errors(lib):
     # reps out of range is rejected before any device work
     assert lib.dd_gemm_tune(8, 8, 8, 0x10000, 8, 64, 0x20000, 8, 64, 0x30000, 8, 64, 0, 0, 0,
                             None, 0, None, None) == E["ARG"]
+
+
+def test_lu_panel_tuner_defaults_workspace_and_errors(lib):
+    import ctypes as C
+    from paper_1510_08642_amd import ddqd
+    ddqd.tune_clear()
+    for P in (2, 4):
+        d = ddqd.getrf_panel_lookup(P, 2048, algo="winograd", levels=1, base="ozaki")
+        assert d == dict(panel=128, candidates=0, ms=0.0)
+    # the AUTO workspace covers every width the tuner may choose (K = 32 .. 320)
+    for P, f in ((2, lib.dd_getrf_workspace), (4, lib.qd_getrf_workspace)):
+        for n in (40, 300, 2048):
+            auto = f(n, -1, 3, 1, 1)
+            assert auto != ddqd.SIZE_MAX
+            for K in [32 * a for a in range(1, 11) if 32 * a <= n] + [128]:
+                assert auto >= f(n, K, 3, 1, 1), (P, n, K)
+        assert f(64, -2, 1, 0, 0) == ddqd.SIZE_MAX
+    # tuning workspace: a copy of A, the pivots, and the product workspace
+    tw = lib.ddqd_getrf_tune_workspace(2, 300, 3, 1, 1)
+    assert tw >= 2 * 300 * 300 * 8 + 4 * 601 + lib.dd_getrf_workspace(300, -1, 3, 1, 1)
+    assert lib.ddqd_getrf_tune_workspace(3, 300, 3, 1, 1) == ddqd.SIZE_MAX
+    assert lib.ddqd_getrf_tune_workspace(2, 9000, 3, 1, 1) == ddqd.SIZE_MAX
+    panel, cands, ms = C.c_int(0), C.c_int(0), C.c_double(0.0)
+    assert lib.ddqd_getrf_panel_lookup(3, 64, 1, 1, 0, 0, C.byref(panel), None, None) == E["ARG"]
+    assert lib.ddqd_getrf_panel_lookup(2, 64, 2, 1, 0, 0, C.byref(panel), None, None) == E["ARG"]
+    assert lib.ddqd_getrf_panel_lookup(2, 64, 1, 1, 0, 0, None, None, None) == E["ARG"]
+    assert lib.ddqd_getrf_panel_lookup(2, 64, 1, 1, 0, 0, C.byref(panel), C.byref(cands),
+                                       C.byref(ms)) == E["OK"]
+    assert (panel.value, cands.value) == (128, 0)
+    # argument errors before any device work
+    A = 0x10000
+    assert lib.ddqd_getrf_tune(3, 8, A, 8, 64, 1, 1, 0, 0, 1, 0x90000, 1 << 20, None, None,
+                               None) == E["ARG"]
+    assert lib.ddqd_getrf_tune(2, 8, A, 8, 64, 1, 1, 0, 0, 0, 0x90000, 1 << 20, None, None,
+                               None) == E["ARG"]
+    assert lib.ddqd_getrf_tune(2, 8, A, 4, 64, 1, 1, 0, 0, 1, 0x90000, 1 << 20, None, None,
+                               None) == E["ARG"]
+    assert lib.ddqd_getrf_tune(2, 8, A, 8, 64, 1, 1, 0, 0, 1, None, 0, None, None,
+                               None) == E["WORKSPACE"]
+    assert lib.ddqd_getrf_tune(2, 8, A, 8, 64, 1, 1, 0, 0, 1, 0x90000, 1 << 20, None, None,
+                               None) == E["NODEVICE"]
 
 
 def test_auto_workspace_covers_every_candidate(lib):

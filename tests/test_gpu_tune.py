@@ -106,3 +106,33 @@ def test_tuned_ozaki_band_is_bit_identical(dd, P):
     Ce = gem(Ad, Bd, algo=r["algo"], levels=r["levels"], base="ozaki")
     torch.cuda.synchronize()
     assert torch.equal(Ca, Ce), r
+
+
+@pytest.mark.parametrize("P,n,base", [(2, 300, "ozaki"), (2, 70, "fma"), (4, 200, "fma")])
+def test_lu_panel_tuner_picks_a_width_and_auto_reproduces_it(dd, P, n, base):
+    """ddqd_getrf_tune times the panel widths K = 32 alpha <= n (Sec. 4's
+    sweep) on a copy of A; panel="auto" then factors with the chosen width,
+    bit for bit as the explicit call, and A is left unchanged."""
+    import torch
+    print(f"case lu panel tune P={P} n={n} {base}", flush=True)
+    dd.tune_clear()
+    g = inputs.rng(420 + n)
+    A = (inputs.dd_lu_matrix if P == 2 else inputs.qd_lu_matrix)(n, g)
+    Ad = to_dev(A)
+    kw = dict(algo="winograd", levels=1, base=base)
+    r = dd.getrf_tune(Ad, reps=1, **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(Ad), A)
+    widths = [32 * a for a in range(1, 11) if 32 * a <= n]
+    assert r["panel"] in widths and r["candidates"] == len(widths) and r["ms"] > 0
+    assert dd.getrf_panel_lookup(P, n, **kw) == r
+    getrf = dd.dd_getrf if P == 2 else dd.qd_getrf
+    A1, A2 = Ad.clone(), Ad.clone()
+    f1 = getrf(A1, panel="auto", **kw)
+    f2 = getrf(A2, panel=r["panel"], **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(A1, A2)
+    assert torch.equal(f1[0], f2[0]) and torch.equal(f1[1], f2[1])
+    assert int(to_host(f1[2])[0]) == 0
+    # an order whose width was not tuned keeps the default
+    assert dd.getrf_panel_lookup(P, n + 1, **kw)["panel"] == 128
