@@ -587,6 +587,9 @@ def main():
     ap.add_argument("--lu-only", type=int, default=0, metavar="N",
                     help="only time the DD LU factor-and-solve of order N (panel 128, Winograd 1 "
                          "on Ozaki leaves), for kernel traces of the LU")
+    ap.add_argument("--latency-probe", action="store_true",
+                    help="print the dependent-chain latencies of the LU column step's "
+                         "operations (ddqd_latency_probe) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB, 5 times "
                          "(reference kernel for scaling HBM byte counters)")
@@ -609,6 +612,11 @@ def main():
     sys.path.insert(0, ROOT)
     from paper_1510_08642_amd import ddqd as dd
     from paper_1510_08642_amd import inputs
+    if args.latency_probe:
+        for threads in (64, 256, 1024):
+            dd.latency_probe(threads)                 # warm-up
+            print(json.dumps({"threads": threads, "ticks_per_step": dd.latency_probe(threads)}))
+        return
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)

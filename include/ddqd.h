@@ -306,6 +306,19 @@ int qd_gemm_tune(int64_t m, int64_t n, int64_t l, const double* A, int64_t lda, 
  * DDQD_E_ARG for bad arguments. */
 int ddqd_tune_lookup(int precision, int64_t m, int64_t n, int64_t l, int base, int slices,
                      ddqd_tune_result* out);
+/*
+ * Diagnostic: dependent-chain latencies, in s_memtime ticks per step, of the
+ * operations the LU column step is made of, timed inside one workgroup of
+ * `threads` (64, 256 or 1024) threads over `steps` steps (1..2^20): out[0] a
+ * dependent FP64 FMA, out[1] a dependent FP64 add, out[2] a TwoSum, out[3] a
+ * lane shuffle with a max, out[4] two readlanes and an add, out[5] an LDS
+ * write and read, out[6] two barriers around an LDS exchange, out[7] one step
+ * of four independent FMA chains.  out: device double[9] (out[8] is
+ * scratch).  Computes nothing the library uses.  DDQD_E_ARG for bad
+ * arguments.
+ */
+int ddqd_latency_probe(double* out, int threads, int steps, void* stream);
+
 /* Empties the caches (products and LU panel widths). */
 void ddqd_tune_clear(void);
 

@@ -104,6 +104,8 @@ _lib.ddqd_getrf_tune_workspace.restype = _sz
 _lib.ddqd_getrf_panel_lookup.argtypes = [_int, _i64, _int, _int, _int, _int, ctypes.POINTER(_int),
                                          ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)]
 _lib.ddqd_getrf_panel_lookup.restype = _int
+_lib.ddqd_latency_probe.argtypes = [_vp, _int, _int, _vp]
+_lib.ddqd_latency_probe.restype = _int
 _lib.ddqd_graph_begin.argtypes = [_vp]
 _lib.ddqd_graph_begin.restype = _int
 _lib.ddqd_graph_end.argtypes = [_vp, ctypes.POINTER(_vp)]
@@ -472,3 +474,18 @@ def getrf_panel_lookup(P: int, n: int, *, pivot="partial", algo="winograd", leve
                                         ctypes.byref(panel), ctypes.byref(cands),
                                         ctypes.byref(ms)), "ddqd_getrf_panel_lookup")
     return dict(panel=panel.value, candidates=cands.value, ms=ms.value)
+
+
+LATENCY_NAMES = ("fma", "add", "two_sum", "shuffle_max", "readlane2_add", "lds_roundtrip",
+                 "two_barriers_lds", "fma_x4_independent")
+
+
+def latency_probe(threads: int = 256, steps: int = 2048, device="cuda"):
+    """ddqd_latency_probe: s_memtime ticks per dependent step of the LU column
+    step's building blocks (a diagnostic; see include/ddqd.h)."""
+    out = torch.zeros(9, dtype=torch.float64, device=device)
+    s = torch.cuda.current_stream(out.device)
+    _check(_lib.ddqd_latency_probe(out.data_ptr(), threads, steps, ctypes.c_void_p(s.cuda_stream)),
+           "ddqd_latency_probe")
+    s.synchronize()
+    return dict(zip(LATENCY_NAMES, [round(v, 1) for v in out[:8].tolist()]))

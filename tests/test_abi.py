@@ -234,6 +234,15 @@ def test_lu_panel_tuner_defaults_workspace_and_errors(lib):
                                None) == E["NODEVICE"]
 
 
+def test_latency_probe_argument_errors(lib):
+    import ctypes as C
+    out = C.c_void_p(0x10000)
+    assert lib.ddqd_latency_probe(None, 64, 16, None) == E["ARG"]
+    assert lib.ddqd_latency_probe(out, 128, 16, None) == E["ARG"]
+    assert lib.ddqd_latency_probe(out, 64, 0, None) == E["ARG"]
+    assert lib.ddqd_latency_probe(out, 64, 16, None) == E["NODEVICE"]
+
+
 def test_auto_workspace_covers_every_candidate(lib):
     for P, f in ((2, lib.dd_gemm_workspace), (4, lib.qd_gemm_workspace)):
         for (m, n, l) in [(1024, 1024, 1024), (300, 129, 257), (40, 40, 40)]:

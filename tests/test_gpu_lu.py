@@ -323,3 +323,12 @@ def test_getrs_with_the_device_busy_is_bit_identical(dd, P):
         torch.cuda.synchronize()
         assert torch.equal(X, ref), rep
         assert torch.equal(LU2, LU) and torch.equal(ipiv2, ipiv), rep
+
+
+def test_latency_probe_runs(dd):
+    """The diagnostic behind the strip kernel's profile: every chain reports a
+    positive latency, and a TwoSum (dependent adds) takes longer than one add."""
+    for threads in (64, 1024):
+        r = dd.latency_probe(threads, steps=256)
+        assert all(v > 0 for v in r.values()), r
+        assert r["two_sum"] > r["add"]
