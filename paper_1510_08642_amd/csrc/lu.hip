@@ -928,22 +928,29 @@ constexpr int kTrsvWgs = 32;  // workgroups of one triangular solve launch
 // One triangle of X := T^-1 X (unit lower, or upper with its diagonal; X is
 // n x nrhs, nrhs <= 16, tight) in one launch of G <= kTrsvWgs workgroups:
 // workgroup w solves the block rows of TB rows in steps s = w, w + G, ...,
-// step s being block row I = s (lower) or nb - 1 - s (upper).  It first applies, in the
-// order they are solved, every block J it depends on (J < I lower, J > I
-// upper): it stages T_IJ while it waits for J's flag, then forms
-// sum_k T_IJ[i][k] X_J[k][c] with tpe threads per entry (each a slice of k
-// accumulated lazily, the slices summed in a fixed butterfly) and subtracts
-// it from its entry of X_I.  Then it solves the diagonal block (one wave per
-// right-hand side, lane = row: step k finishes x_k, broadcasts it with
-// readlane, the other lanes subtract T_ik x_k; the upper solve multiplies by
-// reciprocals of the diagonal formed by all lanes at once), stores X_I and
-// publishes it: flag[I] := tag (1 lower, 2 upper) with release semantics at
-// device scope, after the values were stored with device-coherent stores;
-// readers acquire the flag and load the values device-coherently.  Step s
-// waits only for earlier steps, so the chain progresses once every
-// workgroup of the launch has been dispatched (a few dozen workgroups: a
-// handful of concurrent solves cannot fill the device with waiting ones).
-// The accumulation order is fixed: the result does not depend on timing.
+// step s being block row I = s (lower) or nb - 1 - s (upper).
+//   1. It first forms Z = D^-1 of its diagonal block D = T_II, while it has
+//      nothing else to do (the chain reaches block I only after the blocks
+//      before it): wave v computes the columns v, v + 16, ... of Z, lane =
+//      row, by substitution on the unit vectors (the upper solve multiplies
+//      by reciprocals of the diagonal formed by all lanes at once), the
+//      columns of one wave interleaved so that their dependent chains
+//      overlap.
+//   2. It applies, in the order they are solved, every block J it depends
+//      on (J < I lower, J > I upper): it stages T_IJ while it waits for J's
+//      flag, then forms sum_k T_IJ[i][k] X_J[k][c] with tpe threads per
+//      entry (each a slice of k accumulated lazily, the slices summed in a
+//      fixed butterfly) and subtracts it from its entry r_I.
+//   3. X_I = Z r_I, by the same sliced products, is stored with
+//      device-coherent stores and published: flag[I] := tag (1 lower,
+//      2 upper) with release semantics at device scope; readers acquire the
+//      flag and load the values device-coherently.
+// So the chain's step from one block to the next is two small parallel
+// products and a flag, not a row-by-row substitution.  Step s waits only
+// for earlier steps, so the chain progresses once every workgroup of the
+// launch has been dispatched (a few dozen workgroups: a handful of
+// concurrent solves cannot fill the device with waiting ones).  The
+// accumulation order is fixed: the result does not depend on timing.
 template <int P>
 __global__ __launch_bounds__(1024) void trsv_chain_kernel(const double* T, int64_t ldt,
                                                           int64_t pst, double* X, int64_t n,
@@ -952,8 +959,10 @@ __global__ __launch_bounds__(1024) void trsv_chain_kernel(const double* T, int64
   using V = typename N::T;
   constexpr int TB = trsv_block<P>();
   constexpr int kPer = (TB * TB + 1023) / 1024;  // tile elements per thread
-  __shared__ double Ws[P][TB][TB + 1];            // T_IJ, then the diagonal block
-  __shared__ double Ys[P][TB][17];                // X_J, then X_I
+  constexpr int kZc = TB / 16;                   // columns of Z per wave
+  __shared__ double Ws[P][TB][TB + 1];            // T_IJ
+  __shared__ double Zs[P][TB][TB + 1];            // D = T_II, then Z = D^-1
+  __shared__ double Ys[P][TB][17];                // X_J, then r_I, then X_I
   const int64_t nb = (n + TB - 1) / TB;
   for (int64_t s = blockIdx.x; s < nb; s += gridDim.x) {
     const int64_t I = upper ? nb - 1 - s : s;
@@ -963,8 +972,8 @@ __global__ __launch_bounds__(1024) void trsv_chain_kernel(const double* T, int64
     const int t = threadIdx.x, lane = t % 64, wave = t / 64;
     const int nr = (int)nrhs;
     const int64_t psx = n * nrhs;
-    // threads per entry of X_I in the updates: a power of two <= 16 (lanes of
-    // one wave) with rows * nr * tpe <= 1024
+    // threads per entry of X_I in the products: a power of two <= 16 (lanes
+    // of one wave) with rows * nr * tpe <= 1024
     int tpe = 1;
     while (tpe < 16 && rows * nr * tpe * 2 <= 1024) tpe *= 2;
     const int ent = t / tpe, slice = t % tpe;
@@ -988,17 +997,89 @@ __global__ __launch_bounds__(1024) void trsv_chain_kernel(const double* T, int64
           v[q][c] = in ? T[c * pst + o] : ((J == I && c == 0 && i == k) ? 1.0 : 0.0);
       }
     };
-    auto to_lds = [&](const double (&v)[kPer][P]) {
+    auto to_lds = [&](const double (&v)[kPer][P], double (&W)[P][TB][TB + 1]) {
 #pragma unroll
       for (int q = 0; q < kPer; q++) {
         const int e = t + 1024 * q, i = e / TB, k = e % TB;
         if (e < TB * TB)
 #pragma unroll
-          for (int c = 0; c < P; c++) Ws[c][i][k] = v[q][c];
+          for (int c = 0; c < P; c++) W[c][i][k] = v[q][c];
       }
     };
-    double v[kPer][P], vd[kPer][P];
-    stage(I, vd);  // the diagonal block, needed last, requested first
+    // -(sum over this thread's slice of k of W[ui][k] Ys[k][uc]), the slices
+    // of an entry then summed by a butterfly inside the wave (every thread
+    // of the entry ends with the same value)
+    auto product = [&](const double (&W)[P][TB][TB + 1], int cols) {
+      typename N::Acc a = N::acc(N::zero());
+      if (uin)
+        for (int k = slice; k < cols; k += tpe) {
+          V tv, yv;
+#pragma unroll
+          for (int c = 0; c < P; c++) {
+            N::put(tv, c, W[c][ui][k]);
+            N::put(yv, c, Ys[c][k][uc]);
+          }
+          N::acc_sub(a, tv, yv);
+        }
+      V part = N::value(a);
+      for (int off = 1; off < tpe; off <<= 1) {
+        V o;
+#pragma unroll
+        for (int c = 0; c < P; c++) N::put(o, c, __shfl_xor(N::get(part, c), off, 64));
+        part = (slice & off) ? N::add(o, part) : N::add(part, o);
+      }
+      return part;
+    };
+    {
+      // 1. Z = D^-1
+      double vd[kPer][P];
+      stage(I, vd);
+      __syncthreads();  // the previous step's readers of Zs are done
+      to_lds(vd, Zs);
+      __syncthreads();
+      auto dval = [&](int i, int k) {
+        V r;
+#pragma unroll
+        for (int c = 0; c < P; c++) N::put(r, c, Zs[c][i][k]);
+        return r;
+      };
+      typename N::Acc za[kZc];
+#pragma unroll
+      for (int q = 0; q < kZc; q++) za[q] = N::acc(lane == wave + 16 * q ? N::one() : N::zero());
+      if (!upper) {
+        for (int k = 0; k < TB - 1; k++) {
+#pragma unroll
+          for (int q = 0; q < kZc; q++) {
+            if (k < wave + 16 * q) continue;  // uniform: column j starts at row j
+            const V zk = readlane_words<P>(za[q], k);
+            if (lane > k && lane < TB) N::acc_sub(za[q], dval(lane, k), zk);
+          }
+        }
+      } else {
+        const V inv = lane < TB ? N::div(N::one(), dval(lane, lane)) : N::zero();
+        for (int k = TB - 1; k >= 0; k--) {
+#pragma unroll
+          for (int q = 0; q < kZc; q++) {
+            if (k > wave + 16 * q) continue;  // uniform: column j has rows <= j
+            const V zk = N::mul(readlane_words<P>(za[q], k), readlane_num<P>(inv, k));
+            if (lane == k)
+              za[q] = N::acc(zk);
+            else if (lane < k)
+              N::acc_sub(za[q], dval(lane, k), zk);
+          }
+        }
+      }
+      __syncthreads();  // every wave has read D
+      if (lane < TB)
+#pragma unroll
+        for (int q = 0; q < kZc; q++) {
+          const V z = N::value(za[q]);
+#pragma unroll
+          for (int c = 0; c < P; c++) Zs[c][lane][wave + 16 * q] = N::get(z, c);
+        }
+    }
+    // 2. the blocks this one depends on
+    double v[kPer][P];
     for (int64_t d = 0; d < s; d++) {
       const int64_t J = upper ? nb - 1 - d : d;
       stage(J, v);  // the tile's loads fly while this workgroup waits for J
@@ -1023,79 +1104,39 @@ __global__ __launch_bounds__(1024) void trsv_chain_kernel(const double* T, int64
             Ys[c][yi][yc] = __hip_atomic_load(X + c * psx + (j0 + yi) * nrhs + yc,
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      to_lds(v);
+      to_lds(v, Ws);
       __syncthreads();
-      // sum over this thread's slice of k, then the slices of an entry summed
-      // by a butterfly inside the wave
-      typename N::Acc a = N::acc(N::zero());
-      if (uin)
-        for (int k = slice; k < cols; k += tpe) {
-          V tv, yv;
-#pragma unroll
-          for (int c = 0; c < P; c++) {
-            N::put(tv, c, Ws[c][ui][k]);
-            N::put(yv, c, Ys[c][k][uc]);
-          }
-          N::acc_sub(a, tv, yv);
-        }
-      V part = N::value(a);  // minus the slice's sum
-      for (int off = 1; off < tpe; off <<= 1) {
-        V o;
-#pragma unroll
-        for (int c = 0; c < P; c++) N::put(o, c, __shfl_xor(N::get(part, c), off, 64));
-        part = (slice & off) ? N::add(o, part) : N::add(part, o);
-      }
+      const V part = product(Ws, cols);  // minus T_IJ X_J
       if (uin) x = N::add(x, part);
       __syncthreads();  // Ws and Ys are rewritten by the next step
     }
-    // the diagonal block and this block's values
-    to_lds(vd);
+    // 3. X_I = Z r_I
     if (uin && slice == 0)
 #pragma unroll
       for (int c = 0; c < P; c++) Ys[c][ui][uc] = N::get(x, c);
+    for (int k = rows + t; k < TB; k += 1024)  // rows past the matrix: r = 0
+      for (int cc = 0; cc < nr; cc++)
+#pragma unroll
+        for (int c = 0; c < P; c++) Ys[c][k][cc] = 0.0;
+    __syncthreads();  // r_I and Z are in LDS
+    const V xs = N::sub(N::zero(), product(Zs, TB));
+    __syncthreads();  // every thread has read r_I
+    if (uin && slice == 0)
+#pragma unroll
+      for (int c = 0; c < P; c++) Ys[c][ui][uc] = N::get(xs, c);
     __syncthreads();
     if (wave < nr) {
-      V xinit = N::zero();
       if (lane < rows)
 #pragma unroll
-        for (int c = 0; c < P; c++) N::put(xinit, c, Ys[c][lane][wave]);
-      typename N::Acc acc = N::acc(xinit);
-      auto tval = [&](int i, int k) {
-        V r;
-#pragma unroll
-        for (int c = 0; c < P; c++) N::put(r, c, Ws[c][i][k]);
-        return r;
-      };
-      // a finished x_k is broadcast by readlane_words (DD: unnormalised)
-      if (!upper) {
-        for (int k = 0; k < rows - 1; k++) {
-          const V xk = readlane_words<P>(acc, k);
-          if (lane > k && lane < rows) N::acc_sub(acc, tval(lane, k), xk);
-        }
-      } else {
-        // reciprocals of the diagonal, all lanes at once
-        const V inv = lane < rows ? N::div(N::one(), tval(lane, lane)) : N::zero();
-        for (int k = rows - 1; k >= 0; k--) {
-          const V xk = N::mul(readlane_words<P>(acc, k), readlane_num<P>(inv, k));
-          if (lane == k)
-            acc = N::acc(xk);
-          else if (lane < k)
-            N::acc_sub(acc, tval(lane, k), xk);
-        }
-      }
-      if (lane < rows) {
-        const V xs = N::value(acc);
-#pragma unroll
         for (int c = 0; c < P; c++)
-          __hip_atomic_store(X + c * psx + (i0 + lane) * nrhs + wave, N::get(xs, c),
+          __hip_atomic_store(X + c * psx + (i0 + lane) * nrhs + wave, Ys[c][lane][wave],
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
       // this wave's stores are complete and visible at device scope
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
     __syncthreads();  // every value of X_I is stored
     if (t == 0) __hip_atomic_store(flags + I, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();  // Ws and Ys are reused by the next step
+    __syncthreads();  // Ws, Zs and Ys are reused by the next step
   }
 }
 

@@ -118,7 +118,7 @@ def test_solve_residual_and_paper_solution(dd, n, nrhs):
     fwd_g = np.max(vdiff(xg, want))
     print(f"forward error gpu {fwd:.3e}, oracle solve on gpu factors {fwd_g:.3e}", flush=True)
     diff = np.abs(sum(xs[c] - xg[c] for c in range(4)))[:, 0]
-    assert np.all(diff <= lu_bounds.solve_diff_bound(LU, xg, 2.0 ** -208)[:, 0])
+    assert np.all(diff <= lu_bounds.solve_diff_bound(LU, xg, 2.0 ** -208, block=32)[:, 0])
     # the whole path: x_hat - x = A^-1 (A x_hat - b) with the residual formed
     # exactly, so the forward error is bounded by ||A^-1|| ||r|| (the inverse
     # taken in FP64, a factor 2 covering its relative error cond(A) 2^-53)

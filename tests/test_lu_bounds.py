@@ -93,3 +93,49 @@ def test_solve_bound_holds_for_the_oracle_solve_and_fails_without_a_plane(P, u):
     xb = oracle.getrs(bad, ipiv, b)
     diff = np.abs(vsum(xb - xg))[:, 0]
     assert np.any(diff > solve_diff_bound(LU, xg, u)[:, 0])
+
+
+def block_inverse_solve(T, b, lower, block):
+    """X := T^-1 b by blocks in FP64: each diagonal block's inverse formed by
+    substitution on the unit vectors, applied to the block's residual."""
+    from scipy.linalg import solve_triangular
+    n = T.shape[0]
+    x = b.astype(np.float64).copy()
+    starts = list(range(0, n, block))
+    for i0 in (starts if lower else starts[::-1]):
+        i1 = min(n, i0 + block)
+        r = x[i0:i1] - (T[i0:i1, :i0] @ x[:i0] if lower else T[i0:i1, i1:] @ x[i1:])
+        Z = solve_triangular(T[i0:i1, i0:i1], np.eye(i1 - i0), lower=lower, unit_diagonal=lower)
+        x[i0:i1] = Z @ r
+    return x
+
+
+def test_block_inverse_solve_bound():
+    """The block term: a block-inverse solve in FP64 (u = 2^-53) stays within
+    the block solve's half of the bound of the exact rational solution of the
+    same factors; a block solve that ignores the multipliers inside its
+    diagonal blocks breaks it."""
+    n, block = 24, 8
+    g = inputs.rng(7)
+    A = inputs.paper_random_matrix(n, g, 2)
+    F, ipiv, _ = oracle.getrf(A, panel=4, pivot=True, algo="block", levels=0)
+    LU = F[:1].copy()                        # FP64 factors: the leading plane
+    b = np.zeros((1, n, 1))
+    b[0, :, 0] = g.uniform(-1, 1, n)
+    x = np.array([float(v) for v in exact_lu_solve(LU, ipiv, b)])
+    L, U = split(LU)
+    pb = b[0, :, 0].copy()
+    for k in range(n):
+        p = int(ipiv[k])
+        pb[k], pb[p] = pb[p], pb[k]
+    u = 2.0 ** -53
+    xb = block_inverse_solve(U[0], block_inverse_solve(L[0], pb, True, block), False, block)
+    full = solve_diff_bound(LU, x[None, :, None], u, block=block)[:, 0]
+    sub = solve_diff_bound(LU, x[None, :, None], u)[:, 0] / 2   # the substitution half
+    assert np.all(np.abs(xb - x) <= full - sub)
+    # a wrong block solve: the multipliers inside the diagonal blocks dropped
+    Lw = L[0].copy()
+    for i0 in range(0, n, block):
+        Lw[i0:i0 + block, i0:i0 + block] = np.eye(block)
+    xw = block_inverse_solve(U[0], block_inverse_solve(Lw, pb, True, block), False, block)
+    assert np.any(np.abs(xw - x) > full)
