@@ -924,6 +924,9 @@ constexpr int trsv_block() {
 // block flags.
 constexpr uint64_t kTrsvWaitTicks = 200000000ull;
 constexpr int kTrsvWgs = 32;  // workgroups of one triangular solve launch
+// The first blocks of a triangle are solved by substitution: the chain
+// reaches them before an inverse could be formed.
+constexpr int kTrsvDirect = 3;
 
 // One triangle of X := T^-1 X (unit lower, or upper with its diagonal; X is
 // n x nrhs, nrhs <= 16, tight) in one launch of G <= kTrsvWgs workgroups:
@@ -1030,13 +1033,16 @@ __global__ __launch_bounds__(1024) void trsv_chain_kernel(const double* T, int64
       }
       return part;
     };
+    const bool by_inverse = s >= kTrsvDirect;  // uniform
     {
-      // 1. Z = D^-1
+      // 1. Z = D^-1 (the first blocks keep D)
       double vd[kPer][P];
       stage(I, vd);
       __syncthreads();  // the previous step's readers of Zs are done
       to_lds(vd, Zs);
       __syncthreads();
+    }
+    if (by_inverse) {
       auto dval = [&](int i, int k) {
         V r;
 #pragma unroll
@@ -1110,7 +1116,9 @@ __global__ __launch_bounds__(1024) void trsv_chain_kernel(const double* T, int64
       if (uin) x = N::add(x, part);
       __syncthreads();  // Ws and Ys are rewritten by the next step
     }
-    // 3. X_I = Z r_I
+    // 3. X_I = Z r_I, or by substitution in D (one wave per right-hand side,
+    // lane = row: step k finishes x_k, broadcasts it by readlane, the other
+    // lanes subtract D_ik x_k; DD broadcasts the unnormalised accumulator)
     if (uin && slice == 0)
 #pragma unroll
       for (int c = 0; c < P; c++) Ys[c][ui][uc] = N::get(x, c);
@@ -1118,12 +1126,47 @@ __global__ __launch_bounds__(1024) void trsv_chain_kernel(const double* T, int64
       for (int cc = 0; cc < nr; cc++)
 #pragma unroll
         for (int c = 0; c < P; c++) Ys[c][k][cc] = 0.0;
-    __syncthreads();  // r_I and Z are in LDS
-    const V xs = N::sub(N::zero(), product(Zs, TB));
-    __syncthreads();  // every thread has read r_I
-    if (uin && slice == 0)
+    __syncthreads();  // r_I and Z (or D) are in LDS
+    if (by_inverse) {
+      const V xs = N::sub(N::zero(), product(Zs, TB));
+      __syncthreads();  // every thread has read r_I
+      if (uin && slice == 0)
 #pragma unroll
-      for (int c = 0; c < P; c++) Ys[c][ui][uc] = N::get(xs, c);
+        for (int c = 0; c < P; c++) Ys[c][ui][uc] = N::get(xs, c);
+    } else if (wave < nr) {
+      auto dval = [&](int i, int k) {
+        V r;
+#pragma unroll
+        for (int c = 0; c < P; c++) N::put(r, c, Zs[c][i][k]);
+        return r;
+      };
+      V xinit = N::zero();
+      if (lane < TB)
+#pragma unroll
+        for (int c = 0; c < P; c++) N::put(xinit, c, Ys[c][lane][wave]);
+      typename N::Acc acc = N::acc(xinit);
+      if (!upper) {
+        for (int k = 0; k < TB - 1; k++) {
+          const V xk = readlane_words<P>(acc, k);
+          if (lane > k && lane < TB) N::acc_sub(acc, dval(lane, k), xk);
+        }
+      } else {
+        const V inv = lane < TB ? N::div(N::one(), dval(lane, lane)) : N::zero();
+        for (int k = TB - 1; k >= 0; k--) {
+          const V xk = N::mul(readlane_words<P>(acc, k), readlane_num<P>(inv, k));
+          if (lane == k)
+            acc = N::acc(xk);
+          else if (lane < k)
+            N::acc_sub(acc, dval(lane, k), xk);
+        }
+      }
+      // lane and wave own entry (lane, wave) of Ys alone
+      if (lane < TB) {
+        const V xs = N::value(acc);
+#pragma unroll
+        for (int c = 0; c < P; c++) Ys[c][lane][wave] = N::get(xs, c);
+      }
+    }
     __syncthreads();
     if (wave < nr) {
       if (lane < rows)
