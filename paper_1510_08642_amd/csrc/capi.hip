@@ -107,6 +107,28 @@ void prof_begin(hipStream_t s) {
   g_prof_pending = e;
 }
 
+ProfEvents prof_events(hipStream_t s) {
+  ProfEvents e;
+  if (!g_prof.load(std::memory_order_relaxed)) return e;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return e;
+  if (hipEventCreate(&e.start) != hipSuccess) {
+    e.start = nullptr;
+    return e;
+  }
+  if (hipEventCreate(&e.stop) != hipSuccess) {
+    (void)hipEventDestroy(e.start);
+    e.start = e.stop = nullptr;
+  }
+  return e;
+}
+
+void prof_commit(const char* kernel, const ProfEvents& e) {
+  if (!e.start) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_recs.push_back(ProfRec{kernel, e.start, e.stop});
+}
+
 void prof_record(const char* kernel, hipStream_t s) {
   if (!g_prof_pending) return;
   hipEvent_t e;

@@ -1,6 +1,7 @@
 // Shared host/device structures of libddqd: strided batches of matrices in
 // plane layout, launch helpers and the XCD-aware block remap.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -85,5 +86,21 @@ int check_launch(const char* what);
 // bracketed by HIP events recorded on its stream; no effect when off.
 void prof_begin(hipStream_t s);
 void prof_record(const char* kernel, hipStream_t s);
+
+// The same timing for the kernels the roofline figures are taken from, read
+// at the kernel's own start and end: the launch carries the two events
+// (hipExtLaunchKernel), so no marker sits between them and the kernel.
+struct ProfEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+ProfEvents prof_events(hipStream_t s);  // null events when timing is off
+void prof_commit(const char* kernel, const ProfEvents& e);
+template <typename F, typename... Args>
+inline void launch_timed(const char* kernel, F fn, dim3 grid, dim3 block, uint32_t lds,
+                         hipStream_t s, Args... args) {
+  const ProfEvents e = prof_events(s);
+  hipExtLaunchKernelGGL(fn, grid, block, lds, s, e.start, e.stop, 0, args...);
+  prof_commit(kernel, e);
+}
 
 }  // namespace ddqd

@@ -211,16 +211,12 @@ int launch_dd_block(const GemmBatch& g, int tile, hipStream_t stream) {
   int64_t tm = (g.m + tile - 1) / tile, tn = (g.n + tile - 1) / tile;
   int64_t nblk = tm * tn * g.batch;
   if (nblk > INT32_MAX) return set_error(4 /*DDQD_E_UNSUPPORTED*/, "grid too large");
-  prof_begin(stream);
-  if (tile == 64) {
-    hipLaunchKernelGGL(dd_gemm_block_kernel<64>, dim3((unsigned)nblk), dim3(kThreads), 0, stream,
-                       g, tm, tn);
-    prof_record("dd_gemm_block_kernel", stream);
-  } else {
-    hipLaunchKernelGGL(dd_gemm_block_kernel<32>, dim3((unsigned)nblk), dim3(kThreads), 0, stream,
-                       g, tm, tn);
-    prof_record("dd_gemm_block_kernel<32>", stream);
-  }
+  if (tile == 64)
+    launch_timed("dd_gemm_block_kernel", dd_gemm_block_kernel<64>, dim3((unsigned)nblk),
+                 dim3(kThreads), 0, stream, g, tm, tn);
+  else
+    launch_timed("dd_gemm_block_kernel<32>", dd_gemm_block_kernel<32>, dim3((unsigned)nblk),
+                 dim3(kThreads), 0, stream, g, tm, tn);
   return check_launch("dd_gemm_block_kernel");
 }
 

@@ -181,16 +181,12 @@ int launch_qd_block(const GemmBatch& g, int tile, hipStream_t stream) {
   int64_t tm = (g.m + tile - 1) / tile, tn = (g.n + tile - 1) / tile;
   int64_t nblk = tm * tn * g.batch;
   if (nblk > INT32_MAX) return set_error(4, "grid too large");
-  prof_begin(stream);
-  if (tile == 32) {
-    hipLaunchKernelGGL(qd_gemm_block_kernel<2>, dim3((unsigned)nblk), dim3(kThreads), 0, stream,
-                       g, tm, tn);
-    prof_record("qd_gemm_block_kernel", stream);
-  } else {
-    hipLaunchKernelGGL(qd_gemm_block_kernel<1>, dim3((unsigned)nblk), dim3(kThreads), 0, stream,
-                       g, tm, tn);
-    prof_record("qd_gemm_block_kernel<16>", stream);
-  }
+  if (tile == 32)
+    launch_timed("qd_gemm_block_kernel", qd_gemm_block_kernel<2>, dim3((unsigned)nblk),
+                 dim3(kThreads), 0, stream, g, tm, tn);
+  else
+    launch_timed("qd_gemm_block_kernel<16>", qd_gemm_block_kernel<1>, dim3((unsigned)nblk),
+                 dim3(kThreads), 0, stream, g, tm, tn);
   return check_launch("qd_gemm_block_kernel");
 }
 

@@ -273,11 +273,9 @@ int run_ozaki(const GemmBatch& g, char* ws, hipStream_t s, int band) {
   if (nblk > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "grid too large");
   for (int64_t kc0 = 0; kc0 < o.kb; kc0 += kKChunk / 32) {
     const int64_t kc1 = kc0 + kKChunk / 32 < o.kb ? kc0 + kKChunk / 32 : o.kb;
-    prof_begin(s);
-    hipLaunchKernelGGL(oz_gemm_kernel<S>, dim3((unsigned)nblk), dim3(256), 0, s, g, o,
-                       (const signed char*)Asl, (const signed char*)Bsl, (const int*)ea,
-                       (const int*)fb, tm, tn, kc0, kc1, kc0 == 0 ? g.beta : 1, band);
-    prof_record("oz_gemm_kernel", s);
+    launch_timed("oz_gemm_kernel", oz_gemm_kernel<S>, dim3((unsigned)nblk), dim3(256), 0, s, g, o,
+                 (const signed char*)Asl, (const signed char*)Bsl, (const int*)ea,
+                 (const int*)fb, tm, tn, kc0, kc1, kc0 == 0 ? g.beta : 1, band);
     if ((rc = check_launch("oz_gemm_kernel"))) return rc;
   }
   return DDQD_OK;

@@ -345,11 +345,9 @@ int run_ozaki_qd(const GemmBatch& g, char* ws, hipStream_t s, int band) {
   if (nblk > INT32_MAX) return set_error(DDQD_E_UNSUPPORTED, "grid too large");
   for (int64_t kc0 = 0; kc0 < o.kb; kc0 += kKChunk / 32) {
     const int64_t kc1 = kc0 + kKChunk / 32 < o.kb ? kc0 + kKChunk / 32 : o.kb;
-    prof_begin(s);
-    hipLaunchKernelGGL(ozq_gemm_kernel<S>, dim3((unsigned)nblk), dim3(256), 0, s, g, o,
-                       (const signed char*)Asl, (const signed char*)Bsl, (const int*)ea,
-                       (const int*)fb, kc0, kc1, kc0 == 0 ? g.beta : 1, band);
-    prof_record("ozq_gemm_kernel", s);
+    launch_timed("ozq_gemm_kernel", ozq_gemm_kernel<S>, dim3((unsigned)nblk), dim3(256), 0, s, g,
+                 o, (const signed char*)Asl, (const signed char*)Bsl, (const int*)ea,
+                 (const int*)fb, kc0, kc1, kc0 == 0 ? g.beta : 1, band);
     if ((rc = check_launch("ozq_gemm_kernel"))) return rc;
   }
   return DDQD_OK;

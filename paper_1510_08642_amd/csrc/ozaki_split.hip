@@ -378,10 +378,8 @@ int launch_oz_exponents(const GemmBatch& g, const OzLayout& o, const OzWs& w, hi
   const int64_t ncol = ((o.cb * 32 + 63) / 64) * o.kb;
   if (nrow + ncol > INT32_MAX || g.batch > 65535)
     return set_error(DDQD_E_UNSUPPORTED, "matrix too large for one Ozaki launch");
-  prof_begin(s);
-  hipLaunchKernelGGL(oz_exp_kernel, dim3((unsigned)(nrow + ncol), (unsigned)g.batch), dim3(256),
-                     0, s, g.A, g.B, g.m, g.n, g.l, o, nrow, w.ea, w.part);
-  prof_record("oz_exp_kernel", s);
+  launch_timed("oz_exp_kernel", oz_exp_kernel, dim3((unsigned)(nrow + ncol), (unsigned)g.batch),
+               dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, nrow, w.ea, w.part);
   return check_launch("oz_exp_kernel");
 }
 
@@ -397,22 +395,18 @@ inline int64_t slice_grid(int P, const GemmBatch& g, const OzLayout& o) {
 template <int S>
 int slice_dd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s) {
   const int64_t grid = slice_grid(2, g, o);
-  prof_begin(s);
-  hipLaunchKernelGGL((oz_slice_kernel<2, S>), dim3((unsigned)grid, 1, (unsigned)g.batch),
-                     dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)w.ea,
-                     (const int*)w.part, w.fb, w.Asl, w.Bsl);
-  prof_record("oz_slice_kernel", s);
+  launch_timed("oz_slice_kernel", oz_slice_kernel<2, S>, dim3((unsigned)grid, 1, (unsigned)g.batch),
+               dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)w.ea, (const int*)w.part,
+               w.fb, w.Asl, w.Bsl);
   return check_launch("oz_slice_kernel");
 }
 
 template <int S>
 int slice_qd(const GemmBatch& g, const OzLayout& o, const OzWs& w, hipStream_t s) {
   const int64_t grid = slice_grid(4, g, o);
-  prof_begin(s);
-  hipLaunchKernelGGL((oz_slice_kernel<4, S>), dim3((unsigned)grid, 1, (unsigned)g.batch),
-                     dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)w.ea,
-                     (const int*)w.part, w.fb, w.Asl, w.Bsl);
-  prof_record("oz_slice_kernel", s);
+  launch_timed("oz_slice_kernel", oz_slice_kernel<4, S>, dim3((unsigned)grid, 1, (unsigned)g.batch),
+               dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, o, (const int*)w.ea, (const int*)w.part,
+               w.fb, w.Asl, w.Bsl);
   return check_launch("oz_slice_kernel");
 }
 
