@@ -67,6 +67,21 @@ extern "C" {
  * the digit products run exactly on v_mfma_i32_32x32x32_i8 and are recombined
  * in FP64.  Leaf error at most about l (S+3) 2^(-7S-2) max|a_i.| max|b_.j|
  * times 16, S the slice count.) */
+#define DDQD_BASE_CRT_I8 2 /* DD only: residues on INT8 matrix cores, CRT rebuild */
+/* (the same scaling, each operand then rounded to integers of at most 107
+ * bits and reduced modulo N pairwise coprime moduli <= 256, N = 29..31 by K;
+ * one exact INT8 product per modulus, the integer product rebuilt by the
+ * Chinese remainder theorem in 128-bit fixed point.  Leaf error at most about
+ * 2^-103 l max|a_i.| max|b_.j| for DD inputs with |lo| <= |hi|.  `slices` must
+ * be 0; QD returns DDQD_E_UNSUPPORTED.) */
+
+/*
+ * The moduli DDQD_BASE_CRT_I8 uses for a product with K = l: writes the first
+ * min(N, cap) of them to out (host memory) and returns N, the count (the
+ * product of the N moduli exceeds 2 min(l, 65536) 2^214); -1 for l <= 0, a
+ * negative cap, or out NULL with cap > 0.  No device work.
+ */
+int ddqd_crt_moduli(int64_t l, int* out, int cap);
 
 /* pivoting for dd_getrf */
 #define DDQD_PIVOT_NONE 0
@@ -108,9 +123,9 @@ int ddqd_profile_query(const char* substr, double* ms, int64_t* count);
  *             the top level) or padded with zeros up to one inside the
  *             workspace (the padding is never read from A, B or C, nor
  *             written to C).
- *   base      DDQD_BASE_FMA or DDQD_BASE_OZAKI_I8 for the leaf products
- *             (ignored by DDQD_SIMPLE).
- *   slices    Ozaki slice count (0 = automatic); ignored for FMA.
+ *   base      DDQD_BASE_FMA, DDQD_BASE_OZAKI_I8 or DDQD_BASE_CRT_I8 for the
+ *             leaf products (ignored by DDQD_SIMPLE).
+ *   slices    Ozaki slice count (0 = automatic); ignored for FMA; 0 for CRT.
  *   ws        device workspace of ws_bytes >= dd_gemm_workspace(...) bytes,
  *             8-byte aligned (may be NULL when that size is 0).
  *   stream    hipStream_t to enqueue on.

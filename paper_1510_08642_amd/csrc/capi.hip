@@ -65,6 +65,8 @@ int launch_ozaki_grouped(const GemmBatch* probs, int count, int S, char* ws, siz
 int launch_ozaki(int P, const GemmBatch& g, int slices, void* ws, size_t ws_bytes,
                  hipStream_t stream, int band = 0);
 bool ozaki_slices_ok(int P, int slices);
+size_t crt_workspace(int P, int64_t m, int64_t n, int64_t l, int64_t batch);
+int launch_crt(int P, const GemmBatch& g, void* ws, size_t ws_bytes, hipStream_t s);
 
 static thread_local char g_msg[512];
 
@@ -223,6 +225,8 @@ Plan make_plan(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int
   pl.off_leaf = off;
   if (base == DDQD_BASE_OZAKI_I8 && algo != DDQD_SIMPLE)
     pl.leaf_bytes = ozaki_workspace(P, pl.m[L], pl.n[L], pl.l[L], pow7(L), slices);
+  if (base == DDQD_BASE_CRT_I8 && algo != DDQD_SIMPLE)
+    pl.leaf_bytes = crt_workspace(P, pl.m[L], pl.n[L], pl.l[L], pow7(L));
   pl.total = off + pl.leaf_bytes;
   return pl;
 }
@@ -246,6 +250,7 @@ Mat prodM(const Plan& pl, char* ws, int j) {
 int leaf(int P, const GemmBatch& g, int base, int slices, int tile, int band, void* ws,
          size_t ws_bytes, hipStream_t s) {
   if (base == DDQD_BASE_OZAKI_I8) return launch_ozaki(P, g, slices, ws, ws_bytes, s, band);
+  if (base == DDQD_BASE_CRT_I8) return launch_crt(P, g, ws, ws_bytes, s);
   return P == 2 ? launch_dd_block(g, tile ? tile : 64, s) : launch_qd_block(g, tile, s);
 }
 
@@ -393,7 +398,8 @@ int device_ok() {
 size_t gemm_ws(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int base,
                int slices) {
   if (m < 0 || n < 0 || l < 0 || algo < 0 || algo > DDQD_AUTO || levels < 0 ||
-      levels > kMaxLevels || base < 0 || base > 1 || slices < 0 || slices > 40)
+      levels > kMaxLevels || base < 0 || base > 2 || slices < 0 || slices > 40 ||
+      (base == DDQD_BASE_CRT_I8 && (P != 2 || slices != 0)))
     return SIZE_MAX;
   if (m == 0 || n == 0 || l == 0) return 0;
   if (algo == DDQD_AUTO) return auto_workspace(P, m, n, l, base, slices);
@@ -424,9 +430,13 @@ int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* 
   if (band < 0 || band > 64) return set_error(DDQD_E_ARG, "band must be in 0..64");
   if (levels < 0 || levels > kMaxLevels)
     return set_error(DDQD_E_ARG, "levels must be in 0..%d", kMaxLevels);
-  if (base != DDQD_BASE_FMA && base != DDQD_BASE_OZAKI_I8)
+  if (base != DDQD_BASE_FMA && base != DDQD_BASE_OZAKI_I8 && base != DDQD_BASE_CRT_I8)
     return set_error(DDQD_E_ARG, "unknown base %d", base);
   if (slices < 0 || slices > 40) return set_error(DDQD_E_ARG, "slices must be in 0..40");
+  if (base == DDQD_BASE_CRT_I8 && P != 2)
+    return set_error(DDQD_E_UNSUPPORTED, "the CRT base is DD only");
+  if (base == DDQD_BASE_CRT_I8 && slices != 0)
+    return set_error(DDQD_E_ARG, "the CRT base takes no slice count (0)");
   if (base == DDQD_BASE_OZAKI_I8 && !ozaki_slices_ok(P, slices))
     return set_error(DDQD_E_UNSUPPORTED, "%d slices not supported (DD 8..20, QD 28..31)",
                      slices);
@@ -587,6 +597,9 @@ int check_descs(int count, const ddqd_gemm_desc* d) {
       return set_error(DDQD_E_ARG, "problem %d: negative dimension", i);
     if ((x.alpha != 1 && x.alpha != -1) || (x.beta != 0 && x.beta != 1))
       return set_error(DDQD_E_ARG, "problem %d: alpha must be +-1 and beta 0 or 1", i);
+    if (x.base == DDQD_BASE_CRT_I8)
+      return set_error(DDQD_E_UNSUPPORTED, "problem %d: grouped launches take the FMA or Ozaki base",
+                       i);
     if (x.base != DDQD_BASE_FMA && x.base != DDQD_BASE_OZAKI_I8)
       return set_error(DDQD_E_ARG, "problem %d: unknown base %d", i, x.base);
     if (x.slices < 0 || x.slices > 40)

@@ -1,0 +1,593 @@
+// DD matrix product on INT8 matrix cores by modular integer arithmetic (a
+// base kernel for the leaves of Sec. 2's algorithms, like the Ozaki split in
+// ozaki.hip; not in the paper, which predates both).  Where the split takes
+// every product of S digit slices (S(S+1)/2 INT8 products), this form takes
+// one INT8 product per modulus of a set of N pairwise coprime moduli and
+// rebuilds the exact integer product by the Chinese remainder theorem.
+//
+// 1. Scale (ozaki_split.hip's exponent pass): e_i with max_k |a_ik| < 2^(e_i-1)
+//    for row i of A, f_j likewise for column j of B.
+// 2. Integers.  A'_ik = a_ik 2^(P1 - e_i) rounded to an integer (|A'| <= 2^P1;
+//    2^(P1-1) for normalised DD input), B' likewise; the rounding moves each
+//    by at most 1.
+// 3. Residues.  For every modulus m_s the symmetric residue of A' (and B')
+//    modulo m_s, |r| <= m_s / 2 <= 128, stored as INT8 in the fragment order
+//    of the 32x32x32 MFMA (lane l: line l % 32, k = 16 (l / 32) + 0..15).
+// 4. Products.  C_s = A'_s B'_s exactly in INT32 on v_mfma_i32_32x32x32_i8
+//    (|C_s| <= kc 2^14 <= 2^30 for K chunks kc <= 2^16), reduced to a
+//    symmetric residue c_s of m_s and stored as INT8.
+// 5. Rebuild.  X = A' B' is the integer with X = c_s (mod m_s) for every s and
+//    |X| < M / 2, M = prod m_s (N is chosen so that M > 2 kc 2^(2 P1)):
+//    X / M = frac(sum_s c_s y_s / m_s), y_s = (M / m_s)^-1 mod m_s.  Each term
+//    is taken as c_s Z_s, Z_s = floor(y_s 2^160 / m_s), in 160-bit fixed
+//    point (the sum mod 2^160; error below |c_s| units of 2^-160 a term), and
+//    the signed fraction times M gives X; C_ij = X 2^(e_i + f_j - 2 P1) in DD.
+//
+// Error: the integers move each operand by at most 2^(e_i - P1) (A) and
+// 2^(f_j - P1) (B), so entry (i, j) moves by at most about
+// kc 2^(e_i + f_j - P1) <= kc 2^(4 - P1) max|a_i.| max|b_.j| (P1 = 107:
+// 2^-103 kc max|a_i.| max|b_.j|); the rebuild adds at most 2^12 M 2^-160
+// <= 2^86 units of X (2^(e_i + f_j - 128)) and the DD rounding of the result.
+#include "ddqd.h"
+#include "common.hpp"
+#include "eft.hpp"
+#include "ozaki.hpp"
+
+#include <cmath>
+#include <mutex>
+
+#pragma clang fp contract(off)
+
+namespace ddqd {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kCrtMaxN = 32;
+constexpr int kP1 = 107;              // |A'| <= 2^107
+constexpr int64_t kChunk = 65536;     // K per exact INT32 product
+constexpr int kTileBlocks = 4;        // a product workgroup's tile: 4 x 4 blocks of 32
+constexpr int kStages = 4;            // K blocks of fragments in LDS (prefetch depth 3)
+
+// The moduli: pairwise coprime, largest first (each <= 256, so residues fit
+// INT8); the first N are used.
+constexpr int kModuli[kCrtMaxN] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223,
+                                   217, 211, 199, 197, 193, 191, 181, 179, 173, 167, 163,
+                                   157, 151, 149, 139, 137, 131, 127, 113, 109, 107};
+
+// Residue constants (kernel argument): m_s, 1 / m_s rounded, 2^36 and 2^72
+// modulo m_s.
+struct CrtResidue {
+  int N;
+  double m[kCrtMaxN], inv[kCrtMaxN], t36[kCrtMaxN], t72[kCrtMaxN];
+};
+
+// Rebuild constants (kernel argument): Z_s in 16-bit limbs (least significant
+// first) and M 2^-160 as a DD.
+constexpr int kLimbs = 10;  // 160-bit fixed point
+struct CrtRebuild {
+  int N;
+  int z[kCrtMaxN][kLimbs];
+  double mhi, mlo;
+};
+
+// Product kernel launch description.
+struct CrtProd {
+  const signed char *Ares, *Bres;
+  signed char* Cres;
+  int N;
+  double m[kCrtMaxN], inv[kCrtMaxN];
+  int64_t RB, CB, KB;        // 32-blocks of rows, columns, K (KB a multiple of kStages)
+  int64_t tiles_m, tiles_n;  // 128 x 128 tiles
+  int64_t kb0, kb1;          // K blocks of this chunk
+  int64_t batch;
+};
+
+// ---- host: constants -------------------------------------------------------
+
+struct Consts {
+  CrtResidue res;
+  CrtRebuild reb;
+  double bits;  // log2 M
+};
+
+int64_t inv_mod(int64_t a, int64_t m) {  // a^-1 mod m, gcd(a, m) = 1
+  int64_t t = 0, nt = 1, r = m, nr = a % m;
+  while (nr) {
+    const int64_t q = r / nr, tt = t - q * nt, rr = r - q * nr;
+    t = nt;
+    nt = tt;
+    r = nr;
+    nr = rr;
+  }
+  return t < 0 ? t + m : t;
+}
+
+Consts make_consts(int N) {
+  Consts c{};
+  c.res.N = c.reb.N = N;
+  c.bits = 0;
+  // M as 32-bit words (at most 256 bits for 32 moduli)
+  uint32_t M[9] = {1};
+  for (int s = 0; s < N; s++) {
+    const int64_t m = kModuli[s];
+    c.bits += std::log2((double)m);
+    c.res.m[s] = (double)m;
+    c.res.inv[s] = 1.0 / (double)m;
+    int64_t p36 = 1, p72;
+    for (int b = 0; b < 36; b++) p36 = p36 * 2 % m;
+    p72 = p36 * p36 % m;
+    c.res.t36[s] = (double)p36;
+    c.res.t72[s] = (double)p72;
+    // y_s = (M / m_s)^-1 mod m_s
+    int64_t q = 1;
+    for (int t = 0; t < N; t++)
+      if (t != s) q = q * (kModuli[t] % m) % m;
+    const int64_t y = inv_mod(q, m);
+    // Z_s = floor(y 2^160 / m): long division of y 2^160 (32-bit words; the
+    // quotient is below 2^160 as y < m)
+    uint32_t num[6] = {0, 0, 0, 0, 0, (uint32_t)y}, quo[6];
+    uint64_t rem = 0;
+    for (int w = 5; w >= 0; w--) {
+      const uint64_t cur = (rem << 32) | num[w];
+      quo[w] = (uint32_t)(cur / (uint64_t)m);
+      rem = cur % (uint64_t)m;
+    }
+    for (int j = 0; j < kLimbs; j++)
+      c.reb.z[s][j] = (int)((quo[j / 2] >> (16 * (j % 2))) & 0xFFFF);
+    // M *= m
+    uint64_t carry = 0;
+    for (int w = 0; w < 9; w++) {
+      const uint64_t v = (uint64_t)M[w] * (uint64_t)m + carry;
+      M[w] = (uint32_t)v;
+      carry = v >> 32;
+    }
+  }
+  // M 2^-160 as a DD: its leading 53 bits, then the next 53 (truncated)
+  auto bit = [&](int i) -> uint64_t { return i < 0 ? 0u : (M[i / 32] >> (i % 32)) & 1u; };
+  int top = 9 * 32 - 1;
+  while (top > 0 && !bit(top)) top--;
+  uint64_t h = 0, lw = 0;
+  for (int i = 0; i < 53; i++) h = (h << 1) | bit(top - i);
+  for (int i = 53; i < 106; i++) lw = (lw << 1) | bit(top - i);
+  const double hi = std::ldexp((double)h, top - 52 - 160);
+  const double lo = std::ldexp((double)lw, top - 105 - 160);
+  c.reb.mhi = hi;
+  c.reb.mlo = lo;
+  return c;
+}
+
+const Consts& consts(int N) {
+  static Consts table[kCrtMaxN + 1];
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (int n = 1; n <= kCrtMaxN; n++) table[n] = make_consts(n);
+  });
+  return table[N];
+}
+
+// Moduli for K chunks of kc: M > 2 kc 2^(2 P1) (|A'|, |B'| <= 2^P1).
+int moduli_for(int64_t kc) {
+  const double need = 2.0 * kP1 + std::log2((double)(kc < 1 ? 1 : kc)) + 1.0 + 0.01;
+  for (int n = 1; n <= kCrtMaxN; n++)
+    if (consts(n).bits >= need) return n;
+  return 0;
+}
+
+// ---- layout and workspace ---------------------------------------------------
+
+struct CrtLayout {
+  int64_t m, n, l, batch;
+  int N;
+  int64_t RB, CB, KB;  // 32-blocks: rows (multiple of 4), columns (multiple of 4), K (of kStages)
+  int64_t kc;          // K chunk (multiple of 32 kStages)
+  size_t a_bytes, b_bytes, c_bytes;  // residues, all batch entries
+};
+
+CrtLayout crt_layout(int64_t m, int64_t n, int64_t l, int64_t batch) {
+  CrtLayout L;
+  L.m = m;
+  L.n = n;
+  L.l = l;
+  L.batch = batch;
+  L.RB = (m + 127) / 128 * kTileBlocks;
+  L.CB = (n + 127) / 128 * kTileBlocks;
+  L.KB = ((l + 31) / 32 + kStages - 1) / kStages * kStages;
+  L.kc = l < kChunk ? l : kChunk;
+  L.N = moduli_for(L.kc);
+  L.a_bytes = (size_t)batch * L.N * L.RB * L.KB * kOzFrag;
+  L.b_bytes = (size_t)batch * L.N * L.CB * L.KB * kOzFrag;
+  L.c_bytes = (size_t)batch * L.N * L.RB * L.CB * kOzFrag;
+  return L;
+}
+
+// The exponent pass's layout (ozaki_split.hip): rows and columns padded to
+// the residues' blocks.
+OzLayout exp_layout(const CrtLayout& L) {
+  OzLayout o{};
+  o.m = L.m;
+  o.n = L.n;
+  o.l = L.l;
+  o.rb = L.RB;
+  o.cb = L.CB;
+  o.kb = (L.l + 31) / 32;
+  o.S = 1;
+  return o;
+}
+
+struct CrtWs {
+  signed char *Ares, *Bres, *Cres;
+  OzWs e;  // exponents (Asl / Bsl unused)
+};
+
+size_t crt_ws_bytes(const CrtLayout& L) {
+  const OzLayout o = exp_layout(L);
+  return oz_align256(L.a_bytes) + oz_align256(L.b_bytes) + oz_align256(L.c_bytes) +
+         oz_align256(sizeof(int) * (size_t)(L.batch * (o.rb + o.cb) * 32)) +
+         oz_align256(sizeof(int) * (size_t)(L.batch * o.kb * o.cb * 32));
+}
+
+CrtWs crt_ws(char* ws, const CrtLayout& L) {
+  CrtWs w;
+  w.Ares = (signed char*)ws;
+  ws += oz_align256(L.a_bytes);
+  w.Bres = (signed char*)ws;
+  ws += oz_align256(L.b_bytes);
+  w.Cres = (signed char*)ws;
+  ws += oz_align256(L.c_bytes);
+  const OzLayout o = exp_layout(L);
+  w.e.Asl = w.e.Bsl = nullptr;
+  w.e.ea = (int*)ws;
+  w.e.fb = w.e.ea + L.batch * o.rb * 32;
+  ws += oz_align256(sizeof(int) * (size_t)(L.batch * (o.rb + o.cb) * 32));
+  w.e.part = (int*)ws;
+  return w;
+}
+
+// ---- residues ---------------------------------------------------------------
+// Workgroup = 32 lines (rows of A or columns of B) by 64 k (two K blocks) of
+// one batch entry; A's chunks first, then B's.  Thread t takes line t % 32
+// and k = 8 (t / 32) + 0..7: it forms the 8 integers, then for each modulus
+// their 8 residues (8 bytes of its line's 16-byte fragment slot; a wave's
+// stores cover half a fragment, 512 contiguous bytes).
+__global__ __launch_bounds__(256) void crt_residue_kernel(CMat A, CMat B, int64_t m, int64_t n,
+                                                          int64_t l, int64_t RB, int64_t CB,
+                                                          int64_t KB, int64_t kbe,
+                                                          const int* ea, const int* part,
+                                                          int* fb, CrtResidue cr,
+                                                          signed char* Ares, signed char* Bres) {
+  __shared__ int xc[8][32];
+  const int64_t b = blockIdx.y;
+  const int64_t kchunks = KB / 2;
+  const int64_t ch = blockIdx.x;
+  const int side = ch < RB * kchunks ? 0 : 1;
+  const int64_t x = side == 0 ? ch : ch - RB * kchunks;
+  const int64_t lb = x / kchunks, kc = x % kchunks;
+  const int t = threadIdx.x, ln = t % 32, g = t / 32;
+  const int64_t line = lb * 32 + ln;
+  // exponent of this line (B: the maximum of the column's slab exponents)
+  int ex;
+  if (side == 0) {
+    ex = ea[b * RB * 32 + line];
+  } else {
+    const int c = t % 32, r = t / 32;
+    int e = -(1 << 20);
+    for (int64_t sl = r; sl < kbe; sl += 8) {
+      const int v = part[(b * kbe + sl) * (CB * 32) + lb * 32 + c];
+      e = v > e ? v : e;
+    }
+    xc[r][c] = e;
+    __syncthreads();
+    if (r == 0) {
+#pragma unroll
+      for (int q = 1; q < 8; q++) e = xc[q][c] > e ? xc[q][c] : e;
+      xc[0][c] = e;
+      if (kc == 0) fb[b * CB * 32 + lb * 32 + c] = e;
+    }
+    __syncthreads();
+    ex = xc[0][ln];
+  }
+  // the 8 values
+  const CMat X = side == 0 ? A : B;
+  const int64_t live = side == 0 ? m : n;
+  const double* base = X.p + b * X.bstride;
+  const int64_t k0 = kc * 64 + 8 * g;
+  double hv[8], lv[8];
+#pragma unroll
+  for (int q = 0; q < 8; q++) {
+    const int64_t k = k0 + q;
+    const bool in = line < live && k < l;
+    const int64_t idx = in ? (side == 0 ? line * X.ld + k : k * X.ld + line) : 0;
+    hv[q] = in ? base[idx] : 0.0;
+    lv[q] = in ? base[X.ps + idx] : 0.0;
+  }
+  // integers A' = h + l (h, l integers held in doubles) as three limbs of 36
+  // bits: A' = d0 + d1 2^36 + d2 2^72 (all exact)
+  double d0[8], d1[8], d2[8];
+  const int sh = kP1 - ex;
+#pragma unroll
+  for (int q = 0; q < 8; q++) {
+    double s, e;
+    two_sum(hv[q], lv[q], s, e);  // normalised (exact)
+    const double hs = ldexp(s, sh), h = rint(hs);
+    const double lo = rint(ldexp(e, sh) + (hs - h));
+    const double c2 = trunc(h * 0x1p-72);
+    const double h1 = __builtin_fma(-c2, 0x1p72, h);
+    const double c1 = trunc(h1 * 0x1p-36);
+    const double c0 = __builtin_fma(-c1, 0x1p36, h1);
+    const double l1 = trunc(lo * 0x1p-36);
+    const double l0 = __builtin_fma(-l1, 0x1p36, lo);
+    d0[q] = c0 + l0;
+    d1[q] = c1 + l1;
+    d2[q] = c2;
+  }
+  // fragment slot of (line, k0): K block, half and byte offset
+  const int64_t kb = kc * 2 + g / 4;
+  const int half = (g % 4) / 2, off = 8 * (g % 2);
+  signed char* dst = side == 0 ? Ares : Bres;
+  const int64_t lines = side == 0 ? RB : CB;
+  const int64_t slot = (ln + 32 * half) * 16 + off;
+  for (int s = 0; s < cr.N; s++) {
+    const double mm = cr.m[s], iv = cr.inv[s], t1 = cr.t36[s], t2 = cr.t72[s];
+    uint32_t w[2] = {0u, 0u};
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      const double xr = __builtin_fma(d2[q], t2, __builtin_fma(d1[q], t1, d0[q]));  // exact
+      const double r = __builtin_fma(-rint(xr * iv), mm, xr);  // |r| <= m / 2
+      w[q / 4] |= ((uint32_t)(int)r & 0xFFu) << (8 * (q % 4));
+    }
+    const int64_t frag = ((b * cr.N + s) * lines + lb) * KB + kb;
+    *(uint2*)(dst + frag * kOzFrag + slot) = make_uint2(w[0], w[1]);
+  }
+}
+
+// ---- products ---------------------------------------------------------------
+// Workgroup = one 128 x 128 tile of C for one modulus and batch entry; 4
+// waves (2 x 2), each a 64 x 64 block (2 x 2 MFMA blocks, 64 accumulator
+// registers).  Fragments move global -> LDS by direct loads into a ring of
+// kStages K blocks (wave w loads A row block w and B column block w of a K
+// block), three K blocks ahead of the one the MFMAs read.
+__global__ __launch_bounds__(256) void crt_gemm_kernel(CrtProd a) {
+  __shared__ v4i lds[kStages][2 * kTileBlocks][64];
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wr = w / 2, wc = w % 2;
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  const int64_t per = a.tiles_m * a.tiles_n;
+  const int64_t t = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x);
+  const int64_t bs = t / per;  // batch entry and modulus
+  const int s = (int)(bs % a.N);
+  const int64_t b = bs / a.N;
+  int64_t tm, tn;
+  banded_tile(t % per, a.tiles_m, a.tiles_n, 2, tm, tn);
+
+  const signed char* srcA =
+      a.Ares + (((b * a.N + s) * a.RB + kTileBlocks * tm + wu) * a.KB) * kOzFrag + lane * 16;
+  const signed char* srcB =
+      a.Bres + (((b * a.N + s) * a.CB + kTileBlocks * tn + wu) * a.KB) * kOzFrag + lane * 16;
+  auto stage = [&](int64_t kb) {
+    const int st = (int)(kb % kStages);
+    __builtin_amdgcn_global_load_lds((const void*)(srcA + kb * kOzFrag),
+                                     (__attribute__((address_space(3))) void*)&lds[st][wu][0],
+                                     16, 0, 0);
+    __builtin_amdgcn_global_load_lds(
+        (const void*)(srcB + kb * kOzFrag),
+        (__attribute__((address_space(3))) void*)&lds[st][kTileBlocks + wu][0], 16, 0, 0);
+  };
+
+  v16i acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int q = 0; q < 16; q++) acc[i][j][q] = 0;
+  const int64_t kb0 = a.kb0, kb1 = a.kb1;
+#pragma unroll
+  for (int d = 0; d < kStages - 1; d++)
+    if (kb0 + d < kb1) stage(kb0 + d);
+  for (int64_t kb = kb0; kb < kb1; kb++) {
+    // this wave's loads of block kb have landed (those of kb+1, kb+2 may
+    // still be in flight); after the barrier every wave's have, and every
+    // wave is done reading block kb-1, whose slot the next load refills
+    // (two loads a block; gfx9 encoding: vmcnt in bits 3:0, expcnt and
+    // lgkmcnt left at their maxima)
+    if (kb + 2 < kb1) __builtin_amdgcn_s_waitcnt(0x0F74);       // vmcnt(4)
+    else if (kb + 1 < kb1) __builtin_amdgcn_s_waitcnt(0x0F72);  // vmcnt(2)
+    else __builtin_amdgcn_s_waitcnt(0x0F70);                    // vmcnt(0)
+    // a bare barrier: __syncthreads' fence would wait for every load in flight
+    // (the LDS writes of the blocks ahead too); the waits above and the LDS
+    // reads' own waits are the ordering this ring needs
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (kb + kStages - 1 < kb1) stage(kb + kStages - 1);
+    const int st = (int)(kb % kStages);
+    const v4i fa0 = lds[st][2 * wr][lane], fa1 = lds[st][2 * wr + 1][lane];
+    const v4i fb0 = lds[st][kTileBlocks + 2 * wc][lane];
+    const v4i fb1 = lds[st][kTileBlocks + 2 * wc + 1][lane];
+    acc[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa0, fb0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa0, fb1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa1, fb0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa1, fb1, acc[1][1], 0, 0, 0);
+  }
+  // residues of C_s: 16 bytes per lane and block, the MFMA output order
+  const double mm = a.m[s], iv = a.inv[s];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      uint32_t wd[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int q = 0; q < 16; q++) {
+        const double c = (double)acc[i][j][q];
+        const double r = __builtin_fma(-rint(c * iv), mm, c);  // |r| <= m / 2
+        wd[q / 4] |= ((uint32_t)(int)r & 0xFFu) << (8 * (q % 4));
+      }
+      const int64_t rb = kTileBlocks * tm + 2 * wr + i, cb = kTileBlocks * tn + 2 * wc + j;
+      const int64_t blk = ((b * a.N + s) * a.RB + rb) * a.CB + cb;
+      *(uint4*)(a.Cres + blk * kOzFrag + lane * 16) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+    }
+}
+
+// ---- rebuild ----------------------------------------------------------------
+// Two waves per 32 x 32 block of C (4 waves a workgroup): lane l of half h
+// takes the block's 8 outputs q = 8 h .. 8 h + 7 of column l % 32, rows
+// 8 (q / 4) + 4 (l / 32) + q % 4 (the MFMA output order).  The sum of
+// c_s Z_s accumulates in 10 limbs of 16 bits per output (|limb| < 2^28).
+__global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int64_t n,
+                                                          int64_t RB, int64_t CB,
+                                                          const signed char* Cres,
+                                                          const int* ea, const int* fb,
+                                                          int alpha, int beta, CrtRebuild cb_,
+                                                          int64_t blocks) {
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t blk = (int64_t)blockIdx.x * 2 + w / 2;
+  const int h = w % 2;
+  if (blk >= blocks) return;
+  const int64_t per = RB * CB;
+  const int64_t b = blk / per, rb = (blk % per) / CB, cbk = blk % CB;
+  const int N = cb_.N;
+  int acc[8][kLimbs];
+#pragma unroll
+  for (int q = 0; q < 8; q++)
+#pragma unroll
+    for (int j = 0; j < kLimbs; j++) acc[q][j] = 0;
+  const signed char* src =
+      Cres + ((b * N) * per + rb * CB + cbk) * kOzFrag + lane * 16 + 8 * h;
+  for (int s = 0; s < N; s++) {
+    const uint2 v = *(const uint2*)(src + (int64_t)s * per * kOzFrag);
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      const int c = (int)(signed char)((q < 4 ? v.x : v.y) >> (8 * (q % 4)));
+#pragma unroll
+      for (int j = 0; j < kLimbs; j++) acc[q][j] += c * cb_.z[s][j];
+    }
+  }
+  const int64_t col = cbk * 32 + lane % 32;
+  if (col >= n) return;
+  const int fexp = fb[b * CB * 32 + col];
+  double* Cb = C.p + b * C.bstride;
+#pragma unroll
+  for (int qq = 0; qq < 8; qq++) {
+    const int q = 8 * h + qq;
+    const int64_t row = rb * 32 + 8 * (q / 4) + 4 * (lane / 32) + q % 4;
+    if (row >= m) continue;
+    // carries: limbs of 16 bits, the top one taken modulo 2^16 (the sum mod 2^160)
+    int64_t carry = 0;
+    uint32_t limb[kLimbs];
+#pragma unroll
+    for (int j = 0; j < kLimbs; j++) {
+      const int64_t v = (int64_t)acc[qq][j] + carry;
+      limb[j] = (uint32_t)(v & 0xFFFF);
+      carry = v >> 16;  // arithmetic
+    }
+    // the signed fraction F (units of 2^-160) from five 32-bit words, as a DD
+    uint32_t wd[5];
+#pragma unroll
+    for (int j = 0; j < 5; j++) wd[j] = limb[2 * j] | (limb[2 * j + 1] << 16);
+    double hi = ldexp((double)(int32_t)wd[4], 128), lo = 0.0;
+#pragma unroll
+    for (int j = 3; j >= 0; j--) {
+      double e;
+      two_sum(hi, ldexp((double)wd[j], 32 * j), hi, e);
+      lo += e;
+    }
+    fast_two_sum(hi, lo, hi, lo);
+    dd_t x = dd_mul(dd_t{hi, lo}, dd_t{cb_.mhi, cb_.mlo});  // X = F M 2^-160
+    const int sc = ea[b * RB * 32 + row] + fexp - 2 * kP1;
+    x.hi = ldexp(x.hi, sc);
+    x.lo = ldexp(x.lo, sc);
+    if (alpha < 0) x = dd_neg(x);
+    const int64_t off = row * C.ld + col;
+    if (beta) x = dd_add(dd_t{Cb[off], Cb[C.ps + off]}, x);
+    Cb[off] = x.hi;
+    Cb[C.ps + off] = x.lo;
+  }
+}
+
+int run_crt(const GemmBatch& g, char* ws, hipStream_t s) {
+  const CrtLayout L = crt_layout(g.m, g.n, g.l, g.batch);
+  if (L.N == 0) return set_error(DDQD_E_UNSUPPORTED, "no modulus set covers K = %lld",
+                                 (long long)g.l);
+  const CrtWs w = crt_ws(ws, L);
+  const OzLayout o = exp_layout(L);
+  int rc = launch_oz_exponents(g, o, w.e, s);
+  if (rc) return rc;
+  const Consts& k = consts(L.N);
+  // residues
+  const int64_t chunks = (L.RB + L.CB) * (L.KB / 2);
+  if (chunks > INT32_MAX || g.batch > 65535)
+    return set_error(DDQD_E_UNSUPPORTED, "residue grid too large");
+  launch_timed("crt_residue_kernel", crt_residue_kernel, dim3((unsigned)chunks, (unsigned)g.batch),
+               dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, L.RB, L.CB, L.KB, o.kb,
+               (const int*)w.e.ea, (const int*)w.e.part, w.e.fb, k.res, w.Ares, w.Bres);
+  if ((rc = check_launch("crt_residue_kernel"))) return rc;
+  // products and rebuild, K chunk by K chunk
+  CrtProd p{};
+  p.Ares = w.Ares;
+  p.Bres = w.Bres;
+  p.Cres = w.Cres;
+  p.N = L.N;
+  for (int q = 0; q < L.N; q++) {
+    p.m[q] = k.res.m[q];
+    p.inv[q] = k.res.inv[q];
+  }
+  p.RB = L.RB;
+  p.CB = L.CB;
+  p.KB = L.KB;
+  p.tiles_m = L.RB / kTileBlocks;
+  p.tiles_n = L.CB / kTileBlocks;
+  p.batch = g.batch;
+  const int64_t nblk = p.tiles_m * p.tiles_n * L.N * g.batch;
+  const int64_t blocks = L.RB * L.CB * g.batch;
+  if (nblk > INT32_MAX || (blocks + 1) / 2 > INT32_MAX)
+    return set_error(DDQD_E_UNSUPPORTED, "grid too large");
+  // K blocks per chunk: all of them when l fits one chunk (the padding
+  // blocks hold zeros), else kChunk / 32 (a multiple of kStages)
+  const int64_t kcb = g.l <= kChunk ? L.KB : kChunk / 32;
+  for (int64_t kb0 = 0; kb0 < L.KB; kb0 += kcb) {
+    p.kb0 = kb0;
+    p.kb1 = kb0 + kcb < L.KB ? kb0 + kcb : L.KB;
+    launch_timed("crt_gemm_kernel", crt_gemm_kernel, dim3((unsigned)nblk), dim3(256), 0, s, p);
+    if ((rc = check_launch("crt_gemm_kernel"))) return rc;
+    launch_timed("crt_rebuild_kernel", crt_rebuild_kernel, dim3((unsigned)((blocks + 1) / 2)),
+                 dim3(256), 0, s, g.C, g.m, g.n, L.RB, L.CB, (const signed char*)w.Cres,
+                 (const int*)w.e.ea, (const int*)w.e.fb, g.alpha, kb0 == 0 ? g.beta : 1, k.reb,
+                 blocks);
+    if ((rc = check_launch("crt_rebuild_kernel"))) return rc;
+  }
+  return DDQD_OK;
+}
+
+}  // namespace
+
+size_t crt_workspace(int P, int64_t m, int64_t n, int64_t l, int64_t batch) {
+  if (P != 2 || m <= 0 || n <= 0 || l <= 0 || batch <= 0) return 0;
+  const CrtLayout L = crt_layout(m, n, l, batch);
+  if (L.N == 0) return 0;
+  return crt_ws_bytes(L);
+}
+
+int launch_crt(int P, const GemmBatch& g, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (P != 2) return set_error(DDQD_E_UNSUPPORTED, "the modular INT8 base is DD only");
+  if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return DDQD_OK;
+  if (g.l <= 0) return set_error(DDQD_E_ARG, "empty K reached the modular base");
+  const size_t need = crt_workspace(P, g.m, g.n, g.l, g.batch);
+  if (need == 0 || need > ws_bytes || !ws)
+    return set_error(DDQD_E_WORKSPACE, "modular base: workspace of %zu bytes needed, %zu given",
+                     need, ws_bytes);
+  return run_crt(g, (char*)ws, s);
+}
+
+}  // namespace ddqd
+
+extern "C" int ddqd_crt_moduli(int64_t l, int* out, int cap) {
+  using namespace ddqd;
+  if (l <= 0 || cap < 0 || (cap > 0 && !out)) return -1;
+  const int64_t kc = l < kChunk ? l : kChunk;
+  const int N = moduli_for(kc);
+  for (int s = 0; s < N && s < cap; s++) out[s] = kModuli[s];
+  return N;
+}

@@ -71,6 +71,11 @@ namespace {
 
 constexpr int64_t kMaxLuRows = 8192;
 
+// trailing-update bases: FMA and Ozaki in DD and QD, the CRT base in DD
+bool lu_base_ok(int P, int base) {
+  return base == DDQD_BASE_FMA || base == DDQD_BASE_OZAKI_I8 || (base == DDQD_BASE_CRT_I8 && P == 2);
+}
+
 struct Lu {
   int P;  // 2 = DD, 4 = QD
   double* A;
@@ -260,7 +265,7 @@ size_t auto_panel_ws(int P, int64_t n, int algo, int levels, int base) {
 
 size_t getrf_workspace_entry(int P, int64_t n, int panel_width, int algo, int levels, int base) {
   if (n < 0 || panel_width < DDQD_PANEL_AUTO || algo < 0 || algo > 3 || levels < 0 ||
-      levels > 6 || base < 0 || base > 1)
+      levels > 6 || !lu_base_ok(P, base))
     return SIZE_MAX;
   if (panel_width == 0) return 0;  // the row-wise comparator needs none
   if (panel_width == DDQD_PANEL_AUTO) return auto_panel_ws(P, n, algo, levels, base);
@@ -277,11 +282,11 @@ int getrf_entry(int P, int64_t n, double* A, int64_t lda, int64_t psa, int32_t* 
   if (pivot != DDQD_PIVOT_NONE && pivot != DDQD_PIVOT_PARTIAL)
     return set_error(DDQD_E_ARG, "pivot must be DDQD_PIVOT_NONE or DDQD_PIVOT_PARTIAL");
   if (panel_width == DDQD_PANEL_AUTO && algo >= 0 && algo <= 3 && levels >= 0 && levels <= 6 &&
-      base >= 0 && base <= 1)
+      lu_base_ok(P, base))
     panel_width = panel_choice(P, n, pivot, algo, levels, base).panel;
   if (panel_width == 0 && pivot != DDQD_PIVOT_NONE)
     return set_error(DDQD_E_UNSUPPORTED, "the row-wise form (panel width 0) does not pivot");
-  if (algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 || base > 1)
+  if (algo < 0 || algo > 3 || levels < 0 || levels > 6 || !lu_base_ok(P, base))
     return set_error(DDQD_E_ARG, "bad product algorithm / levels / base");
   if (!info) return set_error(DDQD_E_ARG, "info is NULL");
   if (n > 0 && !ipiv) return set_error(DDQD_E_ARG, "ipiv is NULL");
@@ -355,8 +360,8 @@ int getrs_entry(int P, int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t getrf_tune_ws(int P, int64_t n, int algo, int levels, int base) {
-  if (n < 0 || n > kMaxLuRows || algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 ||
-      base > 1)
+  if (n < 0 || n > kMaxLuRows || algo < 0 || algo > 3 || levels < 0 || levels > 6 ||
+      !lu_base_ok(P, base))
     return SIZE_MAX;
   const size_t prod = auto_panel_ws(P, n, algo, levels, base);
   if (prod == SIZE_MAX) return SIZE_MAX;
@@ -374,7 +379,7 @@ int getrf_tune(int P, int64_t n, const double* A, int64_t lda, int64_t psa, int 
     return set_error(DDQD_E_UNSUPPORTED, "LU of order above %lld", (long long)kMaxLuRows);
   if (pivot != DDQD_PIVOT_NONE && pivot != DDQD_PIVOT_PARTIAL)
     return set_error(DDQD_E_ARG, "pivot must be DDQD_PIVOT_NONE or DDQD_PIVOT_PARTIAL");
-  if (algo < 0 || algo > 3 || levels < 0 || levels > 6 || base < 0 || base > 1)
+  if (algo < 0 || algo > 3 || levels < 0 || levels > 6 || !lu_base_ok(P, base))
     return set_error(DDQD_E_ARG, "bad product algorithm / levels / base");
   int rc;
   if ((rc = check_matrix("A", P, A, n, n, lda, psa))) return rc;
@@ -557,7 +562,7 @@ int ddqd_getrf_panel_lookup(int precision, int64_t n, int pivot, int algo, int l
   if (!panel) return set_error(DDQD_E_ARG, "panel is NULL");
   if ((precision != 2 && precision != 4) || n < 0 ||
       (pivot != DDQD_PIVOT_NONE && pivot != DDQD_PIVOT_PARTIAL) || algo < 0 || algo > 3 ||
-      levels < 0 || levels > 6 || base < 0 || base > 1)
+      levels < 0 || levels > 6 || !lu_base_ok(precision, base))
     return set_error(DDQD_E_ARG, "invalid panel lookup arguments");
   const PanelChoice c = panel_choice(precision, n, pivot, algo, levels, base);
   *panel = c.panel;

@@ -63,9 +63,11 @@ std::vector<Choice> candidates(int P, int64_t m, int64_t n, int64_t l, int base)
     const int big = P == 2 ? 64 : 32;
     c.push_back(Choice{DDQD_BLOCK, 0, big, 0, 0, 0.0});
     c.push_back(Choice{DDQD_BLOCK, 0, big / 2, 0, 0, 0.0});
-  } else {
+  } else if (base == DDQD_BASE_OZAKI_I8) {
     // Ozaki leaves: the band of tile rows an XCD's consecutive tiles span
     for (int band : {2, 4, 8, 16}) c.push_back(Choice{DDQD_BLOCK, 0, 0, band, 0, 0.0});
+  } else {
+    c.push_back(Choice{DDQD_BLOCK, 0, 0, 0, 0, 0.0});
   }
   int64_t batch = 1;
   for (int L = 1; L <= kMaxTuneLevels; L++) {

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libddqd.so")
 
 ALGO = {"simple": 0, "block": 1, "strassen": 2, "winograd": 3, "auto": 4}
 ALGO_NAME = {v: k for k, v in ALGO.items()}
-BASE = {"fma": 0, "ozaki": 1}
+BASE = {"fma": 0, "ozaki": 1, "crt": 2}
 PIVOT = {"none": 0, "partial": 1}
 
 if not os.path.exists(LIB_PATH):
@@ -104,6 +104,8 @@ _lib.ddqd_getrf_tune_workspace.restype = _sz
 _lib.ddqd_getrf_panel_lookup.argtypes = [_int, _i64, _int, _int, _int, _int, ctypes.POINTER(_int),
                                          ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)]
 _lib.ddqd_getrf_panel_lookup.restype = _int
+_lib.ddqd_crt_moduli.argtypes = [_i64, ctypes.POINTER(_int), _int]
+_lib.ddqd_crt_moduli.restype = _int
 _lib.ddqd_latency_probe.argtypes = [_vp, _int, _int, _vp]
 _lib.ddqd_latency_probe.restype = _int
 _lib.ddqd_graph_begin.argtypes = [_vp]
@@ -205,6 +207,15 @@ def qd_gemm(A, B, C=None, *, alpha=1, beta=0, algo="block", levels=0, base="fma"
     """C := beta*C + alpha*(A B) in quad-double; returns C.  base="ozaki" runs
     the leaves on INT8 matrix cores with `slices` digits (0 = 31)."""
     return _gemm(4, A, B, C, alpha, beta, algo, levels, base, slices, ws)
+
+
+def crt_moduli(l: int) -> list:
+    """The moduli base="crt" uses for a product with K = l (host only)."""
+    out = (_int * 32)()
+    N = _lib.ddqd_crt_moduli(l, out, 32)
+    if N < 0:
+        raise ValueError("l must be positive")
+    return list(out[:N])
 
 
 def getrf_workspace(n: int, panel=128, algo="winograd", levels=1, base="fma", P: int = 2) -> int:

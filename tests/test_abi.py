@@ -323,3 +323,38 @@ def test_grouped_descriptor_errors_and_workspace(lib):
     assert lib.dd_gemm_grouped(2, alias, None, 0, None) == E["ALIAS"]
     assert lib.dd_gemm_grouped(0, None, None, 0, None) == E["OK"]
     assert lib.dd_gemm_grouped(-1, None, None, 0, None) == E["ARG"]
+
+
+def test_crt_moduli_cover_the_product_range(lib):
+    """The CRT base's moduli for K = l: pairwise coprime, each fits INT8
+    residues (<= 256), and their product M exceeds 2 kc 2^214 (kc = min(l,
+    65536)), so the rebuilt integer product, |X| <= kc (2^107)^2, is unique."""
+    import math
+    from paper_1510_08642_amd import ddqd
+    for l, want in [(1, 29), (32, 29), (1024, 30), (2048, 30), (4096, 31), (65536, 31),
+                    (1 << 20, 31)]:
+        ms = ddqd.crt_moduli(l)
+        assert len(ms) == want, (l, ms)
+        assert all(2 <= m <= 256 for m in ms)
+        assert all(math.gcd(a, b) == 1 for i, a in enumerate(ms) for b in ms[i + 1:])
+        M = math.prod(ms)
+        kc = min(l, 65536)
+        assert M > 2 * kc * 2 ** 214
+        # the set is minimal for this rule: one modulus fewer does not cover it
+        assert math.log2(math.prod(ms[:-1])) < math.log2(2 * kc * 2 ** 214) + 0.01
+    assert lib.ddqd_crt_moduli(0, None, 0) == -1
+
+
+def test_crt_base_arguments(lib):
+    # QD has no CRT base; the CRT base takes no slice count
+    assert _call(lib, fn="qd_gemm", base=2) == E["UNSUPPORTED"]
+    assert _call(lib, base=2, slices=16) == E["ARG"]
+    assert _call(lib, base=3) == E["ARG"]
+    lib.dd_gemm_workspace.restype = ctypes.c_size_t
+    lib.qd_gemm_workspace.restype = ctypes.c_size_t
+    SIZE_MAX = 2 ** 64 - 1
+    # n = 1024: 30 moduli of 1 KB fragments for A, B and C, plus exponents
+    w = lib.dd_gemm_workspace(1024, 1024, 1024, 1, 0, 2, 0)
+    assert 3 * 30 * 1024 * 1024 <= w < 3 * 30 * 1024 * 1024 + (1 << 20)
+    assert lib.qd_gemm_workspace(64, 64, 64, 1, 0, 2, 0) == SIZE_MAX
+    assert lib.dd_gemm_workspace(64, 64, 64, 1, 0, 2, 8) == SIZE_MAX
