@@ -66,7 +66,7 @@ int launch_ozaki(int P, const GemmBatch& g, int slices, void* ws, size_t ws_byte
                  hipStream_t stream, int band = 0);
 bool ozaki_slices_ok(int P, int slices);
 size_t crt_workspace(int P, int64_t m, int64_t n, int64_t l, int64_t batch);
-int launch_crt(int P, const GemmBatch& g, void* ws, size_t ws_bytes, hipStream_t s);
+int launch_crt(int P, const GemmBatch& g, void* ws, size_t ws_bytes, hipStream_t s, int tile);
 
 static thread_local char g_msg[512];
 
@@ -250,7 +250,7 @@ Mat prodM(const Plan& pl, char* ws, int j) {
 int leaf(int P, const GemmBatch& g, int base, int slices, int tile, int band, void* ws,
          size_t ws_bytes, hipStream_t s) {
   if (base == DDQD_BASE_OZAKI_I8) return launch_ozaki(P, g, slices, ws, ws_bytes, s, band);
-  if (base == DDQD_BASE_CRT_I8) return launch_crt(P, g, ws, ws_bytes, s);
+  if (base == DDQD_BASE_CRT_I8) return launch_crt(P, g, ws, ws_bytes, s, tile);
   return P == 2 ? launch_dd_block(g, tile ? tile : 64, s) : launch_qd_block(g, tile, s);
 }
 
@@ -425,8 +425,10 @@ int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* 
   if (alpha != 1 && alpha != -1) return set_error(DDQD_E_ARG, "alpha must be +1 or -1");
   if (beta != 0 && beta != 1) return set_error(DDQD_E_ARG, "beta must be 0 or 1");
   if (algo < 0 || algo > DDQD_AUTO) return set_error(DDQD_E_ARG, "unknown algo %d", algo);
-  if (tile != 0 && tile != 32 && tile != (P == 2 ? 64 : 16))
-    return set_error(DDQD_E_ARG, P == 2 ? "tile must be 32 or 64" : "tile must be 16 or 32");
+  if (base == DDQD_BASE_CRT_I8 ? (tile != 0 && tile != 128 && tile != 256)
+                               : (tile != 0 && tile != 32 && tile != (P == 2 ? 64 : 16)))
+    return set_error(DDQD_E_ARG, base == DDQD_BASE_CRT_I8 ? "CRT tile must be 128 or 256"
+                                 : P == 2 ? "tile must be 32 or 64" : "tile must be 16 or 32");
   if (band < 0 || band > 64) return set_error(DDQD_E_ARG, "band must be in 0..64");
   if (levels < 0 || levels > kMaxLevels)
     return set_error(DDQD_E_ARG, "levels must be in 0..%d", kMaxLevels);

@@ -33,6 +33,7 @@
 #include "eft.hpp"
 #include "ozaki.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 
@@ -48,8 +49,8 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kCrtMaxN = 32;
 constexpr int kP1 = 107;              // |A'| <= 2^107
 constexpr int64_t kChunk = 65536;     // K per exact INT32 product
-constexpr int kTileBlocks = 4;        // a product workgroup's tile: 4 x 4 blocks of 32
-constexpr int kStages = 4;            // K blocks of fragments in LDS (prefetch depth 3)
+// A product workgroup's tile is TB x TB blocks of 32 (TB = 4: 128 x 128, each
+// wave 2 x 2 blocks; TB = 8: 256 x 256, each wave 4 x 4 blocks).
 
 // The moduli: pairwise coprime, largest first (each <= 256, so residues fit
 // INT8); the first N are used.
@@ -79,9 +80,9 @@ struct CrtProd {
   signed char* Cres;
   int N;
   double m[kCrtMaxN], inv[kCrtMaxN];
-  int64_t RB, CB, KB;        // 32-blocks of rows, columns, K (KB a multiple of kStages)
-  int64_t tiles_m, tiles_n;  // 128 x 128 tiles
-  int64_t kb0, kb1;          // K blocks of this chunk
+  int64_t RB, CB, KB;        // 32-blocks of rows, columns, K (KB a multiple of 4)
+  int64_t tiles_m, tiles_n;  // workgroup tiles
+  int64_t kb0, kb1;          // K blocks of this chunk (a multiple of 4)
   int64_t batch;
 };
 
@@ -180,21 +181,30 @@ int moduli_for(int64_t kc) {
 
 struct CrtLayout {
   int64_t m, n, l, batch;
-  int N;
-  int64_t RB, CB, KB;  // 32-blocks: rows (multiple of 4), columns (multiple of 4), K (of kStages)
-  int64_t kc;          // K chunk (multiple of 32 kStages)
+  int N, TB;
+  int64_t RB, CB, KB;  // 32-blocks: rows and columns (multiples of TB), K (of 4)
+  int64_t kc;          // K chunk
   size_t a_bytes, b_bytes, c_bytes;  // residues, all batch entries
 };
 
-CrtLayout crt_layout(int64_t m, int64_t n, int64_t l, int64_t batch) {
+// The larger tile where each dimension spans at least two of them; `tile`
+// 128 or 256 forces one (the tuner's candidates).
+int crt_tile_blocks(int64_t m, int64_t n, int tile) {
+  if (tile == 128) return 4;
+  if (tile == 256) return 8;
+  return m >= 512 && n >= 512 ? 8 : 4;
+}
+
+CrtLayout crt_layout(int64_t m, int64_t n, int64_t l, int64_t batch, int TB) {
   CrtLayout L;
   L.m = m;
   L.n = n;
   L.l = l;
   L.batch = batch;
-  L.RB = (m + 127) / 128 * kTileBlocks;
-  L.CB = (n + 127) / 128 * kTileBlocks;
-  L.KB = ((l + 31) / 32 + kStages - 1) / kStages * kStages;
+  L.TB = TB;
+  L.RB = (m + 32 * TB - 1) / (32 * TB) * TB;
+  L.CB = (n + 32 * TB - 1) / (32 * TB) * TB;
+  L.KB = ((l + 31) / 32 + 3) / 4 * 4;  // two steps of up to two blocks
   L.kc = l < kChunk ? l : kChunk;
   L.N = moduli_for(L.kc);
   L.a_bytes = (size_t)batch * L.N * L.RB * L.KB * kOzFrag;
@@ -344,13 +354,19 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(CMat A, CMat B, int64_
 }
 
 // ---- products ---------------------------------------------------------------
-// Workgroup = one 128 x 128 tile of C for one modulus and batch entry; 4
-// waves (2 x 2), each a 64 x 64 block (2 x 2 MFMA blocks, 64 accumulator
-// registers).  Fragments move global -> LDS by direct loads into a ring of
-// kStages K blocks (wave w loads A row block w and B column block w of a K
-// block), three K blocks ahead of the one the MFMAs read.
+// Workgroup = one tile of C (TB x TB blocks of 32) for one modulus and batch
+// entry; 4 waves (2 x 2), each WB x WB blocks (WB = TB / 2; 16 WB^2
+// accumulator registers).  K advances G blocks a step (one barrier a step).
+// Fragments move global -> LDS by direct loads into a ring of ST steps' G
+// blocks (each wave loads WB of a block's 2 TB fragments): once every wave
+// holds step x's fragments in registers, its slot takes step x + ST; near the
+// end the last block is loaded again into slots no one reads, so every wait
+// is the same.  A wave reads step x + 1's fragments from LDS while step x's
+// MFMAs run.
+template <int TB, int ST, int G>
 __global__ __launch_bounds__(256) void crt_gemm_kernel(CrtProd a) {
-  __shared__ v4i lds[kStages][2 * kTileBlocks][64];
+  constexpr int WB = TB / 2;
+  __shared__ v4i lds[ST][G][2 * TB][64];
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int wr = w / 2, wc = w % 2;
   const int wu = __builtin_amdgcn_readfirstlane(w);
@@ -362,62 +378,99 @@ __global__ __launch_bounds__(256) void crt_gemm_kernel(CrtProd a) {
   int64_t tm, tn;
   banded_tile(t % per, a.tiles_m, a.tiles_n, 2, tm, tn);
 
-  const signed char* srcA =
-      a.Ares + (((b * a.N + s) * a.RB + kTileBlocks * tm + wu) * a.KB) * kOzFrag + lane * 16;
-  const signed char* srcB =
-      a.Bres + (((b * a.N + s) * a.CB + kTileBlocks * tn + wu) * a.KB) * kOzFrag + lane * 16;
-  auto stage = [&](int64_t kb) {
-    const int st = (int)(kb % kStages);
-    __builtin_amdgcn_global_load_lds((const void*)(srcA + kb * kOzFrag),
-                                     (__attribute__((address_space(3))) void*)&lds[st][wu][0],
-                                     16, 0, 0);
-    __builtin_amdgcn_global_load_lds(
-        (const void*)(srcB + kb * kOzFrag),
-        (__attribute__((address_space(3))) void*)&lds[st][kTileBlocks + wu][0], 16, 0, 0);
+  // wave w stages fragments w, w + 4, ... of the 2 TB (A row blocks, then B
+  // column blocks) of each K block
+  const signed char* src[WB];
+#pragma unroll
+  for (int f = 0; f < WB; f++) {
+    const int x = wu + 4 * f;
+    src[f] = x < TB
+                 ? a.Ares + (((b * a.N + s) * a.RB + TB * tm + x) * a.KB) * kOzFrag + lane * 16
+                 : a.Bres + (((b * a.N + s) * a.CB + TB * tn + (x - TB)) * a.KB) * kOzFrag +
+                       lane * 16;
+  }
+  const int64_t kb0 = a.kb0, kb1 = a.kb1;
+  const int64_t steps = (kb1 - kb0) / G;
+  auto stage = [&](int64_t x) {  // the G blocks of step x
+    const int st = (int)(x % ST);
+#pragma unroll
+    for (int gg = 0; gg < G; gg++) {
+      const int64_t kb = kb0 + x * G + gg;
+      const int64_t kr = kb < kb1 ? kb : kb1 - 1;  // past the end: the last block again
+#pragma unroll
+      for (int f = 0; f < WB; f++)
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(src[f] + kr * kOzFrag),
+            (__attribute__((address_space(3))) void*)&lds[st][gg][wu + 4 * f][0], 16, 0, 0);
+    }
+  };
+  auto frags = [&](int64_t x, v4i (&fa)[G][WB], v4i (&fb)[G][WB]) {
+    const int st = (int)(x % ST);
+#pragma unroll
+    for (int gg = 0; gg < G; gg++) {
+#pragma unroll
+      for (int i = 0; i < WB; i++) fa[gg][i] = lds[st][gg][WB * wr + i][lane];
+#pragma unroll
+      for (int j = 0; j < WB; j++) fb[gg][j] = lds[st][gg][TB + WB * wc + j][lane];
+    }
+  };
+  // s_waitcnt with vmcnt = WB G (ST - 2) (the loads of the ST - 2 steps after
+  // the next one may stay in flight) and lgkmcnt = 0; gfx9 encoding: vmcnt in
+  // bits 3:0 and 15:14, expcnt 6:4 (7: no wait), lgkmcnt 11:8
+  constexpr int kV = WB * G * (ST - 2);
+  static_assert(kV < 64, "vmcnt has six bits");
+  constexpr int kWait = (kV & 15) | ((kV >> 4) << 14) | 0x70;
+  auto sync = [&]() {
+    __builtin_amdgcn_sched_barrier(0);  // the previous step's MFMAs stay before the wait
+    __builtin_amdgcn_s_waitcnt(kWait);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();  // (no fence: it would wait for every load in flight)
+    asm volatile("" ::: "memory");
   };
 
-  v16i acc[2][2];
+  v16i acc[WB][WB];
 #pragma unroll
-  for (int i = 0; i < 2; i++)
+  for (int i = 0; i < WB; i++)
 #pragma unroll
-    for (int j = 0; j < 2; j++)
+    for (int j = 0; j < WB; j++)
 #pragma unroll
       for (int q = 0; q < 16; q++) acc[i][j][q] = 0;
-  const int64_t kb0 = a.kb0, kb1 = a.kb1;
 #pragma unroll
-  for (int d = 0; d < kStages - 1; d++)
-    if (kb0 + d < kb1) stage(kb0 + d);
-  for (int64_t kb = kb0; kb < kb1; kb++) {
-    // this wave's loads of block kb have landed (those of kb+1, kb+2 may
-    // still be in flight); after the barrier every wave's have, and every
-    // wave is done reading block kb-1, whose slot the next load refills
-    // (two loads a block; gfx9 encoding: vmcnt in bits 3:0, expcnt and
-    // lgkmcnt left at their maxima)
-    if (kb + 2 < kb1) __builtin_amdgcn_s_waitcnt(0x0F74);       // vmcnt(4)
-    else if (kb + 1 < kb1) __builtin_amdgcn_s_waitcnt(0x0F72);  // vmcnt(2)
-    else __builtin_amdgcn_s_waitcnt(0x0F70);                    // vmcnt(0)
-    // a bare barrier: __syncthreads' fence would wait for every load in flight
-    // (the LDS writes of the blocks ahead too); the waits above and the LDS
-    // reads' own waits are the ordering this ring needs
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-    if (kb + kStages - 1 < kb1) stage(kb + kStages - 1);
-    const int st = (int)(kb % kStages);
-    const v4i fa0 = lds[st][2 * wr][lane], fa1 = lds[st][2 * wr + 1][lane];
-    const v4i fb0 = lds[st][kTileBlocks + 2 * wc][lane];
-    const v4i fb1 = lds[st][kTileBlocks + 2 * wc + 1][lane];
-    acc[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa0, fb0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa0, fb1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa1, fb0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa1, fb1, acc[1][1], 0, 0, 0);
+  for (int d = 0; d < ST; d++) stage(d);  // the whole ring
+  // two register sets of fragments, taken in turn (the loop runs two steps a
+  // pass, the step count being even, so each set is named statically)
+  v4i fa0[G][WB], fb0[G][WB], fa1[G][WB], fb1[G][WB];
+  // one step: step x + 1 landed for every wave and every wave's reads of
+  // step x are done (lgkmcnt 0), so step x's slot may be refilled
+  auto step = [&](int64_t x, v4i (&ua)[G][WB], v4i (&ub)[G][WB], v4i (&na)[G][WB],
+                  v4i (&nb)[G][WB]) {
+    sync();
+    stage(x + ST);  // into the slot of step x (== x + ST modulo ST)
+    if (x + 1 < steps) frags(x + 1, na, nb);
+#pragma unroll
+    for (int gg = 0; gg < G; gg++)
+#pragma unroll
+      for (int i = 0; i < WB; i++)
+#pragma unroll
+        for (int j = 0; j < WB; j++)
+          acc[i][j] =
+              __builtin_amdgcn_mfma_i32_32x32x32_i8(ua[gg][i], ub[gg][j], acc[i][j], 0, 0, 0);
+  };
+  // steps 0 and 1 in LDS (the ST - 2 later ones may be in flight), step 0
+  // in registers
+  sync();
+  frags(0, fa0, fb0);
+  for (int64_t x = 0; x < steps; x += 2) {
+    step(x, fa0, fb0, fa1, fb1);
+    step(x + 1, fa1, fb1, fa0, fb0);
   }
-  // residues of C_s: 16 bytes per lane and block, the MFMA output order
+  // residues of C_s: per block, quarter h of every lane's 16 outputs (the
+  // MFMA output order, q = 4 h .. 4 h + 3) at bytes 256 h + 4 lane
   const double mm = a.m[s], iv = a.inv[s];
 #pragma unroll
-  for (int i = 0; i < 2; i++)
+  for (int i = 0; i < WB; i++)
 #pragma unroll
-    for (int j = 0; j < 2; j++) {
+    for (int j = 0; j < WB; j++) {
       uint32_t wd[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
       for (int q = 0; q < 16; q++) {
@@ -425,16 +478,18 @@ __global__ __launch_bounds__(256) void crt_gemm_kernel(CrtProd a) {
         const double r = __builtin_fma(-rint(c * iv), mm, c);  // |r| <= m / 2
         wd[q / 4] |= ((uint32_t)(int)r & 0xFFu) << (8 * (q % 4));
       }
-      const int64_t rb = kTileBlocks * tm + 2 * wr + i, cb = kTileBlocks * tn + 2 * wc + j;
+      const int64_t rb = TB * tm + WB * wr + i, cb = TB * tn + WB * wc + j;
       const int64_t blk = ((b * a.N + s) * a.RB + rb) * a.CB + cb;
-      *(uint4*)(a.Cres + blk * kOzFrag + lane * 16) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+#pragma unroll
+      for (int h = 0; h < 4; h++) *(uint32_t*)(a.Cres + blk * kOzFrag + 256 * h + 4 * lane) = wd[h];
     }
 }
 
 // ---- rebuild ----------------------------------------------------------------
-// Two waves per 32 x 32 block of C (4 waves a workgroup): lane l of half h
-// takes the block's 8 outputs q = 8 h .. 8 h + 7 of column l % 32, rows
-// 8 (q / 4) + 4 (l / 32) + q % 4 (the MFMA output order).  The sum of
+// Workgroup = one 32 x 32 block of C; wave h takes quarter h of the block's
+// MFMA output order: lane l's outputs q = 4 h .. 4 h + 3, column l % 32, rows
+// 8 h + 4 (l / 32) + 0..3.  Every modulus' 4 residue bytes are loaded first
+// (32-bit loads, a wave's covering 256 contiguous bytes), then the sum of
 // c_s Z_s accumulates in 10 limbs of 16 bits per output (|limb| < 2^28).
 __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int64_t n,
                                                           int64_t RB, int64_t CB,
@@ -442,27 +497,33 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int6
                                                           const int* ea, const int* fb,
                                                           int alpha, int beta, CrtRebuild cb_,
                                                           int64_t blocks) {
-  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int64_t blk = (int64_t)blockIdx.x * 2 + w / 2;
-  const int h = w % 2;
+  const int h = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t blk = blockIdx.x;
   if (blk >= blocks) return;
   const int64_t per = RB * CB;
   const int64_t b = blk / per, rb = (blk % per) / CB, cbk = blk % CB;
   const int N = cb_.N;
-  int acc[8][kLimbs];
-#pragma unroll
-  for (int q = 0; q < 8; q++)
-#pragma unroll
-    for (int j = 0; j < kLimbs; j++) acc[q][j] = 0;
   const signed char* src =
-      Cres + ((b * N) * per + rb * CB + cbk) * kOzFrag + lane * 16 + 8 * h;
-  for (int s = 0; s < N; s++) {
-    const uint2 v = *(const uint2*)(src + (int64_t)s * per * kOzFrag);
+      Cres + ((b * N) * per + rb * CB + cbk) * kOzFrag + 256 * h + 4 * lane;
+  uint32_t v[kCrtMaxN];
 #pragma unroll
-    for (int q = 0; q < 8; q++) {
-      const int c = (int)(signed char)((q < 4 ? v.x : v.y) >> (8 * (q % 4)));
+  for (int s = 0; s < kCrtMaxN; s++)
+    v[s] = s < N ? *(const uint32_t*)(src + (int64_t)s * per * kOzFrag) : 0u;
+  // 32-bit sums, wrapping (the true sums fit 29 bits): 24-bit multiply-adds
+  uint32_t acc[4][kLimbs];
 #pragma unroll
-      for (int j = 0; j < kLimbs; j++) acc[q][j] += c * cb_.z[s][j];
+  for (int q = 0; q < 4; q++)
+#pragma unroll
+    for (int j = 0; j < kLimbs; j++) acc[q][j] = 0u;
+#pragma unroll
+  for (int s = 0; s < kCrtMaxN; s++) {
+    if (s < N) {
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int c = (int)(signed char)(v[s] >> (8 * q));
+#pragma unroll
+        for (int j = 0; j < kLimbs; j++) acc[q][j] += (uint32_t)__mul24(c, cb_.z[s][j]);
+      }
     }
   }
   const int64_t col = cbk * 32 + lane % 32;
@@ -470,18 +531,17 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int6
   const int fexp = fb[b * CB * 32 + col];
   double* Cb = C.p + b * C.bstride;
 #pragma unroll
-  for (int qq = 0; qq < 8; qq++) {
-    const int q = 8 * h + qq;
-    const int64_t row = rb * 32 + 8 * (q / 4) + 4 * (lane / 32) + q % 4;
+  for (int q = 0; q < 4; q++) {
+    const int64_t row = rb * 32 + 8 * h + 4 * (lane / 32) + q;
     if (row >= m) continue;
     // carries: limbs of 16 bits, the top one taken modulo 2^16 (the sum mod 2^160)
     int64_t carry = 0;
     uint32_t limb[kLimbs];
 #pragma unroll
     for (int j = 0; j < kLimbs; j++) {
-      const int64_t v = (int64_t)acc[qq][j] + carry;
-      limb[j] = (uint32_t)(v & 0xFFFF);
-      carry = v >> 16;  // arithmetic
+      const int64_t x = (int64_t)(int32_t)acc[q][j] + carry;
+      limb[j] = (uint32_t)(x & 0xFFFF);
+      carry = x >> 16;  // arithmetic
     }
     // the signed fraction F (units of 2^-160) from five 32-bit words, as a DD
     uint32_t wd[5];
@@ -507,8 +567,8 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int6
   }
 }
 
-int run_crt(const GemmBatch& g, char* ws, hipStream_t s) {
-  const CrtLayout L = crt_layout(g.m, g.n, g.l, g.batch);
+int run_crt(const GemmBatch& g, char* ws, hipStream_t s, int tile) {
+  const CrtLayout L = crt_layout(g.m, g.n, g.l, g.batch, crt_tile_blocks(g.m, g.n, tile));
   if (L.N == 0) return set_error(DDQD_E_UNSUPPORTED, "no modulus set covers K = %lld",
                                  (long long)g.l);
   const CrtWs w = crt_ws(ws, L);
@@ -537,22 +597,27 @@ int run_crt(const GemmBatch& g, char* ws, hipStream_t s) {
   p.RB = L.RB;
   p.CB = L.CB;
   p.KB = L.KB;
-  p.tiles_m = L.RB / kTileBlocks;
-  p.tiles_n = L.CB / kTileBlocks;
+  p.tiles_m = L.RB / L.TB;
+  p.tiles_n = L.CB / L.TB;
   p.batch = g.batch;
   const int64_t nblk = p.tiles_m * p.tiles_n * L.N * g.batch;
   const int64_t blocks = L.RB * L.CB * g.batch;
-  if (nblk > INT32_MAX || (blocks + 1) / 2 > INT32_MAX)
+  if (nblk > INT32_MAX || blocks > INT32_MAX)
     return set_error(DDQD_E_UNSUPPORTED, "grid too large");
   // K blocks per chunk: all of them when l fits one chunk (the padding
-  // blocks hold zeros), else kChunk / 32 (a multiple of kStages)
+  // blocks hold zeros), else kChunk / 32
   const int64_t kcb = g.l <= kChunk ? L.KB : kChunk / 32;
   for (int64_t kb0 = 0; kb0 < L.KB; kb0 += kcb) {
     p.kb0 = kb0;
     p.kb1 = kb0 + kcb < L.KB ? kb0 + kcb : L.KB;
-    launch_timed("crt_gemm_kernel", crt_gemm_kernel, dim3((unsigned)nblk), dim3(256), 0, s, p);
+    if (L.TB == 8)
+      launch_timed("crt_gemm_kernel", crt_gemm_kernel<8, 5, 2>, dim3((unsigned)nblk), dim3(256),
+                   0, s, p);
+    else
+      launch_timed("crt_gemm_kernel", crt_gemm_kernel<4, 4, 1>, dim3((unsigned)nblk), dim3(256),
+                   0, s, p);
     if ((rc = check_launch("crt_gemm_kernel"))) return rc;
-    launch_timed("crt_rebuild_kernel", crt_rebuild_kernel, dim3((unsigned)((blocks + 1) / 2)),
+    launch_timed("crt_rebuild_kernel", crt_rebuild_kernel, dim3((unsigned)blocks),
                  dim3(256), 0, s, g.C, g.m, g.n, L.RB, L.CB, (const signed char*)w.Cres,
                  (const int*)w.e.ea, (const int*)w.e.fb, g.alpha, kb0 == 0 ? g.beta : 1, k.reb,
                  blocks);
@@ -563,14 +628,16 @@ int run_crt(const GemmBatch& g, char* ws, hipStream_t s) {
 
 }  // namespace
 
+// enough for either tile (the tuner tries both on one workspace)
 size_t crt_workspace(int P, int64_t m, int64_t n, int64_t l, int64_t batch) {
   if (P != 2 || m <= 0 || n <= 0 || l <= 0 || batch <= 0) return 0;
-  const CrtLayout L = crt_layout(m, n, l, batch);
-  if (L.N == 0) return 0;
-  return crt_ws_bytes(L);
+  const CrtLayout L4 = crt_layout(m, n, l, batch, 4), L8 = crt_layout(m, n, l, batch, 8);
+  if (L4.N == 0) return 0;
+  return std::max(crt_ws_bytes(L4), crt_ws_bytes(L8));
 }
 
-int launch_crt(int P, const GemmBatch& g, void* ws, size_t ws_bytes, hipStream_t s) {
+// tile: 0 (by shape), 128 or 256
+int launch_crt(int P, const GemmBatch& g, void* ws, size_t ws_bytes, hipStream_t s, int tile) {
   if (P != 2) return set_error(DDQD_E_UNSUPPORTED, "the modular INT8 base is DD only");
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return DDQD_OK;
   if (g.l <= 0) return set_error(DDQD_E_ARG, "empty K reached the modular base");
@@ -578,7 +645,7 @@ int launch_crt(int P, const GemmBatch& g, void* ws, size_t ws_bytes, hipStream_t
   if (need == 0 || need > ws_bytes || !ws)
     return set_error(DDQD_E_WORKSPACE, "modular base: workspace of %zu bytes needed, %zu given",
                      need, ws_bytes);
-  return run_crt(g, (char*)ws, s);
+  return run_crt(g, (char*)ws, s, tile);
 }
 
 }  // namespace ddqd

@@ -67,7 +67,8 @@ std::vector<Choice> candidates(int P, int64_t m, int64_t n, int64_t l, int base)
     // Ozaki leaves: the band of tile rows an XCD's consecutive tiles span
     for (int band : {2, 4, 8, 16}) c.push_back(Choice{DDQD_BLOCK, 0, 0, band, 0, 0.0});
   } else {
-    c.push_back(Choice{DDQD_BLOCK, 0, 0, 0, 0, 0.0});
+    // CRT leaves: 128 x 128 or 256 x 256 product tiles
+    for (int t : {128, 256}) c.push_back(Choice{DDQD_BLOCK, 0, t, 0, 0, 0.0});
   }
   int64_t batch = 1;
   for (int L = 1; L <= kMaxTuneLevels; L++) {
