@@ -4,8 +4,9 @@ with DD LU and the serving loop's p50/p99 latency beside it.
 
 Step: one double-double product C := A B at n = 1024 (DD uniform inputs,
 seed 0, resident in HBM before timing) through the C ABI with the flagship
-configuration (Block algorithm on the Ozaki INT8-MFMA base, 16 slices, whose
-accuracy matches the FMA base).  W warm-up steps, then K steps timed with HIP
+configuration (Block algorithm on the CRT INT8-MFMA base: 30 moduli, one
+exact INT8 product each, the integer product rebuilt by the Chinese
+remainder theorem; its accuracy matches the FMA base).  W warm-up steps, then K steps timed with HIP
 events on the stream the library launches on, bracketed by device
 synchronisation; rank 0 prints one JSON line.
 
@@ -13,6 +14,7 @@ Also in the line:
   roofline      the dominant kernel's achieved rate against MI355X's peak,
                 from its own launch durations (library event hooks, a second
                 pass of the same K steps so the main timing carries no events)
+  roofline_ozaki the Ozaki split's product kernel (the other INT8 base)
   variants      every algorithm / base for DD at n = 1024, and QD
   lu            dd_getrf / dd_getrs at n = 2048 and 4096 (N(0,1) + n I)
   serving       2000 Poisson requests (60 % DD products, n log-uniform in
@@ -103,6 +105,20 @@ def kernel_avg_ms(dd, fn, steps, name):
 def roofline(dd, args, n, step, steps):
     leaves = 7 ** args.levels if args.algo in ("strassen", "winograd") else 1
     lf = n // (2 ** args.levels) if leaves > 1 else n
+    if args.base == "crt":
+        name = "crt_gemm_kernel"
+        N = len(dd.crt_moduli(lf))
+        avg, cnt = kernel_avg_ms(dd, step, steps, name)
+        per = max(1, cnt // steps)
+        ops = 2.0 * lf ** 3 * N * leaves / per
+        ach = ops / (avg * 1e-3) / 1e12
+        return {"bound": "mfma", "kernel": name, "achieved": round(ach, 1), "peak": INT8_PEAK_T,
+                "unit": "TFLOP/s", "frac": round(ach / INT8_PEAK_T, 4),
+                "traffic": measured_traffic(name), "avg_launch_ms": round(avg, 5),
+                "launches_per_step": per,
+                "note": f"INT8 MFMA operations (2 per multiply-add) of the N = {N} residue "
+                        "products per launch (one per modulus); peak = MI355X dense INT8 "
+                        "5.0 POP/s"}
     if args.base == "ozaki":
         name, S = "oz_gemm_kernel", 16
         avg, cnt = kernel_avg_ms(dd, step, steps, name)
@@ -407,7 +423,7 @@ def bench_equal_accuracy(dd, inputs, torch, dev, n, stream):
     g = inputs.rng(11)
     out = {}
     for P, cases in ((2, [("fma", 0), ("ozaki", 12), ("ozaki", 13), ("ozaki", 14),
-                          ("ozaki", 15), ("ozaki", 16)]),
+                          ("ozaki", 15), ("ozaki", 16), ("crt", 0)]),
                      (4, [("fma", 0), ("ozaki", 28), ("ozaki", 29), ("ozaki", 30),
                           ("ozaki", 31)])):
         gen = inputs.dd_uniform if P == 2 else inputs.qd_uniform
@@ -422,7 +438,7 @@ def bench_equal_accuracy(dd, inputs, torch, dev, n, stream):
 
             def f():
                 prod(A, B, C, algo="block", base=base, slices=S, ws=ws)
-            t = time_steps(f, 10 if (P == 2 or base == "ozaki") else 2, 2, stream)
+            t = time_steps(f, 10 if (P == 2 or base != "fma") else 2, 2, stream)
             f()
             torch.cuda.synchronize()
             err = sampled_error(Ah, Bh, C.cpu().numpy(), n)
@@ -571,7 +587,7 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--algo", default="block")
     ap.add_argument("--levels", type=int, default=0)
-    ap.add_argument("--base", default="ozaki")
+    ap.add_argument("--base", default="crt")
     ap.add_argument("--precision", choices=("dd", "qd"), default="dd",
                     help="timed product: dd_gemm (default) or qd_gemm (for profiling the QD "
                          "kernels; the extra legs still run as configured)")
@@ -654,6 +670,11 @@ def main():
     else:
         roof = roofline(dd, args, n, step, args.steps)
     log(f"bench: roofline {roof}")
+    roof_oz = None
+    if PM == 2 and args.base != "ozaki":
+        oz_args = argparse.Namespace(**{**vars(args), "base": "ozaki"})
+        roof_oz = roofline(dd, oz_args, n, make(args.algo, args.levels, "ozaki"), args.steps)
+        log(f"bench: Ozaki roofline {roof_oz}")
 
     variants = {}
     roof_qd = roof_qd_fma = None
@@ -663,7 +684,9 @@ def main():
                                  ("strassen", 3, "fma"), ("winograd", 1, "fma"),
                                  ("winograd", 2, "fma"), ("winograd", 3, "fma"),
                                  ("block", 0, "ozaki"), ("strassen", 1, "ozaki"),
-                                 ("winograd", 1, "ozaki"), ("winograd", 2, "ozaki")]:
+                                 ("winograd", 1, "ozaki"), ("winograd", 2, "ozaki"),
+                                 ("block", 0, "crt"), ("strassen", 1, "crt"),
+                                 ("winograd", 1, "crt"), ("winograd", 2, "crt")]:
             t = time_steps(make(algo, lv, base), 5 if algo != "simple" else 2, 1, stream)
             variants[f"dd_{algo}{lv}_{base}"] = round(flops / (t * 1e-3) / 1e9, 1)
             log(f"variant dd {algo} L{lv} {base}: {t:.3f} ms")
@@ -699,7 +722,7 @@ def main():
         B2 = torch.from_numpy(inputs.dd_uniform(n2, n2, g2)).to(dev)
         C2 = torch.empty((2, n2, n2), dtype=torch.float64, device=dev)
         recursive = [("block", 0)] + [(a, lv) for a in ("strassen", "winograd") for lv in (1, 2, 3)]
-        for base in ("fma", "ozaki"):
+        for base in ("fma", "ozaki", "crt"):
             for (algo, lv) in recursive:
                 ws2 = torch.empty(max(1, dd.gemm_workspace(2, n2, n2, n2, algo, lv, base)),
                                   dtype=torch.uint8, device=dev)
@@ -733,7 +756,8 @@ def main():
         Bs = B if PM == 2 else torch.from_numpy(inputs.dd_uniform(n, n, inputs.rng(2))).to(dev)
         row_scaled = {}
         for (algo, lv, base) in [("block", 0, "fma"), ("winograd", 1, "fma"),
-                                 ("block", 0, "ozaki"), ("winograd", 1, "ozaki")]:
+                                 ("block", 0, "ozaki"), ("winograd", 1, "ozaki"),
+                                 ("block", 0, "crt"), ("winograd", 1, "crt")]:
             wss = torch.empty(max(1, dd.gemm_workspace(2, n, n, n, algo, lv, base)),
                               dtype=torch.uint8, device=dev)
             t = time_steps(lambda: dd.dd_gemm(As, Bs, Cs, algo=algo, levels=lv, base=base,
@@ -749,7 +773,7 @@ def main():
     if not args.no_lu:
         lu = bench_lu(dd, inputs, torch, dev, [2048, 4096],
                       [(128, "winograd", 1, "fma"), (128, "winograd", 1, "ozaki"),
-                       (256, "block", 0, "ozaki")], stream)
+                       (128, "winograd", 1, "crt"), (256, "block", 0, "ozaki")], stream)
         lu.update(bench_lu(dd, inputs, torch, dev, [1024, 2048],
                            [(64, "block", 0, "fma"), (128, "block", 0, "ozaki")], stream, P=4))
 
@@ -785,14 +809,18 @@ def main():
         "value": round(value, 2), "unit": "GFLOPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": ("i8 mfma (i32 sums) + f64 recombination" if args.base == "ozaki" else "f64"),
+        "dtype": ({"ozaki": "i8 mfma (i32 sums) + f64 recombination",
+                   "crt": "i8 mfma (i32 sums) + crt rebuild (160-bit fixed point) + f64"}
+                  .get(args.base, "f64")),
         "data": "synthetic",
         "config": {"workload": f"{args.precision}_gemm m=n=l={n}, "
                                f"{args.precision.upper()} uniform inputs seed 0",
                    "algo": args.algo, "levels": args.levels, "base": args.base,
-                   "slices": (16 if PM == 2 else 31) if args.base == "ozaki" else None},
+                   "slices": (16 if PM == 2 else 31) if args.base == "ozaki" else None,
+                   "moduli": len(dd.crt_moduli(n)) if args.base == "crt" else None},
         "error_rownorm": err,
         "roofline": roof,
+        "roofline_ozaki": roof_oz,
         "roofline_qd_ozaki": roof_qd,
         "roofline_qd_fma": roof_qd_fma,
         "variants_gflops": variants,

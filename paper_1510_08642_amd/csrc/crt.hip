@@ -187,12 +187,15 @@ struct CrtLayout {
   size_t a_bytes, b_bytes, c_bytes;  // residues, all batch entries
 };
 
-// The larger tile where each dimension spans at least two of them; `tile`
-// 128 or 256 forces one (the tuner's candidates).
+// 128 x 128 unless `tile` asks for 256 x 256 (the tuner's other candidate):
+// the fragments' path from L2 to LDS, not LDS reads or register reuse, bounds
+// both (the larger tile moves half the bytes a multiply-add but runs one
+// workgroup a compute unit), and the smaller measured faster at n = 1024 and
+// 2048.
 int crt_tile_blocks(int64_t m, int64_t n, int tile) {
-  if (tile == 128) return 4;
-  if (tile == 256) return 8;
-  return m >= 512 && n >= 512 ? 8 : 4;
+  (void)m;
+  (void)n;
+  return tile == 256 ? 8 : 4;
 }
 
 CrtLayout crt_layout(int64_t m, int64_t n, int64_t l, int64_t batch, int TB) {
