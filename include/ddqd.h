@@ -284,7 +284,8 @@ size_t qd_getrs_workspace(int64_t n, int64_t nrhs);
  * process-wide, thread-safe cache that algo = DDQD_AUTO then uses.
  * Candidates: Block (FMA leaves: two tiles, DD 64x64 and 32x32, QD 32x32
  * and 16x16, which give bit-identical results; Ozaki leaves: tile orders in
- * bands of 2, 4, 8 or 16 tile rows, bit-identical too), and Strassen and
+ * bands of 2, 4, 8 or 16 tile rows, bit-identical too; CRT leaves: 128x128
+ * or 256x256 product tiles, bit-identical), and Strassen and
  * Winograd with 1..3 levels while the leaves keep at least 16 rows and
  * columns.  The base and the slice count are the caller's: they set the
  * accuracy, the tuner only the speed.  Without a cache entry DDQD_AUTO takes
@@ -303,7 +304,8 @@ size_t qd_getrs_workspace(int64_t n, int64_t nrhs);
 typedef struct {
   int algo;       /* DDQD_BLOCK, DDQD_STRASSEN or DDQD_WINOGRAD */
   int levels;     /* recursion depth */
-  int tile;       /* Block FMA leaf tile edge (DD 64 or 32, QD 32 or 16), 0 for Ozaki */
+  int tile;       /* Block leaf tile edge (FMA: DD 64 or 32, QD 32 or 16; CRT: 128 or
+                     256), 0 for Ozaki */
   int band;       /* Ozaki leaves: tile rows per band of the tile order, 0 = default */
   int candidates; /* configurations timed; 0 = not tuned, default shown */
   double ms;      /* time per call of the chosen configuration (0 if not tuned) */

@@ -23,7 +23,7 @@ def dd():
 
 CASES = [(2, "block", 0, "fma"), (2, "winograd", 1, "fma"), (2, "block", 0, "ozaki"),
          (2, "strassen", 1, "ozaki"), (4, "block", 0, "fma"), (4, "winograd", 1, "fma"),
-         (4, "block", 0, "ozaki")]
+         (4, "block", 0, "ozaki"), (2, "block", 0, "crt"), (2, "winograd", 1, "crt")]
 
 
 @pytest.mark.parametrize("P,algo,lv,base", CASES)

@@ -33,7 +33,8 @@ def _noise(dd, g):
 
 
 @pytest.mark.parametrize("algo,levels,base,n", [("block", 0, "fma", 200), ("winograd", 1, "ozaki", 301),
-                                                ("strassen", 2, "fma", 257)])
+                                                ("strassen", 2, "fma", 257), ("block", 0, "crt", 300),
+                                                ("winograd", 1, "crt", 258)])
 def test_gemm_replay_matches_eager(dd, algo, levels, base, n):
     import torch
     print(f"case graph gemm {algo}{levels} {base} n={n}", flush=True)

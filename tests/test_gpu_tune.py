@@ -31,7 +31,8 @@ def _err_ok(A, B, C, P, l):
 
 
 @pytest.mark.parametrize("P,m,n,l,base", [(2, 70, 75, 66, "fma"), (2, 256, 256, 256, "fma"),
-                                          (2, 300, 200, 310, "ozaki"), (4, 130, 130, 130, "fma")])
+                                          (2, 300, 200, 310, "ozaki"), (2, 300, 200, 310, "crt"),
+                                          (4, 130, 130, 130, "fma")])
 def test_tuned_choice_is_cached_and_exact_to_the_explicit_call(dd, P, m, n, l, base):
     import torch
     print(f"case tune P={P} {m}x{n}x{l} {base}", flush=True)
