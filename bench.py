@@ -107,10 +107,12 @@ def roofline(dd, args, n, step, steps):
     lf = n // (2 ** args.levels) if leaves > 1 else n
     if args.base == "crt":
         name = "crt_gemm_kernel"
-        N = len(dd.crt_moduli(lf))
+        qd = args.precision == "qd"
+        N = len(dd.crt_moduli(lf, precision=4 if qd else 2))
         avg, cnt = kernel_avg_ms(dd, step, steps, name)
         per = max(1, cnt // steps)
-        ops = 2.0 * lf ** 3 * N * leaves / per
+        # QD: H_a H_b over K and the cross product over 2 K per modulus
+        ops = 2.0 * lf ** 3 * N * (3 if qd else 1) * leaves / per
         ach = ops / (avg * 1e-3) / 1e12
         return {"bound": "mfma", "kernel": name, "achieved": round(ach, 1), "peak": INT8_PEAK_T,
                 "unit": "TFLOP/s", "frac": round(ach / INT8_PEAK_T, 4),
@@ -666,6 +668,7 @@ def main():
         if args.algo != "block":
             sys.exit("--precision qd times the QD Block product (either base)")
         roof = (roofline_qd_ozaki(dd, step, n, args.steps) if args.base == "ozaki" else
+                roofline(dd, args, n, step, args.steps) if args.base == "crt" else
                 roofline_qd_fma(dd, step, n, min(args.steps, 5)))
     else:
         roof = roofline(dd, args, n, step, args.steps)
@@ -677,7 +680,7 @@ def main():
         log(f"bench: Ozaki roofline {roof_oz}")
 
     variants = {}
-    roof_qd = roof_qd_fma = None
+    roof_qd = roof_qd_fma = roof_qd_crt = None
     if not args.no_variants:
         for (algo, lv, base) in [("simple", 0, "fma"), ("block", 0, "fma"),
                                  ("strassen", 1, "fma"), ("strassen", 2, "fma"),
@@ -697,7 +700,8 @@ def main():
         for (algo, lv, base) in [("block", 0, "fma"), ("strassen", 1, "fma"),
                                  ("winograd", 1, "fma"), ("winograd", 2, "fma"),
                                  ("winograd", 3, "fma"), ("block", 0, "ozaki"),
-                                 ("winograd", 1, "ozaki")]:
+                                 ("winograd", 1, "ozaki"), ("block", 0, "crt"),
+                                 ("winograd", 1, "crt")]:
             t = time_steps(make(algo, lv, base, 4, Aq, Bq, Cq), 2 if base == "fma" else 5, 1,
                            stream)
             variants[f"qd_{algo}{lv}_{base}"] = round(flops / (t * 1e-3) / 1e9, 1)
@@ -706,6 +710,10 @@ def main():
         log(f"bench: QD Ozaki roofline {roof_qd}")
         roof_qd_fma = roofline_qd_fma(dd, make("block", 0, "fma", 4, Aq, Bq, Cq), n, 2)
         log(f"bench: QD FMA roofline {roof_qd_fma}")
+        qd_args = argparse.Namespace(**{**vars(args), "base": "crt", "precision": "qd",
+                                        "algo": "block", "levels": 0})
+        roof_qd_crt = roofline(dd, qd_args, n, make("block", 0, "crt", 4, Aq, Bq, Cq), 5)
+        log(f"bench: QD CRT roofline {roof_qd_crt}")
         del Aq, Bq, Cq
 
     tuning = equal = None
@@ -817,12 +825,14 @@ def main():
                                f"{args.precision.upper()} uniform inputs seed 0",
                    "algo": args.algo, "levels": args.levels, "base": args.base,
                    "slices": (16 if PM == 2 else 31) if args.base == "ozaki" else None,
-                   "moduli": len(dd.crt_moduli(n)) if args.base == "crt" else None},
+                   "moduli": (len(dd.crt_moduli(n, precision=PM)) if args.base == "crt"
+                              else None)},
         "error_rownorm": err,
         "roofline": roof,
         "roofline_ozaki": roof_oz,
         "roofline_qd_ozaki": roof_qd,
         "roofline_qd_fma": roof_qd_fma,
+        "roofline_qd_crt": roof_qd_crt,
         "variants_gflops": variants,
         "tuned": tuning,
         "ozaki_vs_fma_equal_accuracy": equal,

@@ -67,21 +67,28 @@ extern "C" {
  * the digit products run exactly on v_mfma_i32_32x32x32_i8 and are recombined
  * in FP64.  Leaf error at most about l (S+3) 2^(-7S-2) max|a_i.| max|b_.j|
  * times 16, S the slice count.) */
-#define DDQD_BASE_CRT_I8 2 /* DD only: residues on INT8 matrix cores, CRT rebuild */
+#define DDQD_BASE_CRT_I8 2 /* residues on INT8 matrix cores, CRT rebuild      */
 /* (the same scaling, each operand then rounded to integers of at most 107
  * bits and reduced modulo N pairwise coprime moduli <= 256, N = 29..31 by K;
  * one exact INT8 product per modulus, the integer product rebuilt by the
- * Chinese remainder theorem in 128-bit fixed point.  Leaf error at most about
- * 2^-103 l max|a_i.| max|b_.j| for DD inputs with |lo| <= |hi|.  `slices` must
- * be 0; QD returns DDQD_E_UNSUPPORTED.) */
+ * Chinese remainder theorem in 160-bit fixed point.  Leaf error at most about
+ * 2^-103 l max|a_i.| max|b_.j| for normalised DD inputs (|lo| at most half an
+ * ulp of hi).  QD: integers of 214 bits, each split into a high part H of
+ * 107 bits and a low part L of 108; H_a H_b and H_a L_b + L_a H_b run as two
+ * exact products per modulus (the second over 2 K), L_a L_b is dropped, and
+ * the rebuild works in 270-bit fixed point; leaf error at most about
+ * 2^-211 l max|a_i.| max|b_.j| for normalised QD inputs (each term at most
+ * half an ulp of the one before).  `slices` must be 0.) */
 
 /*
- * The moduli DDQD_BASE_CRT_I8 uses for a product with K = l: writes the first
- * min(N, cap) of them to out (host memory) and returns N, the count (the
- * product of the N moduli exceeds 2 min(l, 65536) 2^214); -1 for l <= 0, a
- * negative cap, or out NULL with cap > 0.  No device work.
+ * The moduli DDQD_BASE_CRT_I8 uses for a product with K = l in precision 2
+ * (DD) or 4 (QD): writes the first min(N, cap) of them to out (host memory)
+ * and returns N, the count (the product of the N moduli exceeds
+ * 2 min(l, 65536) 2^214 in DD, min(l, 32768) 2^215 (1 + 2^-35) in QD); -1 for
+ * another precision, l <= 0, a negative cap, or out NULL with cap > 0.  No
+ * device work.
  */
-int ddqd_crt_moduli(int64_t l, int* out, int cap);
+int ddqd_crt_moduli(int precision, int64_t l, int* out, int cap);
 
 /* pivoting for dd_getrf */
 #define DDQD_PIVOT_NONE 0

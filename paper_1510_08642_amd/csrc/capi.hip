@@ -399,7 +399,7 @@ size_t gemm_ws(int P, int64_t m, int64_t n, int64_t l, int algo, int levels, int
                int slices) {
   if (m < 0 || n < 0 || l < 0 || algo < 0 || algo > DDQD_AUTO || levels < 0 ||
       levels > kMaxLevels || base < 0 || base > 2 || slices < 0 || slices > 40 ||
-      (base == DDQD_BASE_CRT_I8 && (P != 2 || slices != 0)))
+      (base == DDQD_BASE_CRT_I8 && slices != 0))
     return SIZE_MAX;
   if (m == 0 || n == 0 || l == 0) return 0;
   if (algo == DDQD_AUTO) return auto_workspace(P, m, n, l, base, slices);
@@ -435,8 +435,6 @@ int gemm_entry(int P, int64_t m, int64_t n, int64_t l, int alpha, const double* 
   if (base != DDQD_BASE_FMA && base != DDQD_BASE_OZAKI_I8 && base != DDQD_BASE_CRT_I8)
     return set_error(DDQD_E_ARG, "unknown base %d", base);
   if (slices < 0 || slices > 40) return set_error(DDQD_E_ARG, "slices must be in 0..40");
-  if (base == DDQD_BASE_CRT_I8 && P != 2)
-    return set_error(DDQD_E_UNSUPPORTED, "the CRT base is DD only");
   if (base == DDQD_BASE_CRT_I8 && slices != 0)
     return set_error(DDQD_E_ARG, "the CRT base takes no slice count (0)");
   if (base == DDQD_BASE_OZAKI_I8 && !ozaki_slices_ok(P, slices))

@@ -28,10 +28,29 @@
 // kc 2^(e_i + f_j - P1) <= kc 2^(4 - P1) max|a_i.| max|b_.j| (P1 = 107:
 // 2^-103 kc max|a_i.| max|b_.j|); the rebuild adds at most 2^12 M 2^-160
 // <= 2^86 units of X (2^(e_i + f_j - 128)) and the DD rounding of the result.
+//
+// QD.  The integers are T = a 2^(2 P1 + 1 - e) rounded (|T| <= 2^214), split
+// T = H 2^108 + L with |H| <= 2^106 and |L| <= 2^107 (1 + 2^-35) (the low
+// limbs balanced).  Then
+//   A'B' 2^-(430 - e - f) = H_a H_b 2^216 + (H_a L_b + L_a H_b) 2^108 + L_a L_b,
+// the last term dropped (at most kc 2^(e + f - 216)).  Both products run on
+// one set of N moduli (M > kc 2^215 (1 + 2^-35), the cross term's bound; the
+// cross product is one product over 2 K, [H_a L_a] by [L_b; H_b]): the
+// residues of H and L sit in alternate K blocks (A: H then L, B: L then H),
+// so the cross product reads every block and H_a H_b every other one.  The
+// rebuild takes F_hh in 270-bit fixed point (X_hh exact to far below one
+// unit) and F_x in 162-bit (X_x within 2^77 units, needed within 2^106), the
+// latter reduced to its signed value and added 108 bits down (18-bit limbs
+// make that a whole number of limbs), and C = M (F_hh + F_x 2^-108)
+// 2^(e + f - 214) from one QD fraction.
+// Error: the dropped term and the roundings of the integers, each at most
+// about kc 2^(e + f - 216) (in all kc 2^(e + f - 215) <= kc 2^-211 max|a_i.|
+// max|b_.j|), and the QD roundings of the rebuild.
 #include "ddqd.h"
 #include "common.hpp"
 #include "eft.hpp"
 #include "ozaki.hpp"
+#include "qd.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -74,13 +93,26 @@ struct CrtRebuild {
   double mhi, mlo;
 };
 
-// Product kernel launch description.
+// QD rebuild constants: Z_s = floor(y_s 2^270 / m_s) in 18-bit limbs (the
+// top nine are floor(y_s 2^162 / m_s), the cross term's) and M 2^-256 as a QD.
+constexpr int kLimbsQ = 15;  // 270-bit fixed point
+constexpr int kLimbsX = 9;   // 162-bit (the cross term, 108 bits = 6 limbs lower)
+struct CrtRebuildQ {
+  int N;
+  uint32_t z[kCrtMaxN][kLimbsQ];
+  double mq[4];
+};
+
+// Product kernel launch description.  Logical K block kb of a line is stored
+// block kb kst + koa (A) or kb kst + kob (B); NS residue sets are stored per
+// batch entry, of which the first N are multiplied.
 struct CrtProd {
   const signed char *Ares, *Bres;
   signed char* Cres;
-  int N;
+  int N, NS;
   double m[kCrtMaxN], inv[kCrtMaxN];
-  int64_t RB, CB, KB;        // 32-blocks of rows, columns, K (KB a multiple of 4)
+  int64_t kst, koa, kob;
+  int64_t RB, CB, KB;        // 32-blocks of rows, columns, stored K blocks
   int64_t tiles_m, tiles_n;  // workgroup tiles
   int64_t kb0, kb1;          // K blocks of this chunk (a multiple of 4)
   int64_t batch;
@@ -91,6 +123,7 @@ struct CrtProd {
 struct Consts {
   CrtResidue res;
   CrtRebuild reb;
+  CrtRebuildQ rq;
   double bits;  // log2 M
 };
 
@@ -108,7 +141,7 @@ int64_t inv_mod(int64_t a, int64_t m) {  // a^-1 mod m, gcd(a, m) = 1
 
 Consts make_consts(int N) {
   Consts c{};
-  c.res.N = c.reb.N = N;
+  c.res.N = c.reb.N = c.rq.N = N;
   c.bits = 0;
   // M as 32-bit words (at most 256 bits for 32 moduli)
   uint32_t M[9] = {1};
@@ -138,6 +171,22 @@ Consts make_consts(int N) {
     }
     for (int j = 0; j < kLimbs; j++)
       c.reb.z[s][j] = (int)((quo[j / 2] >> (16 * (j % 2))) & 0xFFFF);
+    // Z_s = floor(y 2^270 / m) likewise (QD; y 2^270 = (y 2^14) 2^256)
+    uint32_t numq[9] = {0, 0, 0, 0, 0, 0, 0, 0, (uint32_t)y << 14}, quoq[9];
+    rem = 0;
+    for (int w = 8; w >= 0; w--) {
+      const uint64_t cur = (rem << 32) | numq[w];
+      quoq[w] = (uint32_t)(cur / (uint64_t)m);
+      rem = cur % (uint64_t)m;
+    }
+    for (int j = 0; j < kLimbsQ; j++) {
+      uint32_t v = 0;
+      for (int b = 0; b < 18; b++) {
+        const int i = 18 * j + b;
+        v |= ((quoq[i / 32] >> (i % 32)) & 1u) << b;
+      }
+      c.rq.z[s][j] = v;
+    }
     // M *= m
     uint64_t carry = 0;
     for (int w = 0; w < 9; w++) {
@@ -157,6 +206,13 @@ Consts make_consts(int N) {
   const double lo = std::ldexp((double)lw, top - 105 - 160);
   c.reb.mhi = hi;
   c.reb.mlo = lo;
+  // M 2^-256 as a QD: four consecutive 53-bit pieces of M (truncated:
+  // relative error below 2^-211), each below an ulp of the one before
+  for (int p = 0; p < 4; p++) {
+    uint64_t w = 0;
+    for (int i = 53 * p; i < 53 * p + 53; i++) w = (w << 1) | bit(top - i);
+    c.rq.mq[p] = std::ldexp((double)w, top - 53 * p - 52 - 256);
+  }
   return c;
 }
 
@@ -169,22 +225,29 @@ const Consts& consts(int N) {
   return table[N];
 }
 
-// Moduli for K chunks of kc: M > 2 kc 2^(2 P1) (|A'|, |B'| <= 2^P1).
-int moduli_for(int64_t kc) {
-  const double need = 2.0 * kP1 + std::log2((double)(kc < 1 ? 1 : kc)) + 1.0 + 0.01;
+int moduli_for_bits(double need) {
   for (int n = 1; n <= kCrtMaxN; n++)
     if (consts(n).bits >= need) return n;
   return 0;
+}
+
+// Moduli for K chunks of kc: M > 2 kc 2^(2 P1) (|A'|, |B'| <= 2^P1); QD:
+// M > kc 2^215 (1 + 2^-35), the cross term's bound.
+int moduli_for(int P, int64_t kc) {
+  const double lk = std::log2((double)(kc < 1 ? 1 : kc));
+  return moduli_for_bits(P == 4 ? 215.0 + lk + 0.01 : 2.0 * kP1 + lk + 1.0 + 0.01);
 }
 
 // ---- layout and workspace ---------------------------------------------------
 
 struct CrtLayout {
   int64_t m, n, l, batch;
-  int N, TB;
-  int64_t RB, CB, KB;  // 32-blocks: rows and columns (multiples of TB), K (of 4)
-  int64_t kc;          // K chunk
-  size_t a_bytes, b_bytes, c_bytes;  // residues, all batch entries
+  int P, N, TB;
+  int64_t RB, CB;  // 32-blocks of rows and columns (multiples of TB)
+  int64_t KBo;     // 32-blocks of K (a multiple of 4)
+  int64_t KB;      // stored K blocks a line: KBo (DD), 2 KBo (QD: H and L)
+  int64_t kc;      // K chunk
+  size_t a_bytes, b_bytes, c_bytes;  // residues, all batch entries (c: per product)
 };
 
 // 128 x 128 unless `tile` asks for 256 x 256 (the tuner's other candidate):
@@ -198,18 +261,24 @@ int crt_tile_blocks(int64_t m, int64_t n, int tile) {
   return tile == 256 ? 8 : 4;
 }
 
-CrtLayout crt_layout(int64_t m, int64_t n, int64_t l, int64_t batch, int TB) {
+// K per chunk: the INT32 sums of one product cover kChunk (QD: the cross
+// product runs over twice the chunk)
+int64_t chunk_k(int P) { return P == 4 ? kChunk / 2 : kChunk; }
+
+CrtLayout crt_layout(int P, int64_t m, int64_t n, int64_t l, int64_t batch, int TB) {
   CrtLayout L;
   L.m = m;
   L.n = n;
   L.l = l;
   L.batch = batch;
+  L.P = P;
   L.TB = TB;
   L.RB = (m + 32 * TB - 1) / (32 * TB) * TB;
   L.CB = (n + 32 * TB - 1) / (32 * TB) * TB;
-  L.KB = ((l + 31) / 32 + 3) / 4 * 4;  // two steps of up to two blocks
-  L.kc = l < kChunk ? l : kChunk;
-  L.N = moduli_for(L.kc);
+  L.KBo = ((l + 31) / 32 + 3) / 4 * 4;  // two steps of up to two blocks
+  L.KB = P == 4 ? 2 * L.KBo : L.KBo;
+  L.kc = l < chunk_k(P) ? l : chunk_k(P);
+  L.N = moduli_for(P, L.kc);
   L.a_bytes = (size_t)batch * L.N * L.RB * L.KB * kOzFrag;
   L.b_bytes = (size_t)batch * L.N * L.CB * L.KB * kOzFrag;
   L.c_bytes = (size_t)batch * L.N * L.RB * L.CB * kOzFrag;
@@ -231,13 +300,14 @@ OzLayout exp_layout(const CrtLayout& L) {
 }
 
 struct CrtWs {
-  signed char *Ares, *Bres, *Cres;
+  signed char *Ares, *Bres, *Cres, *Cx;  // Cx: QD's cross product
   OzWs e;  // exponents (Asl / Bsl unused)
 };
 
 size_t crt_ws_bytes(const CrtLayout& L) {
   const OzLayout o = exp_layout(L);
-  return oz_align256(L.a_bytes) + oz_align256(L.b_bytes) + oz_align256(L.c_bytes) +
+  return oz_align256(L.a_bytes) + oz_align256(L.b_bytes) +
+         (L.P == 4 ? 2 : 1) * oz_align256(L.c_bytes) +
          oz_align256(sizeof(int) * (size_t)(L.batch * (o.rb + o.cb) * 32)) +
          oz_align256(sizeof(int) * (size_t)(L.batch * o.kb * o.cb * 32));
 }
@@ -250,6 +320,11 @@ CrtWs crt_ws(char* ws, const CrtLayout& L) {
   ws += oz_align256(L.b_bytes);
   w.Cres = (signed char*)ws;
   ws += oz_align256(L.c_bytes);
+  w.Cx = nullptr;
+  if (L.P == 4) {
+    w.Cx = (signed char*)ws;
+    ws += oz_align256(L.c_bytes);
+  }
   const OzLayout o = exp_layout(L);
   w.e.Asl = w.e.Bsl = nullptr;
   w.e.ea = (int*)ws;
@@ -264,16 +339,18 @@ CrtWs crt_ws(char* ws, const CrtLayout& L) {
 // one batch entry; A's chunks first, then B's.  Thread t takes line t % 32
 // and k = 8 (t / 32) + 0..7: it forms the 8 integers, then for each modulus
 // their 8 residues (8 bytes of its line's 16-byte fragment slot; a wave's
-// stores cover half a fragment, 512 contiguous bytes).
+// stores cover half a fragment, 512 contiguous bytes).  QD: H and L each, in
+// the line's stored blocks 2 kb and 2 kb + 1 (A: H first, B: L first).
+template <int P>
 __global__ __launch_bounds__(256) void crt_residue_kernel(CMat A, CMat B, int64_t m, int64_t n,
                                                           int64_t l, int64_t RB, int64_t CB,
-                                                          int64_t KB, int64_t kbe,
+                                                          int64_t KBo, int64_t KB, int64_t kbe,
                                                           const int* ea, const int* part,
                                                           int* fb, CrtResidue cr,
                                                           signed char* Ares, signed char* Bres) {
   __shared__ int xc[8][32];
   const int64_t b = blockIdx.y;
-  const int64_t kchunks = KB / 2;
+  const int64_t kchunks = KBo / 2;
   const int64_t ch = blockIdx.x;
   const int side = ch < RB * kchunks ? 0 : 1;
   const int64_t x = side == 0 ? ch : ch - RB * kchunks;
@@ -307,34 +384,70 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(CMat A, CMat B, int64_
   const int64_t live = side == 0 ? m : n;
   const double* base = X.p + b * X.bstride;
   const int64_t k0 = kc * 64 + 8 * g;
-  double hv[8], lv[8];
+  double v[P][8];
 #pragma unroll
   for (int q = 0; q < 8; q++) {
     const int64_t k = k0 + q;
     const bool in = line < live && k < l;
     const int64_t idx = in ? (side == 0 ? line * X.ld + k : k * X.ld + line) : 0;
-    hv[q] = in ? base[idx] : 0.0;
-    lv[q] = in ? base[X.ps + idx] : 0.0;
-  }
-  // integers A' = h + l (h, l integers held in doubles) as three limbs of 36
-  // bits: A' = d0 + d1 2^36 + d2 2^72 (all exact)
-  double d0[8], d1[8], d2[8];
-  const int sh = kP1 - ex;
 #pragma unroll
-  for (int q = 0; q < 8; q++) {
-    double s, e;
-    two_sum(hv[q], lv[q], s, e);  // normalised (exact)
-    const double hs = ldexp(s, sh), h = rint(hs);
-    const double lo = rint(ldexp(e, sh) + (hs - h));
-    const double c2 = trunc(h * 0x1p-72);
-    const double h1 = __builtin_fma(-c2, 0x1p72, h);
-    const double c1 = trunc(h1 * 0x1p-36);
-    const double c0 = __builtin_fma(-c1, 0x1p36, h1);
-    const double l1 = trunc(lo * 0x1p-36);
-    const double l0 = __builtin_fma(-l1, 0x1p36, lo);
-    d0[q] = c0 + l0;
-    d1[q] = c1 + l1;
-    d2[q] = c2;
+    for (int c = 0; c < P; c++) v[c][q] = in ? base[c * X.ps + idx] : 0.0;
+  }
+  // limbs of 36 bits (all exact): DD, A' = d0 + d1 2^36 + d2 2^72; QD,
+  // T = sum_j d_j 2^(36 j), H = d3 + d4 2^36 + d5 2^72, L = d0 + d1 2^36 + d2 2^72
+  constexpr int NLB = P == 4 ? 6 : 3;
+  double d[NLB][8];
+  if constexpr (P == 2) {
+    const int sh = kP1 - ex;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      double s, e;
+      two_sum(v[0][q], v[1][q], s, e);  // normalised (exact)
+      const double hs = ldexp(s, sh), h = rint(hs);
+      const double lo = rint(ldexp(e, sh) + (hs - h));
+      const double c2 = trunc(h * 0x1p-72);
+      const double h1 = __builtin_fma(-c2, 0x1p72, h);
+      const double c1 = trunc(h1 * 0x1p-36);
+      const double c0 = __builtin_fma(-c1, 0x1p36, h1);
+      const double l1 = trunc(lo * 0x1p-36);
+      const double l0 = __builtin_fma(-l1, 0x1p36, lo);
+      d[0][q] = c0 + l0;
+      d[1][q] = c1 + l1;
+      d[2][q] = c2;
+    }
+  } else {
+    // T = a 2^(2 P1 + 1 - e) rounded: each component rounded with the
+    // previous one's fraction carried in (that sum is exact or of terms
+    // below 1), then cut into six limbs (|d_j| < 2^38 summed)
+    const int sh = 2 * kP1 + 1 - ex;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+#pragma unroll
+      for (int j = 0; j < 6; j++) d[j][q] = 0.0;
+      double f = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        const double xs = ldexp(v[c][q], sh) + f;
+        double r = rint(xs);
+        f = xs - r;
+        constexpr double up[6] = {1.0, 0x1p36, 0x1p72, 0x1p108, 0x1p144, 0x1p180};
+        constexpr double dn[6] = {1.0, 0x1p-36, 0x1p-72, 0x1p-108, 0x1p-144, 0x1p-180};
+#pragma unroll
+        for (int j = 5; j >= 1; j--) {
+          const double cj = trunc(r * dn[j]);
+          r = __builtin_fma(-cj, up[j], r);
+          d[j][q] += cj;
+        }
+        d[0][q] += r;
+      }
+      // balance the low limbs (|d_j| <= 2^35, j < 3), so |L| <= 2^107 (1 + 2^-35)
+#pragma unroll
+      for (int j = 0; j < 3; j++) {
+        const double cy = rint(d[j][q] * 0x1p-36);
+        d[j][q] = __builtin_fma(-cy, 0x1p36, d[j][q]);
+        d[j + 1][q] += cy;
+      }
+    }
   }
   // fragment slot of (line, k0): K block, half and byte offset
   const int64_t kb = kc * 2 + g / 4;
@@ -344,15 +457,22 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(CMat A, CMat B, int64_
   const int64_t slot = (ln + 32 * half) * 16 + off;
   for (int s = 0; s < cr.N; s++) {
     const double mm = cr.m[s], iv = cr.inv[s], t1 = cr.t36[s], t2 = cr.t72[s];
-    uint32_t w[2] = {0u, 0u};
+    const int64_t line0 = ((b * cr.N + s) * lines + lb) * KB;
 #pragma unroll
-    for (int q = 0; q < 8; q++) {
-      const double xr = __builtin_fma(d2[q], t2, __builtin_fma(d1[q], t1, d0[q]));  // exact
-      const double r = __builtin_fma(-rint(xr * iv), mm, xr);  // |r| <= m / 2
-      w[q / 4] |= ((uint32_t)(int)r & 0xFFu) << (8 * (q % 4));
+    for (int part3 = 0; part3 < NLB / 3; part3++) {  // DD: A'; QD: L, then H
+      uint32_t w[2] = {0u, 0u};
+#pragma unroll
+      for (int q = 0; q < 8; q++) {
+        const double xr = __builtin_fma(d[3 * part3 + 2][q], t2,
+                                        __builtin_fma(d[3 * part3 + 1][q], t1,
+                                                      d[3 * part3][q]));  // exact
+        const double r = __builtin_fma(-rint(xr * iv), mm, xr);  // |r| <= m / 2
+        w[q / 4] |= ((uint32_t)(int)r & 0xFFu) << (8 * (q % 4));
+      }
+      // DD: block kb; QD: L to 2 kb + 1 (A) or 2 kb (B), H to the other
+      const int64_t sb = P == 2 ? kb : 2 * kb + ((part3 == 0) == (side == 0) ? 1 : 0);
+      *(uint2*)(dst + (line0 + sb) * kOzFrag + slot) = make_uint2(w[0], w[1]);
     }
-    const int64_t frag = ((b * cr.N + s) * lines + lb) * KB + kb;
-    *(uint2*)(dst + frag * kOzFrag + slot) = make_uint2(w[0], w[1]);
   }
 }
 
@@ -366,7 +486,7 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(CMat A, CMat B, int64_
 // end the last block is loaded again into slots no one reads, so every wait
 // is the same.  A wave reads step x + 1's fragments from LDS while step x's
 // MFMAs run.
-template <int TB, int ST, int G>
+template <int TB, int ST, int G, int KST>
 __global__ __launch_bounds__(256) void crt_gemm_kernel(CrtProd a) {
   constexpr int WB = TB / 2;
   __shared__ v4i lds[ST][G][2 * TB][64];
@@ -387,11 +507,13 @@ __global__ __launch_bounds__(256) void crt_gemm_kernel(CrtProd a) {
 #pragma unroll
   for (int f = 0; f < WB; f++) {
     const int x = wu + 4 * f;
-    src[f] = x < TB
-                 ? a.Ares + (((b * a.N + s) * a.RB + TB * tm + x) * a.KB) * kOzFrag + lane * 16
-                 : a.Bres + (((b * a.N + s) * a.CB + TB * tn + (x - TB)) * a.KB) * kOzFrag +
-                       lane * 16;
+    src[f] = x < TB ? a.Ares + (((b * a.NS + s) * a.RB + TB * tm + x) * a.KB + a.koa) * kOzFrag +
+                          lane * 16
+                    : a.Bres +
+                          (((b * a.NS + s) * a.CB + TB * tn + (x - TB)) * a.KB + a.kob) * kOzFrag +
+                          lane * 16;
   }
+  constexpr int64_t kstep = KST * kOzFrag;  // bytes between logical K blocks (a.kst)
   const int64_t kb0 = a.kb0, kb1 = a.kb1;
   const int64_t steps = (kb1 - kb0) / G;
   auto stage = [&](int64_t x) {  // the G blocks of step x
@@ -403,7 +525,7 @@ __global__ __launch_bounds__(256) void crt_gemm_kernel(CrtProd a) {
 #pragma unroll
       for (int f = 0; f < WB; f++)
         __builtin_amdgcn_global_load_lds(
-            (const void*)(src[f] + kr * kOzFrag),
+            (const void*)(src[f] + kr * kstep),
             (__attribute__((address_space(3))) void*)&lds[st][gg][wu + 4 * f][0], 16, 0, 0);
     }
   };
@@ -570,8 +692,148 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int6
   }
 }
 
-int run_crt(const GemmBatch& g, char* ws, hipStream_t s, int tile) {
-  const CrtLayout L = crt_layout(g.m, g.n, g.l, g.batch, crt_tile_blocks(g.m, g.n, tile));
+// QD rebuild.  The fraction (H_a H_b's sum of c_s Z_s mod 2^270 plus the
+// cross term's signed fraction 2^-108, in 15 limbs of 18 bits) as a QD value
+// in [-1/2, 1/2): the magnitude's limbs (the sums negated when the sign bit is
+// set), in 36-bit pieces (exact doubles, non-negative and non-overlapping),
+// summed error-free into four terms by bottom-up TwoSum passes as in qd_add.
+__device__ __forceinline__ qd_t crt_fraction_qd(const uint32_t (&acc)[kLimbsQ]) {
+  uint32_t limb[kLimbsQ];
+  int64_t carry = 0;
+#pragma unroll
+  for (int j = 0; j < kLimbsQ; j++) {
+    const int64_t x = (int64_t)(int32_t)acc[j] + carry;
+    limb[j] = (uint32_t)(x & 0x3FFFF);
+    carry = x >> 18;  // arithmetic
+  }
+  const bool neg = (limb[kLimbsQ - 1] & 0x20000u) != 0;
+  if (neg) {
+    carry = 0;
+#pragma unroll
+    for (int j = 0; j < kLimbsQ; j++) {
+      const int64_t x = -(int64_t)(int32_t)acc[j] + carry;
+      limb[j] = (uint32_t)(x & 0x3FFFF);
+      carry = x >> 18;
+    }
+  }
+  constexpr int NP = (kLimbsQ + 1) / 2;  // pieces, most significant first in v
+  double v[NP];
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    const uint64_t w = 2 * p + 1 < kLimbsQ
+                           ? (uint64_t)limb[2 * p] | ((uint64_t)limb[2 * p + 1] << 18)
+                           : (uint64_t)limb[2 * p];
+    v[NP - 1 - p] = ldexp((double)w, 36 * p - 18 * kLimbsQ);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; k++)
+#pragma unroll
+    for (int i = NP - 1; i > k; i--) two_sum(v[i - 1], v[i], v[i - 1], v[i]);
+  double tail = 0.0;
+#pragma unroll
+  for (int i = NP - 1; i >= 4; i--) tail += v[i];
+  qd_t z{{v[0], v[1], v[2], v[3] + tail}};
+  qd_renorm(z.c[0], z.c[1], z.c[2], z.c[3]);
+  return neg ? qd_neg(z) : z;
+}
+
+// Workgroup = one 32 x 32 block of C, threads as in crt_rebuild_kernel (4
+// outputs each).  The cross product's residues first: F_x = sum c_s Z'_s mod
+// 2^162 (Z' = Z's top nine limbs), carried, its sign extended over the frame
+// (F_x 2^-108 sits exactly on the low nine limbs of the 270-bit frame); then
+// H_a H_b's c_s Z_s accumulate on top, and C = M 2^-256 F 2^(e + f + 42).
+// (four waves a SIMD: the grid's 4 waves per SIMD at n = 1024 in one round)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void
+crt_rebuild_qd_kernel(Mat C, int64_t m, int64_t n, int64_t RB, int64_t CB, const signed char* Chh,
+                      const signed char* Cx, const int* ea, const int* fb, int alpha, int beta,
+                      CrtRebuildQ k, int64_t blocks) {
+  const int h = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t blk = blockIdx.x;
+  if (blk >= blocks) return;
+  const int64_t per = RB * CB;
+  const int64_t b = blk / per, rb = (blk % per) / CB, cbk = blk % CB;
+  const int N = k.N;
+  const int64_t off0 = ((b * N) * per + rb * CB + cbk) * kOzFrag + 256 * h + 4 * lane;
+  constexpr int J0 = kLimbsQ - kLimbsX;
+  uint32_t acc[4][kLimbsQ];
+  {
+    uint32_t v[kCrtMaxN];
+#pragma unroll
+    for (int s = 0; s < kCrtMaxN; s++)
+      v[s] = s < N ? *(const uint32_t*)(Cx + off0 + (int64_t)s * per * kOzFrag) : 0u;
+    uint32_t ax[4][kLimbsX];
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+      for (int j = 0; j < kLimbsX; j++) ax[q][j] = 0u;
+#pragma unroll
+    for (int s = 0; s < kCrtMaxN; s++) {
+      if (s < N) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const int c = (int)(signed char)(v[s] >> (8 * q));
+#pragma unroll
+          for (int j = 0; j < kLimbsX; j++)
+            ax[q][j] += (uint32_t)__mul24(c, (int)k.z[s][J0 + j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      int64_t carry = 0;
+#pragma unroll
+      for (int j = 0; j < kLimbsX; j++) {
+        const int64_t x = (int64_t)(int32_t)ax[q][j] + carry;
+        acc[q][j] = (uint32_t)(x & 0x3FFFF);
+        carry = x >> 18;
+      }
+      // F_x negative: F_x - 2^162, i.e. all-ones limbs above
+      const uint32_t ext = (acc[q][kLimbsX - 1] & 0x20000u) ? 0x3FFFFu : 0u;
+#pragma unroll
+      for (int j = kLimbsX; j < kLimbsQ; j++) acc[q][j] = ext;
+    }
+  }
+  {
+    uint32_t v[kCrtMaxN];
+#pragma unroll
+    for (int s = 0; s < kCrtMaxN; s++)
+      v[s] = s < N ? *(const uint32_t*)(Chh + off0 + (int64_t)s * per * kOzFrag) : 0u;
+#pragma unroll
+    for (int s = 0; s < kCrtMaxN; s++) {
+      if (s < N) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const int c = (int)(signed char)(v[s] >> (8 * q));
+#pragma unroll
+          for (int j = 0; j < kLimbsQ; j++) acc[q][j] += (uint32_t)__mul24(c, (int)k.z[s][j]);
+        }
+      }
+    }
+  }
+  const int64_t col = cbk * 32 + lane % 32;
+  if (col >= n) return;
+  const int fexp = fb[b * CB * 32 + col];
+  double* Cb = C.p + b * C.bstride;
+  const qd_t mq{{k.mq[0], k.mq[1], k.mq[2], k.mq[3]}};
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const int64_t row = rb * 32 + 8 * h + 4 * (lane / 32) + q;
+    if (row >= m) continue;
+    qd_t x = qd_mul(crt_fraction_qd(acc[q]), mq);
+    const int sc = ea[b * RB * 32 + row] + fexp + 42;
+#pragma unroll
+    for (int c = 0; c < 4; c++) x.c[c] = ldexp(x.c[c], sc);
+    if (alpha < 0) x = qd_neg(x);
+    const int64_t off = row * C.ld + col;
+    if (beta)
+      x = qd_add(qd_t{{Cb[off], Cb[C.ps + off], Cb[2 * C.ps + off], Cb[3 * C.ps + off]}}, x);
+#pragma unroll
+    for (int c = 0; c < 4; c++) Cb[c * C.ps + off] = x.c[c];
+  }
+}
+
+int run_crt(int P, const GemmBatch& g, char* ws, hipStream_t s, int tile) {
+  const CrtLayout L = crt_layout(P, g.m, g.n, g.l, g.batch, crt_tile_blocks(g.m, g.n, tile));
   if (L.N == 0) return set_error(DDQD_E_UNSUPPORTED, "no modulus set covers K = %lld",
                                  (long long)g.l);
   const CrtWs w = crt_ws(ws, L);
@@ -580,19 +842,25 @@ int run_crt(const GemmBatch& g, char* ws, hipStream_t s, int tile) {
   if (rc) return rc;
   const Consts& k = consts(L.N);
   // residues
-  const int64_t chunks = (L.RB + L.CB) * (L.KB / 2);
+  const int64_t chunks = (L.RB + L.CB) * (L.KBo / 2);
   if (chunks > INT32_MAX || g.batch > 65535)
     return set_error(DDQD_E_UNSUPPORTED, "residue grid too large");
-  launch_timed("crt_residue_kernel", crt_residue_kernel, dim3((unsigned)chunks, (unsigned)g.batch),
-               dim3(256), 0, s, g.A, g.B, g.m, g.n, g.l, L.RB, L.CB, L.KB, o.kb,
-               (const int*)w.e.ea, (const int*)w.e.part, w.e.fb, k.res, w.Ares, w.Bres);
+  if (P == 4)
+    launch_timed("crt_residue_kernel", crt_residue_kernel<4>,
+                 dim3((unsigned)chunks, (unsigned)g.batch), dim3(256), 0, s, g.A, g.B, g.m, g.n,
+                 g.l, L.RB, L.CB, L.KBo, L.KB, o.kb, (const int*)w.e.ea, (const int*)w.e.part,
+                 w.e.fb, k.res, w.Ares, w.Bres);
+  else
+    launch_timed("crt_residue_kernel", crt_residue_kernel<2>,
+                 dim3((unsigned)chunks, (unsigned)g.batch), dim3(256), 0, s, g.A, g.B, g.m, g.n,
+                 g.l, L.RB, L.CB, L.KBo, L.KB, o.kb, (const int*)w.e.ea, (const int*)w.e.part,
+                 w.e.fb, k.res, w.Ares, w.Bres);
   if ((rc = check_launch("crt_residue_kernel"))) return rc;
   // products and rebuild, K chunk by K chunk
   CrtProd p{};
   p.Ares = w.Ares;
   p.Bres = w.Bres;
-  p.Cres = w.Cres;
-  p.N = L.N;
+  p.N = p.NS = L.N;
   for (int q = 0; q < L.N; q++) {
     p.m[q] = k.res.m[q];
     p.inv[q] = k.res.inv[q];
@@ -607,24 +875,47 @@ int run_crt(const GemmBatch& g, char* ws, hipStream_t s, int tile) {
   const int64_t blocks = L.RB * L.CB * g.batch;
   if (nblk > INT32_MAX || blocks > INT32_MAX)
     return set_error(DDQD_E_UNSUPPORTED, "grid too large");
-  // K blocks per chunk: all of them when l fits one chunk (the padding
-  // blocks hold zeros), else kChunk / 32
-  const int64_t kcb = g.l <= kChunk ? L.KB : kChunk / 32;
-  for (int64_t kb0 = 0; kb0 < L.KB; kb0 += kcb) {
+  auto product = [&](signed char* out, int64_t kst, int64_t koa, int64_t kob, int64_t kb0,
+                     int64_t kb1) {
+    p.Cres = out;
+    p.kst = kst;
+    p.koa = koa;
+    p.kob = kob;
     p.kb0 = kb0;
-    p.kb1 = kb0 + kcb < L.KB ? kb0 + kcb : L.KB;
-    if (L.TB == 8)
-      launch_timed("crt_gemm_kernel", crt_gemm_kernel<8, 5, 2>, dim3((unsigned)nblk), dim3(256),
-                   0, s, p);
+    p.kb1 = kb1;
+    const dim3 grid((unsigned)nblk);
+    if (L.TB == 8 && kst == 2)
+      launch_timed("crt_gemm_kernel", crt_gemm_kernel<8, 5, 2, 2>, grid, dim3(256), 0, s, p);
+    else if (L.TB == 8)
+      launch_timed("crt_gemm_kernel", crt_gemm_kernel<8, 5, 2, 1>, grid, dim3(256), 0, s, p);
+    else if (kst == 2)
+      launch_timed("crt_gemm_kernel", crt_gemm_kernel<4, 4, 1, 2>, grid, dim3(256), 0, s, p);
     else
-      launch_timed("crt_gemm_kernel", crt_gemm_kernel<4, 4, 1>, dim3((unsigned)nblk), dim3(256),
-                   0, s, p);
-    if ((rc = check_launch("crt_gemm_kernel"))) return rc;
-    launch_timed("crt_rebuild_kernel", crt_rebuild_kernel, dim3((unsigned)blocks),
-                 dim3(256), 0, s, g.C, g.m, g.n, L.RB, L.CB, (const signed char*)w.Cres,
-                 (const int*)w.e.ea, (const int*)w.e.fb, g.alpha, kb0 == 0 ? g.beta : 1, k.reb,
-                 blocks);
-    if ((rc = check_launch("crt_rebuild_kernel"))) return rc;
+      launch_timed("crt_gemm_kernel", crt_gemm_kernel<4, 4, 1, 1>, grid, dim3(256), 0, s, p);
+    return check_launch("crt_gemm_kernel");
+  };
+  // K blocks per chunk: all of them when l fits one chunk (the padding
+  // blocks hold zeros), else the chunk's
+  const int64_t kcb = g.l <= chunk_k(P) ? L.KBo : chunk_k(P) / 32;
+  for (int64_t kb0 = 0; kb0 < L.KBo; kb0 += kcb) {
+    const int64_t kb1 = kb0 + kcb < L.KBo ? kb0 + kcb : L.KBo;
+    const int bt = kb0 == 0 ? g.beta : 1;
+    if (P == 4) {
+      // H_a H_b: A's even blocks by B's odd ones; the cross product: all
+      if ((rc = product(w.Cres, 2, 0, 1, kb0, kb1))) return rc;
+      if ((rc = product(w.Cx, 1, 0, 0, 2 * kb0, 2 * kb1))) return rc;
+      launch_timed("crt_rebuild_qd_kernel", crt_rebuild_qd_kernel, dim3((unsigned)blocks),
+                   dim3(256), 0, s, g.C, g.m, g.n, L.RB, L.CB, (const signed char*)w.Cres,
+                   (const signed char*)w.Cx, (const int*)w.e.ea, (const int*)w.e.fb, g.alpha, bt,
+                   k.rq, blocks);
+      if ((rc = check_launch("crt_rebuild_qd_kernel"))) return rc;
+    } else {
+      if ((rc = product(w.Cres, 1, 0, 0, kb0, kb1))) return rc;
+      launch_timed("crt_rebuild_kernel", crt_rebuild_kernel, dim3((unsigned)blocks), dim3(256),
+                   0, s, g.C, g.m, g.n, L.RB, L.CB, (const signed char*)w.Cres,
+                   (const int*)w.e.ea, (const int*)w.e.fb, g.alpha, bt, k.reb, blocks);
+      if ((rc = check_launch("crt_rebuild_kernel"))) return rc;
+    }
   }
   return DDQD_OK;
 }
@@ -633,31 +924,31 @@ int run_crt(const GemmBatch& g, char* ws, hipStream_t s, int tile) {
 
 // enough for either tile (the tuner tries both on one workspace)
 size_t crt_workspace(int P, int64_t m, int64_t n, int64_t l, int64_t batch) {
-  if (P != 2 || m <= 0 || n <= 0 || l <= 0 || batch <= 0) return 0;
-  const CrtLayout L4 = crt_layout(m, n, l, batch, 4), L8 = crt_layout(m, n, l, batch, 8);
+  if ((P != 2 && P != 4) || m <= 0 || n <= 0 || l <= 0 || batch <= 0) return 0;
+  const CrtLayout L4 = crt_layout(P, m, n, l, batch, 4), L8 = crt_layout(P, m, n, l, batch, 8);
   if (L4.N == 0) return 0;
   return std::max(crt_ws_bytes(L4), crt_ws_bytes(L8));
 }
 
 // tile: 0 (by shape), 128 or 256
 int launch_crt(int P, const GemmBatch& g, void* ws, size_t ws_bytes, hipStream_t s, int tile) {
-  if (P != 2) return set_error(DDQD_E_UNSUPPORTED, "the modular INT8 base is DD only");
+  if (P != 2 && P != 4) return set_error(DDQD_E_UNSUPPORTED, "the modular INT8 base is DD or QD");
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return DDQD_OK;
   if (g.l <= 0) return set_error(DDQD_E_ARG, "empty K reached the modular base");
   const size_t need = crt_workspace(P, g.m, g.n, g.l, g.batch);
   if (need == 0 || need > ws_bytes || !ws)
     return set_error(DDQD_E_WORKSPACE, "modular base: workspace of %zu bytes needed, %zu given",
                      need, ws_bytes);
-  return run_crt(g, (char*)ws, s, tile);
+  return run_crt(P, g, (char*)ws, s, tile);
 }
 
 }  // namespace ddqd
 
-extern "C" int ddqd_crt_moduli(int64_t l, int* out, int cap) {
+extern "C" int ddqd_crt_moduli(int precision, int64_t l, int* out, int cap) {
   using namespace ddqd;
-  if (l <= 0 || cap < 0 || (cap > 0 && !out)) return -1;
-  const int64_t kc = l < kChunk ? l : kChunk;
-  const int N = moduli_for(kc);
+  if ((precision != 2 && precision != 4) || l <= 0 || cap < 0 || (cap > 0 && !out)) return -1;
+  const int64_t kc = l < chunk_k(precision) ? l : chunk_k(precision);
+  const int N = moduli_for(precision, kc);
   for (int s = 0; s < N && s < cap; s++) out[s] = kModuli[s];
   return N;
 }

@@ -71,9 +71,10 @@ namespace {
 
 constexpr int64_t kMaxLuRows = 8192;
 
-// trailing-update bases: FMA and Ozaki in DD and QD, the CRT base in DD
+// trailing-update bases: FMA, Ozaki and CRT, in DD and QD
 bool lu_base_ok(int P, int base) {
-  return base == DDQD_BASE_FMA || base == DDQD_BASE_OZAKI_I8 || (base == DDQD_BASE_CRT_I8 && P == 2);
+  return (P == 2 || P == 4) &&
+         (base == DDQD_BASE_FMA || base == DDQD_BASE_OZAKI_I8 || base == DDQD_BASE_CRT_I8);
 }
 
 struct Lu {

@@ -207,8 +207,7 @@ int ddqd_tune_lookup(int precision, int64_t m, int64_t n, int64_t l, int base, i
   clear_error();
   if (!out) return set_error(DDQD_E_ARG, "out is NULL");
   if ((precision != 2 && precision != 4) || m < 0 || n < 0 || l < 0 ||
-      (base != DDQD_BASE_FMA && base != DDQD_BASE_OZAKI_I8 &&
-       !(base == DDQD_BASE_CRT_I8 && precision == 2)) ||
+      (base != DDQD_BASE_FMA && base != DDQD_BASE_OZAKI_I8 && base != DDQD_BASE_CRT_I8) ||
       slices < 0 || slices > 40)
     return set_error(DDQD_E_ARG, "invalid tune lookup arguments");
   Choice c = default_choice(precision, m, n, l, base);

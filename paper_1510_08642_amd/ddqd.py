@@ -104,7 +104,7 @@ _lib.ddqd_getrf_tune_workspace.restype = _sz
 _lib.ddqd_getrf_panel_lookup.argtypes = [_int, _i64, _int, _int, _int, _int, ctypes.POINTER(_int),
                                          ctypes.POINTER(_int), ctypes.POINTER(ctypes.c_double)]
 _lib.ddqd_getrf_panel_lookup.restype = _int
-_lib.ddqd_crt_moduli.argtypes = [_i64, ctypes.POINTER(_int), _int]
+_lib.ddqd_crt_moduli.argtypes = [_int, _i64, ctypes.POINTER(_int), _int]
 _lib.ddqd_crt_moduli.restype = _int
 _lib.ddqd_latency_probe.argtypes = [_vp, _int, _int, _vp]
 _lib.ddqd_latency_probe.restype = _int
@@ -205,16 +205,19 @@ def dd_gemm(A, B, C=None, *, alpha=1, beta=0, algo="block", levels=0, base="fma"
 def qd_gemm(A, B, C=None, *, alpha=1, beta=0, algo="block", levels=0, base="fma", slices=0,
             ws=None):
     """C := beta*C + alpha*(A B) in quad-double; returns C.  base="ozaki" runs
-    the leaves on INT8 matrix cores with `slices` digits (0 = 31)."""
+    the leaves on INT8 matrix cores with `slices` digits (0 = 31); base="crt"
+    by residues of 214-bit integers (split in halves) and the Chinese
+    remainder theorem."""
     return _gemm(4, A, B, C, alpha, beta, algo, levels, base, slices, ws)
 
 
-def crt_moduli(l: int) -> list:
-    """The moduli base="crt" uses for a product with K = l (host only)."""
+def crt_moduli(l: int, precision: int = 2) -> list:
+    """The moduli base="crt" uses for a product with K = l in DD (precision
+    2) or QD (4) (host only)."""
     out = (_int * 32)()
-    N = _lib.ddqd_crt_moduli(l, out, 32)
+    N = _lib.ddqd_crt_moduli(precision, l, out, 32)
     if N < 0:
-        raise ValueError("l must be positive")
+        raise ValueError("l must be positive and precision 2 or 4")
     return list(out[:N])
 
 

@@ -185,7 +185,8 @@ def test_tune_defaults_and_errors(lib):
     import ctypes as C
     r = ddqd.TuneResult()
     assert lib.ddqd_tune_lookup(3, 8, 8, 8, 0, 0, C.byref(r)) == E["ARG"]
-    assert lib.ddqd_tune_lookup(4, 8, 8, 8, 2, 0, C.byref(r)) == E["ARG"]
+    assert lib.ddqd_tune_lookup(4, 8, 8, 8, 3, 0, C.byref(r)) == E["ARG"]
+    assert ddqd.tune_lookup(4, 1024, 1024, 1024, base="crt")["algo"] == "block"
     assert ddqd.tune_lookup(4, 1024, 1024, 1024, base="ozaki")["algo"] == "block"
     assert lib.ddqd_tune_lookup(2, 8, 8, 8, 0, 0, None) == E["ARG"]
     # reps out of range is rejected before any device work
@@ -274,10 +275,12 @@ def test_qd_lu_argument_errors(lib):
     call = lambda base, n=8, lda=8: lib.qd_getrf(n, A, lda, lda * n, ip, None, info, 4, 1, 1, 0,
                                                  base, None, 0, None)
     assert call(0, lda=4) == E["ARG"]
-    assert call(2) == E["ARG"]
-    assert lib.qd_getrf_workspace(64, 16, 3, 1, 2) == C.c_size_t(-1).value
-    # QD trailing updates may run on Ozaki leaves (31 slices by default)
+    assert call(3) == E["ARG"]
+    assert lib.qd_getrf_workspace(64, 16, 3, 1, 3) == C.c_size_t(-1).value
+    # QD trailing updates may run on Ozaki leaves (31 slices by default) or
+    # on the CRT base
     assert lib.qd_getrf_workspace(1024, 128, 3, 1, 1) > lib.qd_getrf_workspace(1024, 128, 3, 1, 0)
+    assert lib.qd_getrf_workspace(1024, 128, 3, 1, 2) > lib.qd_getrf_workspace(1024, 128, 3, 1, 0)
     assert lib.qd_getrs_workspace(100, 3) >= 4 * 8 * 100 * 3
     assert lib.qd_getrs_workspace(100, 3) > lib.dd_getrs_workspace(100, 3)
 
@@ -342,12 +345,37 @@ def test_crt_moduli_cover_the_product_range(lib):
         assert M > 2 * kc * 2 ** 214
         # the set is minimal for this rule: one modulus fewer does not cover it
         assert math.log2(math.prod(ms[:-1])) < math.log2(2 * kc * 2 ** 214) + 0.01
-    assert lib.ddqd_crt_moduli(0, None, 0) == -1
+    assert lib.ddqd_crt_moduli(2, 0, None, 0) == -1
+    assert lib.ddqd_crt_moduli(3, 64, None, 0) == -1
+    assert lib.ddqd_crt_moduli(2, 64, None, -1) == -1
+
+
+def test_crt_qd_moduli_cover_the_cross_term(lib):
+    """QD: the 214-bit integers split as T = H 2^108 + L with |H| <= 2^106 and
+    |L| <= 2^107 (1 + 2^-35); the larger of the two exact products is the
+    cross term, |sum_k H_a L_b + L_a H_b| <= kc 2^214 (1 + 2^-35) (kc =
+    min(l, 32768), the cross product running over 2 kc), so M must exceed
+    twice that; both products share the set."""
+    import math
+    from paper_1510_08642_amd import ddqd
+    for l, want in [(1, 29), (33, 29), (34, 30), (1024, 30), (2048, 30), (3835, 30),
+                    (3836, 31), (32768, 31), (1 << 20, 31)]:
+        ms = ddqd.crt_moduli(l, precision=4)
+        assert len(ms) == want, (l, ms)
+        assert all(math.gcd(a, b) == 1 for i, a in enumerate(ms) for b in ms[i + 1:])
+        kc = min(l, 32768)
+        M = math.prod(ms)
+        # 2 kc 2^214 (1 + 2^-35) < M, in exact integers
+        assert 2 * kc * (2 ** 249 + 2 ** 214) < M * 2 ** 35
+        assert math.log2(math.prod(ms[:-1])) < 215 + math.log2(kc) + 0.01
+    assert ddqd.crt_moduli(1024, precision=2) == ddqd.crt_moduli(1024)
 
 
 def test_crt_base_arguments(lib):
-    # QD has no CRT base; the CRT base takes no slice count
-    assert _call(lib, fn="qd_gemm", base=2) == E["UNSUPPORTED"]
+    # the CRT base takes no slice count; QD runs it (the workspace is checked
+    # before any device work)
+    assert _call(lib, fn="qd_gemm", base=2) == E["WORKSPACE"]
+    assert _call(lib, fn="qd_gemm", base=2, slices=30) == E["ARG"]
     assert _call(lib, base=2, slices=16) == E["ARG"]
     assert _call(lib, base=3) == E["ARG"]
     lib.dd_gemm_workspace.restype = ctypes.c_size_t
@@ -356,5 +384,8 @@ def test_crt_base_arguments(lib):
     # n = 1024: 30 moduli of 1 KB fragments for A, B and C, plus exponents
     w = lib.dd_gemm_workspace(1024, 1024, 1024, 1, 0, 2, 0)
     assert 3 * 30 * 1024 * 1024 <= w < 3 * 30 * 1024 * 1024 + (1 << 20)
-    assert lib.qd_gemm_workspace(64, 64, 64, 1, 0, 2, 0) == SIZE_MAX
+    # QD, n = 1024: 30 moduli; H and L residues of A and B (2 KB a line's
+    # 32-block) and two products' residues of C
+    w = lib.qd_gemm_workspace(1024, 1024, 1024, 1, 0, 2, 0)
+    assert 6 * 30 * 1024 * 1024 <= w < 6 * 30 * 1024 * 1024 + (1 << 20)
     assert lib.dd_gemm_workspace(64, 64, 64, 1, 0, 2, 8) == SIZE_MAX

@@ -32,7 +32,7 @@ def _err_ok(A, B, C, P, l):
 
 @pytest.mark.parametrize("P,m,n,l,base", [(2, 70, 75, 66, "fma"), (2, 256, 256, 256, "fma"),
                                           (2, 300, 200, 310, "ozaki"), (2, 300, 200, 310, "crt"),
-                                          (4, 130, 130, 130, "fma")])
+                                          (4, 130, 130, 130, "fma"), (4, 300, 200, 310, "crt")])
 def test_tuned_choice_is_cached_and_exact_to_the_explicit_call(dd, P, m, n, l, base):
     import torch
     print(f"case tune P={P} {m}x{n}x{l} {base}", flush=True)
@@ -44,7 +44,7 @@ def test_tuned_choice_is_cached_and_exact_to_the_explicit_call(dd, P, m, n, l, b
     assert r["candidates"] >= 2 and r["ms"] > 0
     assert dd.tune_lookup(P, m, n, l, base=base) == r
     gem = dd.dd_gemm if P == 2 else dd.qd_gemm
-    kw = dict(base=base) if P == 2 else {}
+    kw = dict(base=base)
     Ca = to_host(gem(Ad, Bd, algo="auto", **kw))
     Ce = to_host(gem(Ad, Bd, algo=r["algo"], levels=r["levels"], **kw))
     torch.cuda.synchronize()
