@@ -86,10 +86,12 @@ struct CrtResidue {
 
 // Rebuild constants (kernel argument): Z_s in 16-bit limbs (least significant
 // first) and M 2^-160 as a DD.
-constexpr int kLimbs = 10;  // 160-bit fixed point
+constexpr int kDigits = 27;  // 6-bit digits of the 160-bit fixed point (162 bits)
 struct CrtRebuild {
   int N;
-  int z[kCrtMaxN][kLimbs];
+  // the rebuild's MFMA operand: lane L holds digit L % 32 of Z_s for
+  // s = 16 (L / 32) + 0..15 (one byte each; zero past N and past kDigits)
+  uint32_t zd[64][4];
   double mhi, mlo;
 };
 
@@ -169,8 +171,15 @@ Consts make_consts(int N) {
       quo[w] = (uint32_t)(cur / (uint64_t)m);
       rem = cur % (uint64_t)m;
     }
-    for (int j = 0; j < kLimbs; j++)
-      c.reb.z[s][j] = (int)((quo[j / 2] >> (16 * (j % 2))) & 0xFFFF);
+    for (int d = 0; d < kDigits; d++) {
+      uint32_t v = 0;
+      for (int b = 0; b < 6; b++) {
+        const int i = 6 * d + b;
+        if (i < 160) v |= ((quo[i / 32] >> (i % 32)) & 1u) << b;
+      }
+      const int L = d + 32 * (s / 16), j = s % 16;
+      c.reb.zd[L][j / 4] |= v << (8 * (j % 4));
+    }
     // Z_s = floor(y 2^270 / m) likewise (QD; y 2^270 = (y 2^14) 2^256)
     uint32_t numq[9] = {0, 0, 0, 0, 0, 0, 0, 0, (uint32_t)y << 14}, quoq[9];
     rem = 0;
@@ -611,11 +620,72 @@ __global__ __launch_bounds__(256) void crt_gemm_kernel(CrtProd a) {
 }
 
 // ---- rebuild ----------------------------------------------------------------
-// Workgroup = one 32 x 32 block of C; wave h takes quarter h of the block's
-// MFMA output order: lane l's outputs q = 4 h .. 4 h + 3, column l % 32, rows
-// 8 h + 4 (l / 32) + 0..3.  Every modulus' 4 residue bytes are loaded first
-// (32-bit loads, a wave's covering 256 contiguous bytes), then the sum of
-// c_s Z_s accumulates in 10 limbs of 16 bits per output (|limb| < 2^28).
+// 4 x 4 byte transpose: y[q] byte j = x[j] byte q.
+__device__ __forceinline__ void transpose4(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                           uint32_t (&y)[4]) {
+  const uint32_t a = __builtin_amdgcn_perm(x1, x0, 0x05010400u);  // x0.0 x1.0 x0.1 x1.1
+  const uint32_t b = __builtin_amdgcn_perm(x1, x0, 0x07030602u);  // x0.2 x1.2 x0.3 x1.3
+  const uint32_t c = __builtin_amdgcn_perm(x3, x2, 0x05010400u);
+  const uint32_t d = __builtin_amdgcn_perm(x3, x2, 0x07030602u);
+  y[0] = __builtin_amdgcn_perm(c, a, 0x05040100u);
+  y[1] = __builtin_amdgcn_perm(c, a, 0x07060302u);
+  y[2] = __builtin_amdgcn_perm(d, b, 0x05040100u);
+  y[3] = __builtin_amdgcn_perm(d, b, 0x07060302u);
+}
+
+// A wave's residues of one product as MFMA B operands.  Wave h of a block
+// loads, per modulus, lane L's four outputs (rows 8 h + 4 (L / 32) + 0..3,
+// column L % 32; 32-bit loads, a wave's covering 256 contiguous bytes); the
+// lane halves then trade moduli (lanes 0-31 keep moduli 0-15, lanes 32-63
+// 16-31), so that after a byte transpose op[t] holds, for the output in row
+// 8 h + t and column L % 32, its residues of the lane half's 16 moduli: the
+// layout of the B operand (column L % 32, k = 16 (L / 32) + 0..15) of
+// v_mfma_i32_32x32x32_i8 with the block's outputs of one row as columns.
+__device__ __forceinline__ void crt_residue_operands(const signed char* src, int64_t stride,
+                                                     int N, v4i (&op)[8]) {
+  uint32_t w[kCrtMaxN];
+#pragma unroll
+  for (int s = 0; s < kCrtMaxN; s++) w[s] = s < N ? *(const uint32_t*)(src + s * stride) : 0u;
+#pragma unroll
+  for (int i = 0; i < 16; i++) {
+    const auto r = __builtin_amdgcn_permlane32_swap(w[i], w[16 + i], false, false);
+    w[i] = r[0];
+    w[16 + i] = r[1];
+  }
+#pragma unroll
+  for (int u = 0; u < 2; u++)
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+      uint32_t y[4];
+      transpose4(w[16 * u + 4 * g], w[16 * u + 4 * g + 1], w[16 * u + 4 * g + 2],
+                 w[16 * u + 4 * g + 3], y);
+#pragma unroll
+      for (int q = 0; q < 4; q++) op[4 * u + q][g] = (int)y[q];
+    }
+}
+
+// Two MFMA results (outputs of rows t and t + 1 as columns, digits as rows:
+// lane L, register r holds digit 8 (r / 4) + 4 (L / 32) + r % 4 of column
+// L % 32) traded between the lane halves so that lane L holds every digit of
+// one output (lanes 0-31: row t, lanes 32-63: row t + 1): digit d is then
+// da[4 (d / 8) + d % 4] for (d / 4) even, db[...] for (d / 4) odd.
+__device__ __forceinline__ void crt_gather_digits(v16i& da, v16i& db) {
+#pragma unroll
+  for (int r = 0; r < 16; r++) {
+    const auto x = __builtin_amdgcn_permlane32_swap(da[r], db[r], false, false);
+    da[r] = (int)x[0];
+    db[r] = (int)x[1];
+  }
+}
+__device__ __forceinline__ int crt_digit(const v16i& da, const v16i& db, int d) {
+  return ((d / 4) % 2 == 0 ? da : db)[4 * (d / 8) + d % 4];
+}
+
+// Workgroup = one 32 x 32 block of C; wave h takes its rows 8 h .. 8 h + 7.
+// The sums G_d = sum_s c_s Zd_s,d (Zd: Z's 6-bit digits, |G_d| < 2^18) run
+// on the matrix cores, one MFMA per 32 outputs; lane L then carries the
+// digits of its outputs (rows 8 h + 2 p + L / 32, column L % 32, p = 0..3)
+// into the 160-bit fraction F (mod 2^160, signed), and X = F M 2^-160 in DD.
 __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int64_t n,
                                                           int64_t RB, int64_t CB,
                                                           const signed char* Cres,
@@ -627,51 +697,37 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int6
   if (blk >= blocks) return;
   const int64_t per = RB * CB;
   const int64_t b = blk / per, rb = (blk % per) / CB, cbk = blk % CB;
-  const int N = cb_.N;
-  const signed char* src =
-      Cres + ((b * N) * per + rb * CB + cbk) * kOzFrag + 256 * h + 4 * lane;
-  uint32_t v[kCrtMaxN];
+  v4i op[8];
+  crt_residue_operands(Cres + ((b * cb_.N) * per + rb * CB + cbk) * kOzFrag + 256 * h + 4 * lane,
+                       per * kOzFrag, cb_.N, op);
+  v4i za;
 #pragma unroll
-  for (int s = 0; s < kCrtMaxN; s++)
-    v[s] = s < N ? *(const uint32_t*)(src + (int64_t)s * per * kOzFrag) : 0u;
-  // 32-bit sums, wrapping (the true sums fit 29 bits): 24-bit multiply-adds
-  uint32_t acc[4][kLimbs];
-#pragma unroll
-  for (int q = 0; q < 4; q++)
-#pragma unroll
-    for (int j = 0; j < kLimbs; j++) acc[q][j] = 0u;
-#pragma unroll
-  for (int s = 0; s < kCrtMaxN; s++) {
-    if (s < N) {
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const int c = (int)(signed char)(v[s] >> (8 * q));
-#pragma unroll
-        for (int j = 0; j < kLimbs; j++) acc[q][j] += (uint32_t)__mul24(c, cb_.z[s][j]);
-      }
-    }
-  }
+  for (int g = 0; g < 4; g++) za[g] = (int)cb_.zd[lane][g];
   const int64_t col = cbk * 32 + lane % 32;
-  if (col >= n) return;
-  const int fexp = fb[b * CB * 32 + col];
+  const bool live = col < n;
+  const int fexp = live ? fb[b * CB * 32 + col] : 0;
   double* Cb = C.p + b * C.bstride;
+  const v16i zero = {};
 #pragma unroll
-  for (int q = 0; q < 4; q++) {
-    const int64_t row = rb * 32 + 8 * h + 4 * (lane / 32) + q;
-    if (row >= m) continue;
-    // carries: limbs of 16 bits, the top one taken modulo 2^16 (the sum mod 2^160)
-    int64_t carry = 0;
-    uint32_t limb[kLimbs];
+  for (int p = 0; p < 4; p++) {
+    v16i da = __builtin_amdgcn_mfma_i32_32x32x32_i8(za, op[2 * p], zero, 0, 0, 0);
+    v16i db = __builtin_amdgcn_mfma_i32_32x32x32_i8(za, op[2 * p + 1], zero, 0, 0, 0);
+    crt_gather_digits(da, db);
+    const int64_t row = rb * 32 + 8 * h + 2 * p + lane / 32;
+    if (!live || row >= m) continue;
+    // carries: 6-bit digits, bits from 160 up dropped (the sum mod 2^160)
+    uint32_t wd[5] = {0u, 0u, 0u, 0u, 0u};
+    int carry = 0;
 #pragma unroll
-    for (int j = 0; j < kLimbs; j++) {
-      const int64_t x = (int64_t)(int32_t)acc[q][j] + carry;
-      limb[j] = (uint32_t)(x & 0xFFFF);
-      carry = x >> 16;  // arithmetic
+    for (int d = 0; d < kDigits; d++) {
+      const int x = crt_digit(da, db, d) + carry;
+      const uint32_t dig = (uint32_t)x & 63u;
+      carry = x >> 6;  // arithmetic
+      const int bit = 6 * d, w = bit / 32, o = bit % 32;
+      wd[w] |= dig << o;
+      if (o > 26 && w + 1 < 5) wd[w + 1] |= dig >> (32 - o);
     }
     // the signed fraction F (units of 2^-160) from five 32-bit words, as a DD
-    uint32_t wd[5];
-#pragma unroll
-    for (int j = 0; j < 5; j++) wd[j] = limb[2 * j] | (limb[2 * j + 1] << 16);
     double hi = ldexp((double)(int32_t)wd[4], 128), lo = 0.0;
 #pragma unroll
     for (int j = 3; j >= 0; j--) {
