@@ -95,13 +95,15 @@ struct CrtRebuild {
   double mhi, mlo;
 };
 
-// QD rebuild constants: Z_s = floor(y_s 2^270 / m_s) in 18-bit limbs (the
-// top nine are floor(y_s 2^162 / m_s), the cross term's) and M 2^-256 as a QD.
-constexpr int kLimbsQ = 15;  // 270-bit fixed point
-constexpr int kLimbsX = 9;   // 162-bit (the cross term, 108 bits = 6 limbs lower)
+// QD rebuild constants: Z_s = floor(y_s 2^270 / m_s) in 6-bit digits (45;
+// digits 18..44 are floor(y_s 2^162 / m_s), the cross term's) as MFMA A
+// operands laid out like CrtRebuild's: digits 0..31 (zh0), 32..44 (zh1),
+// 18..44 (zx, as digits 0..26), and M 2^-256 as a QD.
+constexpr int kDigitsQ = 45;  // 270-bit fixed point
+constexpr int kDigitsX = 27;  // 162-bit (the cross term, 108 bits = 18 digits lower)
 struct CrtRebuildQ {
   int N;
-  uint32_t z[kCrtMaxN][kLimbsQ];
+  uint32_t zh0[64][4], zh1[64][4], zx[64][4];
   double mq[4];
 };
 
@@ -188,13 +190,17 @@ Consts make_consts(int N) {
       quoq[w] = (uint32_t)(cur / (uint64_t)m);
       rem = cur % (uint64_t)m;
     }
-    for (int j = 0; j < kLimbsQ; j++) {
+    for (int d = 0; d < kDigitsQ; d++) {
       uint32_t v = 0;
-      for (int b = 0; b < 18; b++) {
-        const int i = 18 * j + b;
+      for (int b = 0; b < 6; b++) {
+        const int i = 6 * d + b;
         v |= ((quoq[i / 32] >> (i % 32)) & 1u) << b;
       }
-      c.rq.z[s][j] = v;
+      const int j = s % 16, sh = 8 * (j % 4);
+      const int L0 = 32 * (s / 16);
+      if (d < 32) c.rq.zh0[L0 + d][j / 4] |= v << sh;
+      else c.rq.zh1[L0 + d - 32][j / 4] |= v << sh;
+      if (d >= kDigitsQ - kDigitsX) c.rq.zx[L0 + d - (kDigitsQ - kDigitsX)][j / 4] |= v << sh;
     }
     // M *= m
     uint64_t carry = 0;
@@ -633,35 +639,30 @@ __device__ __forceinline__ void transpose4(uint32_t x0, uint32_t x1, uint32_t x2
   y[3] = __builtin_amdgcn_perm(d, b, 0x07060302u);
 }
 
-// A wave's residues of one product as MFMA B operands.  Wave h of a block
-// loads, per modulus, lane L's four outputs (rows 8 h + 4 (L / 32) + 0..3,
-// column L % 32; 32-bit loads, a wave's covering 256 contiguous bytes); the
-// lane halves then trade moduli (lanes 0-31 keep moduli 0-15, lanes 32-63
-// 16-31), so that after a byte transpose op[t] holds, for the output in row
-// 8 h + t and column L % 32, its residues of the lane half's 16 moduli: the
-// layout of the B operand (column L % 32, k = 16 (L / 32) + 0..15) of
-// v_mfma_i32_32x32x32_i8 with the block's outputs of one row as columns.
+// A wave's residues of one product as MFMA B operands, half u of its rows:
+// op[q] holds, for the output in row 8 h + 4 u + q and column L % 32 of the
+// block, its residues of moduli 16 (L / 32) + 0..15 (lane L; zero past N),
+// the layout of the B operand (column L % 32, k = 16 (L / 32) + 0..15) of
+// v_mfma_i32_32x32x32_i8 with the outputs of one row as columns.  Modulus
+// s's residues of the quarter sit at src + s stride: lane l's four outputs
+// (rows 8 h + 4 (l / 32) + 0..3, column l % 32) at bytes 4 l; lane L reads
+// those of lane L % 32 + 32 u (32-bit loads, each lane half's covering 128
+// contiguous bytes), then a 4 x 4 byte transpose per four moduli.
 __device__ __forceinline__ void crt_residue_operands(const signed char* src, int64_t stride,
-                                                     int N, v4i (&op)[8]) {
-  uint32_t w[kCrtMaxN];
+                                                     int N, int u, v4i (&op)[4]) {
+  const int lane = threadIdx.x % 64, s0 = 16 * (lane / 32);
+  const signed char* p = src + 4 * (lane % 32 + 32 * u);
+  uint32_t w[16];
 #pragma unroll
-  for (int s = 0; s < kCrtMaxN; s++) w[s] = s < N ? *(const uint32_t*)(src + s * stride) : 0u;
+  for (int j = 0; j < 16; j++)
+    w[j] = s0 + j < N ? *(const uint32_t*)(p + (int64_t)(s0 + j) * stride) : 0u;
 #pragma unroll
-  for (int i = 0; i < 16; i++) {
-    const auto r = __builtin_amdgcn_permlane32_swap(w[i], w[16 + i], false, false);
-    w[i] = r[0];
-    w[16 + i] = r[1];
+  for (int g = 0; g < 4; g++) {
+    uint32_t y[4];
+    transpose4(w[4 * g], w[4 * g + 1], w[4 * g + 2], w[4 * g + 3], y);
+#pragma unroll
+    for (int q = 0; q < 4; q++) op[q][g] = (int)y[q];
   }
-#pragma unroll
-  for (int u = 0; u < 2; u++)
-#pragma unroll
-    for (int g = 0; g < 4; g++) {
-      uint32_t y[4];
-      transpose4(w[16 * u + 4 * g], w[16 * u + 4 * g + 1], w[16 * u + 4 * g + 2],
-                 w[16 * u + 4 * g + 3], y);
-#pragma unroll
-      for (int q = 0; q < 4; q++) op[4 * u + q][g] = (int)y[q];
-    }
 }
 
 // Two MFMA results (outputs of rows t and t + 1 as columns, digits as rows:
@@ -697,9 +698,7 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int6
   if (blk >= blocks) return;
   const int64_t per = RB * CB;
   const int64_t b = blk / per, rb = (blk % per) / CB, cbk = blk % CB;
-  v4i op[8];
-  crt_residue_operands(Cres + ((b * cb_.N) * per + rb * CB + cbk) * kOzFrag + 256 * h + 4 * lane,
-                       per * kOzFrag, cb_.N, op);
+  const signed char* src = Cres + ((b * cb_.N) * per + rb * CB + cbk) * kOzFrag + 256 * h;
   v4i za;
 #pragma unroll
   for (int g = 0; g < 4; g++) za[g] = (int)cb_.zd[lane][g];
@@ -708,10 +707,12 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int6
   const int fexp = live ? fb[b * CB * 32 + col] : 0;
   double* Cb = C.p + b * C.bstride;
   const v16i zero = {};
+  v4i op[4];
 #pragma unroll
   for (int p = 0; p < 4; p++) {
-    v16i da = __builtin_amdgcn_mfma_i32_32x32x32_i8(za, op[2 * p], zero, 0, 0, 0);
-    v16i db = __builtin_amdgcn_mfma_i32_32x32x32_i8(za, op[2 * p + 1], zero, 0, 0, 0);
+    if (p % 2 == 0) crt_residue_operands(src, per * kOzFrag, cb_.N, p / 2, op);
+    v16i da = __builtin_amdgcn_mfma_i32_32x32x32_i8(za, op[2 * (p % 2)], zero, 0, 0, 0);
+    v16i db = __builtin_amdgcn_mfma_i32_32x32x32_i8(za, op[2 * (p % 2) + 1], zero, 0, 0, 0);
     crt_gather_digits(da, db);
     const int64_t row = rb * 32 + 8 * h + 2 * p + lane / 32;
     if (!live || row >= m) continue;
@@ -748,134 +749,134 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int6
   }
 }
 
-// QD rebuild.  The fraction (H_a H_b's sum of c_s Z_s mod 2^270 plus the
-// cross term's signed fraction 2^-108, in 15 limbs of 18 bits) as a QD value
-// in [-1/2, 1/2): the magnitude's limbs (the sums negated when the sign bit is
-// set), in 36-bit pieces (exact doubles, non-negative and non-overlapping),
-// summed error-free into four terms by bottom-up TwoSum passes as in qd_add.
-__device__ __forceinline__ qd_t crt_fraction_qd(const uint32_t (&acc)[kLimbsQ]) {
-  uint32_t limb[kLimbsQ];
-  int64_t carry = 0;
-#pragma unroll
-  for (int j = 0; j < kLimbsQ; j++) {
-    const int64_t x = (int64_t)(int32_t)acc[j] + carry;
-    limb[j] = (uint32_t)(x & 0x3FFFF);
-    carry = x >> 18;  // arithmetic
-  }
-  const bool neg = (limb[kLimbsQ - 1] & 0x20000u) != 0;
-  if (neg) {
-    carry = 0;
-#pragma unroll
-    for (int j = 0; j < kLimbsQ; j++) {
-      const int64_t x = -(int64_t)(int32_t)acc[j] + carry;
-      limb[j] = (uint32_t)(x & 0x3FFFF);
-      carry = x >> 18;
-    }
-  }
-  constexpr int NP = (kLimbsQ + 1) / 2;  // pieces, most significant first in v
-  double v[NP];
-#pragma unroll
-  for (int p = 0; p < NP; p++) {
-    const uint64_t w = 2 * p + 1 < kLimbsQ
-                           ? (uint64_t)limb[2 * p] | ((uint64_t)limb[2 * p + 1] << 18)
-                           : (uint64_t)limb[2 * p];
-    v[NP - 1 - p] = ldexp((double)w, 36 * p - 18 * kLimbsQ);
-  }
-#pragma unroll
-  for (int k = 0; k < 4; k++)
-#pragma unroll
-    for (int i = NP - 1; i > k; i--) two_sum(v[i - 1], v[i], v[i - 1], v[i]);
-  double tail = 0.0;
-#pragma unroll
-  for (int i = NP - 1; i >= 4; i--) tail += v[i];
-  qd_t z{{v[0], v[1], v[2], v[3] + tail}};
-  qd_renorm(z.c[0], z.c[1], z.c[2], z.c[3]);
-  return neg ? qd_neg(z) : z;
-}
-
-// Workgroup = one 32 x 32 block of C, threads as in crt_rebuild_kernel (4
-// outputs each).  The cross product's residues first: F_x = sum c_s Z'_s mod
-// 2^162 (Z' = Z's top nine limbs), carried, its sign extended over the frame
-// (F_x 2^-108 sits exactly on the low nine limbs of the 270-bit frame); then
-// H_a H_b's c_s Z_s accumulate on top, and C = M 2^-256 F 2^(e + f + 42).
-// (four waves a SIMD: the grid's 4 waves per SIMD at n = 1024 in one round)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void
-crt_rebuild_qd_kernel(Mat C, int64_t m, int64_t n, int64_t RB, int64_t CB, const signed char* Chh,
-                      const signed char* Cx, const int* ea, const int* fb, int alpha, int beta,
-                      CrtRebuildQ k, int64_t blocks) {
+// QD rebuild.  Workgroup and waves as in crt_rebuild_kernel; per pair of
+// rows three MFMA sums each: the cross product's digits against zx, and
+// H_a H_b's against zh0 and zh1.  Lane L's outputs: F_x (mod 2^162) carried
+// and made signed (its sign extended over the frame: F_x 2^-108 sits on the
+// low 27 digits of the 270-bit frame), H_a H_b's digit sums added, the
+// frame carried mod 2^270; the magnitude (the sums negated and carried again
+// when the sign bit is set) in 36-bit pieces (exact doubles, non-negative
+// and non-overlapping), summed error-free into four terms by bottom-up
+// TwoSum passes as in qd_add; C = M 2^-256 F 2^(e + f + 42).
+__global__ __launch_bounds__(256) void crt_rebuild_qd_kernel(Mat C, int64_t m, int64_t n,
+                                                             int64_t RB, int64_t CB,
+                                                             const signed char* Chh,
+                                                             const signed char* Cx,
+                                                             const int* ea, const int* fb,
+                                                             int alpha, int beta,
+                                                             CrtRebuildQ k, int64_t blocks) {
   const int h = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int64_t blk = blockIdx.x;
   if (blk >= blocks) return;
   const int64_t per = RB * CB;
   const int64_t b = blk / per, rb = (blk % per) / CB, cbk = blk % CB;
-  const int N = k.N;
-  const int64_t off0 = ((b * N) * per + rb * CB + cbk) * kOzFrag + 256 * h + 4 * lane;
-  constexpr int J0 = kLimbsQ - kLimbsX;
-  uint32_t acc[4][kLimbsQ];
-  {
-    uint32_t v[kCrtMaxN];
+  const int64_t off0 = ((b * k.N) * per + rb * CB + cbk) * kOzFrag + 256 * h;
+  v4i zx, zh0, zh1;
 #pragma unroll
-    for (int s = 0; s < kCrtMaxN; s++)
-      v[s] = s < N ? *(const uint32_t*)(Cx + off0 + (int64_t)s * per * kOzFrag) : 0u;
-    uint32_t ax[4][kLimbsX];
-#pragma unroll
-    for (int q = 0; q < 4; q++)
-#pragma unroll
-      for (int j = 0; j < kLimbsX; j++) ax[q][j] = 0u;
-#pragma unroll
-    for (int s = 0; s < kCrtMaxN; s++) {
-      if (s < N) {
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-          const int c = (int)(signed char)(v[s] >> (8 * q));
-#pragma unroll
-          for (int j = 0; j < kLimbsX; j++)
-            ax[q][j] += (uint32_t)__mul24(c, (int)k.z[s][J0 + j]);
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      int64_t carry = 0;
-#pragma unroll
-      for (int j = 0; j < kLimbsX; j++) {
-        const int64_t x = (int64_t)(int32_t)ax[q][j] + carry;
-        acc[q][j] = (uint32_t)(x & 0x3FFFF);
-        carry = x >> 18;
-      }
-      // F_x negative: F_x - 2^162, i.e. all-ones limbs above
-      const uint32_t ext = (acc[q][kLimbsX - 1] & 0x20000u) ? 0x3FFFFu : 0u;
-#pragma unroll
-      for (int j = kLimbsX; j < kLimbsQ; j++) acc[q][j] = ext;
-    }
-  }
-  {
-    uint32_t v[kCrtMaxN];
-#pragma unroll
-    for (int s = 0; s < kCrtMaxN; s++)
-      v[s] = s < N ? *(const uint32_t*)(Chh + off0 + (int64_t)s * per * kOzFrag) : 0u;
-#pragma unroll
-    for (int s = 0; s < kCrtMaxN; s++) {
-      if (s < N) {
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-          const int c = (int)(signed char)(v[s] >> (8 * q));
-#pragma unroll
-          for (int j = 0; j < kLimbsQ; j++) acc[q][j] += (uint32_t)__mul24(c, (int)k.z[s][j]);
-        }
-      }
-    }
+  for (int g = 0; g < 4; g++) {
+    zx[g] = (int)k.zx[lane][g];
+    zh0[g] = (int)k.zh0[lane][g];
+    zh1[g] = (int)k.zh1[lane][g];
   }
   const int64_t col = cbk * 32 + lane % 32;
-  if (col >= n) return;
-  const int fexp = fb[b * CB * 32 + col];
+  const bool live = col < n;
+  const int fexp = live ? fb[b * CB * 32 + col] : 0;
   double* Cb = C.p + b * C.bstride;
   const qd_t mq{{k.mq[0], k.mq[1], k.mq[2], k.mq[3]}};
+  const v16i zero = {};
+  // rows 4 u .. 4 u + 3 of the quarter, two at a time (p = 2 u + pp)
+#pragma unroll 1
+  for (int u = 0; u < 2; u++) {
+  v4i ox[4], oh[4];
+  crt_residue_operands(Cx + off0, per * kOzFrag, k.N, u, ox);
+  crt_residue_operands(Chh + off0, per * kOzFrag, k.N, u, oh);
 #pragma unroll
-  for (int q = 0; q < 4; q++) {
-    const int64_t row = rb * 32 + 8 * h + 4 * (lane / 32) + q;
-    if (row >= m) continue;
-    qd_t x = qd_mul(crt_fraction_qd(acc[q]), mq);
+  for (int pp = 0; pp < 2; pp++) {
+    const int p = 2 * u + pp, t = 2 * pp;
+    // F_x carried mod 2^162 (27 digits packed in 32-bit words) and its sign
+    uint32_t xw[6] = {0u, 0u, 0u, 0u, 0u, 0u};
+    int ext;
+    {
+      v16i xa = __builtin_amdgcn_mfma_i32_32x32x32_i8(zx, ox[t], zero, 0, 0, 0);
+      v16i xb = __builtin_amdgcn_mfma_i32_32x32x32_i8(zx, ox[t + 1], zero, 0, 0, 0);
+      crt_gather_digits(xa, xb);
+      int carry = 0;
+#pragma unroll
+      for (int d = 0; d < kDigitsX; d++) {
+        const int x = crt_digit(xa, xb, d) + carry;
+        const uint32_t dg = (uint32_t)x & 63u;
+        carry = x >> 6;
+        const int bit = 6 * d, w = bit / 32, o = bit % 32;
+        xw[w] |= dg << o;
+        if (o > 26) xw[w + 1] |= dg >> (32 - o);
+      }
+      ext = (xw[(6 * kDigitsX - 1) / 32] >> ((6 * kDigitsX - 1) % 32)) & 1 ? 63 : 0;
+    }
+    // the frame: F_x's digits (sign-extended) plus H_a H_b's digit sums,
+    // carried mod 2^270 into 36-bit pieces (six digits; the last three)
+    constexpr int NP = (kDigitsQ + 5) / 6;
+    uint64_t pc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; q++) pc[q] = 0u;
+    int carry = 0;
+    auto put = [&](int d, int hd) {
+      int xd = ext;
+      if (d < kDigitsX) {
+        const int bit = 6 * d, w = bit / 32, o = bit % 32;
+        uint64_t two = xw[w];
+        if (w + 1 < 6) two |= (uint64_t)xw[w + 1] << 32;
+        xd = (int)((two >> o) & 63u);
+      }
+      const int x = xd + hd + carry;
+      carry = x >> 6;
+      pc[d / 6] |= (uint64_t)(x & 63) << (6 * (d % 6));
+    };
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      v16i ha = __builtin_amdgcn_mfma_i32_32x32x32_i8(zh0, oh[t], zero, 0, 0, 0);
+      v16i hb = __builtin_amdgcn_mfma_i32_32x32x32_i8(zh0, oh[t + 1], zero, 0, 0, 0);
+      crt_gather_digits(ha, hb);
+#pragma unroll
+      for (int d = 0; d < 32; d++) put(d, crt_digit(ha, hb, d));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      v16i ga = __builtin_amdgcn_mfma_i32_32x32x32_i8(zh1, oh[t], zero, 0, 0, 0);
+      v16i gb = __builtin_amdgcn_mfma_i32_32x32x32_i8(zh1, oh[t + 1], zero, 0, 0, 0);
+      crt_gather_digits(ga, gb);
+#pragma unroll
+      for (int d = 32; d < kDigitsQ; d++) put(d, crt_digit(ga, gb, d - 32));
+    }
+    const int64_t row = rb * 32 + 8 * h + 2 * p + lane / 32;
+    if (!live || row >= m) continue;
+    // a negative F as its magnitude (two's complement over the pieces)
+    constexpr int topbits = 6 * (kDigitsQ - 6 * (NP - 1));
+    const bool neg = ((pc[NP - 1] >> (topbits - 1)) & 1u) != 0;
+    if (neg) {
+      uint64_t cy = 1u;
+#pragma unroll
+      for (int q = 0; q < NP; q++) {
+        const uint64_t mask = q < NP - 1 ? (1ull << 36) - 1 : (1ull << topbits) - 1;
+        const uint64_t x = (mask - pc[q]) + cy;
+        pc[q] = x & mask;
+        cy = x >> (q < NP - 1 ? 36 : topbits);
+      }
+    }
+    // the pieces as doubles, most significant first
+    double v[NP];
+#pragma unroll
+    for (int q = 0; q < NP; q++) v[NP - 1 - q] = ldexp((double)pc[q], 36 * q - 6 * kDigitsQ);
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+#pragma unroll
+      for (int i = NP - 1; i > r; i--) two_sum(v[i - 1], v[i], v[i - 1], v[i]);
+    double tail = 0.0;
+#pragma unroll
+    for (int i = NP - 1; i >= 4; i--) tail += v[i];
+    qd_t f{{v[0], v[1], v[2], v[3] + tail}};
+    qd_renorm(f.c[0], f.c[1], f.c[2], f.c[3]);
+    if (neg) f = qd_neg(f);
+    qd_t x = qd_mul(f, mq);
     const int sc = ea[b * RB * 32 + row] + fexp + 42;
 #pragma unroll
     for (int c = 0; c < 4; c++) x.c[c] = ldexp(x.c[c], sc);
@@ -885,6 +886,7 @@ crt_rebuild_qd_kernel(Mat C, int64_t m, int64_t n, int64_t RB, int64_t CB, const
       x = qd_add(qd_t{{Cb[off], Cb[C.ps + off], Cb[2 * C.ps + off], Cb[3 * C.ps + off]}}, x);
 #pragma unroll
     for (int c = 0; c < 4; c++) Cb[c * C.ps + off] = x.c[c];
+  }
   }
 }
 
