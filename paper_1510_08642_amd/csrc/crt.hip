@@ -372,29 +372,7 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(CMat A, CMat B, int64_
   const int64_t lb = x / kchunks, kc = x % kchunks;
   const int t = threadIdx.x, ln = t % 32, g = t / 32;
   const int64_t line = lb * 32 + ln;
-  // exponent of this line (B: the maximum of the column's slab exponents)
-  int ex;
-  if (side == 0) {
-    ex = ea[b * RB * 32 + line];
-  } else {
-    const int c = t % 32, r = t / 32;
-    int e = -(1 << 20);
-    for (int64_t sl = r; sl < kbe; sl += 8) {
-      const int v = part[(b * kbe + sl) * (CB * 32) + lb * 32 + c];
-      e = v > e ? v : e;
-    }
-    xc[r][c] = e;
-    __syncthreads();
-    if (r == 0) {
-#pragma unroll
-      for (int q = 1; q < 8; q++) e = xc[q][c] > e ? xc[q][c] : e;
-      xc[0][c] = e;
-      if (kc == 0) fb[b * CB * 32 + lb * 32 + c] = e;
-    }
-    __syncthreads();
-    ex = xc[0][ln];
-  }
-  // the 8 values
+  // the 8 values (loaded first: their latency overlaps the exponent's)
   const CMat X = side == 0 ? A : B;
   const int64_t live = side == 0 ? m : n;
   const double* base = X.p + b * X.bstride;
@@ -407,6 +385,35 @@ __global__ __launch_bounds__(256) void crt_residue_kernel(CMat A, CMat B, int64_
     const int64_t idx = in ? (side == 0 ? line * X.ld + k : k * X.ld + line) : 0;
 #pragma unroll
     for (int c = 0; c < P; c++) v[c][q] = in ? base[c * X.ps + idx] : 0.0;
+  }
+  // exponent of this line (B: the maximum of the column's slab exponents,
+  // four independent loads a pass)
+  int ex;
+  if (side == 0) {
+    ex = ea[b * RB * 32 + line];
+  } else {
+    const int c = t % 32, r = t / 32;
+    int e = -(1 << 20);
+    for (int64_t s0 = r; s0 < kbe; s0 += 32) {
+      int pv[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int64_t sl = s0 + 8 * u;
+        pv[u] = sl < kbe ? part[(b * kbe + sl) * (CB * 32) + lb * 32 + c] : -(1 << 20);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) e = pv[u] > e ? pv[u] : e;
+    }
+    xc[r][c] = e;
+    __syncthreads();
+    if (r == 0) {
+#pragma unroll
+      for (int q = 1; q < 8; q++) e = xc[q][c] > e ? xc[q][c] : e;
+      xc[0][c] = e;
+      if (kc == 0) fb[b * CB * 32 + lb * 32 + c] = e;
+    }
+    __syncthreads();
+    ex = xc[0][ln];
   }
   // limbs of 36 bits (all exact): DD, A' = d0 + d1 2^36 + d2 2^72; QD,
   // T = sum_j d_j 2^(36 j), H = d3 + d4 2^36 + d5 2^72, L = d0 + d1 2^36 + d2 2^72
