@@ -765,7 +765,9 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int6
 // when the sign bit is set) in 36-bit pieces (exact doubles, non-negative
 // and non-overlapping), summed error-free into four terms by bottom-up
 // TwoSum passes as in qd_add; C = M 2^-256 F 2^(e + f + 42).
-__global__ __launch_bounds__(256) void crt_rebuild_qd_kernel(Mat C, int64_t m, int64_t n,
+// (three waves a SIMD: 167 registers and a few spilled, measured faster than
+// two waves without spills)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void crt_rebuild_qd_kernel(Mat C, int64_t m, int64_t n,
                                                              int64_t RB, int64_t CB,
                                                              const signed char* Chh,
                                                              const signed char* Cx,
