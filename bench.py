@@ -818,7 +818,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": ({"ozaki": "i8 mfma (i32 sums) + f64 recombination",
-                   "crt": "i8 mfma (i32 sums) + crt rebuild (160-bit fixed point) + f64"}
+                   "crt": "i8 mfma (i32 sums) + crt rebuild (%d-bit fixed point) + f64"
+                          % (160 if PM == 2 else 270)}
                   .get(args.base, "f64")),
         "data": "synthetic",
         "config": {"workload": f"{args.precision}_gemm m=n=l={n}, "
