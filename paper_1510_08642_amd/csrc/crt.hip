@@ -84,8 +84,8 @@ struct CrtResidue {
   double m[kCrtMaxN], inv[kCrtMaxN], t36[kCrtMaxN], t72[kCrtMaxN];
 };
 
-// Rebuild constants (kernel argument): Z_s in 16-bit limbs (least significant
-// first) and M 2^-160 as a DD.
+// Rebuild constants (kernel argument): Z_s = floor(y_s 2^160 / m_s) in 6-bit
+// digits, laid out as the rebuild's MFMA A operand, and M 2^-160 as a DD.
 constexpr int kDigits = 27;  // 6-bit digits of the 160-bit fixed point (162 bits)
 struct CrtRebuild {
   int N;
