@@ -689,18 +689,20 @@ __device__ __forceinline__ int crt_digit(const v16i& da, const v16i& db, int d) 
   return ((d / 4) % 2 == 0 ? da : db)[4 * (d / 8) + d % 4];
 }
 
-// Workgroup = one 32 x 32 block of C; wave h takes its rows 8 h .. 8 h + 7.
-// The sums G_d = sum_s c_s Zd_s,d (Zd: Z's 6-bit digits, |G_d| < 2^18) run
-// on the matrix cores, one MFMA per 32 outputs; lane L then carries the
-// digits of its outputs (rows 8 h + 2 p + L / 32, column L % 32, p = 0..3)
-// into the 160-bit fraction F (mod 2^160, signed), and X = F M 2^-160 in DD.
-__global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int64_t n,
+// Workgroup = one 32 x 32 block of C; wave 2 h + u takes its rows 8 h + 4 u
+// .. 8 h + 4 u + 3 (the residues' quarter h, half u).  The sums G_d =
+// sum_s c_s Zd_s,d (Zd: Z's 6-bit digits, |G_d| < 2^18) run on the matrix
+// cores, one MFMA per 32 outputs; lane L then carries the digits of its
+// outputs (rows 8 h + 2 p + L / 32, column L % 32, p = 2 u, 2 u + 1) into
+// the 160-bit fraction F (mod 2^160, signed), and X = F M 2^-160 in DD.
+__global__ __launch_bounds__(512) void crt_rebuild_kernel(Mat C, int64_t m, int64_t n,
                                                           int64_t RB, int64_t CB,
                                                           const signed char* Cres,
                                                           const int* ea, const int* fb,
                                                           int alpha, int beta, CrtRebuild cb_,
                                                           int64_t blocks) {
-  const int h = threadIdx.x / 64, lane = threadIdx.x % 64;
+  // 8 waves: wave 2 h + u takes rows 8 h + 4 u .. 8 h + 4 u + 3
+  const int h = threadIdx.x / 128, u = (threadIdx.x / 64) % 2, lane = threadIdx.x % 64;
   const int64_t blk = blockIdx.x;
   if (blk >= blocks) return;
   const int64_t per = RB * CB;
@@ -715,11 +717,12 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int6
   double* Cb = C.p + b * C.bstride;
   const v16i zero = {};
   v4i op[4];
+  crt_residue_operands(src, per * kOzFrag, cb_.N, u, op);
 #pragma unroll
-  for (int p = 0; p < 4; p++) {
-    if (p % 2 == 0) crt_residue_operands(src, per * kOzFrag, cb_.N, p / 2, op);
-    v16i da = __builtin_amdgcn_mfma_i32_32x32x32_i8(za, op[2 * (p % 2)], zero, 0, 0, 0);
-    v16i db = __builtin_amdgcn_mfma_i32_32x32x32_i8(za, op[2 * (p % 2) + 1], zero, 0, 0, 0);
+  for (int pp = 0; pp < 2; pp++) {
+    const int p = 2 * u + pp;
+    v16i da = __builtin_amdgcn_mfma_i32_32x32x32_i8(za, op[2 * pp], zero, 0, 0, 0);
+    v16i db = __builtin_amdgcn_mfma_i32_32x32x32_i8(za, op[2 * pp + 1], zero, 0, 0, 0);
     crt_gather_digits(da, db);
     const int64_t row = rb * 32 + 8 * h + 2 * p + lane / 32;
     if (!live || row >= m) continue;
@@ -765,16 +768,14 @@ __global__ __launch_bounds__(256) void crt_rebuild_kernel(Mat C, int64_t m, int6
 // when the sign bit is set) in 36-bit pieces (exact doubles, non-negative
 // and non-overlapping), summed error-free into four terms by bottom-up
 // TwoSum passes as in qd_add; C = M 2^-256 F 2^(e + f + 42).
-// (three waves a SIMD: 167 registers and a few spilled, measured faster than
-// two waves without spills)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void crt_rebuild_qd_kernel(Mat C, int64_t m, int64_t n,
-                                                             int64_t RB, int64_t CB,
-                                                             const signed char* Chh,
-                                                             const signed char* Cx,
-                                                             const int* ea, const int* fb,
-                                                             int alpha, int beta,
-                                                             CrtRebuildQ k, int64_t blocks) {
-  const int h = threadIdx.x / 64, lane = threadIdx.x % 64;
+// (eight waves a workgroup, one half of a quarter's rows each: 131
+// registers, three waves a SIMD)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void
+crt_rebuild_qd_kernel(Mat C, int64_t m, int64_t n, int64_t RB, int64_t CB, const signed char* Chh,
+                      const signed char* Cx, const int* ea, const int* fb, int alpha, int beta,
+                      CrtRebuildQ k, int64_t blocks) {
+  // 8 waves: wave 2 h + u takes rows 8 h + 4 u .. 8 h + 4 u + 3
+  const int h = threadIdx.x / 128, u = (threadIdx.x / 64) % 2, lane = threadIdx.x % 64;
   const int64_t blk = blockIdx.x;
   if (blk >= blocks) return;
   const int64_t per = RB * CB;
@@ -793,9 +794,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
   double* Cb = C.p + b * C.bstride;
   const qd_t mq{{k.mq[0], k.mq[1], k.mq[2], k.mq[3]}};
   const v16i zero = {};
-  // rows 4 u .. 4 u + 3 of the quarter, two at a time (p = 2 u + pp)
-#pragma unroll 1
-  for (int u = 0; u < 2; u++) {
   v4i ox[4], oh[4];
   crt_residue_operands(Cx + off0, per * kOzFrag, k.N, u, ox);
   crt_residue_operands(Chh + off0, per * kOzFrag, k.N, u, oh);
@@ -896,7 +894,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void c
 #pragma unroll
     for (int c = 0; c < 4; c++) Cb[c * C.ps + off] = x.c[c];
   }
-  }
 }
 
 int run_crt(int P, const GemmBatch& g, char* ws, hipStream_t s, int tile) {
@@ -972,13 +969,13 @@ int run_crt(int P, const GemmBatch& g, char* ws, hipStream_t s, int tile) {
       if ((rc = product(w.Cres, 2, 0, 1, kb0, kb1))) return rc;
       if ((rc = product(w.Cx, 1, 0, 0, 2 * kb0, 2 * kb1))) return rc;
       launch_timed("crt_rebuild_qd_kernel", crt_rebuild_qd_kernel, dim3((unsigned)blocks),
-                   dim3(256), 0, s, g.C, g.m, g.n, L.RB, L.CB, (const signed char*)w.Cres,
+                   dim3(512), 0, s, g.C, g.m, g.n, L.RB, L.CB, (const signed char*)w.Cres,
                    (const signed char*)w.Cx, (const int*)w.e.ea, (const int*)w.e.fb, g.alpha, bt,
                    k.rq, blocks);
       if ((rc = check_launch("crt_rebuild_qd_kernel"))) return rc;
     } else {
       if ((rc = product(w.Cres, 1, 0, 0, kb0, kb1))) return rc;
-      launch_timed("crt_rebuild_kernel", crt_rebuild_kernel, dim3((unsigned)blocks), dim3(256),
+      launch_timed("crt_rebuild_kernel", crt_rebuild_kernel, dim3((unsigned)blocks), dim3(512),
                    0, s, g.C, g.m, g.n, L.RB, L.CB, (const signed char*)w.Cres,
                    (const int*)w.e.ea, (const int*)w.e.fb, g.alpha, bt, k.reb, blocks);
       if ((rc = check_launch("crt_rebuild_kernel"))) return rc;
