@@ -783,7 +783,8 @@ def main():
                       [(128, "winograd", 1, "fma"), (128, "winograd", 1, "ozaki"),
                        (128, "winograd", 1, "crt"), (256, "block", 0, "ozaki")], stream)
         lu.update(bench_lu(dd, inputs, torch, dev, [1024, 2048],
-                           [(64, "block", 0, "fma"), (128, "block", 0, "ozaki")], stream, P=4))
+                           [(64, "block", 0, "fma"), (128, "block", 0, "ozaki"),
+                            (128, "block", 0, "crt")], stream, P=4))
 
     paper = None if args.no_paper else bench_paper(dd, inputs, torch, dev, stream, full=args.paper)
 
