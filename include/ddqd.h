@@ -188,7 +188,9 @@ size_t dd_gemm_grouped_workspace(int count, const ddqd_gemm_desc* descs);
 /* As dd_gemm, in QD (4 planes per matrix; Sec. 3, Table 2's precision).
  * With DDQD_BASE_OZAKI_I8 the slice count is 0 = 31 or 28..31 (else
  * DDQD_E_UNSUPPORTED); 31 slices keep the leaf error below about
- * 2^-209 l max|a_i.| max|b_.j|, QD's accuracy class. */
+ * 2^-209 l max|a_i.| max|b_.j|, QD's accuracy class.  DDQD_BASE_CRT_I8
+ * (slices 0) keeps it below about 2^-211 l max|a_i.| max|b_.j| plus the
+ * rebuild's QD rounding. */
 int qd_gemm(int64_t m, int64_t n, int64_t l, int alpha, const double* A, int64_t lda,
             int64_t psa, const double* B, int64_t ldb, int64_t psb, int beta, double* C,
             int64_t ldc, int64_t psc, int algo, int levels, int base, int slices, void* ws,
@@ -272,7 +274,7 @@ int dd_getrs_noalloc(int64_t n, int64_t nrhs, const double* LU, int64_t ldlu, in
  * The same factorisation and solve in QD (4 planes per matrix; the paper's
  * second LU workload, Sec. 4): arguments, layouts, ipiv / perm / info and
  * errors as dd_getrf / dd_getrs.  Pivots are compared, and the panel is
- * factored, in QD; the trailing update is qd_gemm's product (either base;
+ * factored, in QD; the trailing update is qd_gemm's product (any base;
  * Ozaki leaves with 31 slices).  Orders up to 8192.
  */
 int qd_getrf(int64_t n, double* A, int64_t lda, int64_t psa, int32_t* ipiv, int32_t* perm,
