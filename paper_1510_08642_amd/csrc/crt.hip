@@ -800,41 +800,32 @@ crt_rebuild_qd_kernel(Mat C, int64_t m, int64_t n, int64_t RB, int64_t CB, const
 #pragma unroll
   for (int pp = 0; pp < 2; pp++) {
     const int p = 2 * u + pp, t = 2 * pp;
-    // F_x carried mod 2^162 (27 digits packed in 32-bit words) and its sign
-    uint32_t xw[6] = {0u, 0u, 0u, 0u, 0u, 0u};
-    int ext;
+    // F_x = sum_d Gx_d 2^(6 d) (mod 2^162) taken signed: the raw sum less
+    // (q_x + s_x) 2^162, q_x its carry out of 27 digits and s_x the sign bit
+    // of what remains; in the 270-bit frame F_x 2^-108 sits on digits 0..26
+    // and 2^162 is digit 27
+    v16i xa = __builtin_amdgcn_mfma_i32_32x32x32_i8(zx, ox[t], zero, 0, 0, 0);
+    v16i xb = __builtin_amdgcn_mfma_i32_32x32x32_i8(zx, ox[t + 1], zero, 0, 0, 0);
+    crt_gather_digits(xa, xb);
+    int fix;
     {
-      v16i xa = __builtin_amdgcn_mfma_i32_32x32x32_i8(zx, ox[t], zero, 0, 0, 0);
-      v16i xb = __builtin_amdgcn_mfma_i32_32x32x32_i8(zx, ox[t + 1], zero, 0, 0, 0);
-      crt_gather_digits(xa, xb);
-      int carry = 0;
+      int carry = 0, top = 0;
 #pragma unroll
       for (int d = 0; d < kDigitsX; d++) {
-        const int x = crt_digit(xa, xb, d) + carry;
-        const uint32_t dg = (uint32_t)x & 63u;
-        carry = x >> 6;
-        const int bit = 6 * d, w = bit / 32, o = bit % 32;
-        xw[w] |= dg << o;
-        if (o > 26) xw[w + 1] |= dg >> (32 - o);
+        top = crt_digit(xa, xb, d) + carry;
+        carry = top >> 6;
       }
-      ext = (xw[(6 * kDigitsX - 1) / 32] >> ((6 * kDigitsX - 1) % 32)) & 1 ? 63 : 0;
+      fix = -(carry + ((top >> 5) & 1));
     }
-    // the frame: F_x's digits (sign-extended) plus H_a H_b's digit sums,
-    // carried mod 2^270 into 36-bit pieces (six digits; the last three)
+    // the frame: H_a H_b's digit sums plus F_x's (and the fix), carried
+    // mod 2^270 into 36-bit pieces (six digits; the last three)
     constexpr int NP = (kDigitsQ + 5) / 6;
     uint64_t pc[NP];
 #pragma unroll
     for (int q = 0; q < NP; q++) pc[q] = 0u;
     int carry = 0;
-    auto put = [&](int d, int hd) {
-      int xd = ext;
-      if (d < kDigitsX) {
-        const int bit = 6 * d, w = bit / 32, o = bit % 32;
-        uint64_t two = xw[w];
-        if (w + 1 < 6) two |= (uint64_t)xw[w + 1] << 32;
-        xd = (int)((two >> o) & 63u);
-      }
-      const int x = xd + hd + carry;
+    auto put = [&](int d, int x) {
+      x += carry;
       carry = x >> 6;
       pc[d / 6] |= (uint64_t)(x & 63) << (6 * (d % 6));
     };
@@ -844,7 +835,9 @@ crt_rebuild_qd_kernel(Mat C, int64_t m, int64_t n, int64_t RB, int64_t CB, const
       v16i hb = __builtin_amdgcn_mfma_i32_32x32x32_i8(zh0, oh[t + 1], zero, 0, 0, 0);
       crt_gather_digits(ha, hb);
 #pragma unroll
-      for (int d = 0; d < 32; d++) put(d, crt_digit(ha, hb, d));
+      for (int d = 0; d < 32; d++)
+        put(d, crt_digit(ha, hb, d) + (d < kDigitsX ? crt_digit(xa, xb, d) : 0) +
+                   (d == kDigitsX ? fix : 0));
     }
     __builtin_amdgcn_sched_barrier(0);
     {
