@@ -761,14 +761,13 @@ __global__ __launch_bounds__(512) void crt_rebuild_kernel(Mat C, int64_t m, int6
 
 // QD rebuild.  Workgroup and waves as in crt_rebuild_kernel; per pair of
 // rows three MFMA sums each: the cross product's digits against zx, and
-// H_a H_b's against zh0 and zh1.  Lane L's outputs: F_x (mod 2^162) carried
-// and made signed (its sign extended over the frame: F_x 2^-108 sits on the
-// low 27 digits of the 270-bit frame), H_a H_b's digit sums added, the
-// frame carried mod 2^270; the magnitude (the sums negated and carried again
-// when the sign bit is set) in 36-bit pieces (exact doubles, non-negative
-// and non-overlapping), summed error-free into four terms by bottom-up
-// TwoSum passes as in qd_add; C = M 2^-256 F 2^(e + f + 42).
-// (eight waves a workgroup, one half of a quarter's rows each: 131
+// H_a H_b's against zh0 and zh1.  Lane L's outputs: F_x (mod 2^162) made
+// signed by the carry-out and sign bit of its own carry pass (F_x 2^-108
+// sits on the low 27 digits of the 270-bit frame, 2^162 on digit 27), its
+// digit sums and H_a H_b's carried together mod 2^270; the magnitude (two's
+// complement when the sign bit is set) cut at its leading one into four
+// 53-bit pieces, a QD; C = M 2^-256 F 2^(e + f + 42).
+// (eight waves a workgroup, one half of a quarter's rows each: 143
 // registers, three waves a SIMD)
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void
 crt_rebuild_qd_kernel(Mat C, int64_t m, int64_t n, int64_t RB, int64_t CB, const signed char* Chh,
@@ -862,19 +861,48 @@ crt_rebuild_qd_kernel(Mat C, int64_t m, int64_t n, int64_t RB, int64_t CB, const
         cy = x >> (q < NP - 1 ? 36 : topbits);
       }
     }
-    // the pieces as doubles, most significant first
-    double v[NP];
+    // the magnitude's leading 212 bits as four 53-bit pieces: the 270 bits in
+    // 64-bit words, moved up until the leading one is bit 63 of the top word,
+    // then cut (the truncation is below 2^-211 of F); the pieces do not
+    // overlap, each below an ulp of the one before
+    uint64_t W[5] = {0u, 0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int q = 0; q < NP; q++) v[NP - 1 - q] = ldexp((double)pc[q], 36 * q - 6 * kDigitsQ);
+    for (int q = 0; q < NP; q++) {
+      const int bit = 36 * q, w = bit / 64, o = bit % 64;
+      W[w] |= pc[q] << o;
+      if (o + 36 > 64 && w + 1 < 5) W[w + 1] |= pc[q] >> (64 - o);
+    }
+    int e = 320;  // the top word's bit 63 is bit e - 1 of the integer
 #pragma unroll
-    for (int r = 0; r < 4; r++)
-#pragma unroll
-      for (int i = NP - 1; i > r; i--) two_sum(v[i - 1], v[i], v[i - 1], v[i]);
-    double tail = 0.0;
-#pragma unroll
-    for (int i = NP - 1; i >= 4; i--) tail += v[i];
-    qd_t f{{v[0], v[1], v[2], v[3] + tail}};
-    qd_renorm(f.c[0], f.c[1], f.c[2], f.c[3]);
+    for (int i = 0; i < 4; i++) {
+      const bool z = W[4] == 0u;
+      W[4] = z ? W[3] : W[4];
+      W[3] = z ? W[2] : W[3];
+      W[2] = z ? W[1] : W[2];
+      W[1] = z ? W[0] : W[1];
+      W[0] = z ? 0u : W[0];
+      e -= z ? 64 : 0;
+    }
+    qd_t f{{0.0, 0.0, 0.0, 0.0}};
+    if (W[4] != 0u) {
+      const int lz = __builtin_clzll(W[4]);
+      if (lz) {
+        W[4] = (W[4] << lz) | (W[3] >> (64 - lz));
+        W[3] = (W[3] << lz) | (W[2] >> (64 - lz));
+        W[2] = (W[2] << lz) | (W[1] >> (64 - lz));
+        W[1] = (W[1] << lz) | (W[0] >> (64 - lz));
+      }
+      e -= lz;
+      const uint64_t c0 = W[4] >> 11;
+      const uint64_t c1 = ((W[4] & 0x7FFull) << 42) | (W[3] >> 22);
+      const uint64_t c2 = ((W[3] & 0x3FFFFFull) << 31) | (W[2] >> 33);
+      const uint64_t c3 = ((W[2] & 0x1FFFFFFFFull) << 20) | (W[1] >> 44);
+      const int u0 = e - 53 - 6 * kDigitsQ;  // c0's unit (F in units of 2^-270)
+      f.c[0] = ldexp((double)c0, u0);
+      f.c[1] = ldexp((double)c1, u0 - 53);
+      f.c[2] = ldexp((double)c2, u0 - 106);
+      f.c[3] = ldexp((double)c3, u0 - 159);
+    }
     if (neg) f = qd_neg(f);
     qd_t x = qd_mul(f, mq);
     const int sc = ea[b * RB * 32 + row] + fexp + 42;
