@@ -40,9 +40,9 @@
 // so the cross product reads every block and H_a H_b every other one.  The
 // rebuild takes F_hh in 270-bit fixed point (X_hh exact to far below one
 // unit) and F_x in 162-bit (X_x within 2^77 units, needed within 2^106), the
-// latter reduced to its signed value and added 108 bits down (18-bit limbs
-// make that a whole number of limbs), and C = M (F_hh + F_x 2^-108)
-// 2^(e + f - 214) from one QD fraction.
+// latter taken signed and added 108 bits down (6-bit digits make that a
+// whole number of digits), and C = M (F_hh + F_x 2^-108) 2^(e + f - 214)
+// from one QD fraction.
 // Error: the dropped term and the roundings of the integers, each at most
 // about kc 2^(e + f - 216) (in all kc 2^(e + f - 215) <= kc 2^-211 max|a_i.|
 // max|b_.j|), and the QD roundings of the rebuild.
