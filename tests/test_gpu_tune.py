@@ -137,3 +137,28 @@ def test_lu_panel_tuner_picks_a_width_and_auto_reproduces_it(dd, P, n, base):
     assert int(to_host(f1[2])[0]) == 0
     # an order whose width was not tuned keeps the default
     assert dd.getrf_panel_lookup(P, n + 1, **kw)["panel"] == 128
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_crt_256_tiles_give_the_128_tiles_bits(dd, P):
+    """With K below two leaves' minimum the CRT candidates are the two Block
+    tiles only, timed 128 x 128 first; C then holds the 256 x 256 tiles'
+    product (each wave 4 x 4 MFMA blocks, two K blocks a barrier), which must
+    equal the default 128 x 128 call bit for bit: the tile changes only the
+    order of exact integer sums."""
+    import torch
+    print(f"case tune crt tiles P={P}", flush=True)
+    g = inputs.rng(430 + P)
+    mk = inputs.dd_uniform if P == 2 else inputs.qd_uniform
+    m, n, l = 300, 270, 20
+    A, B = mk(m, l, g), mk(l, n, g)
+    Ad, Bd = to_dev(A), to_dev(B)
+    C256 = torch.empty((P, m, n), dtype=torch.float64, device=Ad.device)
+    r = dd.tune(Ad, Bd, C256, base="crt", reps=1)
+    assert r["candidates"] == 2
+    gem = dd.dd_gemm if P == 2 else dd.qd_gemm
+    C128 = gem(Ad, Bd, algo="block", base="crt")
+    torch.cuda.synchronize()
+    C256h, C128h = to_host(C256), to_host(C128)
+    assert np.array_equal(C256h, C128h)
+    assert _err_ok(A, B, C128h, P, l)
