@@ -84,9 +84,10 @@ struct CrtResidue {
   double m[kCrtMaxN], inv[kCrtMaxN], t36[kCrtMaxN], t72[kCrtMaxN];
 };
 
-// Rebuild constants (kernel argument): Z_s = floor(y_s 2^160 / m_s) in 6-bit
+// Rebuild constants (kernel argument): Z_s = floor(y_s 2^160 / m_s) in 7-bit
 // digits, laid out as the rebuild's MFMA A operand, and M 2^-160 as a DD.
-constexpr int kDigits = 27;  // 6-bit digits of the 160-bit fixed point (162 bits)
+constexpr int kDigitBits = 7;  // digits of the 160-bit fixed point: 23 of 7 bits (161 bits)
+constexpr int kDigits = 23;
 struct CrtRebuild {
   int N;
   // the rebuild's MFMA operand: lane L holds digit L % 32 of Z_s for
@@ -175,8 +176,8 @@ Consts make_consts(int N) {
     }
     for (int d = 0; d < kDigits; d++) {
       uint32_t v = 0;
-      for (int b = 0; b < 6; b++) {
-        const int i = 6 * d + b;
+      for (int b = 0; b < kDigitBits; b++) {
+        const int i = kDigitBits * d + b;
         if (i < 160) v |= ((quo[i / 32] >> (i % 32)) & 1u) << b;
       }
       const int L = d + 32 * (s / 16), j = s % 16;
@@ -691,7 +692,7 @@ __device__ __forceinline__ int crt_digit(const v16i& da, const v16i& db, int d) 
 
 // Workgroup = one 32 x 32 block of C; wave 2 h + u takes its rows 8 h + 4 u
 // .. 8 h + 4 u + 3 (the residues' quarter h, half u).  The sums G_d =
-// sum_s c_s Zd_s,d (Zd: Z's 6-bit digits, |G_d| < 2^18) run on the matrix
+// sum_s c_s Zd_s,d (Zd: Z's 7-bit digits, |G_d| < 2^19) run on the matrix
 // cores, one MFMA per 32 outputs; lane L then carries the digits of its
 // outputs (rows 8 h + 2 p + L / 32, column L % 32, p = 2 u, 2 u + 1) into
 // the 160-bit fraction F (mod 2^160, signed), and X = F M 2^-160 in DD.
@@ -726,17 +727,17 @@ __global__ __launch_bounds__(512) void crt_rebuild_kernel(Mat C, int64_t m, int6
     crt_gather_digits(da, db);
     const int64_t row = rb * 32 + 8 * h + 2 * p + lane / 32;
     if (!live || row >= m) continue;
-    // carries: 6-bit digits, bits from 160 up dropped (the sum mod 2^160)
+    // carries: 7-bit digits, bits from 160 up dropped (the sum mod 2^160)
     uint32_t wd[5] = {0u, 0u, 0u, 0u, 0u};
     int carry = 0;
 #pragma unroll
     for (int d = 0; d < kDigits; d++) {
       const int x = crt_digit(da, db, d) + carry;
-      const uint32_t dig = (uint32_t)x & 63u;
-      carry = x >> 6;  // arithmetic
-      const int bit = 6 * d, w = bit / 32, o = bit % 32;
-      wd[w] |= dig << o;
-      if (o > 26 && w + 1 < 5) wd[w + 1] |= dig >> (32 - o);
+      const uint32_t dig = (uint32_t)x & ((1u << kDigitBits) - 1u);
+      carry = x >> kDigitBits;  // arithmetic
+      const int bit = kDigitBits * d, w = bit / 32, o = bit % 32;
+      if (w < 5) wd[w] |= dig << o;
+      if (o > 32 - kDigitBits && w + 1 < 5) wd[w + 1] |= dig >> (32 - o);
     }
     // the signed fraction F (units of 2^-160) from five 32-bit words, as a DD
     double hi = ldexp((double)(int32_t)wd[4], 128), lo = 0.0;
